@@ -1,0 +1,258 @@
+/*
+ * qs.h -- C ABI of the full-amplitude state-vector library (libqs.so).
+ *
+ * Method: the full-amplitude ("Schrodinger") mode of Wang et al., "A quantum
+ * circuit simulator and its applications on Sunway TaihuLight supercomputer"
+ * (arXiv:2008.07140), Sec. 2.2 and Sec. 2.4, with the instruction set of
+ * App. A-1.  The library keeps all 2^n complex amplitudes of an n-qubit state
+ * in the device memory of one AMD Instinct MI355X (gfx950) and updates them in
+ * place with hand-written HIP kernels.
+ *
+ * Conventions shared by every call
+ *  - Qubit k is bit k of the amplitude index: i = sum_k i_k 2^k (Sec. 2.2,
+ *    Eq. 1).  Amplitudes are stored interleaved (re, im) in index order:
+ *    QS_C128 = two doubles per amplitude (16 B), QS_C64 = two floats (8 B).
+ *  - A gate matrix on nt targets is 2^nt x 2^nt, row-major, given as (re, im)
+ *    double pairs (2 * 4^nt doubles).  Bit (nt-1-b) of its row/column index is
+ *    the value of targets[b]: targets[0] is the most significant bit, as in the
+ *    CNOT / CR / TOFFOLI matrices of App. A-1 where the first listed qubit is
+ *    the high bit.
+ *  - Controls are |1>-controls (Eq. 3; App. A-1 CNOT/CZ/CR/TOFFOLI/CONTROL):
+ *    the gate acts on the amplitudes whose control bits are all 1 and leaves
+ *    the others unchanged.
+ *  - Ownership: every host array passed in is owned by the caller and is only
+ *    read (or written, for outputs) during the call; the library copies what
+ *    it keeps.  Device memory is owned by the state unless it was borrowed
+ *    with qs_create_from_buffer.
+ *  - Ordering: calls that change a state are enqueued on the state's HIP
+ *    stream and return before the device has finished.  Calls that return
+ *    host data (qs_amplitudes, qs_probabilities, qs_norm, qs_apply_noisy_gate,
+ *    qs_run_circuit with noise sites, qs_profile_query) synchronise the stream.
+ *  - Errors: every call returns a qs_status and never aborts.  Arguments are
+ *    validated on the host before anything is enqueued, so a call that fails
+ *    validation leaves the state unchanged.  qs_last_error() returns a text
+ *    description of the last failure on the calling thread (the counterpart
+ *    of the error log of App. A-2).
+ *  - Sizes: 1 <= n <= QS_MAX_QUBITS; a gate has 1 <= nt <= QS_MAX_TARGETS
+ *    targets and nt + nc <= n qubits, all distinct and in [0, n).
+ */
+#ifndef QS_H
+#define QS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QS_MAX_QUBITS 36
+#define QS_MAX_TARGETS 6
+#define QS_MAX_KRAUS 64
+
+typedef enum { QS_C64 = 1, QS_C128 = 2 } qs_dtype;
+
+typedef enum {
+    QS_OK = 0,
+    QS_E_INVAL = -1,       /* malformed argument (null pointer, bad count, non-finite value) */
+    QS_E_RANGE = -2,       /* qubit index out of range or repeated */
+    QS_E_NOMEM = -3,       /* allocation failed or above the memory limit */
+    QS_E_DEVICE = -4,      /* a HIP runtime call failed */
+    QS_E_ZERO_NORM = -5,   /* a Kraus branch or state with zero probability */
+    QS_E_UNSUPPORTED = -6  /* valid request that the library does not implement */
+} qs_status;
+
+typedef struct qs_state qs_state;     /* opaque */
+typedef struct qs_circuit qs_circuit; /* opaque */
+
+/* ---------------------------------------------------------------- state -- */
+
+/* Allocate a 2^n-amplitude state on the current HIP device and initialise it
+ * to |0...0> (App. A-1 QINIT).  The state gets its own non-blocking stream of
+ * default priority.  Errors: QS_E_INVAL (n, dt or out), QS_E_NOMEM (device
+ * allocation failed, or 2^n * sizeof(amplitude) above qs_set_memory_limit). */
+qs_status qs_create(int n, qs_dtype dt, qs_state **out);
+
+/* Same as qs_create, but the amplitudes live in a caller-owned device buffer
+ * of `bytes` bytes (at least 2^n * sizeof(amplitude), 16-byte aligned), for
+ * example a torch tensor's storage, and work is enqueued on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  The buffer must outlive the
+ * state; qs_destroy does not free it.  The buffer is initialised to |0...0>. */
+qs_status qs_create_from_buffer(int n, qs_dtype dt, void *device_buffer, size_t bytes,
+                                void *hip_stream, qs_state **out);
+
+/* Free the state (and its device memory when owned).  NULL is accepted. */
+qs_status qs_destroy(qs_state *s);
+
+/* Re-initialise to |0...0> (App. A-1 QINIT). */
+qs_status qs_reset(qs_state *s);
+
+/* Overwrite all amplitudes from host memory: 2^n (re, im) double pairs in
+ * index order (converted to float for QS_C64).  Synchronous. */
+qs_status qs_set_amplitudes(qs_state *s, const double *amps);
+
+/* Number of qubits, dtype, and the device pointer / stream of the state. */
+qs_status qs_info(const qs_state *s, int *n, qs_dtype *dt, void **device_ptr, void **hip_stream);
+
+/* Wait for all work enqueued on the state's stream. */
+qs_status qs_synchronize(qs_state *s);
+
+/* Upper bound on the bytes one state may allocate (0 = no limit, the
+ * default).  Process-wide; lets a caller refuse oversized states up front. */
+qs_status qs_set_memory_limit(size_t bytes);
+
+/* ---------------------------------------------------------------- gates -- */
+
+/* Apply a gate: Eq. 2 for one target (the pair (alpha_i, alpha_{i+2^k}) of
+ * every i with i_k = 0 is multiplied by the 2x2 matrix), Eq. 3 for controls,
+ * and its generalisation to nt <= 6 targets (the 2^nt amplitudes that differ
+ * only in the target bits are multiplied by the matrix).  `m` holds 2 * 4^nt
+ * doubles as described above; it need not be unitary.  Diagonal matrices and
+ * matrices that act as the identity unless some target bit is 1 are
+ * recognised and applied by cheaper kernels that touch only the amplitudes
+ * they change.  Errors: QS_E_INVAL, QS_E_RANGE. */
+qs_status qs_apply_gate(qs_state *s, const int *targets, int nt, const int *controls, int nc,
+                        const double *m);
+
+/* Noisy gate of Sec. 2.4: U = `m` on the targets (no controls: nc must be 0,
+ * else QS_E_UNSUPPORTED), followed by the Kraus channel {K_b}, b < nk, given
+ * in `kraus` as nk matrices of the same layout as `m`, one after another.
+ * Branch probabilities are p_b = ||K_b U psi||^2 on the post-gate state,
+ * computed in FP64; the branch is the first b with u < p_0 + ... + p_b (if
+ * rounding leaves u beyond the total, the last b with p_b > 0); the state
+ * becomes K_b U psi / sqrt(p_b).  u in [0, 1) is supplied by the caller.
+ * On return *chosen = b and *p_chosen = p_b (either may be NULL).
+ * The Kraus set must satisfy sum_b K_b^dagger K_b = I to 1e-10 (Sec. 2.4),
+ * else QS_E_INVAL.  QS_E_ZERO_NORM if every p_b is 0.  Synchronises. */
+qs_status qs_apply_noisy_gate(qs_state *s, const int *targets, int nt, const int *controls,
+                              int nc, const double *m, const double *kraus, int nk, double u,
+                              int *chosen, double *p_chosen);
+
+/* ------------------------------------------------------------- circuits -- */
+
+/* A circuit is a flat list of gates and noise sites with DAGGER / CONTROL
+ * groups (App. A-1), built by the append calls below and consumed by
+ * qs_run_circuit.  Group markers must be balanced when the circuit is run.
+ * DAGGER: the group is replaced by the conjugate transposes of its gates in
+ * reverse order.  CONTROL q: every gate of the group gains control qubit q.
+ * Groups nest.  Noise sites inside a group are QS_E_UNSUPPORTED. */
+qs_status qs_circuit_create(qs_circuit **out);
+qs_status qs_circuit_destroy(qs_circuit *c);
+qs_status qs_circuit_append_gate(qs_circuit *c, const int *targets, int nt, const int *controls,
+                                 int nc, const double *m);
+/* A Kraus channel on `targets` acting right after the previous gate, which
+ * must have the same targets in the same order and no controls: together they
+ * form the noisy gate K_b * U of Sec. 2.4.  Noise site s of a run (s = 0, 1, ...
+ * in order) draws u = Philox4x32-10 uniform (see qs_philox_uniform) with the
+ * run's seed and trajectory. */
+qs_status qs_circuit_append_noise(qs_circuit *c, const int *targets, int nt, const double *kraus,
+                                  int nk);
+qs_status qs_circuit_begin_dagger(qs_circuit *c);
+qs_status qs_circuit_end_dagger(qs_circuit *c);
+qs_status qs_circuit_begin_control(qs_circuit *c, int qubit);
+qs_status qs_circuit_end_control(qs_circuit *c);
+/* Counts after group expansion: gates, noise sites, and logical gates (gates
+ * whose matrix is not the identity). */
+qs_status qs_circuit_counts(const qs_circuit *c, int64_t *gates, int64_t *noise_sites,
+                            int64_t *logical_gates);
+
+typedef enum {
+    QS_PLAN_UNFUSED = 0, /* one kernel launch per gate (Eq. 2 / Eq. 3 sweeps) */
+    QS_PLAN_GREEDY = 1,  /* gates fused into dense blocks of <= k_max qubits */
+    QS_PLAN_LEARNED = 2  /* fusion partition chosen with the trained cost model */
+} qs_plan;
+
+typedef struct {
+    int plan;           /* qs_plan */
+    int k_max;          /* widest fused block, 1..6 (0 = default) */
+    uint64_t seed;      /* Philox key of the noise sites */
+    uint64_t traj;      /* trajectory index (Philox counter words 2-3) */
+    int64_t *chosen;    /* optional output: Kraus branch of every noise site */
+    int64_t chosen_len; /* capacity of `chosen` */
+} qs_run_opts;
+
+/* Apply every gate and noise site of the circuit to the state, in order
+ * (Sec. 2.2, third step: one traversal of the instruction list).  opts may be
+ * NULL (= unfused, seed 0, trajectory 0).  Fused plans apply the same
+ * operator up to rounding.  Synchronises only when the circuit has noise
+ * sites.  Errors: QS_E_INVAL (unbalanced groups, k_max), QS_E_RANGE (a qubit
+ * >= n), QS_E_UNSUPPORTED (noise inside a group, or a fused plan with noise
+ * sites). */
+qs_status qs_run_circuit(qs_state *s, const qs_circuit *c, const qs_run_opts *opts);
+
+/* ------------------------------------------------------------- readout -- */
+
+/* Copy amplitudes to the host as (re, im) doubles: out[2k], out[2k+1] =
+ * alpha_{idx[k]} for k < m; idx == NULL means all 2^n amplitudes in index
+ * order (m must then be 2^n).  Indices >= 2^n are QS_E_RANGE. */
+qs_status qs_amplitudes(const qs_state *s, const uint64_t *idx, size_t m, double *out);
+
+/* PMEASURE (App. A-1): probabilities of the 2^nq outcomes of the listed
+ * qubits, accumulated in FP64; bit (nq-1-b) of the outcome index is the
+ * value of qubits[b] (first listed = most significant, as in the output of
+ * App. A-2).  qubits == NULL means all n qubits in the order n-1, ..., 0, so
+ * that out[i] = |alpha_i|^2.  The state is unchanged.  nq <= 30. */
+qs_status qs_probabilities(const qs_state *s, const int *qubits, int nq, double *out);
+
+/* Squared norm sum_i |alpha_i|^2, accumulated in FP64. */
+qs_status qs_norm(const qs_state *s, double *out);
+
+/* <Z_q> = sum_i |alpha_i|^2 (1 - 2 i_q) for every qubit q < n, in FP64. */
+qs_status qs_expect_z(const qs_state *s, double *out);
+
+/* ----------------------------------------------------- noisy trajectories -- */
+
+/* Run `count` independent noisy trajectories: trajectory t evolves a state of
+ * widths[t] qubits from |0...0> under circs[t] with Philox trajectory index t
+ * and key `seed` (noise sites drawn as in qs_run_circuit), then writes its
+ * <Z_q> for q < widths[t] to z_out at offset sum_{t' < t} widths[t'].
+ * States of all trajectories are batched on the device.  *seconds (may be
+ * NULL) receives the device time of the batch.  Errors as qs_run_circuit. */
+qs_status qs_run_trajectories(const qs_circuit *const *circs, const int *widths, int count,
+                              qs_dtype dt, uint64_t seed, double *z_out, double *seconds);
+
+/* ------------------------------------------------------------------ misc -- */
+
+/* The uniform number used for noise site `site` of trajectory `traj`:
+ * Philox4x32-10 (Salmon et al., SC'11) with counter (site lo, site hi,
+ * traj lo, traj hi) and key (seed lo, seed hi); the first two output words
+ * form x = w1 * 2^32 + w0 and u = (x >> 11) * 2^-53 in [0, 1). */
+double qs_philox_uniform(uint64_t seed, uint64_t traj, uint64_t site);
+
+/* Philox4x32-10 block function itself (counter[4], key[2] -> out[4]). */
+void qs_philox4x32_10(const uint32_t *counter, const uint32_t *key, uint32_t *out);
+
+/* Kernel timing.  While enabled, every launch on the state's stream is
+ * bracketed by HIP events.  qs_profile_query synchronises and returns, for
+ * kernel class `kernel` (qs_kernel_class), the number of launches, their
+ * summed device time in ms and their summed algorithmic bytes and flops
+ * (the bytes the method must move: read + write of every amplitude the
+ * launch changes; reductions read every amplitude once). */
+typedef enum {
+    QS_K_INIT = 0,
+    QS_K_DENSE1 = 1,  /* one target, Eq. 2 / Eq. 3 */
+    QS_K_DENSE2 = 2,  /* two targets */
+    QS_K_DENSE3 = 3,  /* three targets */
+    QS_K_DENSEN = 4,  /* four to six targets, FP64/FP32 vector units */
+    QS_K_PHASE = 5,   /* diagonal gates */
+    QS_K_FUSED = 6,   /* fused dense block on matrix cores */
+    QS_K_TILE = 7,    /* multi-gate tile sweep */
+    QS_K_REDUCE = 8,  /* FP64 reductions */
+    QS_K_OTHER = 9,
+    QS_K_COUNT = 10
+} qs_kernel_class;
+
+qs_status qs_profile_enable(qs_state *s, int on);
+qs_status qs_profile_reset(qs_state *s);
+qs_status qs_profile_query(qs_state *s, int kernel, int64_t *launches, double *total_ms,
+                           double *alg_bytes, double *alg_flops);
+
+/* Text of the last error on this thread ("" if none).  Valid until the next
+ * failing call on the same thread. */
+const char *qs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QS_H */

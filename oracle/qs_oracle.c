@@ -74,10 +74,10 @@ double or_norm2(const cplx *psi, int n)
 /* to nt targets.                                                      */
 /* ------------------------------------------------------------------ */
 
-static int check_qubits(int n, const int *t, int nt, const int *c, int nc)
+static int check_qubit_list(int n, const int *t, int nt, const int *c, int nc, int max_nt)
 {
     uint64_t seen = 0;
-    if (nt < 0 || nt > OR_MAX_T || nc < 0 || nt + nc > n) return -1;
+    if (nt < 0 || nt > max_nt || nc < 0 || nt + nc > n) return -1;
     for (int a = 0; a < nt + nc; ++a) {
         int q = a < nt ? t[a] : c[a - nt];
         if (q < 0 || q >= n) return -1;
@@ -85,6 +85,11 @@ static int check_qubits(int n, const int *t, int nt, const int *c, int nc)
         seen |= (uint64_t)1 << q;
     }
     return 0;
+}
+
+static int check_qubits(int n, const int *t, int nt, const int *c, int nc)
+{
+    return check_qubit_list(n, t, nt, c, nc, OR_MAX_T);
 }
 
 /*
@@ -133,7 +138,7 @@ int or_apply(cplx *psi, int n, const int *targets, int nt,
 /* ------------------------------------------------------------------ */
 int or_probabilities(const cplx *psi, int n, const int *qubits, int nq, double *out)
 {
-    if (check_qubits(n, qubits, nq, NULL, 0)) return -1;
+    if (check_qubit_list(n, qubits, nq, NULL, 0, n)) return -1;
     uint64_t dim = (uint64_t)1 << n;
     memset(out, 0, ((size_t)1 << nq) * sizeof(double));
     for (uint64_t i = 0; i < dim; ++i) {

@@ -1,0 +1,912 @@
+// Host side of libqs: the C ABI declared in include/qs.h.
+//
+// Validation happens here before anything is enqueued; gates are brought to
+// a canonical form (controls pulled out of the matrix, diagonal gates routed
+// to the phase kernel) and launched on the state's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "qs_internal.h"
+#include "qs_plan.h"
+
+using cd = std::complex<double>;
+
+namespace {
+
+thread_local std::string g_err;
+std::atomic<size_t> g_mem_limit{0};
+
+qs_status fail(qs_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+qs_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(QS_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                    \
+    do {                                                 \
+        hipError_t e_ = (expr);                          \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr); \
+    } while (0)
+
+size_t amp_bytes(qs_dtype dt) { return dt == QS_C128 ? 16 : 8; }
+
+struct ProfRec {
+    int kid;
+    hipEvent_t a, b;
+    double bytes, flops;
+};
+
+struct ProfAcc {
+    int64_t launches = 0;
+    double ms = 0, bytes = 0, flops = 0;
+};
+
+}  // namespace
+
+struct qs_state {
+    int n = 0;
+    qs_dtype dt = QS_C128;
+    int device = 0;
+    void *amp = nullptr;
+    size_t bytes = 0;
+    bool owned = true;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    double *red = nullptr;      // reduction scratch
+    size_t red_doubles = 0;
+    double *dout = nullptr;     // small device results (<= 64 KiB)
+    void *dmat = nullptr;       // device staging for one gate matrix
+    void *prog = nullptr;       // device matrices of a planned circuit segment
+    size_t prog_bytes = 0;
+    double *hpin = nullptr;     // pinned host results (64 KiB)
+    bool prof = false;
+    std::vector<ProfRec> pending;
+    std::vector<hipEvent_t> pool;
+    ProfAcc acc[QS_K_COUNT];
+};
+
+struct qs_circuit {
+    std::vector<qs::Op> ops;
+};
+
+namespace {
+
+// ------------------------------------------------------------ profiling --
+
+hipEvent_t take_event(qs_state *s)
+{
+    if (!s->pool.empty()) {
+        hipEvent_t e = s->pool.back();
+        s->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+qs_status harvest(qs_state *s)
+{
+    for (auto &r : s->pending) {
+        HIP_TRY(hipEventSynchronize(r.b));
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+        auto &a = s->acc[r.kid];
+        a.launches += 1;
+        a.ms += ms;
+        a.bytes += r.bytes;
+        a.flops += r.flops;
+        s->pool.push_back(r.a);
+        s->pool.push_back(r.b);
+    }
+    s->pending.clear();
+    return QS_OK;
+}
+
+struct Timed {
+    qs_state *s;
+    int kid;
+    double bytes, flops;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timed(qs_state *s_, int kid_, double bytes_, double flops_)
+        : s(s_), kid(kid_), bytes(bytes_), flops(flops_)
+    {
+        if (s->prof) {
+            if (s->pending.size() > 8192) harvest(s);
+            a = take_event(s);
+            b = take_event(s);
+            if (a) hipEventRecord(a, s->stream);
+        }
+    }
+    ~Timed()
+    {
+        if (s->prof && a && b) {
+            hipEventRecord(b, s->stream);
+            s->pending.push_back({kid, a, b, bytes, flops});
+        }
+    }
+};
+
+// ----------------------------------------------------------- validation --
+
+qs_status check_state(const qs_state *s)
+{
+    if (!s) return fail(QS_E_INVAL, "state is NULL");
+    return QS_OK;
+}
+
+qs_status check_qubits(int n, const int *t, int nt, const int *c, int nc, int max_nt)
+{
+    if (nt < 1 || nt > max_nt) return fail(QS_E_INVAL, "number of targets %d not in [1, %d]", nt, max_nt);
+    if (nc < 0) return fail(QS_E_INVAL, "negative number of controls");
+    if (!t) return fail(QS_E_INVAL, "targets is NULL");
+    if (nc > 0 && !c) return fail(QS_E_INVAL, "controls is NULL");
+    if (nt + nc > n) return fail(QS_E_RANGE, "%d qubits named on a %d-qubit state", nt + nc, n);
+    uint64_t seen = 0;
+    for (int k = 0; k < nt + nc; ++k) {
+        const int q = k < nt ? t[k] : c[k - nt];
+        if (q < 0 || q >= n) return fail(QS_E_RANGE, "qubit %d out of range [0, %d)", q, n);
+        if (seen >> q & 1) return fail(QS_E_RANGE, "qubit %d named twice", q);
+        seen |= uint64_t(1) << q;
+    }
+    return QS_OK;
+}
+
+qs_status check_matrix(const double *m, int nt)
+{
+    if (!m) return fail(QS_E_INVAL, "matrix is NULL");
+    const size_t len = size_t(2) << (2 * nt);
+    for (size_t k = 0; k < len; ++k)
+        if (!std::isfinite(m[k])) return fail(QS_E_INVAL, "matrix entry %zu is not finite", k / 2);
+    return QS_OK;
+}
+
+qs_status check_kraus(const double *kr, int nk, int nt)
+{
+    if (!kr) return fail(QS_E_INVAL, "Kraus matrices are NULL");
+    if (nk < 1 || nk > QS_MAX_KRAUS) return fail(QS_E_INVAL, "Kraus count %d not in [1, %d]", nk, QS_MAX_KRAUS);
+    const int d = 1 << nt;
+    const size_t blk = size_t(2) * d * d;
+    for (size_t k = 0; k < blk * nk; ++k)
+        if (!std::isfinite(kr[k])) return fail(QS_E_INVAL, "Kraus entry is not finite");
+    // sum_b K_b^dagger K_b = I (Sec. 2.4)
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c) {
+            cd s = 0;
+            for (int b = 0; b < nk; ++b) {
+                const double *K = kr + blk * b;
+                for (int j = 0; j < d; ++j) {
+                    cd kjr(K[2 * (j * d + r)], K[2 * (j * d + r) + 1]);
+                    cd kjc(K[2 * (j * d + c)], K[2 * (j * d + c) + 1]);
+                    s += std::conj(kjr) * kjc;
+                }
+            }
+            const cd want = (r == c) ? 1.0 : 0.0;
+            if (std::abs(s - want) > 1e-10)
+                return fail(QS_E_INVAL, "Kraus set is not complete: (sum K^dagger K)[%d][%d] = %g%+gi", r, c,
+                            s.real(), s.imag());
+        }
+    return QS_OK;
+}
+
+// ---------------------------------------------------------------- launch --
+
+double flops_dense(int nt) { return 8.0 * double(1 << nt); }  // per amplitude
+
+// Matrices of the 4-6 target kernels live in device memory.  A single gate
+// waits for earlier work on the stream before it overwrites the staging
+// buffer; a circuit uploads the matrices of a whole segment at once.
+qs_status stage_matrix(qs_state *s, const qs::CanonGate &g)
+{
+    const int d = 1 << g.targets.size();
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (s->dt == QS_C128) {
+        HIP_TRY(hipMemcpy(s->dmat, g.m.data(), size_t(16) * d * d, hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> f(size_t(2) * d * d);
+        for (size_t k = 0; k < f.size(); ++k) f[k] = float(g.m[k]);
+        HIP_TRY(hipMemcpy(s->dmat, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    return QS_OK;
+}
+
+// Launch one canonical gate.  Algorithmic bytes: every amplitude the kernel
+// changes is read and written once.  dev_m: device copy of a 4-6 target
+// matrix in the state's dtype (staged here when NULL).
+qs_status launch_canon(qs_state *s, const qs::CanonGate &g, const void *dev_m = nullptr)
+{
+    const int n = s->n;
+    const double ab = double(amp_bytes(s->dt));
+    if (g.kind == qs::CanonGate::IDENTITY) return QS_OK;
+    qs::IdxSpec ix{};
+    int all[2 * qs::kMaxQ];
+    int na = 0;
+    for (int q : g.targets) all[na++] = q;
+    for (int q : g.controls) all[na++] = q;
+    std::sort(all, all + na);
+    ix.npos = na;
+    for (int k = 0; k < na; ++k) ix.pos[k] = all[k];
+    ix.set = 0;
+    for (int q : g.controls) ix.set |= uint64_t(1) << q;
+    const int nt = int(g.targets.size());
+    const double groups = std::ldexp(1.0, n - na);
+    hipError_t e = hipSuccess;
+    if (g.kind == qs::CanonGate::PHASE) {
+        int active = 0;
+        for (int x = 0; x < (1 << nt); ++x)
+            if (!(g.m[2 * x] == 1.0 && g.m[2 * x + 1] == 0.0)) ++active;
+        Timed t(s, QS_K_PHASE, 2.0 * ab * groups * active, 6.0 * groups * active);
+        e = qs::launch_phase(s->dt, s->amp, n, ix, g.targets.data(), nt, g.m.data(), s->stream);
+    } else if (nt == 1) {
+        Timed t(s, QS_K_DENSE1, 2.0 * ab * groups * 2, flops_dense(1) * groups * 2);
+        e = qs::launch_dense1(s->dt, s->amp, n, ix, g.targets[0], g.m.data(), s->stream);
+    } else if (nt == 2) {
+        Timed t(s, QS_K_DENSE2, 2.0 * ab * groups * 4, flops_dense(2) * groups * 4);
+        e = qs::launch_dense2(s->dt, s->amp, n, ix, g.targets.data(), g.m.data(), s->stream);
+    } else if (nt == 3) {
+        Timed t(s, QS_K_DENSE3, 2.0 * ab * groups * 8, flops_dense(3) * groups * 8);
+        e = qs::launch_dense3(s->dt, s->amp, n, ix, g.targets.data(), g.m.data(), s->stream);
+    } else {
+        const int d = 1 << nt;
+        if (!dev_m) {
+            if (qs_status st = stage_matrix(s, g)) return st;
+            dev_m = s->dmat;
+        }
+        Timed t(s, QS_K_DENSEN, 2.0 * ab * groups * d, flops_dense(nt) * groups * d);
+        e = qs::launch_denseN(s->dt, s->amp, n, ix, g.targets.data(), nt, dev_m, s->stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "gate kernel launch");
+    return QS_OK;
+}
+
+// Launch a planned segment: matrices of the 4-6 target gates are uploaded
+// together first (after earlier users of the upload buffer have finished).
+qs_status launch_plan(qs_state *s, const std::vector<qs::CanonGate> &plan)
+{
+    const size_t esz = s->dt == QS_C128 ? 16 : 8;
+    std::vector<size_t> off(plan.size(), SIZE_MAX);
+    size_t total = 0;
+    for (size_t k = 0; k < plan.size(); ++k)
+        if (plan[k].kind == qs::CanonGate::DENSE && plan[k].targets.size() >= 4) {
+            off[k] = total;
+            total += esz << (2 * plan[k].targets.size());
+        }
+    if (total) {
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        if (total > s->prog_bytes) {
+            if (s->prog) HIP_TRY(hipFree(s->prog));
+            s->prog = nullptr;
+            s->prog_bytes = 0;
+            HIP_TRY(hipMalloc(&s->prog, total));
+            s->prog_bytes = total;
+        }
+        std::vector<unsigned char> host(total);
+        for (size_t k = 0; k < plan.size(); ++k) {
+            if (off[k] == SIZE_MAX) continue;
+            const std::vector<double> &m = plan[k].m;
+            if (s->dt == QS_C128) {
+                std::memcpy(host.data() + off[k], m.data(), m.size() * sizeof(double));
+            } else {
+                float *f = reinterpret_cast<float *>(host.data() + off[k]);
+                for (size_t j = 0; j < m.size(); ++j) f[j] = float(m[j]);
+            }
+        }
+        HIP_TRY(hipMemcpy(s->prog, host.data(), total, hipMemcpyHostToDevice));
+    }
+    for (size_t k = 0; k < plan.size(); ++k) {
+        const void *dm = off[k] == SIZE_MAX ? nullptr : static_cast<unsigned char *>(s->prog) + off[k];
+        if (qs_status st = launch_canon(s, plan[k], dm)) return st;
+    }
+    return QS_OK;
+}
+
+qs_status apply_gate_host(qs_state *s, const int *t, int nt, const int *c, int nc, const double *m)
+{
+    qs::CanonGate g = qs::canonicalize(t, nt, c, nc, m);
+    return launch_canon(s, g);
+}
+
+// ------------------------------------------------------------ reductions --
+
+qs_status rdm_host(qs_state *s, const int *tq, int nt, double *out /* 2*4^nt */)
+{
+    const double ab = double(amp_bytes(s->dt));
+    {
+        Timed t(s, QS_K_REDUCE, ab * std::ldexp(1.0, s->n), 8.0 * std::ldexp(1.0, s->n) * (1 << nt));
+        hipError_t e = qs::launch_rdm(s->dt, s->amp, s->n, tq, nt, s->red, s->dout, s->stream);
+        if (e != hipSuccess) return hip_fail(e, "rdm launch");
+    }
+    const size_t len = size_t(2) << (2 * nt);
+    HIP_TRY(hipMemcpyAsync(s->hpin, s->dout, len * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    std::memcpy(out, s->hpin, len * sizeof(double));
+    return QS_OK;
+}
+
+// Noise channel on the present (post-gate) state: Sec. 2.4 steps 1-3 with the
+// branch weights p_b = Tr(K_b rho_T K_b^dagger) taken from the FP64 reduced
+// density matrix of the targets (one read sweep), or directly as c_b when
+// every K_b^dagger K_b = c_b I (then p_b does not depend on the state).
+qs_status apply_channel(qs_state *s, const int *tq, int nt, const double *kr, int nk, double u,
+                        int *chosen, double *pchosen)
+{
+    const int d = 1 << nt;
+    const size_t blk = size_t(2) * d * d;
+    std::vector<double> p(nk);
+    std::vector<std::vector<cd>> KK(nk, std::vector<cd>(size_t(d) * d));
+    bool scalar = true;
+    std::vector<double> cb(nk);
+    for (int b = 0; b < nk; ++b) {
+        const double *K = kr + blk * b;
+        for (int r = 0; r < d; ++r)
+            for (int c = 0; c < d; ++c) {
+                cd acc = 0;
+                for (int j = 0; j < d; ++j)
+                    acc += std::conj(cd(K[2 * (j * d + r)], K[2 * (j * d + r) + 1])) *
+                           cd(K[2 * (j * d + c)], K[2 * (j * d + c) + 1]);
+                KK[b][size_t(r) * d + c] = acc;
+            }
+        cb[b] = KK[b][0].real();
+        for (int r = 0; r < d; ++r)
+            for (int c = 0; c < d; ++c) {
+                const cd want = (r == c) ? cd(cb[b]) : cd(0);
+                if (std::abs(KK[b][size_t(r) * d + c] - want) > 1e-14) scalar = false;
+            }
+    }
+    if (scalar) {
+        for (int b = 0; b < nk; ++b) p[b] = cb[b];
+    } else {
+        if (nt > 2) return fail(QS_E_UNSUPPORTED, "state-dependent Kraus sets on more than 2 qubits");
+        std::vector<double> rho(size_t(2) * d * d);
+        qs_status st = rdm_host(s, tq, nt, rho.data());
+        if (st) return st;
+        for (int b = 0; b < nk; ++b) {
+            // Tr(K^dagger K rho) = sum_{y,x} (K^dagger K)_{y x} rho_{x y}
+            cd tr = 0;
+            for (int y = 0; y < d; ++y)
+                for (int x = 0; x < d; ++x)
+                    tr += KK[b][size_t(y) * d + x] * cd(rho[2 * (x * d + y)], rho[2 * (x * d + y) + 1]);
+            p[b] = tr.real();
+        }
+    }
+    int pick = -1;
+    double run = 0.0;
+    for (int b = 0; b < nk; ++b) {
+        run += p[b];
+        if (u < run) {
+            pick = b;
+            break;
+        }
+    }
+    if (pick < 0)
+        for (int b = nk - 1; b >= 0; --b)
+            if (p[b] > 0) {
+                pick = b;
+                break;
+            }
+    if (pick < 0 || !(p[pick] > 0)) return fail(QS_E_ZERO_NORM, "every Kraus branch has probability 0");
+    const double sc = 1.0 / std::sqrt(p[pick]);
+    std::vector<double> m(blk);
+    const double *K = kr + blk * pick;
+    bool ident = true;
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c) {
+            const size_t k = size_t(r) * d + c;
+            m[2 * k] = K[2 * k] * sc;
+            m[2 * k + 1] = K[2 * k + 1] * sc;
+            const double want = (r == c) ? 1.0 : 0.0;
+            if (std::abs(m[2 * k] - want) > 1e-14 || std::abs(m[2 * k + 1]) > 1e-14) ident = false;
+        }
+    if (chosen) *chosen = pick;
+    if (pchosen) *pchosen = p[pick];
+    // K_b / sqrt(p_b) equal to the identity up to 1e-14 (a scaled identity
+    // branch): the renormalised state is the present one.
+    if (ident) return QS_OK;
+    return apply_gate_host(s, tq, nt, nullptr, 0, m.data());
+}
+
+qs_status alloc_state_buffers(qs_state *s)
+{
+    s->red_doubles = qs::reduce_scratch_doubles(s->n, 1024);
+    HIP_TRY(hipMalloc(&s->red, s->red_doubles * sizeof(double)));
+    HIP_TRY(hipMalloc(&s->dout, 65536));
+    HIP_TRY(hipMalloc(&s->dmat, size_t(16) << (2 * QS_MAX_TARGETS)));
+    HIP_TRY(hipHostMalloc((void **)&s->hpin, 65536, hipHostMallocDefault));
+    return QS_OK;
+}
+
+void free_state(qs_state *s)
+{
+    if (!s) return;
+    if (s->stream) hipStreamSynchronize(s->stream);
+    for (auto &r : s->pending) {
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    for (auto e : s->pool) hipEventDestroy(e);
+    if (s->owned && s->amp) hipFree(s->amp);
+    if (s->red) hipFree(s->red);
+    if (s->dout) hipFree(s->dout);
+    if (s->dmat) hipFree(s->dmat);
+    if (s->prog) hipFree(s->prog);
+    if (s->hpin) hipHostFree(s->hpin);
+    if (s->own_stream && s->stream) hipStreamDestroy(s->stream);
+    delete s;
+}
+
+qs_status init_amplitudes(qs_state *s)
+{
+    const uint64_t na = uint64_t(1) << s->n;
+    Timed t(s, QS_K_INIT, double(amp_bytes(s->dt)) * double(na), 0.0);
+    hipError_t e = qs::launch_init(s->dt, s->amp, na, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "init launch");
+    return QS_OK;
+}
+
+qs_status create_common(int n, qs_dtype dt, qs_state **out)
+{
+    if (!out) return fail(QS_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || n > QS_MAX_QUBITS) return fail(QS_E_INVAL, "n = %d not in [1, %d]", n, QS_MAX_QUBITS);
+    if (dt != QS_C64 && dt != QS_C128) return fail(QS_E_INVAL, "unknown dtype %d", int(dt));
+    return QS_OK;
+}
+
+}  // namespace
+
+// =================================================================== ABI ==
+
+extern "C" {
+
+const char *qs_last_error(void) { return g_err.c_str(); }
+
+qs_status qs_set_memory_limit(size_t bytes)
+{
+    g_mem_limit.store(bytes);
+    return QS_OK;
+}
+
+qs_status qs_create(int n, qs_dtype dt, qs_state **out)
+{
+    qs_status st = create_common(n, dt, out);
+    if (st) return st;
+    const size_t bytes = amp_bytes(dt) << n;
+    const size_t lim = g_mem_limit.load();
+    if (lim && bytes > lim)
+        return fail(QS_E_NOMEM, "state of %zu bytes exceeds the memory limit of %zu bytes", bytes, lim);
+    qs_state *s = new (std::nothrow) qs_state();
+    if (!s) return fail(QS_E_NOMEM, "host allocation failed");
+    s->n = n;
+    s->dt = dt;
+    s->bytes = bytes;
+    hipGetDevice(&s->device);
+    hipError_t e = hipMalloc(&s->amp, bytes);
+    if (e != hipSuccess) {
+        s->amp = nullptr;
+        free_state(s);
+        hipGetLastError();
+        return fail(QS_E_NOMEM, "device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+    }
+    e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        free_state(s);
+        return hip_fail(e, "hipStreamCreateWithFlags");
+    }
+    s->own_stream = true;
+    if ((st = alloc_state_buffers(s)) || (st = init_amplitudes(s))) {
+        free_state(s);
+        return st;
+    }
+    *out = s;
+    return QS_OK;
+}
+
+qs_status qs_create_from_buffer(int n, qs_dtype dt, void *buf, size_t bytes, void *stream,
+                                qs_state **out)
+{
+    qs_status st = create_common(n, dt, out);
+    if (st) return st;
+    if (!buf) return fail(QS_E_INVAL, "device buffer is NULL");
+    const size_t need = amp_bytes(dt) << n;
+    if (bytes < need) return fail(QS_E_INVAL, "buffer of %zu bytes, %zu needed", bytes, need);
+    if (reinterpret_cast<uintptr_t>(buf) % 16) return fail(QS_E_INVAL, "buffer is not 16-byte aligned");
+    qs_state *s = new (std::nothrow) qs_state();
+    if (!s) return fail(QS_E_NOMEM, "host allocation failed");
+    s->n = n;
+    s->dt = dt;
+    s->bytes = need;
+    s->amp = buf;
+    s->owned = false;
+    s->stream = (hipStream_t)stream;
+    hipGetDevice(&s->device);
+    if ((st = alloc_state_buffers(s)) || (st = init_amplitudes(s))) {
+        free_state(s);
+        return st;
+    }
+    *out = s;
+    return QS_OK;
+}
+
+qs_status qs_destroy(qs_state *s)
+{
+    free_state(s);
+    return QS_OK;
+}
+
+qs_status qs_reset(qs_state *s)
+{
+    if (qs_status st = check_state(s)) return st;
+    return init_amplitudes(s);
+}
+
+qs_status qs_set_amplitudes(qs_state *s, const double *amps)
+{
+    if (qs_status st = check_state(s)) return st;
+    if (!amps) return fail(QS_E_INVAL, "amplitudes are NULL");
+    const size_t na = size_t(1) << s->n;
+    if (s->dt == QS_C128) {
+        HIP_TRY(hipMemcpyAsync(s->amp, amps, na * 16, hipMemcpyHostToDevice, s->stream));
+    } else {
+        std::vector<float> f(2 * na);
+        for (size_t k = 0; k < 2 * na; ++k) f[k] = float(amps[k]);
+        HIP_TRY(hipMemcpyAsync(s->amp, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice,
+                               s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return QS_OK;
+}
+
+qs_status qs_info(const qs_state *s, int *n, qs_dtype *dt, void **dev, void **stream)
+{
+    if (qs_status st = check_state(s)) return st;
+    if (n) *n = s->n;
+    if (dt) *dt = s->dt;
+    if (dev) *dev = s->amp;
+    if (stream) *stream = (void *)s->stream;
+    return QS_OK;
+}
+
+qs_status qs_synchronize(qs_state *s)
+{
+    if (qs_status st = check_state(s)) return st;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return QS_OK;
+}
+
+qs_status qs_apply_gate(qs_state *s, const int *targets, int nt, const int *controls, int nc,
+                        const double *m)
+{
+    if (qs_status st = check_state(s)) return st;
+    if (qs_status st = check_qubits(s->n, targets, nt, controls, nc, QS_MAX_TARGETS)) return st;
+    if (qs_status st = check_matrix(m, nt)) return st;
+    return apply_gate_host(s, targets, nt, controls, nc, m);
+}
+
+qs_status qs_apply_noisy_gate(qs_state *s, const int *targets, int nt, const int *controls, int nc,
+                              const double *m, const double *kraus, int nk, double u, int *chosen,
+                              double *p_chosen)
+{
+    if (qs_status st = check_state(s)) return st;
+    if (nc != 0) return fail(QS_E_UNSUPPORTED, "noisy gates with controls are not supported");
+    if (qs_status st = check_qubits(s->n, targets, nt, controls, 0, QS_MAX_TARGETS)) return st;
+    if (qs_status st = check_matrix(m, nt)) return st;
+    if (qs_status st = check_kraus(kraus, nk, nt)) return st;
+    if (!(u >= 0.0 && u < 1.0)) return fail(QS_E_INVAL, "u = %g not in [0, 1)", u);
+    if (qs_status st = apply_gate_host(s, targets, nt, nullptr, 0, m)) return st;
+    return apply_channel(s, targets, nt, kraus, nk, u, chosen, p_chosen);
+}
+
+// ------------------------------------------------------------- circuits --
+
+qs_status qs_circuit_create(qs_circuit **out)
+{
+    if (!out) return fail(QS_E_INVAL, "out is NULL");
+    *out = new (std::nothrow) qs_circuit();
+    if (!*out) return fail(QS_E_NOMEM, "host allocation failed");
+    return QS_OK;
+}
+
+qs_status qs_circuit_destroy(qs_circuit *c)
+{
+    delete c;
+    return QS_OK;
+}
+
+qs_status qs_circuit_append_gate(qs_circuit *c, const int *targets, int nt, const int *controls,
+                                 int nc, const double *m)
+{
+    if (!c) return fail(QS_E_INVAL, "circuit is NULL");
+    if (qs_status st = check_qubits(QS_MAX_QUBITS, targets, nt, controls, nc, QS_MAX_TARGETS)) return st;
+    if (qs_status st = check_matrix(m, nt)) return st;
+    qs::Op op;
+    op.kind = qs::Op::GATE;
+    op.targets.assign(targets, targets + nt);
+    if (nc) op.controls.assign(controls, controls + nc);
+    op.m.assign(m, m + (size_t(2) << (2 * nt)));
+    c->ops.push_back(std::move(op));
+    return QS_OK;
+}
+
+qs_status qs_circuit_append_noise(qs_circuit *c, const int *targets, int nt, const double *kraus, int nk)
+{
+    if (!c) return fail(QS_E_INVAL, "circuit is NULL");
+    if (qs_status st = check_qubits(QS_MAX_QUBITS, targets, nt, nullptr, 0, QS_MAX_TARGETS)) return st;
+    if (qs_status st = check_kraus(kraus, nk, nt)) return st;
+    if (c->ops.empty() || c->ops.back().kind != qs::Op::GATE)
+        return fail(QS_E_INVAL, "a noise site must follow a gate");
+    const qs::Op &g = c->ops.back();
+    if (!g.controls.empty() || g.targets != std::vector<int>(targets, targets + nt))
+        return fail(QS_E_INVAL, "a noise site must have the targets of the gate before it and that gate no controls");
+    qs::Op op;
+    op.kind = qs::Op::NOISE;
+    op.targets.assign(targets, targets + nt);
+    op.nk = nk;
+    op.m.assign(kraus, kraus + (size_t(2) << (2 * nt)) * nk);
+    c->ops.push_back(std::move(op));
+    return QS_OK;
+}
+
+static qs_status push_marker(qs_circuit *c, qs::Op::Kind k, int q)
+{
+    if (!c) return fail(QS_E_INVAL, "circuit is NULL");
+    if (k == qs::Op::BEGIN_CONTROL && (q < 0 || q >= QS_MAX_QUBITS))
+        return fail(QS_E_RANGE, "control qubit %d out of range", q);
+    qs::Op op;
+    op.kind = k;
+    op.qubit = q;
+    c->ops.push_back(std::move(op));
+    return QS_OK;
+}
+
+qs_status qs_circuit_begin_dagger(qs_circuit *c) { return push_marker(c, qs::Op::BEGIN_DAGGER, -1); }
+qs_status qs_circuit_end_dagger(qs_circuit *c) { return push_marker(c, qs::Op::END_DAGGER, -1); }
+qs_status qs_circuit_begin_control(qs_circuit *c, int q) { return push_marker(c, qs::Op::BEGIN_CONTROL, q); }
+qs_status qs_circuit_end_control(qs_circuit *c) { return push_marker(c, qs::Op::END_CONTROL, -1); }
+
+qs_status qs_circuit_counts(const qs_circuit *c, int64_t *gates, int64_t *noise, int64_t *logical)
+{
+    if (!c) return fail(QS_E_INVAL, "circuit is NULL");
+    std::vector<qs::FlatOp> flat;
+    std::string err;
+    if (qs::expand(c->ops, flat, err)) return fail(QS_E_INVAL, "%s", err.c_str());
+    int64_t g = 0, z = 0, l = 0;
+    for (auto &f : flat) {
+        if (f.kind == qs::FlatOp::GATE) {
+            ++g;
+            if (!qs::is_identity(f.m, int(f.targets.size()))) ++l;
+        } else {
+            ++z;
+        }
+    }
+    if (gates) *gates = g;
+    if (noise) *noise = z;
+    if (logical) *logical = l;
+    return QS_OK;
+}
+
+qs_status qs_run_circuit(qs_state *s, const qs_circuit *c, const qs_run_opts *opts)
+{
+    if (qs_status st = check_state(s)) return st;
+    if (!c) return fail(QS_E_INVAL, "circuit is NULL");
+    qs_run_opts o{};
+    if (opts) o = *opts;
+    if (o.plan < QS_PLAN_UNFUSED || o.plan > QS_PLAN_LEARNED) return fail(QS_E_INVAL, "unknown plan %d", o.plan);
+    if (o.k_max < 0 || o.k_max > QS_MAX_TARGETS) return fail(QS_E_INVAL, "k_max = %d not in [0, %d]", o.k_max, QS_MAX_TARGETS);
+    std::vector<qs::FlatOp> flat;
+    std::string err;
+    int rc = qs::expand(c->ops, flat, err);
+    if (rc == 2) return fail(QS_E_UNSUPPORTED, "%s", err.c_str());
+    if (rc) return fail(QS_E_INVAL, "%s", err.c_str());
+    for (auto &f : flat) {
+        for (int q : f.targets)
+            if (q >= s->n) return fail(QS_E_RANGE, "qubit %d out of range [0, %d)", q, s->n);
+        for (int q : f.controls)
+            if (q >= s->n) return fail(QS_E_RANGE, "qubit %d out of range [0, %d)", q, s->n);
+    }
+    uint64_t site = 0;
+    size_t k = 0;
+    while (k < flat.size()) {
+        // segment of gates up to the next noise site
+        size_t e = k;
+        while (e < flat.size() && flat[e].kind == qs::FlatOp::GATE) ++e;
+        if (e > k) {
+            std::vector<qs::CanonGate> plan;
+            if (o.plan == QS_PLAN_UNFUSED) {
+                for (size_t j = k; j < e; ++j)
+                    plan.push_back(qs::canonicalize(flat[j].targets.data(), int(flat[j].targets.size()),
+                                                    flat[j].controls.data(), int(flat[j].controls.size()),
+                                                    flat[j].m.data()));
+            } else {
+                const int kmax = o.k_max ? o.k_max : qs::default_kmax(s->n, s->dt);
+                qs::greedy_fuse(flat, k, e, kmax, plan);
+            }
+            if (qs_status st = launch_plan(s, plan)) return st;
+        }
+        if (e < flat.size()) {
+            const qs::FlatOp &z = flat[e];
+            const double u = qs_philox_uniform(o.seed, o.traj, site);
+            int ch = -1;
+            if (qs_status st = apply_channel(s, z.targets.data(), int(z.targets.size()), z.m.data(), z.nk,
+                                             u, &ch, nullptr))
+                return st;
+            if (o.chosen && int64_t(site) < o.chosen_len) o.chosen[site] = ch;
+            ++site;
+            ++e;
+        }
+        k = e;
+    }
+    return QS_OK;
+}
+
+// -------------------------------------------------------------- readout --
+
+qs_status qs_amplitudes(const qs_state *cs, const uint64_t *idx, size_t m, double *out)
+{
+    qs_state *s = const_cast<qs_state *>(cs);
+    if (qs_status st = check_state(s)) return st;
+    if (!out && m) return fail(QS_E_INVAL, "out is NULL");
+    const uint64_t na = uint64_t(1) << s->n;
+    if (!idx) {
+        if (m != na) return fail(QS_E_INVAL, "m = %zu but the state has %llu amplitudes", m, (unsigned long long)na);
+        if (s->dt == QS_C128) {
+            HIP_TRY(hipMemcpyAsync(out, s->amp, na * 16, hipMemcpyDeviceToHost, s->stream));
+            HIP_TRY(hipStreamSynchronize(s->stream));
+        } else {
+            std::vector<float> f(2 * na);
+            HIP_TRY(hipMemcpyAsync(f.data(), s->amp, na * 8, hipMemcpyDeviceToHost, s->stream));
+            HIP_TRY(hipStreamSynchronize(s->stream));
+            for (size_t k = 0; k < 2 * na; ++k) out[k] = double(f[k]);
+        }
+        return QS_OK;
+    }
+    for (size_t k = 0; k < m; ++k)
+        if (idx[k] >= na) return fail(QS_E_RANGE, "index %llu >= 2^%d", (unsigned long long)idx[k], s->n);
+    if (m == 0) return QS_OK;
+    uint64_t *didx = nullptr;
+    double *dvals = nullptr;
+    HIP_TRY(hipMalloc(&didx, m * sizeof(uint64_t)));
+    hipError_t e = hipMalloc(&dvals, m * 2 * sizeof(double));
+    if (e != hipSuccess) {
+        hipFree(didx);
+        return hip_fail(e, "hipMalloc");
+    }
+    e = hipMemcpyAsync(didx, idx, m * sizeof(uint64_t), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = qs::launch_gather(s->dt, s->amp, didx, m, dvals, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, dvals, m * 2 * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    hipFree(didx);
+    hipFree(dvals);
+    if (e != hipSuccess) return hip_fail(e, "amplitude gather");
+    return QS_OK;
+}
+
+qs_status qs_probabilities(const qs_state *cs, const int *qubits, int nq, double *out)
+{
+    qs_state *s = const_cast<qs_state *>(cs);
+    if (qs_status st = check_state(s)) return st;
+    if (!out) return fail(QS_E_INVAL, "out is NULL");
+    std::vector<int> q;
+    if (!qubits) {
+        nq = s->n;
+        for (int k = s->n - 1; k >= 0; --k) q.push_back(k);
+    } else {
+        if (qs_status st = check_qubits(s->n, qubits, nq, nullptr, 0, 30)) return st;
+        q.assign(qubits, qubits + nq);
+    }
+    if (nq > 30) return fail(QS_E_UNSUPPORTED, "PMEASURE over more than 30 qubits");
+    const size_t nb = size_t(1) << nq;
+    double *dres = s->dout;
+    const bool big = nb * sizeof(double) > 65536;
+    if (big) HIP_TRY(hipMalloc(&dres, nb * sizeof(double)));
+    hipError_t e;
+    {
+        Timed t(s, QS_K_REDUCE, double(amp_bytes(s->dt)) * std::ldexp(1.0, s->n), 3.0 * std::ldexp(1.0, s->n));
+        e = qs::launch_probs(s->dt, s->amp, s->n, q.data(), nq, s->red, dres, s->stream);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(out, dres, nb * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (big) hipFree(dres);
+    if (e != hipSuccess) return hip_fail(e, "probabilities");
+    return QS_OK;
+}
+
+qs_status qs_norm(const qs_state *cs, double *out)
+{
+    qs_state *s = const_cast<qs_state *>(cs);
+    if (qs_status st = check_state(s)) return st;
+    if (!out) return fail(QS_E_INVAL, "out is NULL");
+    {
+        Timed t(s, QS_K_REDUCE, double(amp_bytes(s->dt)) * std::ldexp(1.0, s->n), 3.0 * std::ldexp(1.0, s->n));
+        hipError_t e = qs::launch_norm2(s->dt, s->amp, s->n, s->red, s->dout, s->stream);
+        if (e != hipSuccess) return hip_fail(e, "norm launch");
+    }
+    HIP_TRY(hipMemcpyAsync(s->hpin, s->dout, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    *out = s->hpin[0];
+    return QS_OK;
+}
+
+qs_status qs_expect_z(const qs_state *cs, double *out)
+{
+    qs_state *s = const_cast<qs_state *>(cs);
+    if (qs_status st = check_state(s)) return st;
+    if (!out) return fail(QS_E_INVAL, "out is NULL");
+    {
+        Timed t(s, QS_K_REDUCE, double(amp_bytes(s->dt)) * std::ldexp(1.0, s->n),
+                (3.0 + s->n) * std::ldexp(1.0, s->n));
+        hipError_t e = qs::launch_expect_z(s->dt, s->amp, s->n, s->red, s->dout, s->stream);
+        if (e != hipSuccess) return hip_fail(e, "expect_z launch");
+    }
+    HIP_TRY(hipMemcpyAsync(s->hpin, s->dout, s->n * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    std::memcpy(out, s->hpin, s->n * sizeof(double));
+    return QS_OK;
+}
+
+// ---------------------------------------------------------- trajectories --
+
+qs_status qs_run_trajectories(const qs_circuit *const *circs, const int *widths, int count,
+                              qs_dtype dt, uint64_t seed, double *z_out, double *seconds)
+{
+    return qs::run_trajectories(circs, widths, count, dt, seed, z_out, seconds);
+}
+
+// ------------------------------------------------------------- profiling --
+
+qs_status qs_profile_enable(qs_state *s, int on)
+{
+    if (qs_status st = check_state(s)) return st;
+    s->prof = on != 0;
+    return QS_OK;
+}
+
+qs_status qs_profile_reset(qs_state *s)
+{
+    if (qs_status st = check_state(s)) return st;
+    if (qs_status st = harvest(s)) return st;
+    for (auto &a : s->acc) a = ProfAcc{};
+    return QS_OK;
+}
+
+qs_status qs_profile_query(qs_state *s, int kernel, int64_t *launches, double *total_ms,
+                           double *alg_bytes, double *alg_flops)
+{
+    if (qs_status st = check_state(s)) return st;
+    if (kernel < 0 || kernel >= QS_K_COUNT) return fail(QS_E_INVAL, "unknown kernel class %d", kernel);
+    if (qs_status st = harvest(s)) return st;
+    const ProfAcc &a = s->acc[kernel];
+    if (launches) *launches = a.launches;
+    if (total_ms) *total_ms = a.ms;
+    if (alg_bytes) *alg_bytes = a.bytes;
+    if (alg_flops) *alg_flops = a.flops;
+    return QS_OK;
+}
+
+}  // extern "C"
+
+namespace qs {
+qs_status set_error(qs_status st, const char *msg) { return fail(st, "%s", msg); }
+qs_status run_on_state(qs_state *s, const qs_circuit *c, const qs_run_opts *o) { return qs_run_circuit(s, c, o); }
+}  // namespace qs

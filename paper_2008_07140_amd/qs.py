@@ -1,0 +1,312 @@
+"""ctypes binding of libqs.so (include/qs.h): argument marshalling only.
+
+Every step of the simulation runs in the library's HIP kernels; this module
+converts numpy arrays and circuit objects to the C ABI and raises
+``QSError`` on a negative status.  The library must have been built
+(``python -m paper_2008_07140_amd.build``); importing this module without
+it raises immediately instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Iterable, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqs.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libqs.so is not built: run `python -m paper_2008_07140_amd.build` "
+                      "(or __graft_entry__.build())")
+
+_lib = C.CDLL(LIB_PATH)
+
+C64, C128 = 1, 2
+PLAN_UNFUSED, PLAN_GREEDY, PLAN_LEARNED = 0, 1, 2
+(K_INIT, K_DENSE1, K_DENSE2, K_DENSE3, K_DENSEN, K_PHASE, K_FUSED, K_TILE, K_REDUCE,
+ K_OTHER) = range(10)
+KERNEL_NAMES = ["init", "dense1", "dense2", "dense3", "denseN", "phase", "fused", "tile",
+                "reduce", "other"]
+
+STATUS = {0: "QS_OK", -1: "QS_E_INVAL", -2: "QS_E_RANGE", -3: "QS_E_NOMEM", -4: "QS_E_DEVICE",
+          -5: "QS_E_ZERO_NORM", -6: "QS_E_UNSUPPORTED"}
+
+
+class QSError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class RunOpts(C.Structure):
+    _fields_ = [("plan", C.c_int), ("k_max", C.c_int), ("seed", C.c_uint64),
+                ("traj", C.c_uint64), ("chosen", C.POINTER(C.c_int64)),
+                ("chosen_len", C.c_int64)]
+
+
+P, I, D, U64, I64, SZ = C.c_void_p, C.c_int, C.c_double, C.c_uint64, C.c_int64, C.c_size_t
+PP = C.POINTER(C.c_void_p)
+_sig = {
+    "qs_create": ([I, I, PP], I),
+    "qs_create_from_buffer": ([I, I, P, SZ, P, PP], I),
+    "qs_destroy": ([P], I),
+    "qs_reset": ([P], I),
+    "qs_set_amplitudes": ([P, P], I),
+    "qs_info": ([P, P, P, PP, PP], I),
+    "qs_synchronize": ([P], I),
+    "qs_set_memory_limit": ([SZ], I),
+    "qs_apply_gate": ([P, P, I, P, I, P], I),
+    "qs_apply_noisy_gate": ([P, P, I, P, I, P, P, I, D, P, P], I),
+    "qs_circuit_create": ([PP], I),
+    "qs_circuit_destroy": ([P], I),
+    "qs_circuit_append_gate": ([P, P, I, P, I, P], I),
+    "qs_circuit_append_noise": ([P, P, I, P, I], I),
+    "qs_circuit_begin_dagger": ([P], I),
+    "qs_circuit_end_dagger": ([P], I),
+    "qs_circuit_begin_control": ([P, I], I),
+    "qs_circuit_end_control": ([P], I),
+    "qs_circuit_counts": ([P, P, P, P], I),
+    "qs_run_circuit": ([P, P, C.POINTER(RunOpts)], I),
+    "qs_amplitudes": ([P, P, SZ, P], I),
+    "qs_probabilities": ([P, P, I, P], I),
+    "qs_norm": ([P, P], I),
+    "qs_expect_z": ([P, P], I),
+    "qs_run_trajectories": ([P, P, I, I, U64, P, P], I),
+    "qs_philox_uniform": ([U64, U64, U64], D),
+    "qs_philox4x32_10": ([P, P, P], None),
+    "qs_profile_enable": ([P, I], I),
+    "qs_profile_reset": ([P], I),
+    "qs_profile_query": ([P, I, P, P, P, P], I),
+    "qs_last_error": ([], C.c_char_p),
+}
+for _name, (_args, _res) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+EXPORTED = sorted(_sig)
+
+
+def lib():
+    return _lib
+
+
+def last_error() -> str:
+    return _lib.qs_last_error().decode()
+
+
+def _check(st: int):
+    if st != 0:
+        raise QSError(st, last_error())
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _ints(xs) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(list(xs), dtype=np.int32))
+
+
+def _mat(m) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(m, dtype=np.complex128))
+    return a.view(np.float64).reshape(-1)
+
+
+def set_memory_limit(nbytes: int) -> None:
+    _check(_lib.qs_set_memory_limit(nbytes))
+
+
+def philox_uniform(seed: int, traj: int, site: int) -> float:
+    return _lib.qs_philox_uniform(seed, traj, site)
+
+
+def philox4x32_10(ctr, key):
+    c = np.asarray(ctr, dtype=np.uint32)
+    k = np.asarray(key, dtype=np.uint32)
+    o = np.zeros(4, dtype=np.uint32)
+    _lib.qs_philox4x32_10(_ptr(c), _ptr(k), _ptr(o))
+    return [int(v) for v in o]
+
+
+class Circuit:
+    """qs_circuit built from generator objects (Gate / Noise / Marker)."""
+
+    def __init__(self, ops: Iterable = ()):
+        h = C.c_void_p()
+        _check(_lib.qs_circuit_create(C.byref(h)))
+        self._h = h
+        for o in ops:
+            self.append(o)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def append(self, o) -> None:
+        k = o.kind
+        if k == "gate":
+            t, c, m = _ints(o.targets), _ints(o.controls), _mat(o.matrix)
+            _check(_lib.qs_circuit_append_gate(self._h, _ptr(t), len(t), _ptr(c), len(c), _ptr(m)))
+        elif k == "noise":
+            t, kr = _ints(o.targets), _mat(o.kraus)
+            _check(_lib.qs_circuit_append_noise(self._h, _ptr(t), len(t), _ptr(kr),
+                                                int(np.asarray(o.kraus).shape[0])))
+        elif k == "dagger":
+            _check(_lib.qs_circuit_begin_dagger(self._h))
+        elif k == "enddagger":
+            _check(_lib.qs_circuit_end_dagger(self._h))
+        elif k == "control":
+            _check(_lib.qs_circuit_begin_control(self._h, int(o.qubit)))
+        elif k == "endcontrol":
+            _check(_lib.qs_circuit_end_control(self._h))
+        else:
+            raise ValueError("unknown op kind %r" % k)
+
+    def counts(self):
+        g, z, l = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(_lib.qs_circuit_counts(self._h, C.byref(g), C.byref(z), C.byref(l)))
+        return g.value, z.value, l.value
+
+    def close(self):
+        if self._h:
+            _lib.qs_circuit_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class State:
+    """A 2^n-amplitude state on the current HIP device (qs_state)."""
+
+    def __init__(self, n: int, dtype: int = C128, buffer=None, stream=None):
+        h = C.c_void_p()
+        self._keep = None
+        if buffer is None:
+            _check(_lib.qs_create(n, dtype, C.byref(h)))
+        else:
+            # torch tensor (or anything exposing data_ptr / nbytes) as borrowed storage
+            ptr = buffer.data_ptr()
+            nbytes = buffer.numel() * buffer.element_size()
+            self._keep = buffer
+            _check(_lib.qs_create_from_buffer(n, dtype, C.c_void_p(ptr), nbytes,
+                                              C.c_void_p(stream or 0), C.byref(h)))
+        self._h = h
+        self.n = n
+        self.dtype = dtype
+
+    @property
+    def handle(self):
+        return self._h
+
+    def reset(self):
+        _check(_lib.qs_reset(self._h))
+
+    def set_amplitudes(self, psi: np.ndarray):
+        a = np.ascontiguousarray(np.asarray(psi, dtype=np.complex128))
+        assert a.size == 1 << self.n
+        _check(_lib.qs_set_amplitudes(self._h, _ptr(a.view(np.float64))))
+
+    def synchronize(self):
+        _check(_lib.qs_synchronize(self._h))
+
+    def apply_gate(self, targets: Sequence[int], controls: Sequence[int], matrix) -> None:
+        t, c, m = _ints(targets), _ints(controls), _mat(matrix)
+        _check(_lib.qs_apply_gate(self._h, _ptr(t), len(t), _ptr(c), len(c), _ptr(m)))
+
+    def apply_noisy_gate(self, targets, matrix, kraus, u: float, controls=()):
+        t, c, m, kr = _ints(targets), _ints(controls), _mat(matrix), _mat(kraus)
+        ch, pc = C.c_int(), C.c_double()
+        _check(_lib.qs_apply_noisy_gate(self._h, _ptr(t), len(t), _ptr(c), len(c), _ptr(m),
+                                        _ptr(kr), int(np.asarray(kraus).shape[0]), u,
+                                        C.byref(ch), C.byref(pc)))
+        return ch.value, pc.value
+
+    def run(self, circuit: Circuit, plan: int = PLAN_UNFUSED, k_max: int = 0, seed: int = 0,
+            traj: int = 0, nsites: int = 0):
+        o = RunOpts(plan=plan, k_max=k_max, seed=seed, traj=traj)
+        chosen = None
+        if nsites:
+            chosen = (C.c_int64 * nsites)()
+            o.chosen = chosen
+            o.chosen_len = nsites
+        _check(_lib.qs_run_circuit(self._h, circuit.handle, C.byref(o)))
+        return np.array(chosen[:], dtype=np.int64) if chosen is not None else None
+
+    def amplitudes(self, idx: Optional[np.ndarray] = None) -> np.ndarray:
+        if idx is None:
+            out = np.empty(1 << self.n, dtype=np.complex128)
+            _check(_lib.qs_amplitudes(self._h, None, out.size, _ptr(out.view(np.float64))))
+            return out
+        ix = np.ascontiguousarray(np.asarray(idx, dtype=np.uint64))
+        out = np.empty(ix.size, dtype=np.complex128)
+        _check(_lib.qs_amplitudes(self._h, _ptr(ix), ix.size, _ptr(out.view(np.float64))))
+        return out
+
+    def probabilities(self, qubits: Optional[Sequence[int]] = None) -> np.ndarray:
+        if qubits is None:
+            out = np.empty(1 << self.n, dtype=np.float64)
+            _check(_lib.qs_probabilities(self._h, None, 0, _ptr(out)))
+            return out
+        q = _ints(qubits)
+        out = np.empty(1 << len(q), dtype=np.float64)
+        _check(_lib.qs_probabilities(self._h, _ptr(q), len(q), _ptr(out)))
+        return out
+
+    def norm(self) -> float:
+        v = C.c_double()
+        _check(_lib.qs_norm(self._h, C.byref(v)))
+        return v.value
+
+    def expect_z(self) -> np.ndarray:
+        out = np.empty(self.n, dtype=np.float64)
+        _check(_lib.qs_expect_z(self._h, _ptr(out)))
+        return out
+
+    def profile(self, on: bool = True):
+        _check(_lib.qs_profile_enable(self._h, 1 if on else 0))
+
+    def profile_reset(self):
+        _check(_lib.qs_profile_reset(self._h))
+
+    def profile_query(self, kernel: int):
+        l, ms, b, f = C.c_int64(), C.c_double(), C.c_double(), C.c_double()
+        _check(_lib.qs_profile_query(self._h, kernel, C.byref(l), C.byref(ms), C.byref(b),
+                                     C.byref(f)))
+        return {"launches": l.value, "ms": ms.value, "bytes": b.value, "flops": f.value}
+
+    def info(self):
+        n, dt = C.c_int(), C.c_int()
+        dev, st = C.c_void_p(), C.c_void_p()
+        _check(_lib.qs_info(self._h, C.byref(n), C.byref(dt), C.byref(dev), C.byref(st)))
+        return {"n": n.value, "dtype": dt.value, "device_ptr": dev.value, "stream": st.value}
+
+    def close(self):
+        if self._h:
+            _lib.qs_destroy(self._h)
+            self._h = None
+            self._keep = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def run_trajectories(circuits: Sequence[Circuit], widths: Sequence[int], dtype: int = C64,
+                     seed: int = 0):
+    """Returns (z [sum widths], seconds)."""
+    arr = (C.c_void_p * len(circuits))(*[c.handle.value for c in circuits])
+    w = _ints(widths)
+    z = np.empty(int(w.sum()), dtype=np.float64)
+    sec = C.c_double()
+    _check(_lib.qs_run_trajectories(C.cast(arr, C.c_void_p), _ptr(w), len(circuits), dtype, seed,
+                                    _ptr(z), C.byref(sec)))
+    return z, sec.value

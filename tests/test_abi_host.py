@@ -1,0 +1,131 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol
+include/qs.h declares, and validates arguments before touching a device.
+No call here reaches the GPU."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2008_07140_amd import circuits as cg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def qs():
+    lib = os.path.join(ROOT, "paper_2008_07140_amd", "libqs.so")
+    if not os.path.exists(lib):
+        from paper_2008_07140_amd import build
+        build.build(verbose=False)
+    from paper_2008_07140_amd import qs as mod
+    return mod
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "qs.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qs_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_symbols_all_exported(qs):
+    syms = declared_symbols()
+    assert len(syms) >= 30
+    for s in syms:
+        assert hasattr(qs.lib(), s), s
+    # the binding wraps exactly the declared calls
+    assert sorted(qs.EXPORTED) == syms
+
+
+def test_philox_known_answers_and_agreement_with_oracle(qs):
+    assert qs.philox4x32_10([0, 0, 0, 0], [0, 0]) == [0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8]
+    assert qs.philox4x32_10([0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344],
+                            [0xA4093822, 0x299F31D0]) == [0xD16CFE09, 0x94FDCCEB, 0x5001E420,
+                                                          0x24126EA1]
+    rng = np.random.default_rng(1)
+    for _ in range(200):
+        seed, traj, site = (int(x) for x in rng.integers(0, 2**63, size=3))
+        assert qs.philox_uniform(seed, traj, site) == oracle.uniform(seed, traj, site)
+
+
+def test_create_validation_without_device(qs):
+    with pytest.raises(qs.QSError) as e:
+        qs.State(0)
+    assert e.value.status == -1
+    with pytest.raises(qs.QSError) as e:
+        qs.State(3, dtype=7)
+    assert e.value.status == -1
+    qs.set_memory_limit(1 << 20)
+    try:
+        with pytest.raises(qs.QSError) as e:
+            qs.State(20, qs.C128)  # 16 MiB > 1 MiB
+        assert e.value.status == -3
+        assert "memory limit" in qs.last_error()
+    finally:
+        qs.set_memory_limit(0)
+
+
+def test_circuit_validation(qs):
+    c = qs.Circuit()
+    with pytest.raises(qs.QSError) as e:
+        c.append(cg.Gate((1, 1), (), np.eye(4)))
+    assert e.value.status == -2
+    with pytest.raises(qs.QSError) as e:
+        c.append(cg.Gate((0,), (0,), np.eye(2)))
+    assert e.value.status == -2
+    with pytest.raises(qs.QSError) as e:
+        c.append(cg.Gate((0,), (), np.array([[np.nan, 0], [0, 1]])))
+    assert e.value.status == -1
+    with pytest.raises(qs.QSError) as e:
+        c.append(cg.Gate(tuple(range(7)), (), np.eye(128)))
+    assert e.value.status == -1
+    # noise must follow a gate on the same targets
+    with pytest.raises(qs.QSError):
+        c.append(cg.Noise((0,), cg.kraus_depolarizing(0.1)))
+    c.append(cg.Gate((0,), (), cg.H_GATE))
+    with pytest.raises(qs.QSError):
+        c.append(cg.Noise((1,), cg.kraus_depolarizing(0.1)))
+    bad = cg.kraus_depolarizing(0.1).copy()
+    bad[0] *= 1.01
+    with pytest.raises(qs.QSError) as e:
+        c.append(cg.Noise((0,), bad))
+    assert "not complete" in qs.last_error()
+    c.append(cg.Noise((0,), cg.kraus_depolarizing(0.1)))
+    assert c.counts() == (1, 1, 1)
+
+
+def test_circuit_group_expansion_counts(qs):
+    ops = [cg.Gate((0,), (), cg.H_GATE), cg.Marker("control", 2), cg.Marker("dagger"),
+           cg.Gate((0,), (), cg.T_GATE), cg.Gate((1,), (), np.eye(2)), cg.Marker("enddagger"),
+           cg.Marker("endcontrol")]
+    c = qs.Circuit(ops)
+    assert c.counts() == (3, 0, 2)
+    c2 = qs.Circuit([cg.Marker("dagger"), cg.Gate((0,), (), cg.H_GATE)])
+    with pytest.raises(qs.QSError) as e:
+        c2.counts()
+    assert e.value.status == -1
+    c3 = qs.Circuit([cg.Marker("control", 0), cg.Gate((1,), (), cg.H_GATE),
+                     cg.Marker("enddagger")])
+    with pytest.raises(qs.QSError):
+        c3.counts()
+    c4 = qs.Circuit([cg.Marker("control", 0), cg.Gate((0,), (), cg.H_GATE),
+                     cg.Marker("endcontrol")])
+    with pytest.raises(qs.QSError):
+        c4.counts()
+
+
+def test_workload_shapes():
+    """The generator reproduces the CZ counts per pattern of the grids."""
+    assert [len(cg.cz_pairs(4, 4, p)) for p in range(4)] == [8, 8, 4, 4]
+    assert [len(cg.cz_pairs(6, 5, p)) for p in range(4)] == [12, 15, 12, 10]
+    assert [len(cg.cz_pairs(8, 4, p)) for p in range(4)] == [16, 16, 8, 12]
+    assert [len(cg.cz_pairs(17, 2, p)) for p in range(4)] == [17, 16, 0, 16]
+    n, ops = cg.workload("rqc30_d40")
+    assert n == 30 and cg.count_gates(ops) == 1200 + 490
+    ncu3 = sum(1 for o in ops if o.name == "cu3")
+    assert 80 < ncu3 < 160
+    for o in ops:
+        if o.kind == "gate":
+            m = o.matrix
+            assert np.allclose(m.conj().T @ m, np.eye(m.shape[0]), atol=1e-14)

@@ -1,0 +1,309 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+complex128: max |delta amp| <= 1e-12 (element by element).
+complex64: infidelity <= 1e-5 and max |delta amp| <= 2e-5 after a few gates.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2008_07140_amd import circuits as cg
+from tests import appa_script
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+TOL128 = 1e-12
+
+
+@pytest.fixture(scope="module")
+def qs():
+    from paper_2008_07140_amd import qs as mod
+    return mod
+
+
+def infidelity(a, b):
+    ov = abs(np.vdot(a, b)) ** 2
+    return 1 - ov / (np.vdot(a, a).real * np.vdot(b, b).real)
+
+
+def random_gate(rng, n, nt, nc):
+    qs_ = rng.permutation(n)[: nt + nc]
+    return (tuple(int(q) for q in qs_[:nt]), tuple(int(q) for q in qs_[nt:]),
+            cg.random_unitary(1 << nt, rng))
+
+
+# ------------------------------------------------------------ single gates --
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("nt", [1, 2, 3, 4, 5, 6])
+def test_dense_gates_match_oracle(qs, dtype, nt):
+    n = 13
+    rng = np.random.default_rng(1000 + nt)
+    dt = qs.C128 if dtype == "c128" else qs.C64
+    s = qs.State(n, dt)
+    psi = cg.random_state(n, 3 + nt)
+    s.set_amplitudes(psi)
+    ref = psi.copy()
+    for trial in range(6):
+        nc = trial % 3
+        t, c, m = random_gate(rng, n, nt, nc)
+        if trial == 0:  # include the extreme positions
+            t = tuple([n - 1] + list(t[1:])) if n - 1 not in c else t
+            if 0 not in t and 0 not in c:
+                t = tuple(list(t[:-1]) + [0]) if nt > 1 else t
+        s.apply_gate(t, c, m)
+        oracle.apply(ref, t, c, m)
+    got = s.amplitudes()
+    if dtype == "c128":
+        assert np.max(np.abs(got - ref)) <= TOL128
+    else:
+        assert infidelity(ref, got) <= 1e-5
+        assert np.max(np.abs(got - ref)) <= 2e-5
+    s.close()
+
+
+@pytest.mark.parametrize("target", [0, 1, 2, 3, 5, 8, 15, 16])
+def test_one_qubit_every_position_with_controls(qs, target):
+    n = 17
+    rng = np.random.default_rng(target)
+    s = qs.State(n, qs.C128)
+    psi = cg.random_state(n, 50 + target)
+    s.set_amplitudes(psi)
+    ref = psi.copy()
+    for controls in [(), ((target + 1) % n,), ((target + 3) % n, (target + 7) % n)]:
+        m = cg.random_unitary(2, rng)
+        s.apply_gate((target,), controls, m)
+        oracle.apply(ref, (target,), controls, m)
+    assert np.max(np.abs(s.amplitudes() - ref)) <= TOL128
+
+
+def test_diagonal_and_controlled_forms(qs):
+    n = 11
+    rng = np.random.default_rng(5)
+    s = qs.State(n, qs.C128)
+    psi = cg.random_state(n, 9)
+    s.set_amplitudes(psi)
+    ref = psi.copy()
+    gates = [
+        ((3,), (), cg.T_GATE), ((0,), (), cg.rz(0.7)), ((10,), (), cg.PZ),
+        ((2, 7), (), cg.CZ_GATE), ((7, 2), (), cg.CZ_GATE), ((0, 1), (), cg.CZ_GATE),
+        ((4, 9), (), oracle.named_gate("CR", (0.3,))), ((9, 4), (), oracle.named_gate("CNOT")),
+        ((1, 5, 8), (), oracle.named_gate("TOFFOLI")), ((6,), (2, 3), cg.PX),
+        ((5,), (), np.eye(2)), ((5, 6), (), np.diag(np.exp(1j * rng.uniform(0, 6, 4)))),
+        (tuple(range(6)), (), np.diag(np.exp(1j * rng.uniform(0, 6, 64)))),
+        ((3, 8), (), oracle.named_gate("SWAP")), ((2, 9), (), oracle.named_gate("ISWAP")),
+        ((4,), (), -np.eye(2)),  # global phase
+    ]
+    for t, c, m in gates:
+        s.apply_gate(t, c, m)
+        oracle.apply(ref, t, c, m)
+        got = s.amplitudes()
+        assert np.max(np.abs(got - ref)) <= TOL128, (t, c)
+
+
+def test_edge_sizes(qs):
+    # n = 1, gate on every qubit of the state, controls on all others
+    for n in [1, 2, 6]:
+        rng = np.random.default_rng(n)
+        s = qs.State(n, qs.C128)
+        psi = cg.random_state(n, n)
+        s.set_amplitudes(psi)
+        ref = psi.copy()
+        nt = min(n, 6)
+        m = cg.random_unitary(1 << nt, rng)
+        t = tuple(range(nt))[::-1]
+        s.apply_gate(t, (), m)
+        oracle.apply(ref, t, (), m)
+        if n > 1:
+            m1 = cg.random_unitary(2, rng)
+            s.apply_gate((0,), tuple(range(1, n)), m1)
+            oracle.apply(ref, (0,), tuple(range(1, n)), m1)
+        assert np.max(np.abs(s.amplitudes() - ref)) <= TOL128
+
+
+def test_invalid_gate_leaves_state_unchanged(qs):
+    s = qs.State(5, qs.C128)
+    psi = cg.random_state(5, 2)
+    s.set_amplitudes(psi)
+    with pytest.raises(qs.QSError):
+        s.apply_gate((5,), (), cg.H_GATE)
+    with pytest.raises(qs.QSError):
+        s.apply_gate((1,), (1,), cg.H_GATE)
+    with pytest.raises(qs.QSError):
+        s.apply_noisy_gate((1,), cg.H_GATE, cg.kraus_depolarizing(0.1), 1.5)
+    assert np.max(np.abs(s.amplitudes() - psi)) == 0
+
+
+# -------------------------------------------------------------- reductions --
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_reductions(qs, dtype):
+    n = 14
+    dt = qs.C128 if dtype == "c128" else qs.C64
+    s = qs.State(n, dt)
+    psi = cg.random_state(n, 77)
+    s.set_amplitudes(psi)
+    ref = s.amplitudes()  # the stored (possibly rounded) state, exactly as doubles
+    assert abs(s.norm() - np.vdot(ref, ref).real) < 1e-13
+    for qubits in [[0], [13], [5, 2], [0, 13, 7], [1, 3, 5, 7, 9], list(range(11)),
+                   list(range(12, -1, -1)), None]:
+        got = s.probabilities(qubits)
+        want = oracle.probabilities(ref, qubits if qubits is not None else list(range(n - 1, -1, -1)))
+        assert np.max(np.abs(got - want)) < 1e-13, qubits
+    z = s.expect_z()
+    assert np.max(np.abs(z - oracle.expect_z(ref))) < 1e-12
+    rng = np.random.default_rng(0)
+    idx = rng.choice(1 << n, 500, replace=False).astype(np.uint64)
+    assert np.array_equal(s.amplitudes(idx), ref[idx])
+
+
+def test_appendix_a2_worked_example_on_gpu(qs):
+    with open(os.path.join(GOLDEN, "appA2_example.txt")) as f:
+        n, ops, pm, printed = appa_script.parse(f.read(), oracle.named_gate)
+    s = qs.State(n, qs.C128)
+    s.run(qs.Circuit(ops))
+    probs = s.probabilities(pm)
+    assert np.max(np.abs(probs - printed)) < 1e-6
+    psi, _ = oracle.run(n, ops)
+    assert np.max(np.abs(s.amplitudes() - psi)) <= TOL128
+
+
+# ------------------------------------------------------------------ circuits --
+
+
+@pytest.mark.parametrize("plan,kmax", [(0, 0), (1, 2), (1, 3), (1, 4), (1, 5), (1, 6)])
+def test_rqc16_depth20_full_vector(qs, plan, kmax):
+    n, ops = cg.workload("rqc16_d20")
+    ref, _ = oracle.run(n, ops)
+    s = qs.State(n, qs.C128)
+    s.run(qs.Circuit(ops), plan=plan, k_max=kmax)
+    got = s.amplitudes()
+    assert np.max(np.abs(got - ref)) <= TOL128
+    p = s.probabilities()
+    assert np.max(np.abs(p - np.abs(ref) ** 2)) <= 1e-14
+    s.close()
+
+
+@pytest.mark.parametrize("plan,kmax", [(0, 0), (1, 4), (1, 6)])
+def test_rqc_c64_infidelity(qs, plan, kmax):
+    rows, cols, depth = 4, 5, 40
+    ops = cg.random_circuit(rows, cols, depth, seed=2001, cu3_prob=0.1)
+    n = rows * cols
+    ref, _ = oracle.run(n, ops)
+    s = qs.State(n, qs.C64)
+    s.run(qs.Circuit(ops), plan=plan, k_max=kmax)
+    got = s.amplitudes()
+    assert infidelity(ref, got) <= 1e-5
+
+
+def test_groups_dagger_control(qs):
+    n, ops = 9, cg.random_circuit(2, 4, 5, seed=3, cu3_prob=0.3)  # gates on qubits 0..7
+    full = ([cg.Marker("control", 8)] + list(ops[:20]) + [cg.Marker("endcontrol")]
+            + [cg.Marker("dagger")] + list(ops) + [cg.Marker("control", 8)] + list(ops[:9])
+            + [cg.Marker("endcontrol"), cg.Marker("enddagger")])
+    ref, _ = oracle.run(n, full)
+    s = qs.State(n, qs.C128)
+    s.set_amplitudes(cg.random_state(n, 1))
+    s.reset()
+    s.run(qs.Circuit(full))
+    assert np.max(np.abs(s.amplitudes() - ref)) <= TOL128
+
+
+# ------------------------------------------------------------------- noise --
+
+
+def test_noisy_gate_matches_oracle_branch_and_state(qs):
+    n = 8
+    rng = np.random.default_rng(4)
+    psi = cg.random_state(n, 4)
+    cases = [((3,), cg.u3(0.4, 1.0, 2.0), cg.kraus_depolarizing(0.3)),
+             ((0,), cg.SQRT_X, cg.kraus_amplitude_damping(0.4)),
+             ((7,), cg.H_GATE, cg.kraus_phase_damping(0.5)),
+             ((2,), cg.T_GATE, cg.kraus_bit_flip(0.6)),
+             ((1, 6), cg.CZ_GATE, cg.kraus_kron(cg.kraus_depolarizing(0.2), cg.kraus_depolarizing(0.3))),
+             ((5, 4), cg.random_unitary(4, rng), cg.kraus_kron(cg.kraus_amplitude_damping(0.3),
+                                                               cg.kraus_phase_flip(0.7)))]
+    for t, m, ks in cases:
+        for u in [0.01, 0.35, 0.62, 0.97]:
+            s = qs.State(n, qs.C128)
+            s.set_amplitudes(psi)
+            ch, pc = s.apply_noisy_gate(t, m, ks, u)
+            ref = psi.copy()
+            och, opc, _ = oracle.apply_noisy(ref, t, m, ks, u)
+            assert ch == och, (t, u)
+            assert abs(pc - opc) < 1e-12
+            assert np.max(np.abs(s.amplitudes() - ref)) <= TOL128
+            s.close()
+
+
+def test_noisy_circuit_matches_oracle_trajectories(qs):
+    n = 8
+    ops = cg.random_circuit(2, 4, 6, seed=31, dep1=0.05, dep2=0.05, damping=0.05)
+    nsites = sum(1 for o in ops if o.kind == "noise")
+    c = qs.Circuit(ops)
+    s = qs.State(n, qs.C128)
+    for traj in range(6):
+        s.reset()
+        chosen = s.run(c, seed=77, traj=traj, nsites=nsites)
+        ref, och = oracle.run(n, ops, seed=77, traj=traj)
+        assert np.array_equal(chosen, och)
+        assert np.max(np.abs(s.amplitudes() - ref)) <= TOL128
+
+
+# -------------------------------------------------------- full-size checks --
+
+
+def test_rqc30_depth40_c128_full_size_properties(qs):
+    """At the benchmark size: norm preserved, and the circuit followed by its
+    DAGGER group returns |0...0> (any index error or dropped term breaks it)."""
+    n, ops = cg.workload("rqc30_d40")
+    s = qs.State(n, qs.C128)
+    s.run(qs.Circuit(ops))
+    assert abs(s.norm() - 1) < 1e-10
+    inv = [cg.Marker("dagger")] + list(ops) + [cg.Marker("enddagger")]
+    s.run(qs.Circuit(inv))
+    a = s.amplitudes(np.array([0, 1, 2, 1 << 29, (1 << 30) - 1], dtype=np.uint64))
+    assert abs(a[0] - 1) < 1e-10 and np.max(np.abs(a[1:])) < 1e-10
+    s.close()
+
+
+def test_rqc30_product_circuit_sampled_amplitudes(qs):
+    """A 30-qubit circuit made of two independent 15-qubit random circuits on
+    the even and the odd qubits: each amplitude is the product of two oracle
+    amplitudes, so 2^16 sampled outputs of the full-size launch are checked."""
+    half = cg.random_circuit(5, 3, 12, seed=909, cu3_prob=0.1)
+    half2 = cg.random_circuit(3, 5, 12, seed=910, cu3_prob=0.1)
+
+    def remap(ops, f):
+        out = []
+        for o in ops:
+            out.append(cg.Gate(tuple(f(q) for q in o.targets), tuple(f(q) for q in o.controls),
+                               o.matrix, o.name))
+        return out
+
+    ev = remap(half, lambda q: 2 * q)
+    od = remap(half2, lambda q: 2 * q + 1)
+    ops = [g for pair in zip(ev, od) for g in pair]
+    a_ev, _ = oracle.run(15, half)
+    a_od, _ = oracle.run(15, half2)
+    rng = np.random.default_rng(1)
+    idx = rng.choice(1 << 30, 1 << 16, replace=False).astype(np.uint64)
+    idx[:4] = [0, 1, (1 << 30) - 1, 1 << 29]
+    ev_idx = np.zeros(idx.size, dtype=np.int64)
+    od_idx = np.zeros(idx.size, dtype=np.int64)
+    for b in range(15):
+        ev_idx |= ((idx >> np.uint64(2 * b)) & np.uint64(1)).astype(np.int64) << b
+        od_idx |= ((idx >> np.uint64(2 * b + 1)) & np.uint64(1)).astype(np.int64) << b
+    want = a_ev[ev_idx] * a_od[od_idx]
+    for dt, plan, kmax, tol in [(qs.C128, 0, 0, TOL128), (qs.C64, 1, 4, 2e-6)]:
+        s = qs.State(30, dt)
+        s.run(qs.Circuit(ops), plan=plan, k_max=kmax)
+        got = s.amplitudes(idx)
+        assert np.max(np.abs(got - want)) <= tol
+        s.close()
