@@ -169,12 +169,25 @@ typedef struct {
     uint64_t traj;      /* trajectory index (Philox counter words 2-3) */
     int64_t *chosen;    /* optional output: Kraus branch of every noise site */
     int64_t chosen_len; /* capacity of `chosen` */
+    int tile_qubits;    /* complex64 fused plans: qubits per LDS tile, 9..13 (0 = default) */
 } qs_run_opts;
+
+/* Shape of the plan qs_run_circuit would execute for this circuit on an
+ * n-qubit state of dtype dt with these options (opts may be NULL): the number
+ * of kernel launches that sweep the whole state, the number of fused blocks
+ * (dense matrix-core blocks and diagonal passes inside those sweeps, or fused
+ * gates of the per-block plan) and the number of logical gates.  Host only. */
+qs_status qs_circuit_plan_info(const qs_circuit *c, int n, qs_dtype dt, const qs_run_opts *opts,
+                               int64_t *sweeps, int64_t *blocks, int64_t *logical_gates);
 
 /* Apply every gate and noise site of the circuit to the state, in order
  * (Sec. 2.2, third step: one traversal of the instruction list).  opts may be
  * NULL (= unfused, seed 0, trajectory 0).  Fused plans apply the same
- * operator up to rounding.  Synchronises only when the circuit has noise
+ * operator up to rounding: on complex64 states they run as tile sweeps (a
+ * tile of 2^tile_qubits amplitudes in LDS receives a run of fused 4- and
+ * 5-qubit blocks on the matrix cores, with split-bfloat16 operands and FP32
+ * accumulation, keeping about 16 significant bits per block); on complex128
+ * states as one FP64 sweep per fused block.  Synchronises only when the circuit has noise
  * sites.  Errors: QS_E_INVAL (unbalanced groups, k_max), QS_E_RANGE (a qubit
  * >= n), QS_E_UNSUPPORTED (noise inside a group, or a fused plan with noise
  * sites). */

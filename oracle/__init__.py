@@ -41,6 +41,8 @@ def lib():
             L = C.CDLL(LIB)
             P = C.c_void_p
             i, d, u64 = C.c_int, C.c_double, C.c_uint64
+            L.or_num_threads.argtypes = []
+            L.or_num_threads.restype = i
             L.or_init.argtypes = [P, i]
             L.or_norm2.argtypes = [P, i]
             L.or_norm2.restype = d
@@ -74,6 +76,10 @@ def _ints(xs):
 
 def _cmat(m):
     return np.ascontiguousarray(np.asarray(m, dtype=np.complex128))
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())
 
 
 def zero_state(n: int) -> np.ndarray:

@@ -38,6 +38,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -45,6 +46,9 @@
 typedef double complex cplx;
 
 #define OR_MAX_T 8 /* largest dense gate the oracle accepts: 2^8 x 2^8 */
+
+/* Threads the OpenMP loops of the oracle use. */
+int or_num_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------ */
 /* State                                                               */

@@ -19,6 +19,7 @@
 
 #include "qs_internal.h"
 #include "qs_plan.h"
+#include "qs_tile.h"
 
 using cd = std::complex<double>;
 
@@ -325,6 +326,172 @@ qs_status apply_gate_host(qs_state *s, const int *t, int nt, const int *c, int n
 {
     qs::CanonGate g = qs::canonicalize(t, nt, c, nc, m);
     return launch_canon(s, g);
+}
+
+// ---------------------------------------------------------- tile sweeps --
+
+uint16_t bf16_rne(float f)
+{
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
+}
+
+float bf16_float(uint16_t h)
+{
+    const uint32_t u = uint32_t(h) << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+// Matrix-core operand fragments of a dense 2^k block, in the order the tile
+// kernel's lanes read them: for the real form A (2D x 2D, D = 2^k, entries
+// [[Re U, -Im U], [Im U, Re U]] per complex entry with re/im interleaved),
+// fragment (mt, s) of lane l holds A[16 mt + l % 16][32 s + 8 (l / 16) + j],
+// j < 8, as bfloat16 (hi), followed by the same layout of the remainders (lo).
+void append_fragments(const std::vector<double> &m, int k, std::vector<uint16_t> &out)
+{
+    const int D = 1 << k, MT = 2 * D / 16, KS = 2 * D / 32;
+    const size_t base = out.size();
+    const size_t nfr = size_t(MT) * KS * 64 * 8;
+    out.resize(base + 2 * nfr);
+    for (int mt = 0; mt < MT; ++mt)
+        for (int s2 = 0; s2 < KS; ++s2)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int j = 0; j < 8; ++j) {
+                    const int row = 16 * mt + lane % 16, col = 32 * s2 + 8 * (lane / 16) + j;
+                    const int r = row / 2, a = row % 2, c = col / 2, b = col % 2;
+                    const double ur = m[2 * (size_t(r) * D + c)], ui = m[2 * (size_t(r) * D + c) + 1];
+                    const double v = (a == 0) ? (b == 0 ? ur : -ui) : (b == 0 ? ui : ur);
+                    const uint16_t h = bf16_rne(float(v));
+                    const uint16_t l = bf16_rne(float(v - double(bf16_float(h))));
+                    const size_t idx = ((size_t(mt) * KS + s2) * 64 + lane) * 8 + j;
+                    out[base + idx] = h;
+                    out[base + nfr + idx] = l;
+                }
+}
+
+struct TileProgram {
+    std::vector<qs::TileOpDev> ops;
+    std::vector<uint16_t> data;  // 16-byte aligned records
+    std::vector<size_t> first;   // first op of each sweep step
+};
+
+void pad16(std::vector<uint16_t> &d)
+{
+    while (d.size() % 8) d.push_back(0);
+}
+
+void build_tile_program(const std::vector<qs::PlanStep> &steps, TileProgram &tp)
+{
+    for (const auto &st : steps) {
+        tp.first.push_back(tp.ops.size());
+        if (!st.sweep) continue;
+        const auto &Q = st.sw.Q;
+        auto lpos = [&](int q) {
+            for (size_t b = 0; b < Q.size(); ++b)
+                if (Q[b] == q) return int(b);
+            return -1;
+        };
+        for (const auto &op : st.sw.ops) {
+            qs::TileOpDev d{};
+            pad16(tp.data);
+            d.data_off = uint32_t(tp.data.size() / 8);
+            d.k = int(op.qubits.size());
+            d.no = int(op.outer.size());
+            for (int b = 0; b < d.k; ++b) d.lpos[b] = lpos(op.qubits[b]);
+            for (int b = 0; b < d.no; ++b) d.opos[b] = op.outer[b];
+            if (op.kind == qs::TileOp::DENSE) {
+                d.kind = 0;
+                d.skip = op.skip;
+                const int D = 1 << d.k;
+                const size_t per = size_t(2) * D * D;
+                const size_t before = tp.data.size();
+                for (size_t p = 0; p < op.m.size() / per; ++p) {
+                    std::vector<double> mp(op.m.begin() + p * per, op.m.begin() + (p + 1) * per);
+                    append_fragments(mp, d.k, tp.data);
+                    if (p == 0) d.frag_stride = uint32_t((tp.data.size() - before) / 8);
+                }
+            } else {
+                d.kind = 1;
+                const size_t ent = op.m.size() / 2;
+                for (size_t x = 0; x < ent; ++x) {
+                    const float re = float(op.m[2 * x]), im = float(op.m[2 * x + 1]);
+                    uint32_t ur, ui;
+                    std::memcpy(&ur, &re, 4);
+                    std::memcpy(&ui, &im, 4);
+                    tp.data.push_back(uint16_t(ur));
+                    tp.data.push_back(uint16_t(ur >> 16));
+                    tp.data.push_back(uint16_t(ui));
+                    tp.data.push_back(uint16_t(ui >> 16));
+                }
+            }
+            tp.ops.push_back(d);
+        }
+    }
+    pad16(tp.data);
+    if (tp.data.empty()) tp.data.resize(8, 0);
+    if (tp.ops.empty()) tp.ops.resize(1);
+}
+
+qs::TileParams tile_params(int n, const qs_run_opts &o)
+{
+    qs::TileParams tp;
+    tp.m = o.tile_qubits ? o.tile_qubits : qs::default_tile_qubits(n);
+    tp.m = std::min(tp.m, n);
+    tp.L = 4;
+    tp.kmax = (o.k_max >= 4 && o.k_max <= 5) ? o.k_max : 5;
+    return tp;
+}
+
+bool tiled_plan(const qs_state *s, const qs_run_opts &o)
+{
+    return o.plan != QS_PLAN_UNFUSED && s->dt == QS_C64 && s->n >= 9;
+}
+
+qs_status launch_tiled(qs_state *s, const std::vector<qs::PlanStep> &steps)
+{
+    TileProgram tp;
+    build_tile_program(steps, tp);
+    const size_t ob = tp.ops.size() * sizeof(qs::TileOpDev);
+    const size_t db = tp.data.size() * sizeof(uint16_t);
+    const size_t total = ((ob + 255) / 256) * 256 + db;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (total > s->prog_bytes) {
+        if (s->prog) HIP_TRY(hipFree(s->prog));
+        s->prog = nullptr;
+        s->prog_bytes = 0;
+        HIP_TRY(hipMalloc(&s->prog, total));
+        s->prog_bytes = total;
+    }
+    unsigned char *dev = static_cast<unsigned char *>(s->prog);
+    const size_t doff = ((ob + 255) / 256) * 256;
+    HIP_TRY(hipMemcpy(dev, tp.ops.data(), ob, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dev + doff, tp.data.data(), db, hipMemcpyHostToDevice));
+    const qs::TileOpDev *dops = reinterpret_cast<const qs::TileOpDev *>(dev);
+    const double sweep_bytes = 2.0 * 8.0 * std::ldexp(1.0, s->n);
+    for (size_t i = 0; i < steps.size(); ++i) {
+        const qs::PlanStep &st = steps[i];
+        if (!st.sweep) {
+            if (qs_status e = launch_canon(s, st.gate)) return e;
+            continue;
+        }
+        qs::TileArgs ta{};
+        ta.m = int(st.sw.Q.size());
+        ta.L = 4;
+        ta.nops = int(st.sw.ops.size());
+        for (int b = 0; b < ta.m; ++b) ta.Q[b] = st.sw.Q[b];
+        double flops = 0;
+        for (const auto &op : st.sw.ops)
+            flops += (op.kind == qs::TileOp::DENSE ? 8.0 * double(1 << op.qubits.size()) : 6.0) *
+                     std::ldexp(1.0, s->n);
+        Timed t(s, QS_K_TILE, sweep_bytes, flops);
+        hipError_t e = qs::launch_tile(s->amp, s->n, ta, dops + tp.first[i], dev + doff, s->stream);
+        if (e != hipSuccess) return hip_fail(e, "tile kernel launch");
+    }
+    return QS_OK;
 }
 
 // ------------------------------------------------------------ reductions --
@@ -706,6 +873,57 @@ qs_status qs_circuit_counts(const qs_circuit *c, int64_t *gates, int64_t *noise,
     return QS_OK;
 }
 
+qs_status qs_circuit_plan_info(const qs_circuit *c, int n, qs_dtype dt, const qs_run_opts *opts,
+                               int64_t *sweeps, int64_t *blocks, int64_t *logical)
+{
+    if (!c) return fail(QS_E_INVAL, "circuit is NULL");
+    if (n < 1 || n > QS_MAX_QUBITS) return fail(QS_E_INVAL, "n = %d not in [1, %d]", n, QS_MAX_QUBITS);
+    qs_run_opts o{};
+    if (opts) o = *opts;
+    std::vector<qs::FlatOp> flat;
+    std::string err;
+    if (int rc = qs::expand(c->ops, flat, err)) return fail(rc == 2 ? QS_E_UNSUPPORTED : QS_E_INVAL, "%s", err.c_str());
+    int64_t sw = 0, bl = 0, lg = 0;
+    qs_state probe;
+    probe.n = n;
+    probe.dt = dt;
+    size_t k = 0;
+    while (k < flat.size()) {
+        size_t e = k;
+        while (e < flat.size() && flat[e].kind == qs::FlatOp::GATE) {
+            if (!qs::is_identity(flat[e].m, int(flat[e].targets.size()))) ++lg;
+            ++e;
+        }
+        if (e > k) {
+            if (tiled_plan(&probe, o)) {
+                std::vector<qs::PlanStep> steps;
+                qs::plan_tiles(flat, k, e, n, tile_params(n, o), steps);
+                for (auto &st : steps) {
+                    ++sw;
+                    bl += st.sweep ? int64_t(st.sw.ops.size()) : 1;
+                }
+            } else {
+                std::vector<qs::CanonGate> plan;
+                if (o.plan == QS_PLAN_UNFUSED) {
+                    for (size_t j = k; j < e; ++j)
+                        plan.push_back(qs::canonicalize(flat[j].targets.data(), int(flat[j].targets.size()),
+                                                        flat[j].controls.data(), int(flat[j].controls.size()),
+                                                        flat[j].m.data()));
+                } else {
+                    qs::greedy_fuse(flat, k, e, o.k_max ? o.k_max : qs::default_kmax(n, dt), plan);
+                }
+                for (auto &g : plan)
+                    if (g.kind != qs::CanonGate::IDENTITY) ++sw, ++bl;
+            }
+        }
+        k = e < flat.size() ? e + 1 : e;
+    }
+    if (sweeps) *sweeps = sw;
+    if (blocks) *blocks = bl;
+    if (logical) *logical = lg;
+    return QS_OK;
+}
+
 qs_status qs_run_circuit(qs_state *s, const qs_circuit *c, const qs_run_opts *opts)
 {
     if (qs_status st = check_state(s)) return st;
@@ -714,6 +932,8 @@ qs_status qs_run_circuit(qs_state *s, const qs_circuit *c, const qs_run_opts *op
     if (opts) o = *opts;
     if (o.plan < QS_PLAN_UNFUSED || o.plan > QS_PLAN_LEARNED) return fail(QS_E_INVAL, "unknown plan %d", o.plan);
     if (o.k_max < 0 || o.k_max > QS_MAX_TARGETS) return fail(QS_E_INVAL, "k_max = %d not in [0, %d]", o.k_max, QS_MAX_TARGETS);
+    if (o.tile_qubits && (o.tile_qubits < 9 || o.tile_qubits > 13))
+        return fail(QS_E_INVAL, "tile_qubits = %d not in [9, 13]", o.tile_qubits);
     std::vector<qs::FlatOp> flat;
     std::string err;
     int rc = qs::expand(c->ops, flat, err);
@@ -733,7 +953,11 @@ qs_status qs_run_circuit(qs_state *s, const qs_circuit *c, const qs_run_opts *op
         while (e < flat.size() && flat[e].kind == qs::FlatOp::GATE) ++e;
         if (e > k) {
             std::vector<qs::CanonGate> plan;
-            if (o.plan == QS_PLAN_UNFUSED) {
+            if (tiled_plan(s, o)) {
+                std::vector<qs::PlanStep> steps;
+                qs::plan_tiles(flat, k, e, s->n, tile_params(s->n, o), steps);
+                if (qs_status st = launch_tiled(s, steps)) return st;
+            } else if (o.plan == QS_PLAN_UNFUSED) {
                 for (size_t j = k; j < e; ++j)
                     plan.push_back(qs::canonicalize(flat[j].targets.data(), int(flat[j].targets.size()),
                                                     flat[j].controls.data(), int(flat[j].controls.size()),
@@ -742,7 +966,8 @@ qs_status qs_run_circuit(qs_state *s, const qs_circuit *c, const qs_run_opts *op
                 const int kmax = o.k_max ? o.k_max : qs::default_kmax(s->n, s->dt);
                 qs::greedy_fuse(flat, k, e, kmax, plan);
             }
-            if (qs_status st = launch_plan(s, plan)) return st;
+            if (!plan.empty())
+                if (qs_status st = launch_plan(s, plan)) return st;
         }
         if (e < flat.size()) {
             const qs::FlatOp &z = flat[e];

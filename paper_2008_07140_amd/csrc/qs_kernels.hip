@@ -16,7 +16,7 @@ namespace qs {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr uint64_t kMaxBlocks = 1u << 20;  // grid-stride above this
+constexpr uint64_t kMaxBlocks = 1u << 22;  // grid-stride above this (grid * 256 < 2^32)
 
 __device__ __forceinline__ uint64_t insert_zeros(uint64_t t, const IdxSpec &ix)
 {
@@ -77,11 +77,73 @@ __global__ __launch_bounds__(kBlock) void k_scale(typename Cpx<R>::T *a, uint64_
     }
 }
 
+// Streaming loads and stores of amplitudes.  A gate sweep touches every
+// amplitude once, so the accesses are marked non-temporal (no reuse).
+template <typename R>
+struct Vec2;
+template <>
+struct Vec2<double> {
+    typedef double T __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Vec2<float> {
+    typedef float T __attribute__((ext_vector_type(2)));
+};
+
+template <typename C>
+__device__ __forceinline__ C ld_stream(const C *p)
+{
+    using R = decltype(C().x);
+    using V = typename Vec2<R>::T;
+    const V v = __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
+    C c;
+    c.x = v.x;
+    c.y = v.y;
+    return c;
+}
+
+template <typename C>
+__device__ __forceinline__ void st_stream(C *p, C c)
+{
+    using R = decltype(C().x);
+    using V = typename Vec2<R>::T;
+    V v;
+    v.x = c.x;
+    v.y = c.y;
+    __builtin_nontemporal_store(v, reinterpret_cast<V *>(p));
+}
+
 // ------------------------------------------------------ one target, Eq. 2 --
 // U pairs per thread: all loads are issued before any store so that 2U
 // independent requests are in flight per lane.
 
-template <typename R, int U>
+template <typename C, bool NT>
+__device__ __forceinline__ C ld_amp(const C *p)
+{
+    if constexpr (NT) return ld_stream(p);
+    else return *p;
+}
+
+template <typename C, bool NT>
+__device__ __forceinline__ void st_amp(C *p, C v)
+{
+    if constexpr (NT) st_stream(p, v);
+    else *p = v;
+}
+
+// Non-temporal accesses pay off only when every 128-byte line a wavefront
+// touches is fully used by one instruction: the lowest inserted bit must
+// leave contiguous runs of at least 128 bytes.
+template <typename R>
+bool stream_ok(const IdxSpec &ix)
+{
+    const int need = sizeof(R) == 8 ? 3 : 4;  // 2^need amplitudes = 128 bytes
+    for (int k = 0; k < ix.npos; ++k)
+        if (ix.pos[k] < need) return false;
+    return true;
+}
+
+template <typename R, int U, bool NT>
 __global__ __launch_bounds__(kBlock) void k_dense1(typename Cpx<R>::T *a, uint64_t npairs,
                                                    IdxSpec ix, uint64_t tbit, MatArg<R, 2> m)
 {
@@ -97,8 +159,8 @@ __global__ __launch_bounds__(kBlock) void k_dense1(typename Cpx<R>::T *a, uint64
             const uint64_t t = base + uint64_t(u) * kBlock;
             i0[u] = insert_zeros(t < npairs ? t : 0, ix);
             if (t < npairs) {
-                x0[u] = a[i0[u]];
-                x1[u] = a[i0[u] | tbit];
+                x0[u] = ld_amp<C, NT>(a + i0[u]);
+                x1[u] = ld_amp<C, NT>(a + (i0[u] | tbit));
             }
         }
 #pragma unroll
@@ -109,8 +171,49 @@ __global__ __launch_bounds__(kBlock) void k_dense1(typename Cpx<R>::T *a, uint64
                 cfma<C, R>(y0, m.v[2], m.v[3], x1[u]);
                 C y1 = cmul<C, R>(m.v[4], m.v[5], x0[u]);
                 cfma<C, R>(y1, m.v[6], m.v[7], x1[u]);
-                a[i0[u]] = y0;
-                a[i0[u] | tbit] = y1;
+                st_amp<C, NT>(a + i0[u], y0);
+                st_amp<C, NT>(a + (i0[u] | tbit), y1);
+            }
+        }
+    }
+}
+
+// Target below 6 (its partner lies in the same wavefront) and no control
+// below 6: lane l of a wavefront holds amplitude i with the low six bits of i
+// equal to l, so every load and store is one contiguous run; the partner
+// amplitude alpha_{i ^ 2^k} comes from lane l ^ 2^k by a cross-lane shuffle.
+template <typename R, int U>
+__global__ __launch_bounds__(kBlock) void k_dense1_lane(typename Cpx<R>::T *a, uint64_t nitems,
+                                                        IdxSpec ix, int k, MatArg<R, 2> m)
+{
+    using C = typename Cpx<R>::T;
+    const uint64_t per = uint64_t(kBlock) * U;
+    const uint64_t nchunks = (nitems + per - 1) / per;
+    const int lane_bit = (threadIdx.x >> k) & 1;
+    // own coefficient and partner coefficient of the output row of this lane
+    const R sr = lane_bit ? m.v[6] : m.v[0], si = lane_bit ? m.v[7] : m.v[1];
+    const R pr = lane_bit ? m.v[4] : m.v[2], pi = lane_bit ? m.v[5] : m.v[3];
+    const int xmask = 1 << k;
+    for (uint64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const uint64_t base = ch * per + threadIdx.x;
+        C x[U];
+        uint64_t idx[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t t = base + uint64_t(u) * kBlock;
+            idx[u] = insert_zeros(t < nitems ? t : 0, ix);
+            if (t < nitems) x[u] = ld_stream(a + idx[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t t = base + uint64_t(u) * kBlock;
+            C p;
+            p.x = __shfl_xor(x[u].x, xmask);
+            p.y = __shfl_xor(x[u].y, xmask);
+            if (t < nitems) {
+                C y = cmul<C, R>(sr, si, x[u]);
+                cfma<C, R>(y, pr, pi, p);
+                st_stream(a + idx[u], y);
             }
         }
     }
@@ -118,7 +221,7 @@ __global__ __launch_bounds__(kBlock) void k_dense1(typename Cpx<R>::T *a, uint64
 
 // ---------------------------------------------------- 2 and 3 targets --
 
-template <typename R, int NT, int U>
+template <typename R, int NT, int U, bool STREAM>
 __global__ __launch_bounds__(kBlock) void k_dense_small(typename Cpx<R>::T *a, uint64_t ngroups,
                                                         IdxSpec ix, MatArg<R, (1 << NT)> m,
                                                         int tq0, int tq1, int tq2)
@@ -147,7 +250,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_small(typename Cpx<R>::T *a, u
             i0[u] = insert_zeros(t < ngroups ? t : 0, ix);
             if (t < ngroups) {
 #pragma unroll
-                for (int x = 0; x < D; ++x) v[u][x] = a[i0[u] | off[x]];
+                for (int x = 0; x < D; ++x) v[u][x] = ld_amp<C, STREAM>(a + (i0[u] | off[x]));
             }
         }
 #pragma unroll
@@ -162,7 +265,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_small(typename Cpx<R>::T *a, u
 #pragma unroll
                     for (int c = 0; c < D; ++c)
                         cfma<C, R>(acc, m.v[2 * (r * D + c)], m.v[2 * (r * D + c) + 1], v[u][c]);
-                    a[i0[u] | off[r]] = acc;
+                    st_amp<C, STREAM>(a + (i0[u] | off[r]), acc);
                 }
             }
         }
@@ -218,7 +321,7 @@ __global__ __launch_bounds__(kBlock) void k_denseN(typename Cpx<R>::T *a, uint64
 // pattern of the (at most 3) remaining target bits; factors equal to 1 are
 // skipped, so only changed amplitudes are read and written.
 
-template <typename R, int U>
+template <typename R, int U, bool STREAM>
 __global__ __launch_bounds__(kBlock) void k_phase(typename Cpx<R>::T *a, uint64_t ngroups,
                                                   IdxSpec ix, DiagArg<R> d)
 {
@@ -238,8 +341,8 @@ __global__ __launch_bounds__(kBlock) void k_phase(typename Cpx<R>::T *a, uint64_
                 uint64_t o = 0;
                 for (int b = 0; b < d.nt; ++b)
                     if ((x >> (d.nt - 1 - b)) & 1) o |= uint64_t(1) << d.tq[b];
-                const C v = a[i0 | o];
-                a[i0 | o] = cmul<C, R>(d.v[2 * x], d.v[2 * x + 1], v);
+                const C v = ld_amp<C, STREAM>(a + (i0 | o));
+                st_amp<C, STREAM>(a + (i0 | o), cmul<C, R>(d.v[2 * x], d.v[2 * x + 1], v));
             }
         }
     }
@@ -474,11 +577,33 @@ hipError_t dense1_impl(void *amp, int n, const IdxSpec &ix, int target, const do
     using C = typename Cpx<R>::T;
     MatArg<R, 2> mm;
     for (int k = 0; k < 8; ++k) mm.v[k] = R(m[k]);
+    bool low_ctl = false;
+    for (int k = 0; k < ix.npos; ++k)
+        if (ix.pos[k] < 6 && ix.pos[k] != target) low_ctl = true;
+    constexpr int U = 2;
+    if (target < 6 && !low_ctl && n >= 8) {
+        // enumerate every amplitude whose control bits are set (the target
+        // bit is not removed: both halves of each pair are work items)
+        IdxSpec cx{};
+        int c = 0;
+        for (int k = 0; k < ix.npos; ++k)
+            if (ix.pos[k] != target) cx.pos[c++] = ix.pos[k];
+        cx.npos = c;
+        cx.set = ix.set;
+        const uint64_t nitems = uint64_t(1) << (n - c);
+        const uint64_t grid = grid_for(nitems, uint64_t(kBlock) * U);
+        hipLaunchKernelGGL((k_dense1_lane<R, U>), dim3(unsigned(grid)), dim3(kBlock), 0, st,
+                           (C *)amp, nitems, cx, target, mm);
+        return hipGetLastError();
+    }
     const uint64_t npairs = uint64_t(1) << (n - ix.npos);
-    constexpr int U = 4;
     const uint64_t grid = grid_for(npairs, uint64_t(kBlock) * U);
-    hipLaunchKernelGGL((k_dense1<R, U>), dim3(unsigned(grid)), dim3(kBlock), 0, st, (C *)amp,
-                       npairs, ix, uint64_t(1) << target, mm);
+    if (stream_ok<R>(ix))
+        hipLaunchKernelGGL((k_dense1<R, U, true>), dim3(unsigned(grid)), dim3(kBlock), 0, st,
+                           (C *)amp, npairs, ix, uint64_t(1) << target, mm);
+    else
+        hipLaunchKernelGGL((k_dense1<R, U, false>), dim3(unsigned(grid)), dim3(kBlock), 0, st,
+                           (C *)amp, npairs, ix, uint64_t(1) << target, mm);
     return hipGetLastError();
 }
 
@@ -493,8 +618,12 @@ hipError_t dense_small_impl(void *amp, int n, const IdxSpec &ix, const int *tq, 
     const uint64_t ng = uint64_t(1) << (n - ix.npos);
     constexpr int U = (NT == 2) ? 2 : 1;
     const uint64_t grid = grid_for(ng, uint64_t(kBlock) * U);
-    hipLaunchKernelGGL((k_dense_small<R, NT, U>), dim3(unsigned(grid)), dim3(kBlock), 0, st,
-                       (C *)amp, ng, ix, mm, tq[0], NT > 1 ? tq[1] : 0, NT > 2 ? tq[2] : 0);
+    if (stream_ok<R>(ix))
+        hipLaunchKernelGGL((k_dense_small<R, NT, U, true>), dim3(unsigned(grid)), dim3(kBlock), 0,
+                           st, (C *)amp, ng, ix, mm, tq[0], NT > 1 ? tq[1] : 0, NT > 2 ? tq[2] : 0);
+    else
+        hipLaunchKernelGGL((k_dense_small<R, NT, U, false>), dim3(unsigned(grid)), dim3(kBlock), 0,
+                           st, (C *)amp, ng, ix, mm, tq[0], NT > 1 ? tq[1] : 0, NT > 2 ? tq[2] : 0);
     return hipGetLastError();
 }
 
@@ -547,8 +676,12 @@ hipError_t phase_impl(void *amp, int n, const IdxSpec &ix, const int *tq, int nt
     const uint64_t ng = uint64_t(1) << (n - ix.npos);
     constexpr int U = 4;
     const uint64_t grid = grid_for(ng, uint64_t(kBlock) * U);
-    hipLaunchKernelGGL((k_phase<R, U>), dim3(unsigned(grid)), dim3(kBlock), 0, st, (C *)amp, ng, ix,
-                       da);
+    if (stream_ok<R>(ix))
+        hipLaunchKernelGGL((k_phase<R, U, true>), dim3(unsigned(grid)), dim3(kBlock), 0, st, (C *)amp,
+                           ng, ix, da);
+    else
+        hipLaunchKernelGGL((k_phase<R, U, false>), dim3(unsigned(grid)), dim3(kBlock), 0, st,
+                           (C *)amp, ng, ix, da);
     return hipGetLastError();
 }
 

@@ -240,11 +240,13 @@ CanonGate canonicalize(const int *t, int nt, const int *c, int nc, const double 
     return g;
 }
 
+int default_tile_qubits(int n) { return n < 13 ? n : 13; }
+
 int default_kmax(int n, qs_dtype dt)
 {
     (void)n;
     (void)dt;
-    return 4;
+    return 3;
 }
 
 // Greedy fusion over the gate sequence: open blocks own disjoint qubit sets;
@@ -414,3 +416,372 @@ void qs_philox4x32_10(const uint32_t *counter, const uint32_t *key, uint32_t *ou
 }
 
 }  // extern "C"
+
+// ======================================================== tile planning ==
+
+namespace qs {
+
+namespace {
+
+struct GInfo {
+    CanonGate c;
+    uint64_t qmask = 0;  // targets | controls
+    uint64_t tmask = 0;  // targets
+    uint64_t cmask = 0;  // controls
+    bool diag = false;
+    bool logical = true;
+};
+
+uint64_t mask_of(const std::vector<int> &v)
+{
+    uint64_t m = 0;
+    for (int q : v) m |= uint64_t(1) << q;
+    return m;
+}
+
+std::vector<int> bits_desc(uint64_t m)
+{
+    std::vector<int> v;
+    for (int q = 63; q >= 0; --q)
+        if (m >> q & 1) v.push_back(q);
+    return v;
+}
+
+// Matrix of a sequence of gates over the qubit list `qs` (qs[0] = MSB).
+std::vector<double> block_matrix(const std::vector<int> &qs, const std::vector<const GInfo *> &gates)
+{
+    const int k = int(qs.size());
+    const int D = 1 << k;
+    auto local = [&](int q) {
+        for (int i = 0; i < k; ++i)
+            if (qs[i] == q) return k - 1 - i;
+        return -1;
+    };
+    std::vector<cd> M(size_t(D) * D, cd(0));
+    for (int i = 0; i < D; ++i) M[size_t(i) * D + i] = 1;
+    for (const GInfo *g : gates) {
+        std::vector<int> tb, cb;
+        for (int q : g->c.targets) tb.push_back(local(q));
+        for (int q : g->c.controls) cb.push_back(local(q));
+        if (g->c.kind == CanonGate::PHASE) {
+            // diagonal: expand to a dense diagonal matrix on the targets
+            const int nt = int(g->c.targets.size());
+            const int d = 1 << nt;
+            std::vector<double> dm(size_t(2) * d * d, 0.0);
+            for (int x = 0; x < d; ++x) {
+                dm[2 * (x * d + x)] = g->c.m[2 * x];
+                dm[2 * (x * d + x) + 1] = g->c.m[2 * x + 1];
+            }
+            if (nt == 0) {
+                // scalar phase on the control pattern: a diagonal on the controls
+                std::vector<int> none;
+                std::vector<double> one = {g->c.m[0], g->c.m[1]};
+                // apply as a 1x1 "matrix": multiply the amplitudes whose control bits are set
+                int cm = 0;
+                for (int b : cb) cm |= 1 << b;
+                const cd f(one[0], one[1]);
+                for (int col = 0; col < D; ++col)
+                    for (int i = 0; i < D; ++i)
+                        if ((i & cm) == cm) M[size_t(i) * D + col] *= f;
+                continue;
+            }
+            apply_local(M, k, tb, cb, dm);
+        } else {
+            apply_local(M, k, tb, cb, g->c.m);
+        }
+    }
+    std::vector<double> out(size_t(2) * D * D);
+    for (int i = 0; i < D * D; ++i) {
+        out[2 * i] = M[i].real();
+        out[2 * i + 1] = M[i].imag();
+    }
+    return out;
+}
+
+bool is_diag_matrix(const std::vector<double> &m, int k)
+{
+    const int D = 1 << k;
+    for (int r = 0; r < D; ++r)
+        for (int c = 0; c < D; ++c)
+            if (r != c && (m[2 * (r * D + c)] != 0.0 || m[2 * (r * D + c) + 1] != 0.0)) return false;
+    return true;
+}
+
+// Diagonal factor of a canonical PHASE gate for a full assignment of the
+// qubits in `qs` (pattern bit (|qs|-1-b) = value of qs[b]).
+cd phase_factor(const CanonGate &g, const std::vector<int> &qs, int pattern)
+{
+    auto val = [&](int q) {
+        for (size_t b = 0; b < qs.size(); ++b)
+            if (qs[b] == q) return (pattern >> (qs.size() - 1 - b)) & 1;
+        return 0;
+    };
+    for (int c : g.controls)
+        if (!val(c)) return cd(1);
+    int x = 0;
+    for (int t : g.targets) x = (x << 1) | val(t);
+    return cd(g.m[2 * x], g.m[2 * x + 1]);
+}
+
+struct OpenBlock {
+    uint64_t qmask = 0;  // qubits inside the tile
+    uint64_t omask = 0;  // qubits outside the tile (constant per tile)
+    std::vector<const GInfo *> gates;
+    size_t first = 0;
+};
+
+// Matrix over the tile qubits `qs` (qs[0] = MSB) of a gate sequence with the
+// outer qubits `os` fixed to `pattern` (bit |os|-1-b = value of os[b]).
+std::vector<double> block_matrix_outer(const std::vector<int> &qs, const std::vector<int> &os, int pattern,
+                                       const std::vector<const GInfo *> &gates)
+{
+    auto oval = [&](int q) {
+        for (size_t b = 0; b < os.size(); ++b)
+            if (os[b] == q) return (pattern >> (os.size() - 1 - b)) & 1;
+        return -1;
+    };
+    std::vector<GInfo> eff;
+    eff.reserve(gates.size());
+    for (const GInfo *g : gates) {
+        if (g->c.kind == CanonGate::DENSE) {
+            // outer qubits of a dense gate are controls: keep the gate only
+            // when they are all 1, with its inner controls
+            GInfo e = *g;
+            bool on = true;
+            std::vector<int> cin;
+            for (int c : g->c.controls) {
+                const int v = oval(c);
+                if (v == 0) on = false;
+                if (v < 0) cin.push_back(c);
+            }
+            if (!on) continue;
+            e.c.controls = cin;
+            eff.push_back(std::move(e));
+            continue;
+        }
+        // diagonal: restrict the table to the inner qubits
+        std::vector<int> inner;
+        for (int q : g->c.targets)
+            if (oval(q) < 0) inner.push_back(q);
+        for (int q : g->c.controls)
+            if (oval(q) < 0) inner.push_back(q);
+        std::vector<int> all = os;
+        all.insert(all.end(), inner.begin(), inner.end());
+        GInfo e;
+        e.c.kind = CanonGate::PHASE;
+        e.c.targets = inner;
+        const int D = 1 << inner.size();
+        e.c.m.resize(size_t(2) * D);
+        for (int x = 0; x < D; ++x) {
+            const cd f = phase_factor(g->c, all, (pattern << inner.size()) | x);
+            e.c.m[2 * x] = f.real();
+            e.c.m[2 * x + 1] = f.imag();
+        }
+        eff.push_back(std::move(e));
+    }
+    std::vector<const GInfo *> ptrs;
+    for (auto &e : eff) ptrs.push_back(&e);
+    return block_matrix(qs, ptrs);
+}
+
+}  // namespace
+
+void plan_tiles(const std::vector<FlatOp> &flat, size_t k0, size_t e, int n, const TileParams &tp,
+                std::vector<PlanStep> &out)
+{
+    const int m = std::min(tp.m, n);
+    const int L = std::min(tp.L, m);
+    const int kmax = std::min(tp.kmax, m);
+    std::vector<GInfo> info;
+    info.reserve(e - k0);
+    for (size_t i = k0; i < e; ++i) {
+        const FlatOp &f = flat[i];
+        GInfo g;
+        g.c = canonicalize(f.targets.data(), int(f.targets.size()), f.controls.data(),
+                           int(f.controls.size()), f.m.data());
+        if (g.c.kind == CanonGate::IDENTITY) continue;
+        g.tmask = mask_of(g.c.targets);
+        g.cmask = mask_of(g.c.controls);
+        g.qmask = g.tmask | g.cmask;
+        g.diag = g.c.kind == CanonGate::PHASE;
+        info.push_back(std::move(g));
+    }
+    const uint64_t low = (L >= 64) ? ~uint64_t(0) : ((uint64_t(1) << L) - 1);
+    std::vector<size_t> remaining(info.size());
+    for (size_t i = 0; i < info.size(); ++i) remaining[i] = i;
+    auto fits_tile = [&](const GInfo &g) {
+        // a gate can live in a tile when its qubits inside any Q are few
+        // enough: dense gates need all targets in Q and at most kmax local
+        // qubits; diagonal gates at most 3 local and 3 outer qubits (table)
+        if (g.diag) return __builtin_popcountll(g.qmask) <= kmax + 3;
+        return __builtin_popcountll(g.tmask) <= kmax && __builtin_popcountll(g.cmask) <= kmax + 3;
+    };
+    while (!remaining.empty()) {
+        // ---- choose Q and the gates this sweep applies
+        uint64_t Q = low;
+        uint64_t blocked = 0;
+        std::vector<size_t> applied, deferred;
+        for (size_t gi : remaining) {
+            const GInfo &g = info[gi];
+            if ((g.qmask & blocked) || !fits_tile(g)) {
+                deferred.push_back(gi);
+                blocked |= g.qmask;
+                continue;
+            }
+            if (g.diag) {
+                applied.push_back(gi);
+                continue;
+            }
+            const uint64_t need = g.tmask & ~Q;
+            if (!need || __builtin_popcountll(Q | need) <= m) {
+                Q |= need;
+                applied.push_back(gi);
+                continue;
+            }
+            deferred.push_back(gi);
+            blocked |= g.qmask;
+        }
+        if (applied.empty()) {
+            // the first gate does not fit any tile: apply it on its own
+            PlanStep st;
+            st.sweep = false;
+            st.gate = info[remaining[0]].c;
+            out.push_back(std::move(st));
+            remaining.erase(remaining.begin());
+            continue;
+        }
+        for (int q = 0; q < n && __builtin_popcountll(Q) < m; ++q) Q |= uint64_t(1) << q;
+        // diagonal gates with more than 3 qubits inside or outside the final Q
+        // are left for a later step
+        {
+            std::vector<size_t> keep;
+            uint64_t blk = 0;
+            std::vector<size_t> later;
+            for (size_t gi : applied) {
+                const GInfo &g = info[gi];
+                const bool bad = __builtin_popcountll(g.qmask & Q) > kmax ||
+                                 __builtin_popcountll(g.qmask & ~Q) > 3;
+                if (bad || (g.qmask & blk)) {
+                    later.push_back(gi);
+                    blk |= g.qmask;
+                } else {
+                    keep.push_back(gi);
+                }
+            }
+            if (!later.empty()) {
+                // re-merge into circuit order with the deferred gates
+                std::vector<size_t> rest = later;
+                rest.insert(rest.end(), deferred.begin(), deferred.end());
+                std::sort(rest.begin(), rest.end());
+                deferred.swap(rest);
+                applied.swap(keep);
+            }
+        }
+        // ---- fuse the applied gates into tile ops
+        Sweep sw;
+        for (int q = 0; q < 64; ++q)
+            if (Q >> q & 1) sw.Q.push_back(q);
+        sw.gates = int(applied.size());
+        std::vector<std::unique_ptr<OpenBlock>> open;
+        size_t serial = 0;
+        auto emit_block = [&](OpenBlock &b) {
+            const std::vector<int> os = bits_desc(b.omask);
+            const int P = 1 << os.size();
+            std::vector<int> qs = bits_desc(b.qmask);
+            std::vector<std::vector<double>> mats(P);
+            bool all_diag = true;
+            for (int p = 0; p < P; ++p) {
+                mats[p] = block_matrix_outer(qs, os, p, b.gates);
+                all_diag = all_diag && is_diag_matrix(mats[p], int(qs.size()));
+            }
+            TileOp op;
+            op.outer = os;
+            if (all_diag && qs.size() <= 3) {
+                op.kind = TileOp::PHASE;
+                op.qubits = qs;
+                const int D = 1 << qs.size();
+                op.m.resize(size_t(2) * D * P);
+                for (int p = 0; p < P; ++p)
+                    for (int x = 0; x < D; ++x) {
+                        op.m[2 * (p * D + x)] = mats[p][2 * (x * D + x)];
+                        op.m[2 * (p * D + x) + 1] = mats[p][2 * (x * D + x) + 1];
+                    }
+                sw.ops.push_back(std::move(op));
+                return;
+            }
+            uint64_t pm = b.qmask;
+            // widen narrow blocks to the 4-qubit matrix-core shape with
+            // identity factors on otherwise untouched tile qubits
+            for (int q : sw.Q) {
+                if (__builtin_popcountll(pm) >= 4) break;
+                pm |= uint64_t(1) << q;
+            }
+            op.kind = TileOp::DENSE;
+            op.qubits = bits_desc(pm);
+            const int k = int(op.qubits.size());
+            for (int p = 0; p < P; ++p) {
+                std::vector<double> mp = (pm == b.qmask) ? std::move(mats[p])
+                                                         : block_matrix_outer(op.qubits, os, p, b.gates);
+                if (is_identity(mp, k)) op.skip |= 1u << p;
+                op.m.insert(op.m.end(), mp.begin(), mp.end());
+            }
+            sw.ops.push_back(std::move(op));
+        };
+        auto by_first = [](const std::unique_ptr<OpenBlock> &a, const std::unique_ptr<OpenBlock> &b) {
+            return a->first < b->first;
+        };
+        for (size_t gi : applied) {
+            const GInfo &g = info[gi];
+            const uint64_t loc = g.qmask & Q, outm = g.qmask & ~Q;
+            if (!loc) {
+                // only outer qubits: a per-tile phase, commutes with the
+                // whole sweep; attach it to the newest block with room
+                OpenBlock *host = nullptr;
+                for (auto &b : open)
+                    if (__builtin_popcountll(b->omask | outm) <= 3 && (!host || b->first > host->first))
+                        host = b.get();
+                if (host) {
+                    host->omask |= outm;
+                    host->gates.push_back(&g);
+                    continue;
+                }
+            }
+            std::vector<size_t> hit;
+            uint64_t uni = loc, ouni = outm;
+            for (size_t b = 0; b < open.size(); ++b)
+                if (open[b]->qmask & loc) {
+                    hit.push_back(b);
+                    uni |= open[b]->qmask;
+                    ouni |= open[b]->omask;
+                }
+            std::sort(hit.begin(), hit.end(), [&](size_t a, size_t b) { return open[a]->first < open[b]->first; });
+            auto nb = std::make_unique<OpenBlock>();
+            nb->first = serial++;
+            if (__builtin_popcountll(uni) <= kmax && __builtin_popcountll(ouni) <= 3) {
+                nb->qmask = uni;
+                nb->omask = ouni;
+                for (size_t b : hit) nb->gates.insert(nb->gates.end(), open[b]->gates.begin(), open[b]->gates.end());
+                if (!hit.empty()) nb->first = open[hit[0]]->first;
+            } else {
+                for (size_t b : hit) emit_block(*open[b]);
+                nb->qmask = loc;
+                nb->omask = outm;
+            }
+            nb->gates.push_back(&g);
+            std::vector<std::unique_ptr<OpenBlock>> keep;
+            for (size_t b = 0; b < open.size(); ++b)
+                if (std::find(hit.begin(), hit.end(), b) == hit.end()) keep.push_back(std::move(open[b]));
+            keep.push_back(std::move(nb));
+            open.swap(keep);
+        }
+        std::sort(open.begin(), open.end(), by_first);
+        for (auto &b : open) emit_block(*b);
+        PlanStep st;
+        st.sweep = true;
+        st.sw = std::move(sw);
+        out.push_back(std::move(st));
+        remaining.swap(deferred);
+    }
+}
+
+}  // namespace qs

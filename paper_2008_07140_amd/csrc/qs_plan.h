@@ -53,11 +53,61 @@ void greedy_fuse(const std::vector<FlatOp> &flat, size_t k, size_t e, int kmax,
                  std::vector<CanonGate> &plan);
 
 int default_kmax(int n, qs_dtype dt);
+int default_tile_qubits(int n);
 
 qs_status run_trajectories(const qs_circuit *const *circs, const int *widths, int count, qs_dtype dt,
                            uint64_t seed, double *z_out, double *seconds);
 
 qs_status set_error(qs_status st, const char *msg);
 qs_status run_on_state(qs_state *s, const qs_circuit *c, const qs_run_opts *o);
+
+}  // namespace qs
+
+namespace qs {
+
+// ---------------------------------------------------------------- tiles --
+// A tile sweep keeps 2^m amplitudes of the qubit set Q (ascending, always
+// starting with the L lowest qubits) in LDS and applies a list of ops to
+// every tile; the other n - m bits index the tiles.
+
+struct TileOp {
+    enum Kind { DENSE, PHASE };
+    Kind kind = DENSE;
+    // `qubits` lie in Q (qubits[0] = most significant bit of a matrix index),
+    // `outer` outside Q (at most 3, outer[0] most significant); the outer
+    // bits are constant over a tile and select one of 2^|outer| operators.
+    // DENSE: m holds 2^|outer| matrices of 2^k x 2^k complex one after
+    // another; `skip` bit p is set when matrix p is the identity.
+    // PHASE: m is the diagonal table, entry (outer pattern << k) | (qubit
+    // pattern).
+    std::vector<int> qubits;
+    std::vector<int> outer;
+    std::vector<double> m;
+    uint32_t skip = 0;
+};
+
+struct Sweep {
+    std::vector<int> Q;
+    std::vector<TileOp> ops;
+    int gates = 0;  // logical gates applied in this sweep
+};
+
+struct TileParams {
+    int m = 12;     // tile qubits
+    int L = 4;      // lowest qubits always in the tile
+    int kmax = 5;   // widest dense block (4 or 5)
+};
+
+// One step of a tiled plan: a tile sweep, or a gate that does not fit a tile
+// (more qubits than kmax) applied by the per-gate kernels.
+struct PlanStep {
+    bool sweep = true;
+    Sweep sw;
+    CanonGate gate;
+};
+
+// Plan the gates flat[k, e) as tile sweeps.
+void plan_tiles(const std::vector<FlatOp> &flat, size_t k, size_t e, int n, const TileParams &tp,
+                std::vector<PlanStep> &out);
 
 }  // namespace qs

@@ -1,0 +1,34 @@
+// Device-side description of a tile sweep (see qs_fused.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "qs_internal.h"
+
+namespace qs {
+
+struct TileArgs {
+    int m;          // tile qubits (9..13)
+    int L;          // Q[b] = b for b < L
+    int nops;
+    int Q[kMaxQ];   // tile qubits, ascending
+};
+
+struct TileOpDev {
+    int kind;            // 0 = dense block, 1 = phase
+    int k;               // dense: 4 or 5 qubits; phase: number of tile bits (0..3)
+    int no;              // number of outer selector bits (0..3)
+    uint32_t data_off;   // offset of fragments / table in the data buffer, 16-byte units
+    int lpos[6];         // tile-local bit positions, [0] = most significant
+    int opos[4];         // global positions of the outer bits, [0] = most significant
+    uint32_t skip;       // dense: bit p set = identity for outer pattern p
+    uint32_t frag_stride;  // dense: 16-byte units per outer pattern
+};
+
+size_t tile_lds_bytes(int m);
+hipError_t launch_tile(void *amp, int n, const TileArgs &ta, const TileOpDev *dev_ops,
+                       const void *dev_data, hipStream_t st);
+
+}  // namespace qs

@@ -43,7 +43,7 @@ class QSError(RuntimeError):
 class RunOpts(C.Structure):
     _fields_ = [("plan", C.c_int), ("k_max", C.c_int), ("seed", C.c_uint64),
                 ("traj", C.c_uint64), ("chosen", C.POINTER(C.c_int64)),
-                ("chosen_len", C.c_int64)]
+                ("chosen_len", C.c_int64), ("tile_qubits", C.c_int)]
 
 
 P, I, D, U64, I64, SZ = C.c_void_p, C.c_int, C.c_double, C.c_uint64, C.c_int64, C.c_size_t
@@ -69,6 +69,7 @@ _sig = {
     "qs_circuit_end_control": ([P], I),
     "qs_circuit_counts": ([P, P, P, P], I),
     "qs_run_circuit": ([P, P, C.POINTER(RunOpts)], I),
+    "qs_circuit_plan_info": ([P, I, I, C.POINTER(RunOpts), P, P, P], I),
     "qs_amplitudes": ([P, P, SZ, P], I),
     "qs_probabilities": ([P, P, I, P], I),
     "qs_norm": ([P, P], I),
@@ -165,6 +166,14 @@ class Circuit:
         else:
             raise ValueError("unknown op kind %r" % k)
 
+    def plan_info(self, n: int, dtype: int = C64, plan: int = PLAN_GREEDY, k_max: int = 0,
+                  tile_qubits: int = 0):
+        o = RunOpts(plan=plan, k_max=k_max, tile_qubits=tile_qubits)
+        sw, bl, lg = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(_lib.qs_circuit_plan_info(self._h, n, dtype, C.byref(o), C.byref(sw), C.byref(bl),
+                                         C.byref(lg)))
+        return {"sweeps": sw.value, "blocks": bl.value, "gates": lg.value}
+
     def counts(self):
         g, z, l = C.c_int64(), C.c_int64(), C.c_int64()
         _check(_lib.qs_circuit_counts(self._h, C.byref(g), C.byref(z), C.byref(l)))
@@ -229,8 +238,8 @@ class State:
         return ch.value, pc.value
 
     def run(self, circuit: Circuit, plan: int = PLAN_UNFUSED, k_max: int = 0, seed: int = 0,
-            traj: int = 0, nsites: int = 0):
-        o = RunOpts(plan=plan, k_max=k_max, seed=seed, traj=traj)
+            traj: int = 0, nsites: int = 0, tile_qubits: int = 0):
+        o = RunOpts(plan=plan, k_max=k_max, seed=seed, traj=traj, tile_qubits=tile_qubits)
         chosen = None
         if nsites:
             chosen = (C.c_int64 * nsites)()

@@ -301,9 +301,88 @@ def test_rqc30_product_circuit_sampled_amplitudes(qs):
         ev_idx |= ((idx >> np.uint64(2 * b)) & np.uint64(1)).astype(np.int64) << b
         od_idx |= ((idx >> np.uint64(2 * b + 1)) & np.uint64(1)).astype(np.int64) << b
     want = a_ev[ev_idx] * a_od[od_idx]
-    for dt, plan, kmax, tol in [(qs.C128, 0, 0, TOL128), (qs.C64, 1, 4, 2e-6)]:
+    for dt, plan, kmax, tol in [(qs.C128, 0, 0, TOL128), (qs.C64, 1, 5, 2e-6), (qs.C128, 1, 3, TOL128)]:
         s = qs.State(30, dt)
         s.run(qs.Circuit(ops), plan=plan, k_max=kmax)
         got = s.amplitudes(idx)
         assert np.max(np.abs(got - want)) <= tol
         s.close()
+
+
+# ------------------------------------------------------------ tile sweeps --
+
+
+def _mixed_circuit(n, count, seed):
+    """Random gates of every shape the planner distinguishes: dense 1-3
+    targets, controls (which land inside or outside a tile), diagonal gates
+    on up to 4 qubits, and an occasional 6-target dense gate (too wide for a
+    tile, applied on its own)."""
+    rng = np.random.default_rng(seed)
+    ops = []
+    for i in range(count):
+        kind = rng.integers(0, 6)
+        if kind == 0:
+            t, c, m = random_gate(rng, n, 1, 0)
+        elif kind == 1:
+            t, c, m = random_gate(rng, n, 1, int(rng.integers(1, 3)))
+        elif kind == 2:
+            t, c, m = random_gate(rng, n, 2, int(rng.integers(0, 2)))
+        elif kind == 3:
+            t, c, m = random_gate(rng, n, 3, 0)
+        elif kind == 4:
+            nt = int(rng.integers(1, 5))
+            q = rng.permutation(n)[:nt]
+            t, c = tuple(int(x) for x in q), ()
+            m = np.diag(np.exp(1j * rng.uniform(0, 2 * np.pi, 1 << nt)))
+        else:
+            if i % 17 == 0:
+                t, c, m = random_gate(rng, n, 6, 0)
+            else:
+                a, b = (int(x) for x in rng.permutation(n)[:2])
+                t, c, m = (a, b), (), cg.CZ_GATE
+        ops.append(cg.Gate(t, c, m))
+    return ops
+
+
+@pytest.mark.parametrize("m,kmax", [(9, 4), (10, 5), (12, 4), (13, 5)])
+def test_tile_sweeps_c64_mixed_gates(qs, m, kmax):
+    n = 14
+    ops = _mixed_circuit(n, 160, seed=100 + m)
+    ref, _ = oracle.run(n, ops)
+    s = qs.State(n, qs.C64)
+    info = qs.Circuit(ops).plan_info(n, qs.C64, plan=1, k_max=kmax, tile_qubits=m)
+    assert info["sweeps"] < 160
+    s.run(qs.Circuit(ops), plan=1, k_max=kmax, tile_qubits=m)
+    got = s.amplitudes()
+    assert infidelity(ref, got) <= 1e-6
+    assert np.max(np.abs(got - ref)) <= 1e-5
+
+
+@pytest.mark.parametrize("m", [9, 11, 13])
+def test_tile_sweeps_rqc16_and_rqc20(qs, m):
+    for name, (rows, cols, depth, seed, cu3) in [("rqc16", (4, 4, 20, 1001, 0.0)),
+                                                  ("rqc20", (4, 5, 40, 2001, 0.1))]:
+        ops = cg.random_circuit(rows, cols, depth, seed, cu3_prob=cu3)
+        n = rows * cols
+        ref, _ = oracle.run(n, ops)
+        s = qs.State(n, qs.C64)
+        s.run(qs.Circuit(ops), plan=1, k_max=5, tile_qubits=m)
+        got = s.amplitudes()
+        assert infidelity(ref, got) <= 1e-6, name
+        assert abs(s.norm() - 1) < 1e-4
+        s.close()
+
+
+def test_tile_sweeps_with_noise_segments(qs):
+    """Noise sites split the circuit into segments; each segment is tiled."""
+    n = 10
+    ops = cg.random_circuit(2, 5, 6, seed=41, dep1=0.05, dep2=0.05, damping=0.05)
+    nsites = sum(1 for o in ops if o.kind == "noise")
+    c = qs.Circuit(ops)
+    s = qs.State(n, qs.C64)
+    for traj in range(3):
+        s.reset()
+        chosen = s.run(c, plan=1, k_max=5, tile_qubits=9, seed=5, traj=traj, nsites=nsites)
+        ref, och = oracle.run(n, ops, seed=5, traj=traj)
+        assert np.array_equal(chosen, och)
+        assert infidelity(ref, s.amplitudes()) <= 1e-6
