@@ -45,9 +45,13 @@ def parse():
     p.add_argument("--workload", default="rqc30_d40")
     p.add_argument("--paths", default="fused_c64,plain_c128")
     p.add_argument("--kmax", type=int, default=0, help="fused block width (0 = library default)")
+    p.add_argument("--tile-qubits", type=int, default=0, help="qubits per LDS tile (0 = library default)")
     p.add_argument("--plan", default="greedy", choices=["greedy", "learned"])
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only run a plain 4 GiB device-to-device copy (5 times), the reference "
+                        "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
     return p.parse_args()
 
 
@@ -75,7 +79,7 @@ def traffic_for(kernel_class: str):
     return rec.get("bytes_per_launch")
 
 
-def run_path(qs, torch, cg, name, n, circuit, gates, steps, warmup, kmax, plan):
+def run_path(qs, torch, cg, name, n, circuit, gates, steps, warmup, kmax, plan, tile_qubits=0):
     dt = qs.C64 if name.endswith("c64") else qs.C128
     fused = name.startswith("fused")
     tdt = torch.complex64 if dt == qs.C64 else torch.complex128
@@ -87,7 +91,7 @@ def run_path(qs, torch, cg, name, n, circuit, gates, steps, warmup, kmax, plan):
 
     def step():
         st.reset()
-        st.run(circuit, plan=plan_id, k_max=kmax)
+        st.run(circuit, plan=plan_id, k_max=kmax, tile_qubits=tile_qubits if fused else 0)
         nrm = st.norm()
         pr = st.probabilities(pm)
         return nrm, pr
@@ -168,12 +172,22 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2008_07140_amd import circuits as cg
-    from paper_2008_07140_amd import qs
-
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        a = torch.ones(1 << 30, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read_per_launch": 4 << 30, "copy_bytes_written_per_launch": 4 << 30,
+                          "launches": 5}))
+        return
+
+    from paper_2008_07140_amd import circuits as cg
+    from paper_2008_07140_amd import qs
+
     n, ops = cg.workload(args.workload)
     gates = cg.count_gates(ops)
     circuit = qs.Circuit(ops)
@@ -183,7 +197,7 @@ def main():
     states = {}
     for p in paths:
         res, st, buf = run_path(qs, torch, cg, p, n, circuit, gates, args.steps, args.warmup,
-                                args.kmax, args.plan)
+                                args.kmax, args.plan, args.tile_qubits)
         out[p] = res
         states[p] = (st, buf)
     acc = None
@@ -225,6 +239,7 @@ def main():
         "config": {"workload": "%s: %d-qubit random circuit, depth %d, %d logical gates"
                                % (args.workload, n, cg.WORKLOADS[args.workload][2], gates),
                    "path": primary, "plan": args.plan, "k_max": args.kmax,
+                   "tile_qubits": args.tile_qubits,
                    "state": "complex64 (FP32), FP64 reductions" if primary.endswith("c64")
                    else "complex128 (FP64)"},
         "roofline": prim["roofline"],

@@ -169,7 +169,7 @@ typedef struct {
     uint64_t traj;      /* trajectory index (Philox counter words 2-3) */
     int64_t *chosen;    /* optional output: Kraus branch of every noise site */
     int64_t chosen_len; /* capacity of `chosen` */
-    int tile_qubits;    /* complex64 fused plans: qubits per LDS tile, 9..13 (0 = default) */
+    int tile_qubits;    /* complex64 fused plans: qubits per LDS tile, 10..13 (0 = default) */
 } qs_run_opts;
 
 /* Shape of the plan qs_run_circuit would execute for this circuit on an

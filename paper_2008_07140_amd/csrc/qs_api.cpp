@@ -351,8 +351,34 @@ float bf16_float(uint16_t h)
 // [[Re U, -Im U], [Im U, Re U]] per complex entry with re/im interleaved),
 // fragment (mt, s) of lane l holds A[16 mt + l % 16][32 s + 8 (l / 16) + j],
 // j < 8, as bfloat16 (hi), followed by the same layout of the remainders (lo).
+// Five-qubit blocks use the split form instead: fragment f < 4 of lane l
+// holds (f < 2 ? Re U : Im U)[16 (f % 2) + l % 16][8 (l / 16) + j], j < 8,
+// hi values for the four fragments first, then the remainders.
+void append_fragments5(const std::vector<double> &m, std::vector<uint16_t> &out)
+{
+    const int D = 32;
+    const size_t base = out.size();
+    const size_t nfr = size_t(4) * 64 * 8;
+    out.resize(base + 2 * nfr);
+    for (int f = 0; f < 4; ++f)
+        for (int lane = 0; lane < 64; ++lane)
+            for (int j = 0; j < 8; ++j) {
+                const int r = 16 * (f % 2) + lane % 16, c = 8 * (lane / 16) + j;
+                const double v = m[2 * (size_t(r) * D + c) + (f < 2 ? 0 : 1)];
+                const uint16_t h = bf16_rne(float(v));
+                const uint16_t l = bf16_rne(float(v - double(bf16_float(h))));
+                const size_t idx = (size_t(f) * 64 + lane) * 8 + j;
+                out[base + idx] = h;
+                out[base + nfr + idx] = l;
+            }
+}
+
 void append_fragments(const std::vector<double> &m, int k, std::vector<uint16_t> &out)
 {
+    if (k == 5) {
+        append_fragments5(m, out);
+        return;
+    }
     const int D = 1 << k, MT = 2 * D / 16, KS = 2 * D / 32;
     const size_t base = out.size();
     const size_t nfr = size_t(MT) * KS * 64 * 8;
@@ -448,7 +474,7 @@ qs::TileParams tile_params(int n, const qs_run_opts &o)
 
 bool tiled_plan(const qs_state *s, const qs_run_opts &o)
 {
-    return o.plan != QS_PLAN_UNFUSED && s->dt == QS_C64 && s->n >= 9;
+    return o.plan != QS_PLAN_UNFUSED && s->dt == QS_C64 && s->n >= 10;
 }
 
 qs_status launch_tiled(qs_state *s, const std::vector<qs::PlanStep> &steps)
@@ -480,9 +506,21 @@ qs_status launch_tiled(qs_state *s, const std::vector<qs::PlanStep> &steps)
         }
         qs::TileArgs ta{};
         ta.m = int(st.sw.Q.size());
-        ta.L = 4;
         ta.nops = int(st.sw.ops.size());
-        for (int b = 0; b < ta.m; ++b) ta.Q[b] = st.sw.Q[b];
+        const auto &Q = st.sw.Q;
+        for (int b = 0; b < 10; ++b) ta.qlo[b] = uint16_t(b < ta.m ? Q[b] : 0);
+        for (int r = 0; r < 16; ++r) {
+            uint64_t off = 0;
+            const uint64_t j = uint64_t(r) * 512;  // local index of slot r (2 x 256 threads)
+            for (int b = 9; b < ta.m; ++b)
+                if ((j >> b) & 1) off |= uint64_t(1) << Q[b];
+            ta.slot[r] = off;
+        }
+        uint64_t qm = 0;
+        for (int q : Q) qm |= uint64_t(1) << q;
+        ta.nouter = 0;
+        for (int q = 0; q < s->n; ++q)
+            if (!(qm >> q & 1)) ta.outer[ta.nouter++] = uint8_t(q);
         double flops = 0;
         for (const auto &op : st.sw.ops)
             flops += (op.kind == qs::TileOp::DENSE ? 8.0 * double(1 << op.qubits.size()) : 6.0) *
@@ -932,8 +970,8 @@ qs_status qs_run_circuit(qs_state *s, const qs_circuit *c, const qs_run_opts *op
     if (opts) o = *opts;
     if (o.plan < QS_PLAN_UNFUSED || o.plan > QS_PLAN_LEARNED) return fail(QS_E_INVAL, "unknown plan %d", o.plan);
     if (o.k_max < 0 || o.k_max > QS_MAX_TARGETS) return fail(QS_E_INVAL, "k_max = %d not in [0, %d]", o.k_max, QS_MAX_TARGETS);
-    if (o.tile_qubits && (o.tile_qubits < 9 || o.tile_qubits > 13))
-        return fail(QS_E_INVAL, "tile_qubits = %d not in [9, 13]", o.tile_qubits);
+    if (o.tile_qubits && (o.tile_qubits < 10 || o.tile_qubits > 13))
+        return fail(QS_E_INVAL, "tile_qubits = %d not in [10, 13]", o.tile_qubits);
     std::vector<qs::FlatOp> flat;
     std::string err;
     int rc = qs::expand(c->ops, flat, err);

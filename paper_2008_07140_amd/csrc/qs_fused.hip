@@ -1,8 +1,8 @@
 // Tile sweep kernel for complex64 states on gfx950.
 //
 // One workgroup holds a tile of 2^m amplitudes in LDS: the amplitudes whose
-// index differs only in the tile qubits Q (ascending, Q[b] = b for b < L, so
-// a tile is 2^(m-L) contiguous runs of 2^L amplitudes).  The other n - m bits
+// index differs only in the tile qubits Q (ascending, Q[b] = b for the lowest
+// few b, so a tile is a set of contiguous runs of at least 128 bytes).  The other n - m bits
 // select the tile.  After the tile is loaded, a list of ops is applied to it
 // in LDS, then the tile is written back: one HBM read and one write of the
 // state for the whole list.
@@ -46,15 +46,10 @@ __device__ __forceinline__ uint32_t insert_zero_bits(uint32_t t, const int *pos,
 
 constexpr int kMaxM = 13;
 
-// local tile index j -> global index bits (without the tile base)
-__device__ __forceinline__ uint64_t scatter_local(uint32_t j, const TileArgs &ta)
-{
-    uint64_t g = j & ((1u << ta.L) - 1u);
-#pragma unroll
-    for (int b = 1; b < kMaxM; ++b)
-        if (b >= ta.L && b < ta.m && ((j >> b) & 1u)) g |= uint64_t(1) << ta.Q[b];
-    return g;
-}
+// LDS layout of a tile: amplitude j lives at j ^ ((j >> 5) & 31).  Blocks on
+// the low tile qubits make the 16 groups of a matrix-core operand differ
+// only in high index bits; the XOR spreads those accesses over the banks.
+__device__ __forceinline__ uint32_t sw(uint32_t j) { return j ^ ((j >> 5) & 31u); }
 
 template <int K>
 __device__ void dense_op(float2 *tile, const TileOpDev &op, const uint4 *data, int m, int outer)
@@ -102,34 +97,174 @@ __device__ void dense_op(float2 *tile, const TileOpDev &op, const uint4 *data, i
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int j = 0; j < 2; ++j) woff[mt][j] = offset(8 * mt + 2 * (lane >> 4) + j);
-    const int ntiles = 1 << (m - K - 4);  // 16 groups per column tile
-    for (int nt = wave; nt < ntiles; nt += kThreads / 64) {
+    // 16 groups per column tile; for k = 4 each wave takes two column tiles
+    // at a time so that four independent accumulators interleave on the
+    // matrix cores (k = 5 has four row tiles already)
+    constexpr int H = (K == 4) ? 2 : 1;
+    const int ntiles = 1 << (m - K - 4);
+    constexpr int kWaves = kThreads / 64;
+    for (int nt0 = H * wave; nt0 < ntiles; nt0 += H * kWaves) {
+        uint32_t gb[H];
+        bf16x8 bhi[H][KS], blo[H][KS];
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            const uint32_t g = uint32_t(nt0 + h) * 16 + (lane & 15);
+            gb[h] = insert_zero_bits(g, srt, K);
+            float2 v[KS][4];
+#pragma unroll
+            for (int s = 0; s < KS; ++s)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) v[s][j] = tile[sw(gb[h] | roff[s][j])];
+#pragma unroll
+            for (int s = 0; s < KS; ++s)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const __bf16 hr = __bf16(v[s][j].x), hi = __bf16(v[s][j].y);
+                    bhi[h][s][2 * j] = hr;
+                    bhi[h][s][2 * j + 1] = hi;
+                    blo[h][s][2 * j] = __bf16(v[s][j].x - float(hr));
+                    blo[h][s][2 * j + 1] = __bf16(v[s][j].y - float(hi));
+                }
+        }
+        f32x4 acc[H][MT];
+#pragma unroll
+        for (int h = 0; h < H; ++h)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) acc[h][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int h = 0; h < H; ++h)
+                    acc[h][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[mt][s], bhi[h][s], acc[h][mt], 0, 0, 0);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int h = 0; h < H; ++h)
+                    acc[h][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[mt][s], blo[h][s], acc[h][mt], 0, 0, 0);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int h = 0; h < H; ++h)
+                    acc[h][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[mt][s], bhi[h][s], acc[h][mt], 0, 0, 0);
+        }
+#pragma unroll
+        for (int h = 0; h < H; ++h)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                tile[sw(gb[h] | woff[mt][0])] = make_float2(acc[h][mt][0], acc[h][mt][1]);
+                tile[sw(gb[h] | woff[mt][1])] = make_float2(acc[h][mt][2], acc[h][mt][3]);
+            }
+    }
+}
+
+// Five-qubit blocks in split form: with Ur = Re U and Ui = Im U (32 x 32
+// each) and the re / im parts of a group as separate columns,
+//   Yr = Ur Xr - Ui Xi,   Yi = Ui Xr + Ur Xi,
+// which needs half the operand registers of the real form at the same
+// number of matrix-core products.  Fragment order: Ur row tiles 0, 1, Ui row
+// tiles 0, 1 (hi), then the same four (lo).
+__device__ void dense_op5(float2 *tile, const TileOpDev &op, const uint4 *data, int m, int outer)
+{
+    constexpr int K = 5;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bf16x8 *fr =
+        reinterpret_cast<const bf16x8 *>(data + op.data_off + uint32_t(outer) * op.frag_stride);
+    bf16x8 urh[2], uih[2], url[2], uil[2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+        urh[mt] = fr[(0 + mt) * 64 + lane];
+        uih[mt] = fr[(2 + mt) * 64 + lane];
+        url[mt] = fr[(4 + mt) * 64 + lane];
+        uil[mt] = fr[(6 + mt) * 64 + lane];
+    }
+    int srt[K];
+#pragma unroll
+    for (int b = 0; b < K; ++b) srt[b] = op.lpos[b];
+#pragma unroll
+    for (int i = 1; i < K; ++i)
+#pragma unroll
+        for (int j = K - 1; j >= i; --j)
+            if (srt[j - 1] > srt[j]) {
+                const int t = srt[j];
+                srt[j] = srt[j - 1];
+                srt[j - 1] = t;
+            }
+    auto offset = [&](int x) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int b = 0; b < K; ++b)
+            if ((x >> (K - 1 - b)) & 1) o |= 1u << op.lpos[b];
+        return o;
+    };
+    uint32_t roff[8], woff[2][4];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) roff[j] = offset(8 * (lane >> 4) + j);
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) woff[mt][j] = offset(16 * mt + 4 * (lane >> 4) + j);
+    const int ntiles = 1 << (m - K - 4);
+    constexpr int kWaves = kThreads / 64;
+    for (int nt = wave; nt < ntiles; nt += kWaves) {
         const uint32_t g = uint32_t(nt) * 16 + (lane & 15);
         const uint32_t gb = insert_zero_bits(g, srt, K);
-        bf16x8 bhi[KS], blo[KS];
+        float2 v[8];
 #pragma unroll
-        for (int s = 0; s < KS; ++s)
+        for (int j = 0; j < 8; ++j) v[j] = tile[sw(gb | roff[j])];
+        bf16x8 xrh, xrl, xih, xil, nxih, nxil;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const float2 v = tile[gb | roff[s][j]];
-                const __bf16 hr = __bf16(v.x), hi = __bf16(v.y);
-                bhi[s][2 * j] = hr;
-                bhi[s][2 * j + 1] = hi;
-                blo[s][2 * j] = __bf16(v.x - float(hr));
-                blo[s][2 * j + 1] = __bf16(v.y - float(hi));
-            }
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int s = 0; s < KS; ++s) {
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[mt][s], bhi[s], acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[mt][s], blo[s], acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[mt][s], bhi[s], acc, 0, 0, 0);
-            }
-            tile[gb | woff[mt][0]] = make_float2(acc[0], acc[1]);
-            tile[gb | woff[mt][1]] = make_float2(acc[2], acc[3]);
+        for (int j = 0; j < 8; ++j) {
+            const __bf16 hr = __bf16(v[j].x), hi = __bf16(v[j].y);
+            const __bf16 lr = __bf16(v[j].x - float(hr)), li = __bf16(v[j].y - float(hi));
+            xrh[j] = hr;
+            xrl[j] = lr;
+            xih[j] = hi;
+            xil[j] = li;
+            nxih[j] = -hi;
+            nxil[j] = -li;
         }
+        f32x4 ar[2], ai[2];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+            ar[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+            ai[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+            ar[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(urh[mt], xrh, ar[mt], 0, 0, 0);
+            ai[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(uih[mt], xrh, ai[mt], 0, 0, 0);
+        }
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+            ar[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(uih[mt], nxih, ar[mt], 0, 0, 0);
+            ai[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(urh[mt], xih, ai[mt], 0, 0, 0);
+        }
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+            ar[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(urh[mt], xrl, ar[mt], 0, 0, 0);
+            ai[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(uih[mt], xrl, ai[mt], 0, 0, 0);
+        }
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+            ar[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(uih[mt], nxil, ar[mt], 0, 0, 0);
+            ai[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(urh[mt], xil, ai[mt], 0, 0, 0);
+        }
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+            ar[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(url[mt], xrh, ar[mt], 0, 0, 0);
+            ai[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(uil[mt], xrh, ai[mt], 0, 0, 0);
+        }
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+            ar[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(uil[mt], nxih, ar[mt], 0, 0, 0);
+            ai[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(url[mt], xih, ai[mt], 0, 0, 0);
+        }
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) tile[sw(gb | woff[mt][j])] = make_float2(ar[mt][j], ai[mt][j]);
     }
 }
 
@@ -158,47 +293,42 @@ __device__ void phase_op(float2 *tile, float2 *ptab, const TileOpDev &op, const 
             if (b < op.k) x |= int((j >> lp[b]) & 1) << sh[b];
         if ((active >> x) & 1) {
             const float2 f = ptab[x];
-            const float2 v = tile[j];
-            tile[j] = make_float2(f.x * v.x - f.y * v.y, f.x * v.y + f.y * v.x);
+            const float2 v = tile[sw(j)];
+            tile[sw(j)] = make_float2(f.x * v.x - f.y * v.y, f.x * v.y + f.y * v.x);
         }
     }
 }
 
+template <int M>
 __global__ __launch_bounds__(kThreads) void k_tile(float2 *amp, uint64_t ntiles, TileArgs ta,
                                                    const TileOpDev *ops, const uint4 *data)
 {
     extern __shared__ float2 lds[];
     float2 *tile = lds;
-    float2 *ptab = lds + (size_t(1) << ta.m);
-    const uint32_t n_amp = 1u << ta.m;
-    const int per = int(n_amp / (2 * kThreads));  // float4 (2 amplitudes) per thread
-    // global offset of this thread's first amplitude pair within a tile; the
-    // pair r adds the (uniform) offset of local index 512 r
-    const uint64_t toff = scatter_local(2u * threadIdx.x, ta);
+    float2 *ptab = lds + (size_t(1) << M);
+    constexpr int PER = (1 << M) / (2 * kThreads);  // 16-byte slots (2 amplitudes) per thread
+    // global offset of this thread's amplitude pair within a tile: local
+    // index 2 * tid (bits 1..8); slot r adds the uniform offset ta.slot[r]
+    uint64_t toff = 0;
+#pragma unroll
+    for (int b = 1; b < 9; ++b)
+        if (((2u * threadIdx.x) >> b) & 1u) toff |= uint64_t(1) << ta.qlo[b];
     for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        // tile base: insert a zero at every tile qubit
-        uint64_t base = t;
-#pragma unroll
-        for (int b = 0; b < kMaxM; ++b)
-            if (b < ta.m) {
-                const uint64_t lo = base & ((uint64_t(1) << ta.Q[b]) - 1);
-                base = ((base ^ lo) << 1) | lo;
-            }
+        // tile base: the tile index spread over the bits outside the tile
+        uint64_t base = 0;
+        for (int b = 0; b < ta.nouter; ++b)
+            if ((t >> b) & 1) base |= uint64_t(1) << ta.outer[b];
         // ---- load (non-temporal: every amplitude is read once per sweep)
-        constexpr int kMaxPer = 16;
-        vf4 buf[kMaxPer];
+        vf4 buf[PER];
 #pragma unroll
-        for (int r = 0; r < kMaxPer; ++r)
-            if (r < per) {
-                const uint64_t gi = base | toff | scatter_local(uint32_t(r) * 2u * kThreads, ta);
-                buf[r] = __builtin_nontemporal_load(reinterpret_cast<const vf4 *>(amp + gi));
-            }
+        for (int r = 0; r < PER; ++r)
+            buf[r] = __builtin_nontemporal_load(reinterpret_cast<const vf4 *>(amp + (base | toff | ta.slot[r])));
 #pragma unroll
-        for (int r = 0; r < kMaxPer; ++r)
-            if (r < per) {
-                const uint32_t j = 2u * (threadIdx.x + uint32_t(r) * kThreads);
-                *reinterpret_cast<vf4 *>(tile + j) = buf[r];
-            }
+        for (int r = 0; r < PER; ++r) {
+            const uint32_t j = 2u * (threadIdx.x + uint32_t(r) * kThreads);
+            tile[sw(j)] = make_float2(buf[r].x, buf[r].y);
+            tile[sw(j + 1)] = make_float2(buf[r].z, buf[r].w);
+        }
         __syncthreads();
         // ---- ops
         for (int oi = 0; oi < ta.nops; ++oi) {
@@ -210,27 +340,24 @@ __global__ __launch_bounds__(kThreads) void k_tile(float2 *amp, uint64_t ntiles,
             if (op.kind == 0) {
                 if ((op.skip >> outer) & 1u) continue;  // identity on this tile
                 if (op.k == 4)
-                    dense_op<4>(tile, op, data, ta.m, outer);
+                    dense_op<4>(tile, op, data, M, outer);
                 else
-                    dense_op<5>(tile, op, data, ta.m, outer);
+                    dense_op5(tile, op, data, M, outer);
             } else {
-                phase_op(tile, ptab, op, data, outer, ta.m);
+                phase_op(tile, ptab, op, data, outer, M);
             }
             __syncthreads();
         }
         // ---- store
 #pragma unroll
-        for (int r = 0; r < kMaxPer; ++r)
-            if (r < per) {
-                const uint32_t j = 2u * (threadIdx.x + uint32_t(r) * kThreads);
-                buf[r] = *reinterpret_cast<const vf4 *>(tile + j);
-            }
+        for (int r = 0; r < PER; ++r) {
+            const uint32_t j = 2u * (threadIdx.x + uint32_t(r) * kThreads);
+            const float2 a0 = tile[sw(j)], a1 = tile[sw(j + 1)];
+            buf[r] = vf4{a0.x, a0.y, a1.x, a1.y};
+        }
 #pragma unroll
-        for (int r = 0; r < kMaxPer; ++r)
-            if (r < per) {
-                const uint64_t gi = base | toff | scatter_local(uint32_t(r) * 2u * kThreads, ta);
-                __builtin_nontemporal_store(buf[r], reinterpret_cast<vf4 *>(amp + gi));
-            }
+        for (int r = 0; r < PER; ++r)
+            __builtin_nontemporal_store(buf[r], reinterpret_cast<vf4 *>(amp + (base | toff | ta.slot[r])));
         __syncthreads();
     }
 }
@@ -242,19 +369,35 @@ size_t tile_lds_bytes(int m) { return (size_t(8) << m) + 64 * sizeof(float2); }
 hipError_t launch_tile(void *amp, int n, const TileArgs &ta, const TileOpDev *dev_ops,
                        const void *dev_data, hipStream_t st)
 {
-    if (ta.m < 9 || ta.m > 13 || ta.L < 1 || ta.L > ta.m || ta.m > n) return hipErrorInvalidValue;
+    if (ta.m < 10 || ta.m > 13 || ta.m > n || ta.nouter != n - ta.m) return hipErrorInvalidValue;
     const size_t lds = tile_lds_bytes(ta.m);
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_tile, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           int(tile_lds_bytes(13)));
+        const int big = int(tile_lds_bytes(13));
+        hipError_t e = hipFuncSetAttribute((const void *)k_tile<13>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void *)k_tile<12>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
     const uint64_t ntiles = uint64_t(1) << (n - ta.m);
     const uint64_t grid = ntiles < (uint64_t(1) << 20) ? ntiles : (uint64_t(1) << 20);
-    hipLaunchKernelGGL(k_tile, dim3(unsigned(grid)), dim3(kThreads), lds, st, (float2 *)amp, ntiles, ta,
-                       dev_ops, (const uint4 *)dev_data);
+    float2 *a = (float2 *)amp;
+    const uint4 *d = (const uint4 *)dev_data;
+    switch (ta.m) {
+    case 10:
+        hipLaunchKernelGGL(k_tile<10>, dim3(unsigned(grid)), dim3(kThreads), lds, st, a, ntiles, ta, dev_ops, d);
+        break;
+    case 11:
+        hipLaunchKernelGGL(k_tile<11>, dim3(unsigned(grid)), dim3(kThreads), lds, st, a, ntiles, ta, dev_ops, d);
+        break;
+    case 12:
+        hipLaunchKernelGGL(k_tile<12>, dim3(unsigned(grid)), dim3(kThreads), lds, st, a, ntiles, ta, dev_ops, d);
+        break;
+    default:
+        hipLaunchKernelGGL(k_tile<13>, dim3(unsigned(grid)), dim3(kThreads), lds, st, a, ntiles, ta, dev_ops, d);
+        break;
+    }
     return hipGetLastError();
 }
 

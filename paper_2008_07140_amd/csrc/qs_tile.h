@@ -10,10 +10,13 @@
 namespace qs {
 
 struct TileArgs {
-    int m;          // tile qubits (9..13)
-    int L;          // Q[b] = b for b < L
+    int m;               // tile qubits (10..13)
     int nops;
-    int Q[kMaxQ];   // tile qubits, ascending
+    int nouter;          // n - m
+    int pad;
+    uint64_t slot[16];   // global offset of local index 512 r (the r-th 16-byte slot of a thread)
+    uint16_t qlo[10];    // global positions of local bits 0..9
+    uint8_t outer[kMaxQ];  // positions of the bits outside the tile, ascending
 };
 
 struct TileOpDev {

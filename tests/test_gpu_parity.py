@@ -344,7 +344,7 @@ def _mixed_circuit(n, count, seed):
     return ops
 
 
-@pytest.mark.parametrize("m,kmax", [(9, 4), (10, 5), (12, 4), (13, 5)])
+@pytest.mark.parametrize("m,kmax", [(10, 4), (11, 5), (12, 4), (13, 5)])
 def test_tile_sweeps_c64_mixed_gates(qs, m, kmax):
     n = 14
     ops = _mixed_circuit(n, 160, seed=100 + m)
@@ -358,7 +358,7 @@ def test_tile_sweeps_c64_mixed_gates(qs, m, kmax):
     assert np.max(np.abs(got - ref)) <= 1e-5
 
 
-@pytest.mark.parametrize("m", [9, 11, 13])
+@pytest.mark.parametrize("m", [10, 11, 13])
 def test_tile_sweeps_rqc16_and_rqc20(qs, m):
     for name, (rows, cols, depth, seed, cu3) in [("rqc16", (4, 4, 20, 1001, 0.0)),
                                                   ("rqc20", (4, 5, 40, 2001, 0.1))]:
@@ -382,7 +382,7 @@ def test_tile_sweeps_with_noise_segments(qs):
     s = qs.State(n, qs.C64)
     for traj in range(3):
         s.reset()
-        chosen = s.run(c, plan=1, k_max=5, tile_qubits=9, seed=5, traj=traj, nsites=nsites)
+        chosen = s.run(c, plan=1, k_max=5, tile_qubits=10, seed=5, traj=traj, nsites=nsites)
         ref, och = oracle.run(n, ops, seed=5, traj=traj)
         assert np.array_equal(chosen, och)
         assert infidelity(ref, s.amplitudes()) <= 1e-6
