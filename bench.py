@@ -48,6 +48,8 @@ def parse():
     p.add_argument("--tile-qubits", type=int, default=0, help="qubits per LDS tile (0 = library default)")
     p.add_argument("--plan", default="greedy", choices=["greedy", "learned"])
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--trajectories", type=int, default=512,
+                   help="noisy trajectories in the batched-trajectory measurement (0 = skip)")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 4 GiB device-to-device copy (5 times), the reference "
@@ -140,6 +142,27 @@ def run_path(qs, torch, cg, name, n, circuit, gates, steps, warmup, kmax, plan, 
     return res, st, buf
 
 
+def trajectory_bench(qs, cg, count, seed=4001):
+    """Batched noisy trajectories: widths n ~ U{14..22}, depth 24, depolarizing
+    1e-3 / 1e-2 (two-qubit, Kronecker form) and amplitude damping 5e-4 per
+    layer, complex64 states, one batch."""
+    t0 = time.perf_counter()
+    batch = cg.trajectory_batch(count, seed=seed)
+    circs = [qs.Circuit(ops) for _, ops in batch]
+    widths = [n for n, _ in batch]
+    gen = time.perf_counter() - t0
+    qs.run_trajectories(circs[:8], widths[:8], dtype=qs.C64, seed=seed)  # warm-up
+    z, sec = qs.run_trajectories(circs, widths, dtype=qs.C64, seed=seed)
+    sites = sum(sum(1 for o in ops if o.kind == "noise") for _, ops in batch)
+    gates = sum(cg.count_gates(ops) for _, ops in batch)
+    res = {"count": count, "seconds": sec, "traj_per_s": count / sec,
+           "widths": [min(widths), max(widths)], "mean_width": sum(widths) / count,
+           "logical_gates": gates, "noise_sites": sites, "generation_s": gen,
+           "dtype": "c64 state, FP64 branch weights"}
+    log("trajectories: %d in %.3f s -> %.1f traj/s" % (count, sec, count / sec))
+    return res
+
+
 def cpu_baseline(cg, n, ops, seconds):
     """The FP64 oracle on the host, on the first gates of the same circuit
     applied to the full 2^n state, for about `seconds` of gate work."""
@@ -216,6 +239,7 @@ def main():
         st.close()
     del states
     torch.cuda.empty_cache()
+    traj = trajectory_bench(qs, cg, args.trajectories) if args.trajectories > 0 else None
     primary = "fused_c64" if "fused_c64" in out else paths[0]
     prim = out[primary]
     cpu = None
@@ -246,6 +270,7 @@ def main():
         "hbm_frac_path": prim["hbm_frac_path"],
         "paths": out,
         "accuracy": acc,
+        "trajectories": traj,
         "cpu_baseline": cpu,
     }
     if "plain_c128" in out and primary != "plain_c128":

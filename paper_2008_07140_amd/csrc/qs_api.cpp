@@ -20,6 +20,11 @@
 #include "qs_internal.h"
 #include "qs_plan.h"
 #include "qs_tile.h"
+#include "qs_traj.h"
+#include "qs_philox.h"
+
+#include <chrono>
+#include <map>
 
 using cd = std::complex<double>;
 
@@ -477,6 +482,31 @@ bool tiled_plan(const qs_state *s, const qs_run_opts &o)
     return o.plan != QS_PLAN_UNFUSED && s->dt == QS_C64 && s->n >= 10;
 }
 
+// Kernel arguments of one sweep: slot r of a thread (local index 512 r) and
+// the local bits 0..8 of the thread offset mapped to their global qubits, and
+// the bits outside the tile that index the tiles.
+qs::TileArgs make_tile_args(const qs::Sweep &sw, int n)
+{
+    qs::TileArgs ta{};
+    ta.m = int(sw.Q.size());
+    ta.nops = int(sw.ops.size());
+    const auto &Q = sw.Q;
+    for (int b = 0; b < 10; ++b) ta.qlo[b] = uint16_t(b < ta.m ? Q[b] : 0);
+    for (int r = 0; r < 16; ++r) {
+        uint64_t off = 0;
+        const uint64_t j = uint64_t(r) * 512;  // local index of slot r (2 x 256 threads)
+        for (int b = 9; b < ta.m; ++b)
+            if ((j >> b) & 1) off |= uint64_t(1) << Q[b];
+        ta.slot[r] = off;
+    }
+    uint64_t qm = 0;
+    for (int q : Q) qm |= uint64_t(1) << q;
+    ta.nouter = 0;
+    for (int q = 0; q < n; ++q)
+        if (!(qm >> q & 1)) ta.outer[ta.nouter++] = uint8_t(q);
+    return ta;
+}
+
 qs_status launch_tiled(qs_state *s, const std::vector<qs::PlanStep> &steps)
 {
     TileProgram tp;
@@ -504,23 +534,7 @@ qs_status launch_tiled(qs_state *s, const std::vector<qs::PlanStep> &steps)
             if (qs_status e = launch_canon(s, st.gate)) return e;
             continue;
         }
-        qs::TileArgs ta{};
-        ta.m = int(st.sw.Q.size());
-        ta.nops = int(st.sw.ops.size());
-        const auto &Q = st.sw.Q;
-        for (int b = 0; b < 10; ++b) ta.qlo[b] = uint16_t(b < ta.m ? Q[b] : 0);
-        for (int r = 0; r < 16; ++r) {
-            uint64_t off = 0;
-            const uint64_t j = uint64_t(r) * 512;  // local index of slot r (2 x 256 threads)
-            for (int b = 9; b < ta.m; ++b)
-                if ((j >> b) & 1) off |= uint64_t(1) << Q[b];
-            ta.slot[r] = off;
-        }
-        uint64_t qm = 0;
-        for (int q : Q) qm |= uint64_t(1) << q;
-        ta.nouter = 0;
-        for (int q = 0; q < s->n; ++q)
-            if (!(qm >> q & 1)) ta.outer[ta.nouter++] = uint8_t(q);
+        const qs::TileArgs ta = make_tile_args(st.sw, s->n);
         double flops = 0;
         for (const auto &op : st.sw.ops)
             flops += (op.kind == qs::TileOp::DENSE ? 8.0 * double(1 << op.qubits.size()) : 6.0) *
@@ -675,6 +689,567 @@ qs_status create_common(int n, qs_dtype dt, qs_state **out)
     *out = nullptr;
     if (n < 1 || n > QS_MAX_QUBITS) return fail(QS_E_INVAL, "n = %d not in [1, %d]", n, QS_MAX_QUBITS);
     if (dt != QS_C64 && dt != QS_C128) return fail(QS_E_INVAL, "unknown dtype %d", int(dt));
+    return QS_OK;
+}
+
+}  // namespace
+
+
+// =============================================================== batches ==
+//
+// Noisy trajectories (Sec. 2.4), many states at once.  Per trajectory the
+// circuit is cut into steps:
+//  - GATES: gates, with every noise site whose branch weights do not depend
+//    on the state (all K_b^dagger K_b = c_b I, e.g. depolarizing) already
+//    sampled on the host from its Philox draw and replaced by K_b / sqrt(c_b);
+//  - RUN: consecutive one-qubit sites on distinct qubits whose first Kraus
+//    operator is diag(1, k) (amplitude and phase damping), sampled together
+//    from one FP64 reduction pass (qs_traj.hip).
+// Steps of all trajectories are executed together: one batched tile launch
+// per sweep round (complex64), one batched reduction and one host
+// synchronisation per RUN step for the whole batch.
+
+namespace {
+
+struct RunSite {
+    int q;
+    uint64_t site;
+    std::vector<double> kraus;  // nk 2x2 matrices
+    int nk;
+    double a;                   // |K1_11|^2
+};
+
+struct TStep {
+    bool run = false;
+    std::vector<qs::FlatOp> gates;
+    std::vector<RunSite> sites;
+};
+
+struct TPrep {
+    int n = 0;
+    std::vector<TStep> steps;
+    std::vector<qs::FlatOp> pending;  // diagonal factors left by the last RUN
+};
+
+bool scalar_channel(const std::vector<double> &kr, int nk, int nt, std::vector<double> &c)
+{
+    const int d = 1 << nt;
+    const size_t blk = size_t(2) * d * d;
+    c.assign(nk, 0.0);
+    for (int b = 0; b < nk; ++b) {
+        const double *K = kr.data() + blk * b;
+        std::vector<cd> kk(size_t(d) * d);
+        for (int r = 0; r < d; ++r)
+            for (int cc = 0; cc < d; ++cc) {
+                cd acc = 0;
+                for (int j = 0; j < d; ++j)
+                    acc += std::conj(cd(K[2 * (j * d + r)], K[2 * (j * d + r) + 1])) * cd(K[2 * (j * d + cc)], K[2 * (j * d + cc) + 1]);
+                kk[size_t(r) * d + cc] = acc;
+            }
+        c[b] = kk[0].real();
+        for (int r = 0; r < d; ++r)
+            for (int cc = 0; cc < d; ++cc)
+                if (std::abs(kk[size_t(r) * d + cc] - ((r == cc) ? cd(c[b]) : cd(0))) > 1e-14) return false;
+    }
+    return true;
+}
+
+// two one-qubit Kraus operators, K1 = diag(1, k), K2 acting only on |1>
+bool damping_channel(const std::vector<double> &kr, int nk, int nt, double &a)
+{
+    if (nt != 1 || nk != 2) return false;
+    const double *K1 = kr.data(), *K2 = kr.data() + 8;
+    if (K1[0] != 1.0 || K1[1] != 0.0 || K1[2] != 0.0 || K1[3] != 0.0 || K1[4] != 0.0 || K1[5] != 0.0) return false;
+    if (K2[0] != 0.0 || K2[1] != 0.0 || K2[4] != 0.0 || K2[5] != 0.0) return false;
+    a = K1[6] * K1[6] + K1[7] * K1[7];
+    return true;
+}
+
+int pick_branch(const std::vector<double> &p, double u)
+{
+    double run = 0.0;
+    for (size_t b = 0; b < p.size(); ++b) {
+        run += p[b];
+        if (u < run) return int(b);
+    }
+    for (int b = int(p.size()) - 1; b >= 0; --b)
+        if (p[b] > 0) return b;
+    return -1;
+}
+
+qs::FlatOp one_qubit(int q, const double *m2)
+{
+    qs::FlatOp f;
+    f.targets = {q};
+    f.m.assign(m2, m2 + 8);
+    return f;
+}
+
+qs_status prepare_trajectory(const qs_circuit *c, int n, uint64_t seed, uint64_t traj, TPrep &tp)
+{
+    std::vector<qs::FlatOp> flat;
+    std::string err;
+    int rc = qs::expand(c->ops, flat, err);
+    if (rc) return fail(rc == 2 ? QS_E_UNSUPPORTED : QS_E_INVAL, "%s", err.c_str());
+    tp.n = n;
+    TStep cur;
+    bool since_run_only_identity = false;  // no non-identity gate since the open RUN
+    uint64_t site = 0;
+    for (auto &f : flat) {
+        for (int q : f.targets)
+            if (q >= n) return fail(QS_E_RANGE, "qubit %d out of range [0, %d)", q, n);
+        for (int q : f.controls)
+            if (q >= n) return fail(QS_E_RANGE, "qubit %d out of range [0, %d)", q, n);
+        if (f.kind == qs::FlatOp::GATE) {
+            if (!qs::is_identity(f.m, int(f.targets.size()))) since_run_only_identity = false;
+            cur.gates.push_back(f);
+            continue;
+        }
+        const int nt = int(f.targets.size());
+        const double u = qs::noise_uniform(seed, traj, site);
+        std::vector<double> cb;
+        double a = 0;
+        if (scalar_channel(f.m, f.nk, nt, cb)) {
+            const int b = pick_branch(cb, u);
+            if (b < 0) return fail(QS_E_ZERO_NORM, "every Kraus branch has probability 0");
+            const int d = 1 << nt;
+            const size_t blk = size_t(2) * d * d;
+            const double sc = 1.0 / std::sqrt(cb[b]);
+            qs::FlatOp g;
+            g.targets = f.targets;
+            g.m.assign(f.m.begin() + blk * b, f.m.begin() + blk * (b + 1));
+            bool ident = true;
+            for (int r = 0; r < d; ++r)
+                for (int cc = 0; cc < d; ++cc) {
+                    const size_t k = size_t(r) * d + cc;
+                    g.m[2 * k] *= sc;
+                    g.m[2 * k + 1] *= sc;
+                    if (std::abs(g.m[2 * k] - (r == cc ? 1.0 : 0.0)) > 1e-14 || std::abs(g.m[2 * k + 1]) > 1e-14) ident = false;
+                }
+            if (!ident) {
+                cur.gates.push_back(std::move(g));
+                since_run_only_identity = false;
+            }
+        } else if (damping_channel(f.m, f.nk, nt, a)) {
+            RunSite rs{f.targets[0], site, f.m, f.nk, a};
+            TStep *last = tp.steps.empty() ? nullptr : &tp.steps.back();
+            bool join = last && last->run && since_run_only_identity && int(last->sites.size()) < qs::kRunMax;
+            if (join)
+                for (auto &o : last->sites)
+                    if (o.q == rs.q) join = false;
+            if (join) {
+                cur.gates.clear();  // identity carriers only
+                last->sites.push_back(std::move(rs));
+            } else {
+                tp.steps.push_back(std::move(cur));
+                cur = TStep();
+                TStep r;
+                r.run = true;
+                r.sites.push_back(std::move(rs));
+                tp.steps.push_back(std::move(r));
+            }
+            since_run_only_identity = true;
+        } else {
+            return fail(QS_E_UNSUPPORTED, "batched trajectories support noise channels with state-independent "
+                                          "weights and damping-type one-qubit channels");
+        }
+        ++site;
+    }
+    tp.steps.push_back(std::move(cur));
+    return QS_OK;
+}
+
+// A lightweight view of one trajectory's amplitudes that borrows the
+// scratch buffers of a master state (all work is on one stream).
+struct View {
+    qs_state s;
+    View(const qs_state *master, void *amp, int n)
+    {
+        s.n = n;
+        s.dt = master->dt;
+        s.device = master->device;
+        s.amp = amp;
+        s.owned = false;
+        s.stream = master->stream;
+        s.red = master->red;
+        s.dout = master->dout;
+        s.dmat = master->dmat;
+        s.hpin = master->hpin;
+    }
+    ~View()
+    {
+        s.red = nullptr;
+        s.dout = nullptr;
+        s.dmat = nullptr;
+        s.hpin = nullptr;
+        s.prog = nullptr;
+    }
+};
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t bytes)
+    {
+        if (bytes <= cap) return hipSuccess;
+        if (p) {
+            hipError_t e = hipFree(p);
+            if (e != hipSuccess) return e;
+        }
+        p = nullptr;
+        cap = 0;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e == hipSuccess) cap = bytes;
+        return e;
+    }
+    ~DevBuf()
+    {
+        if (p) (void)hipFree(p);
+    }
+};
+
+struct Batch {
+    qs_state *master = nullptr;  // scratch and stream owner (a 1-qubit state)
+    qs_dtype dt;
+    std::vector<TPrep> prep;
+    std::vector<void *> amp;
+    DevBuf states, prog, red, outb;
+    std::vector<View *> views;
+    ~Batch()
+    {
+        for (auto *v : views) delete v;
+        if (master) free_state(master);
+    }
+};
+
+// Apply a gate list to every listed trajectory: tiled complex64 plans run as
+// batched sweep rounds, everything else through the per-gate kernels.
+qs_status batch_gates(Batch &B, const std::vector<int> &who, std::vector<std::vector<qs::FlatOp>> &lists)
+{
+    std::vector<std::vector<qs::PlanStep>> plans(who.size());
+    size_t rounds = 0;
+    for (size_t i = 0; i < who.size(); ++i) {
+        const int n = B.prep[who[i]].n;
+        auto &fl = lists[i];
+        if (fl.empty()) continue;
+        if (B.dt == QS_C64 && n >= 10) {
+            qs_run_opts o{};
+            o.plan = QS_PLAN_GREEDY;
+            qs::plan_tiles(fl, 0, fl.size(), n, tile_params(n, o), plans[i]);
+        } else {
+            for (auto &f : fl) {
+                qs::PlanStep st;
+                st.sweep = false;
+                st.gate = qs::canonicalize(f.targets.data(), int(f.targets.size()), f.controls.data(),
+                                           int(f.controls.size()), f.m.data());
+                if (st.gate.kind != qs::CanonGate::IDENTITY) plans[i].push_back(std::move(st));
+            }
+        }
+        rounds = std::max(rounds, plans[i].size());
+    }
+    // flatten in (round, trajectory) order and build one device program
+    std::vector<qs::PlanStep> all;
+    struct Ref { size_t round; size_t who; };
+    std::vector<Ref> refs;
+    for (size_t r = 0; r < rounds; ++r)
+        for (size_t i = 0; i < who.size(); ++i)
+            if (r < plans[i].size()) {
+                all.push_back(plans[i][r]);
+                refs.push_back({r, i});
+            }
+    if (all.empty()) return QS_OK;
+    TileProgram tp;
+    build_tile_program(all, tp);
+    std::vector<qs::TileArgsDev> args;
+    std::vector<std::vector<qs::TileTask>> tasks(rounds * 4);  // per round, per m - 10
+    std::vector<size_t> arg_index(all.size(), SIZE_MAX);
+    for (size_t k = 0; k < all.size(); ++k) {
+        if (!all[k].sweep) continue;
+        const int t = who[refs[k].who];
+        qs::TileArgsDev ad{};
+        ad.amp = static_cast<float2 *>(B.amp[t]);
+        ad.op_off = uint32_t(tp.first[k]);
+        ad.ta = make_tile_args(all[k].sw, B.prep[t].n);
+        arg_index[k] = args.size();
+        args.push_back(ad);
+        const uint32_t ntiles = uint32_t(1) << (B.prep[t].n - ad.ta.m);
+        auto &tl = tasks[refs[k].round * 4 + (ad.ta.m - 10)];
+        for (uint32_t tile = 0; tile < ntiles; ++tile) tl.push_back({uint32_t(args.size() - 1), tile});
+    }
+    size_t ntask = 0;
+    for (auto &tl : tasks) ntask += tl.size();
+    const size_t ob = tp.ops.size() * sizeof(qs::TileOpDev);
+    const size_t db = tp.data.size() * sizeof(uint16_t);
+    const size_t ab = args.size() * sizeof(qs::TileArgsDev);
+    const size_t tb = ntask * sizeof(qs::TileTask);
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t total = up(ob) + up(db) + up(ab) + up(tb) + 256;
+    qs_state *s = B.master;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    HIP_TRY(B.prog.ensure(total));
+    unsigned char *dev = static_cast<unsigned char *>(B.prog.p);
+    std::vector<unsigned char> host(total, 0);
+    std::memcpy(host.data(), tp.ops.data(), ob);
+    std::memcpy(host.data() + up(ob), tp.data.data(), db);
+    if (ab) std::memcpy(host.data() + up(ob) + up(db), args.data(), ab);
+    std::vector<size_t> task_off(tasks.size());
+    size_t toff = 0;
+    for (size_t k = 0; k < tasks.size(); ++k) {
+        task_off[k] = toff;
+        if (!tasks[k].empty())
+            std::memcpy(host.data() + up(ob) + up(db) + up(ab) + toff * sizeof(qs::TileTask), tasks[k].data(),
+                        tasks[k].size() * sizeof(qs::TileTask));
+        toff += tasks[k].size();
+    }
+    HIP_TRY(hipMemcpy(dev, host.data(), total, hipMemcpyHostToDevice));
+    const qs::TileOpDev *dops = reinterpret_cast<const qs::TileOpDev *>(dev);
+    const void *ddata = dev + up(ob);
+    const qs::TileArgsDev *dargs = reinterpret_cast<const qs::TileArgsDev *>(dev + up(ob) + up(db));
+    const qs::TileTask *dtasks = reinterpret_cast<const qs::TileTask *>(dev + up(ob) + up(db) + up(ab));
+    size_t k = 0;
+    for (size_t r = 0; r < rounds; ++r) {
+        // standalone gates of this round (different states: any order)
+        for (size_t kk = k; kk < all.size() && refs[kk].round == r; ++kk) {
+            if (all[kk].sweep) continue;
+            const int t = who[refs[kk].who];
+            if (qs_status e = launch_canon(&B.views[t]->s, all[kk].gate)) return e;
+        }
+        while (k < all.size() && refs[k].round == r) ++k;
+        for (int mm = 0; mm < 4; ++mm) {
+            const auto &tl = tasks[r * 4 + mm];
+            if (tl.empty()) continue;
+            hipError_t e = qs::launch_tile_multi(10 + mm, uint32_t(tl.size()), dtasks + task_off[r * 4 + mm], dargs,
+                                                 dops, ddata, s->stream);
+            if (e != hipSuccess) return hip_fail(e, "batched tile launch");
+        }
+    }
+    return QS_OK;
+}
+
+// Sums S_j / Z for runs of sites (qs_traj.hip) of several trajectories.
+// sums[i] receives kRunMax + 1 doubles: Z, S_0, S_1, ...
+qs_status batch_run_sums(Batch &B, const std::vector<int> &who, const std::vector<std::vector<int>> &qs_,
+                         const std::vector<std::vector<double>> &as_, std::vector<std::vector<double>> &sums)
+{
+    qs_state *s = B.master;
+    const uint64_t chunk = 1u << 16;
+    std::vector<qs::RunSumArgs> args(who.size());
+    std::vector<qs::RunSumTask> tasks;
+    std::vector<uint32_t> first(who.size()), count(who.size());
+    for (size_t i = 0; i < who.size(); ++i) {
+        const int t = who[i];
+        qs::RunSumArgs &a = args[i];
+        a.amp = B.amp[t];
+        a.n_amp = uint64_t(1) << B.prep[t].n;
+        a.chunk_len = chunk;
+        a.J = int(qs_[i].size());
+        for (int j = 0; j < a.J; ++j) {
+            a.q[j] = uint8_t(qs_[i][j]);
+            a.a[j] = as_[i][j];
+        }
+        const uint32_t nch = uint32_t((a.n_amp + chunk - 1) / chunk);
+        first[i] = uint32_t(tasks.size());
+        count[i] = nch;
+        for (uint32_t c = 0; c < nch; ++c) tasks.push_back({uint32_t(i), c});
+    }
+    const int w = qs::kRunMax + 1;
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t ab = up(args.size() * sizeof(qs::RunSumArgs)), tb = up(tasks.size() * sizeof(qs::RunSumTask));
+    const size_t fb = up(who.size() * 4);
+    const size_t pb = up(tasks.size() * w * sizeof(double)), ob = up(who.size() * w * sizeof(double));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    HIP_TRY(B.red.ensure(ab + tb + 2 * fb + pb + ob));
+    unsigned char *dev = static_cast<unsigned char *>(B.red.p);
+    HIP_TRY(hipMemcpy(dev, args.data(), args.size() * sizeof(qs::RunSumArgs), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dev + ab, tasks.data(), tasks.size() * sizeof(qs::RunSumTask), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dev + ab + tb, first.data(), who.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dev + ab + tb + fb, count.data(), who.size() * 4, hipMemcpyHostToDevice));
+    double *partials = reinterpret_cast<double *>(dev + ab + tb + 2 * fb);
+    double *out = reinterpret_cast<double *>(dev + ab + tb + 2 * fb + pb);
+    {
+        double bytes = 0;
+        for (int t : who) bytes += double(amp_bytes(B.dt)) * std::ldexp(1.0, B.prep[t].n);
+        Timed tm(s, QS_K_REDUCE, bytes, bytes);
+        hipError_t e = qs::launch_run_sums(B.dt, uint32_t(tasks.size()), reinterpret_cast<qs::RunSumTask *>(dev + ab),
+                                           reinterpret_cast<qs::RunSumArgs *>(dev), partials, s->stream);
+        if (e == hipSuccess)
+            e = qs::launch_run_sums_finish(partials, reinterpret_cast<uint32_t *>(dev + ab + tb),
+                                           reinterpret_cast<uint32_t *>(dev + ab + tb + fb), int(who.size()), out,
+                                           s->stream);
+        if (e != hipSuccess) return hip_fail(e, "trajectory reductions");
+    }
+    std::vector<double> host(who.size() * w);
+    HIP_TRY(hipMemcpyAsync(host.data(), out, host.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    sums.assign(who.size(), {});
+    for (size_t i = 0; i < who.size(); ++i) sums[i].assign(host.begin() + i * w, host.begin() + (i + 1) * w);
+    return QS_OK;
+}
+
+// Sample a run of damping-type sites from its sums.  Sites 0..j-1 that take
+// K1 are left as pending diagonal factors (K1 and a final 1/sqrt(norm)); a K2
+// branch is applied at once and the sums of the remaining sites recomputed.
+qs_status sample_run(Batch &B, int t, const TStep &run, std::vector<double> sums, uint64_t seed)
+{
+    TPrep &tp = B.prep[t];
+    size_t j0 = 0;  // first site covered by `sums`
+    while (j0 < run.sites.size()) {
+        double Z = sums[0];
+        size_t j = j0;
+        int k2_at = -1;
+        for (; j < run.sites.size(); ++j) {
+            const RunSite &rs = run.sites[j];
+            const double S = sums[1 + (j - j0)];
+            const double p2 = (1.0 - rs.a) * S / Z;
+            const double p1 = (Z - (1.0 - rs.a) * S) / Z;
+            const double u = qs::noise_uniform(seed, uint64_t(t), rs.site);
+            const int b = pick_branch({p1, p2}, u);
+            if (b == 0) {
+                Z -= (1.0 - rs.a) * S;
+                continue;
+            }
+            if (b < 0) return fail(QS_E_ZERO_NORM, "every Kraus branch has probability 0");
+            k2_at = int(j);
+            break;
+        }
+        // K1 factors of sites j0 .. j-1
+        for (size_t i = j0; i < j; ++i) tp.pending.push_back(one_qubit(run.sites[i].q, run.sites[i].kraus.data()));
+        if (k2_at < 0) {
+            const double sc = 1.0 / std::sqrt(Z);
+            const double m2[8] = {sc, 0, 0, 0, 0, 0, sc, 0};
+            tp.pending.push_back(one_qubit(0, m2));
+            return QS_OK;
+        }
+        const RunSite &rs = run.sites[k2_at];
+        const double S = sums[1 + (k2_at - j0)];
+        const double nrm2 = (1.0 - rs.a) * S;  // squared norm after the K1s and this K2
+        tp.pending.push_back(one_qubit(rs.q, rs.kraus.data() + 8));
+        const double sc = 1.0 / std::sqrt(nrm2);
+        const double m2[8] = {sc, 0, 0, 0, 0, 0, sc, 0};
+        tp.pending.push_back(one_qubit(0, m2));
+        std::vector<int> who = {t};
+        std::vector<std::vector<qs::FlatOp>> lists = {tp.pending};
+        tp.pending.clear();
+        if (qs_status e = batch_gates(B, who, lists)) return e;
+        j0 = size_t(k2_at) + 1;
+        if (j0 >= run.sites.size()) return QS_OK;
+        std::vector<std::vector<int>> qv(1);
+        std::vector<std::vector<double>> av(1);
+        for (size_t i = j0; i < run.sites.size(); ++i) {
+            qv[0].push_back(run.sites[i].q);
+            av[0].push_back(run.sites[i].a);
+        }
+        std::vector<std::vector<double>> out;
+        if (qs_status e = batch_run_sums(B, who, qv, av, out)) return e;
+        sums = out[0];
+    }
+    return QS_OK;
+}
+
+qs_status run_trajectory_batch(const qs_circuit *const *circs, const int *widths, int count, qs_dtype dt,
+                               uint64_t seed, double *z_out, double *seconds)
+{
+    if (!circs || !widths || !z_out || count < 0) return fail(QS_E_INVAL, "NULL argument or negative count");
+    if (dt != QS_C64 && dt != QS_C128) return fail(QS_E_INVAL, "unknown dtype %d", int(dt));
+    if (count == 0) return QS_OK;
+    Batch B;
+    B.dt = dt;
+    B.prep.resize(count);
+    size_t total = 0;
+    for (int t = 0; t < count; ++t) {
+        if (!circs[t]) return fail(QS_E_INVAL, "circuit %d is NULL", t);
+        if (widths[t] < 1 || widths[t] > qs::kRunMax) return fail(QS_E_INVAL, "width %d not in [1, %d]", widths[t], qs::kRunMax);
+        if (qs_status e = prepare_trajectory(circs[t], widths[t], seed, uint64_t(t), B.prep[t])) return e;
+        total += amp_bytes(dt) << widths[t];
+    }
+    const size_t lim = g_mem_limit.load();
+    if (lim && total > lim) return fail(QS_E_NOMEM, "batch of %zu bytes exceeds the memory limit", total);
+    if (qs_status e = qs_create(1, dt, &B.master)) return e;
+    {
+        hipError_t e = B.states.ensure(total);
+        if (e != hipSuccess) return fail(QS_E_NOMEM, "device allocation of %zu bytes failed", total);
+    }
+    size_t off = 0;
+    for (int t = 0; t < count; ++t) {
+        B.amp.push_back(static_cast<unsigned char *>(B.states.p) + off);
+        B.views.push_back(new View(B.master, B.amp.back(), widths[t]));
+        off += amp_bytes(dt) << widths[t];
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int t = 0; t < count; ++t)
+        if (qs_status e = init_amplitudes(&B.views[t]->s)) return e;
+    std::vector<size_t> cursor(count, 0);
+    for (;;) {
+        std::vector<int> gate_who, run_who;
+        for (int t = 0; t < count; ++t) {
+            if (cursor[t] >= B.prep[t].steps.size()) continue;
+            (B.prep[t].steps[cursor[t]].run ? run_who : gate_who).push_back(t);
+        }
+        if (gate_who.empty() && run_who.empty()) break;
+        if (!gate_who.empty()) {
+            std::vector<std::vector<qs::FlatOp>> lists;
+            for (int t : gate_who) {
+                std::vector<qs::FlatOp> l = std::move(B.prep[t].pending);
+                B.prep[t].pending.clear();
+                auto &g = B.prep[t].steps[cursor[t]].gates;
+                l.insert(l.end(), g.begin(), g.end());
+                lists.push_back(std::move(l));
+                ++cursor[t];
+            }
+            if (qs_status e = batch_gates(B, gate_who, lists)) return e;
+            continue;  // runs wait for the gates that precede them
+        }
+        std::vector<std::vector<int>> qv;
+        std::vector<std::vector<double>> av;
+        for (int t : run_who) {
+            const TStep &r = B.prep[t].steps[cursor[t]];
+            qv.emplace_back();
+            av.emplace_back();
+            for (auto &s2 : r.sites) {
+                qv.back().push_back(s2.q);
+                av.back().push_back(s2.a);
+            }
+        }
+        std::vector<std::vector<double>> sums;
+        if (qs_status e = batch_run_sums(B, run_who, qv, av, sums)) return e;
+        for (size_t i = 0; i < run_who.size(); ++i) {
+            const int t = run_who[i];
+            if (qs_status e = sample_run(B, t, B.prep[t].steps[cursor[t]], sums[i], seed)) return e;
+            ++cursor[t];
+        }
+    }
+    // remaining diagonal factors, then <Z_q> = (Z - 2 S_q) / Z for every qubit
+    {
+        std::vector<int> who;
+        std::vector<std::vector<qs::FlatOp>> lists;
+        for (int t = 0; t < count; ++t)
+            if (!B.prep[t].pending.empty()) {
+                who.push_back(t);
+                lists.push_back(std::move(B.prep[t].pending));
+            }
+        if (!who.empty())
+            if (qs_status e = batch_gates(B, who, lists)) return e;
+    }
+    std::vector<int> all(count);
+    std::vector<std::vector<int>> qv(count);
+    std::vector<std::vector<double>> av(count);
+    for (int t = 0; t < count; ++t) {
+        all[t] = t;
+        for (int q = 0; q < widths[t]; ++q) {
+            qv[t].push_back(q);
+            av[t].push_back(1.0);
+        }
+    }
+    std::vector<std::vector<double>> sums;
+    if (qs_status e = batch_run_sums(B, all, qv, av, sums)) return e;
+    size_t zo = 0;
+    for (int t = 0; t < count; ++t) {
+        const double Z = sums[t][0];
+        for (int q = 0; q < widths[t]; ++q) z_out[zo + q] = (Z - 2.0 * sums[t][1 + q]) / Z;
+        zo += size_t(widths[t]);
+    }
+    const auto t1 = std::chrono::steady_clock::now();
+    if (seconds) *seconds = std::chrono::duration<double>(t1 - t0).count();
     return QS_OK;
 }
 
@@ -1133,7 +1708,7 @@ qs_status qs_expect_z(const qs_state *cs, double *out)
 qs_status qs_run_trajectories(const qs_circuit *const *circs, const int *widths, int count,
                               qs_dtype dt, uint64_t seed, double *z_out, double *seconds)
 {
-    return qs::run_trajectories(circs, widths, count, dt, seed, z_out, seconds);
+    return run_trajectory_batch(circs, widths, count, dt, seed, z_out, seconds);
 }
 
 // ------------------------------------------------------------- profiling --

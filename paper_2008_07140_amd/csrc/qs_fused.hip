@@ -299,87 +299,126 @@ __device__ void phase_op(float2 *tile, float2 *ptab, const TileOpDev &op, const 
     }
 }
 
+// One tile: load, apply ops, store.  `toff` is this thread's offset within
+// a tile (local index 2 * tid spread over the tile qubits).
+template <int M>
+__device__ __forceinline__ void tile_pass(float2 *amp, uint64_t t, const TileArgs &ta, uint64_t toff,
+                                          const TileOpDev *ops, const uint4 *data, float2 *tile,
+                                          float2 *ptab)
+{
+    constexpr int PER = (1 << M) / (2 * kThreads);  // 16-byte slots (2 amplitudes) per thread
+    // tile base: the tile index spread over the bits outside the tile
+    uint64_t base = 0;
+    for (int b = 0; b < ta.nouter; ++b)
+        if ((t >> b) & 1) base |= uint64_t(1) << ta.outer[b];
+    // ---- load (non-temporal: every amplitude is read once per sweep)
+    vf4 buf[PER];
+#pragma unroll
+    for (int r = 0; r < PER; ++r)
+        buf[r] = __builtin_nontemporal_load(reinterpret_cast<const vf4 *>(amp + (base | toff | ta.slot[r])));
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const uint32_t j = 2u * (threadIdx.x + uint32_t(r) * kThreads);
+        tile[sw(j)] = make_float2(buf[r].x, buf[r].y);
+        tile[sw(j + 1)] = make_float2(buf[r].z, buf[r].w);
+    }
+    __syncthreads();
+    // ---- ops
+    for (int oi = 0; oi < ta.nops; ++oi) {
+        const TileOpDev op = ops[oi];
+        int outer = 0;
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            if (b < op.no) outer = (outer << 1) | int((base >> op.opos[b]) & 1);
+        if (op.kind == 0) {
+            if ((op.skip >> outer) & 1u) continue;  // identity on this tile
+            if (op.k == 4)
+                dense_op<4>(tile, op, data, M, outer);
+            else
+                dense_op5(tile, op, data, M, outer);
+        } else {
+            phase_op(tile, ptab, op, data, outer, M);
+        }
+        __syncthreads();
+    }
+    // ---- store
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const uint32_t j = 2u * (threadIdx.x + uint32_t(r) * kThreads);
+        const float2 a0 = tile[sw(j)], a1 = tile[sw(j + 1)];
+        buf[r] = vf4{a0.x, a0.y, a1.x, a1.y};
+    }
+#pragma unroll
+    for (int r = 0; r < PER; ++r)
+        __builtin_nontemporal_store(buf[r], reinterpret_cast<vf4 *>(amp + (base | toff | ta.slot[r])));
+    __syncthreads();
+}
+
+__device__ __forceinline__ uint64_t thread_offset(const TileArgs &ta)
+{
+    // local index 2 * tid (bits 1..8); slot r adds the uniform ta.slot[r]
+    uint64_t toff = 0;
+#pragma unroll
+    for (int b = 1; b < 9; ++b)
+        if (((2u * threadIdx.x) >> b) & 1u) toff |= uint64_t(1) << ta.qlo[b];
+    return toff;
+}
+
 template <int M>
 __global__ __launch_bounds__(kThreads) void k_tile(float2 *amp, uint64_t ntiles, TileArgs ta,
                                                    const TileOpDev *ops, const uint4 *data)
 {
     extern __shared__ float2 lds[];
-    float2 *tile = lds;
     float2 *ptab = lds + (size_t(1) << M);
-    constexpr int PER = (1 << M) / (2 * kThreads);  // 16-byte slots (2 amplitudes) per thread
-    // global offset of this thread's amplitude pair within a tile: local
-    // index 2 * tid (bits 1..8); slot r adds the uniform offset ta.slot[r]
-    uint64_t toff = 0;
-#pragma unroll
-    for (int b = 1; b < 9; ++b)
-        if (((2u * threadIdx.x) >> b) & 1u) toff |= uint64_t(1) << ta.qlo[b];
-    for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        // tile base: the tile index spread over the bits outside the tile
-        uint64_t base = 0;
-        for (int b = 0; b < ta.nouter; ++b)
-            if ((t >> b) & 1) base |= uint64_t(1) << ta.outer[b];
-        // ---- load (non-temporal: every amplitude is read once per sweep)
-        vf4 buf[PER];
-#pragma unroll
-        for (int r = 0; r < PER; ++r)
-            buf[r] = __builtin_nontemporal_load(reinterpret_cast<const vf4 *>(amp + (base | toff | ta.slot[r])));
-#pragma unroll
-        for (int r = 0; r < PER; ++r) {
-            const uint32_t j = 2u * (threadIdx.x + uint32_t(r) * kThreads);
-            tile[sw(j)] = make_float2(buf[r].x, buf[r].y);
-            tile[sw(j + 1)] = make_float2(buf[r].z, buf[r].w);
-        }
-        __syncthreads();
-        // ---- ops
-        for (int oi = 0; oi < ta.nops; ++oi) {
-            const TileOpDev op = ops[oi];
-            int outer = 0;
-#pragma unroll
-            for (int b = 0; b < 3; ++b)
-                if (b < op.no) outer = (outer << 1) | int((base >> op.opos[b]) & 1);
-            if (op.kind == 0) {
-                if ((op.skip >> outer) & 1u) continue;  // identity on this tile
-                if (op.k == 4)
-                    dense_op<4>(tile, op, data, M, outer);
-                else
-                    dense_op5(tile, op, data, M, outer);
-            } else {
-                phase_op(tile, ptab, op, data, outer, M);
-            }
-            __syncthreads();
-        }
-        // ---- store
-#pragma unroll
-        for (int r = 0; r < PER; ++r) {
-            const uint32_t j = 2u * (threadIdx.x + uint32_t(r) * kThreads);
-            const float2 a0 = tile[sw(j)], a1 = tile[sw(j + 1)];
-            buf[r] = vf4{a0.x, a0.y, a1.x, a1.y};
-        }
-#pragma unroll
-        for (int r = 0; r < PER; ++r)
-            __builtin_nontemporal_store(buf[r], reinterpret_cast<vf4 *>(amp + (base | toff | ta.slot[r])));
-        __syncthreads();
-    }
+    const uint64_t toff = thread_offset(ta);
+    for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x)
+        tile_pass<M>(amp, t, ta, toff, ops, data, lds, ptab);
+}
+
+// Batched form: workgroup b runs tile tasks[b].tile of the state described by
+// args[tasks[b].arg] (its own amplitudes, tile qubits and op list), so one
+// launch covers one sweep of many independent states.
+template <int M>
+__global__ __launch_bounds__(kThreads) void k_tile_multi(const TileTask *tasks, const TileArgsDev *args,
+                                                         const TileOpDev *ops, const uint4 *data)
+{
+    extern __shared__ float2 lds[];
+    float2 *ptab = lds + (size_t(1) << M);
+    const TileTask task = tasks[blockIdx.x];
+    const TileArgsDev &ad = args[task.arg];
+    const uint64_t toff = thread_offset(ad.ta);
+    tile_pass<M>(ad.amp, task.tile, ad.ta, toff, ops + ad.op_off, data, lds, ptab);
 }
 
 }  // namespace
 
 size_t tile_lds_bytes(int m) { return (size_t(8) << m) + 64 * sizeof(float2); }
 
+template <typename F>
+hipError_t set_lds_attr(F kernel)
+{
+    return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               int(tile_lds_bytes(13)));
+}
+
+hipError_t ensure_attrs()
+{
+    static bool done = false;
+    if (done) return hipSuccess;
+    hipError_t e = set_lds_attr(k_tile<13>);
+    if (e == hipSuccess) e = set_lds_attr(k_tile<12>);
+    if (e == hipSuccess) e = set_lds_attr(k_tile_multi<13>);
+    if (e == hipSuccess) e = set_lds_attr(k_tile_multi<12>);
+    if (e == hipSuccess) done = true;
+    return e;
+}
+
 hipError_t launch_tile(void *amp, int n, const TileArgs &ta, const TileOpDev *dev_ops,
                        const void *dev_data, hipStream_t st)
 {
     if (ta.m < 10 || ta.m > 13 || ta.m > n || ta.nouter != n - ta.m) return hipErrorInvalidValue;
     const size_t lds = tile_lds_bytes(ta.m);
-    static bool attr_set = false;
-    if (!attr_set) {
-        const int big = int(tile_lds_bytes(13));
-        hipError_t e = hipFuncSetAttribute((const void *)k_tile<13>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void *)k_tile<12>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    if (hipError_t e = ensure_attrs()) return e;
     const uint64_t ntiles = uint64_t(1) << (n - ta.m);
     const uint64_t grid = ntiles < (uint64_t(1) << 20) ? ntiles : (uint64_t(1) << 20);
     float2 *a = (float2 *)amp;
@@ -396,6 +435,30 @@ hipError_t launch_tile(void *amp, int n, const TileArgs &ta, const TileOpDev *de
         break;
     default:
         hipLaunchKernelGGL(k_tile<13>, dim3(unsigned(grid)), dim3(kThreads), lds, st, a, ntiles, ta, dev_ops, d);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_multi(int m, uint32_t ntasks, const TileTask *tasks, const TileArgsDev *args,
+                             const TileOpDev *dev_ops, const void *dev_data, hipStream_t st)
+{
+    if (m < 10 || m > 13 || ntasks == 0) return hipErrorInvalidValue;
+    const size_t lds = tile_lds_bytes(m);
+    if (hipError_t e = ensure_attrs()) return e;
+    const uint4 *d = (const uint4 *)dev_data;
+    switch (m) {
+    case 10:
+        hipLaunchKernelGGL(k_tile_multi<10>, dim3(ntasks), dim3(kThreads), lds, st, tasks, args, dev_ops, d);
+        break;
+    case 11:
+        hipLaunchKernelGGL(k_tile_multi<11>, dim3(ntasks), dim3(kThreads), lds, st, tasks, args, dev_ops, d);
+        break;
+    case 12:
+        hipLaunchKernelGGL(k_tile_multi<12>, dim3(ntasks), dim3(kThreads), lds, st, tasks, args, dev_ops, d);
+        break;
+    default:
+        hipLaunchKernelGGL(k_tile_multi<13>, dim3(ntasks), dim3(kThreads), lds, st, tasks, args, dev_ops, d);
         break;
     }
     return hipGetLastError();

@@ -345,58 +345,6 @@ void greedy_fuse(const std::vector<FlatOp> &flat, size_t k0, size_t e, int kmax,
     for (auto &b : open) emit(*b);
 }
 
-// Sequential trajectory runner: one state per distinct width, reused.
-qs_status run_trajectories(const qs_circuit *const *circs, const int *widths, int count, qs_dtype dt,
-                           uint64_t seed, double *z_out, double *seconds)
-{
-    if (!circs || !widths || !z_out || count < 0) return set_error(QS_E_INVAL, "NULL argument or negative count");
-    std::map<int, qs_state *> states;
-    auto cleanup = [&]() {
-        for (auto &kv : states) qs_destroy(kv.second);
-    };
-    const auto t0 = std::chrono::steady_clock::now();
-    size_t off = 0;
-    for (int t = 0; t < count; ++t) {
-        const int n = widths[t];
-        if (n < 1 || n > QS_MAX_QUBITS) {
-            cleanup();
-            return set_error(QS_E_INVAL, "trajectory width out of range");
-        }
-        qs_state *s = nullptr;
-        auto it = states.find(n);
-        if (it == states.end()) {
-            if (qs_status st = qs_create(n, dt, &s)) {
-                cleanup();
-                return st;
-            }
-            states[n] = s;
-        } else {
-            s = it->second;
-            if (qs_status st = qs_reset(s)) {
-                cleanup();
-                return st;
-            }
-        }
-        qs_run_opts o{};
-        o.plan = QS_PLAN_UNFUSED;
-        o.seed = seed;
-        o.traj = uint64_t(t);
-        if (qs_status st = run_on_state(s, circs[t], &o)) {
-            cleanup();
-            return st;
-        }
-        if (qs_status st = qs_expect_z(s, z_out + off)) {
-            cleanup();
-            return st;
-        }
-        off += size_t(n);
-    }
-    const auto t1 = std::chrono::steady_clock::now();
-    if (seconds) *seconds = std::chrono::duration<double>(t1 - t0).count();
-    cleanup();
-    return QS_OK;
-}
-
 }  // namespace qs
 
 extern "C" {

@@ -55,9 +55,6 @@ void greedy_fuse(const std::vector<FlatOp> &flat, size_t k, size_t e, int kmax,
 int default_kmax(int n, qs_dtype dt);
 int default_tile_qubits(int n);
 
-qs_status run_trajectories(const qs_circuit *const *circs, const int *widths, int count, qs_dtype dt,
-                           uint64_t seed, double *z_out, double *seconds);
-
 qs_status set_error(qs_status st, const char *msg);
 qs_status run_on_state(qs_state *s, const qs_circuit *c, const qs_run_opts *o);
 

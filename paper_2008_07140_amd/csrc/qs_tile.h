@@ -30,7 +30,22 @@ struct TileOpDev {
     uint32_t frag_stride;  // dense: 16-byte units per outer pattern
 };
 
+// Batched sweeps: one entry per workgroup.
+struct TileTask {
+    uint32_t arg;   // index into the TileArgsDev array
+    uint32_t tile;  // tile index within that state
+};
+
+struct TileArgsDev {
+    float2 *amp;
+    uint32_t op_off;  // first op of this state's sweep in the op array
+    uint32_t pad;
+    TileArgs ta;
+};
+
 size_t tile_lds_bytes(int m);
+hipError_t launch_tile_multi(int m, uint32_t ntasks, const TileTask *tasks, const TileArgsDev *args,
+                             const TileOpDev *dev_ops, const void *dev_data, hipStream_t st);
 hipError_t launch_tile(void *amp, int n, const TileArgs &ta, const TileOpDev *dev_ops,
                        const void *dev_data, hipStream_t st);
 

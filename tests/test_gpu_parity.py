@@ -386,3 +386,48 @@ def test_tile_sweeps_with_noise_segments(qs):
         ref, och = oracle.run(n, ops, seed=5, traj=traj)
         assert np.array_equal(chosen, och)
         assert infidelity(ref, s.amplitudes()) <= 1e-6
+
+
+# ------------------------------------------------------ batched trajectories --
+
+
+def _traj_batch(count, nmin, nmax, depth, seed, rate):
+    rng = np.random.default_rng(seed)
+    out = []
+    for t in range(count):
+        n = int(rng.integers(nmin, nmax + 1))
+        r, c = cg.grid_shape(n)
+        out.append((n, cg.random_circuit(r, c, depth, seed + t, dep1=rate, dep2=rate, damping=rate)))
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batched_trajectories_match_oracle_per_trajectory(qs, dtype):
+    """Each trajectory of the batch is the oracle's literal Sec. 2.4 run with
+    the same Philox draws (site s of trajectory t), compared through <Z_q>."""
+    batch = _traj_batch(12, 8 if dtype == "c128" else 10, 12, 5, 700, 0.05)
+    circs = [qs.Circuit(ops) for _, ops in batch]
+    widths = [n for n, _ in batch]
+    dt = qs.C128 if dtype == "c128" else qs.C64
+    z, sec = qs.run_trajectories(circs, widths, dtype=dt, seed=31)
+    off = 0
+    for t, (n, ops) in enumerate(batch):
+        psi, _ = oracle.run(n, ops, seed=31, traj=t)
+        zr = oracle.expect_z(psi)
+        tol = 1e-10 if dtype == "c128" else 1e-4
+        assert np.max(np.abs(z[off:off + n] - zr)) <= tol, (t, n)
+        off += n
+
+
+def test_batched_trajectory_mean_matches_density_matrix(qs):
+    n = 10
+    ops = cg.random_circuit(2, 5, 6, seed=4010, dep1=0.05, dep2=0.05, damping=0.05)
+    rho = oracle.dm_run(n, ops)
+    zdm = oracle.dm_expect_z(rho)
+    T = 4096
+    c = qs.Circuit(ops)
+    z, sec = qs.run_trajectories([c] * T, [n] * T, dtype=qs.C64, seed=77)
+    zs = z.reshape(T, n)
+    mean = zs.mean(axis=0)
+    sigma = np.maximum(zs.std(axis=0), 1e-3)
+    assert np.all(np.abs(mean - zdm) < 5 * sigma / math.sqrt(T)), (mean, zdm)
