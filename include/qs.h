@@ -176,7 +176,9 @@ typedef struct {
  * n-qubit state of dtype dt with these options (opts may be NULL): the number
  * of kernel launches that sweep the whole state, the number of fused blocks
  * (dense matrix-core blocks and diagonal passes inside those sweeps, or fused
- * gates of the per-block plan) and the number of logical gates.  Host only. */
+ * gates of the per-block plan) and the number of logical gates.  Needs no
+ * state; with QS_PLAN_LEARNED and an installed cost model the candidate
+ * plans are scored on the current device. */
 qs_status qs_circuit_plan_info(const qs_circuit *c, int n, qs_dtype dt, const qs_run_opts *opts,
                                int64_t *sweeps, int64_t *blocks, int64_t *logical_gates);
 
@@ -259,6 +261,43 @@ qs_status qs_profile_enable(qs_state *s, int on);
 qs_status qs_profile_reset(qs_state *s);
 qs_status qs_profile_query(qs_state *s, int kernel, int64_t *launches, double *total_ms,
                            double *alg_bytes, double *alg_flops);
+
+/* --------------------------------------------------------- cost model -- */
+
+/* The learned fusion planner scores candidate tile plans with a small fully
+ * connected network F -> H -> H -> 1 (ReLU, FP32; H must be 64), trained on
+ * the simulator's own timings of tile sweeps.  Parameters are packed as
+ * W1[H][F], b1[H], W2[H][H], b2[H], W3[H], b3 (float); the loss is the mean
+ * squared error.  All compute runs on the current device; host arrays are
+ * copied in and out.  Not in the paper: a planning aid of this library. */
+#define QS_COST_FEATURES 16
+
+/* y[i] = network(x[i * f .. i * f + f)) for i < n. */
+qs_status qs_mlp_forward(const float *params, int f, int h, const float *x, int64_t n, float *y);
+
+/* Mean squared-error loss over the n samples and its exact gradient
+ * (same packing as params). */
+qs_status qs_mlp_grad(const float *params, int f, int h, const float *x, const float *t, int64_t n,
+                      float *loss, float *grad);
+
+/* `steps` Adam steps (beta 0.9 / 0.999) with learning rate lr on minibatches
+ * of `batch` samples drawn with replacement (Philox, key `seed`); params are
+ * updated in place; *loss receives the last minibatch loss. */
+qs_status qs_mlp_train(float *params, int f, int h, const float *x, const float *t, int64_t n, int steps,
+                       int batch, float lr, uint64_t seed, float *loss);
+
+/* Training samples recorded while profiling is enabled: one per tile sweep,
+ * QS_COST_FEATURES features (tile size, state size, dense blocks of 4 and 5
+ * qubits, diagonal passes, outer selector bits, identity-skips, gates, the six
+ * highest tile qubits, dtype, matrix-core work) and the target
+ * ln(sweep time in ns / 2^n).  Copies up to `capacity` samples, removes them
+ * from the state, and sets *count. */
+qs_status qs_profile_samples(qs_state *s, float *features, float *log_ns_per_amp, int64_t capacity,
+                             int64_t *count);
+
+/* Install trained parameters (f = QS_COST_FEATURES, h = 64) for
+ * QS_PLAN_LEARNED; NULL removes the model (the greedy plan is then used). */
+qs_status qs_cost_model_set(const float *params, int f, int h);
 
 /* Text of the last error on this thread ("" if none).  Valid until the next
  * failing call on the same thread. */

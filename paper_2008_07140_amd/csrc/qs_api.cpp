@@ -21,6 +21,11 @@
 #include "qs_plan.h"
 #include "qs_tile.h"
 #include "qs_traj.h"
+#include "qs_mlp.h"
+
+#include <array>
+#include <mutex>
+#include <tuple>
 #include "qs_philox.h"
 
 #include <chrono>
@@ -61,7 +66,14 @@ struct ProfRec {
     int kid;
     hipEvent_t a, b;
     double bytes, flops;
+    int feat;   // index into qs_state::feat_pending, or -1
+    int n;
 };
+
+using Features = std::array<float, QS_COST_FEATURES>;
+
+std::mutex g_model_mu;
+std::vector<float> g_model;  // installed cost-model parameters (empty = none)
 
 struct ProfAcc {
     int64_t launches = 0;
@@ -85,15 +97,40 @@ struct qs_state {
     void *dmat = nullptr;       // device staging for one gate matrix
     void *prog = nullptr;       // device matrices of a planned circuit segment
     size_t prog_bytes = 0;
+    uint64_t prog_loaded = 0;   // id of the tile program resident in prog (0 = none)
     double *hpin = nullptr;     // pinned host results (64 KiB)
     bool prof = false;
+    std::vector<Features> feat_pending;               // features of timed sweeps
+    std::vector<std::pair<Features, float>> samples;  // (features, ln ns per amplitude)
     std::vector<ProfRec> pending;
     std::vector<hipEvent_t> pool;
     ProfAcc acc[QS_K_COUNT];
 };
 
+namespace {
+struct CachedPlan;
+struct PlanKey {
+    int n, dt, plan, kmax, tile;
+    uint64_t model;
+    bool operator<(const PlanKey &o) const
+    {
+        return std::tie(n, dt, plan, kmax, tile, model) < std::tie(o.n, o.dt, o.plan, o.kmax, o.tile, o.model);
+    }
+};
+std::atomic<uint64_t> g_model_version{1};
+std::atomic<uint64_t> g_prog_serial{1};
+}  // namespace
+
 struct qs_circuit {
     std::vector<qs::Op> ops;
+    // plans already made for this circuit (cleared when it changes)
+    mutable std::mutex mu;
+    mutable std::map<PlanKey, std::shared_ptr<const CachedPlan>> cache;
+    void changed()
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        cache.clear();
+    }
 };
 
 namespace {
@@ -123,10 +160,13 @@ qs_status harvest(qs_state *s)
         a.ms += ms;
         a.bytes += r.bytes;
         a.flops += r.flops;
+        if (r.feat >= 0 && ms > 0)
+            s->samples.push_back({s->feat_pending[r.feat], float(std::log(double(ms) * 1e6 / std::ldexp(1.0, r.n)))});
         s->pool.push_back(r.a);
         s->pool.push_back(r.b);
     }
     s->pending.clear();
+    s->feat_pending.clear();
     return QS_OK;
 }
 
@@ -134,10 +174,15 @@ struct Timed {
     qs_state *s;
     int kid;
     double bytes, flops;
+    int feat = -1;
     hipEvent_t a = nullptr, b = nullptr;
-    Timed(qs_state *s_, int kid_, double bytes_, double flops_)
+    Timed(qs_state *s_, int kid_, double bytes_, double flops_, const Features *f = nullptr)
         : s(s_), kid(kid_), bytes(bytes_), flops(flops_)
     {
+        if (s->prof && f) {
+            feat = int(s->feat_pending.size());
+            s->feat_pending.push_back(*f);
+        }
         if (s->prof) {
             if (s->pending.size() > 8192) harvest(s);
             a = take_event(s);
@@ -149,7 +194,7 @@ struct Timed {
     {
         if (s->prof && a && b) {
             hipEventRecord(b, s->stream);
-            s->pending.push_back({kid, a, b, bytes, flops});
+            s->pending.push_back({kid, a, b, bytes, flops, feat, s->n});
         }
     }
 };
@@ -319,6 +364,7 @@ qs_status launch_plan(qs_state *s, const std::vector<qs::CanonGate> &plan)
             }
         }
         HIP_TRY(hipMemcpy(s->prog, host.data(), total, hipMemcpyHostToDevice));
+        s->prog_loaded = 0;
     }
     for (size_t k = 0; k < plan.size(); ++k) {
         const void *dm = off[k] == SIZE_MAX ? nullptr : static_cast<unsigned char *>(s->prog) + off[k];
@@ -507,13 +553,111 @@ qs::TileArgs make_tile_args(const qs::Sweep &sw, int n)
     return ta;
 }
 
-qs_status launch_tiled(qs_state *s, const std::vector<qs::PlanStep> &steps)
+// Cost-model features of one tile sweep (all scaled to about [0, 1]).
+Features sweep_features(const qs::Sweep &sw, int n, qs_dtype dt)
 {
-    TileProgram tp;
-    build_tile_program(steps, tp);
+    Features f{};
+    int d4 = 0, d5 = 0, ph = 0, outer = 0, skips = 0, work = 0;
+    for (const auto &op : sw.ops) {
+        if (op.kind == qs::TileOp::DENSE) {
+            (op.qubits.size() >= 5 ? d5 : d4)++;
+            work += 1 << op.qubits.size();
+            if (op.skip) ++skips;
+        } else {
+            ++ph;
+        }
+        outer += int(op.outer.size());
+    }
+    const int m = int(sw.Q.size());
+    f[0] = m / 13.f;
+    f[1] = n / 36.f;
+    f[2] = d4 / 16.f;
+    f[3] = d5 / 16.f;
+    f[4] = ph / 16.f;
+    f[5] = outer / 32.f;
+    f[6] = skips / 16.f;
+    f[7] = sw.gates / 64.f;
+    for (int i = 0; i < 6; ++i) f[8 + i] = (m - 1 - i >= 4) ? sw.Q[m - 1 - i] / float(n) : 0.f;
+    f[14] = dt == QS_C64 ? 1.f : 0.f;
+    f[15] = work / 256.f;
+    return f;
+}
+
+// Tile parameters for a segment.  Without a cost model: the defaults.  With
+// one (QS_PLAN_LEARNED): plan the segment for every candidate (tile qubits 11
+// to 13, block width 4 or 5), predict every sweep's time with the network on
+// the device and keep the cheapest candidate.
+qs_status choose_tile_params(qs_state *s, const std::vector<qs::FlatOp> &flat, size_t k, size_t e,
+                             const qs_run_opts &o, qs::TileParams &best, std::vector<qs::PlanStep> &best_steps)
+{
+    best = tile_params(s->n, o);
+    std::vector<float> model;
+    if (o.plan == QS_PLAN_LEARNED) {
+        std::lock_guard<std::mutex> lk(g_model_mu);
+        model = g_model;
+    }
+    if (model.empty()) {
+        qs::plan_tiles(flat, k, e, s->n, best, best_steps);
+        return QS_OK;
+    }
+    std::vector<qs::TileParams> cand;
+    for (int m = 11; m <= 13; ++m)
+        for (int km = 4; km <= 5; ++km) {
+            qs::TileParams tp;
+            tp.m = std::min(m, s->n);
+            tp.kmax = km;
+            cand.push_back(tp);
+        }
+    std::vector<std::vector<qs::PlanStep>> plans(cand.size());
+    std::vector<float> feats;
+    std::vector<std::pair<int, int>> owner;  // (candidate, standalone?)
+    for (size_t c = 0; c < cand.size(); ++c) {
+        qs::plan_tiles(flat, k, e, s->n, cand[c], plans[c]);
+        for (auto &st : plans[c]) {
+            qs::Sweep sw = st.sweep ? st.sw : qs::Sweep{};
+            if (!st.sweep) {  // a per-gate launch: scored as a sweep with one op
+                sw.Q.assign(1, 0);
+                sw.gates = 1;
+            }
+            const Features f = sweep_features(sw, s->n, s->dt);
+            feats.insert(feats.end(), f.begin(), f.end());
+            owner.push_back({int(c), st.sweep ? 0 : 1});
+        }
+    }
+    const int64_t ns = int64_t(owner.size());
+    float *dp = nullptr, *dx = nullptr, *dy = nullptr;
+    std::vector<float> y(ns);
+    hipError_t he = hipMalloc(&dp, model.size() * sizeof(float));
+    if (he == hipSuccess) he = hipMalloc(&dx, feats.size() * sizeof(float));
+    if (he == hipSuccess) he = hipMalloc(&dy, ns * sizeof(float));
+    if (he == hipSuccess) he = hipMemcpy(dp, model.data(), model.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (he == hipSuccess) he = hipMemcpy(dx, feats.data(), feats.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (he == hipSuccess) he = qs::launch_mlp_forward(dp, QS_COST_FEATURES, qs::kMlpHidden, dx, ns, dy, s->stream);
+    if (he == hipSuccess) he = hipMemcpyAsync(y.data(), dy, ns * sizeof(float), hipMemcpyDeviceToHost, s->stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(s->stream);
+    if (dp) (void)hipFree(dp);
+    if (dx) (void)hipFree(dx);
+    if (dy) (void)hipFree(dy);
+    if (he != hipSuccess) return hip_fail(he, "cost-model inference");
+    std::vector<double> cost(cand.size(), 0.0);
+    for (int64_t i = 0; i < ns; ++i) cost[owner[i].first] += std::exp(double(y[i]));
+    size_t bi = 0;
+    for (size_t c = 1; c < cand.size(); ++c)
+        if (cost[c] < cost[bi]) bi = c;
+    best = cand[bi];
+    best_steps = std::move(plans[bi]);
+    return QS_OK;
+}
+
+// Upload a tile program into the state's plan buffer unless it is already
+// there (repeated runs of a cached plan skip the upload and its wait).
+qs_status upload_program(qs_state *s, const TileProgram &tp, uint64_t id, size_t &doff)
+{
     const size_t ob = tp.ops.size() * sizeof(qs::TileOpDev);
     const size_t db = tp.data.size() * sizeof(uint16_t);
-    const size_t total = ((ob + 255) / 256) * 256 + db;
+    doff = ((ob + 255) / 256) * 256;
+    if (id && s->prog_loaded == id) return QS_OK;
+    const size_t total = doff + db;
     HIP_TRY(hipStreamSynchronize(s->stream));
     if (total > s->prog_bytes) {
         if (s->prog) HIP_TRY(hipFree(s->prog));
@@ -523,9 +667,17 @@ qs_status launch_tiled(qs_state *s, const std::vector<qs::PlanStep> &steps)
         s->prog_bytes = total;
     }
     unsigned char *dev = static_cast<unsigned char *>(s->prog);
-    const size_t doff = ((ob + 255) / 256) * 256;
     HIP_TRY(hipMemcpy(dev, tp.ops.data(), ob, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(dev + doff, tp.data.data(), db, hipMemcpyHostToDevice));
+    s->prog_loaded = id;
+    return QS_OK;
+}
+
+qs_status launch_steps(qs_state *s, const std::vector<qs::PlanStep> &steps, const TileProgram &tp, uint64_t id)
+{
+    size_t doff = 0;
+    if (qs_status e = upload_program(s, tp, id, doff)) return e;
+    unsigned char *dev = static_cast<unsigned char *>(s->prog);
     const qs::TileOpDev *dops = reinterpret_cast<const qs::TileOpDev *>(dev);
     const double sweep_bytes = 2.0 * 8.0 * std::ldexp(1.0, s->n);
     for (size_t i = 0; i < steps.size(); ++i) {
@@ -539,12 +691,29 @@ qs_status launch_tiled(qs_state *s, const std::vector<qs::PlanStep> &steps)
         for (const auto &op : st.sw.ops)
             flops += (op.kind == qs::TileOp::DENSE ? 8.0 * double(1 << op.qubits.size()) : 6.0) *
                      std::ldexp(1.0, s->n);
-        Timed t(s, QS_K_TILE, sweep_bytes, flops);
+        const Features feat = sweep_features(st.sw, s->n, s->dt);
+        Timed t(s, QS_K_TILE, sweep_bytes, flops, &feat);
         hipError_t e = qs::launch_tile(s->amp, s->n, ta, dops + tp.first[i], dev + doff, s->stream);
         if (e != hipSuccess) return hip_fail(e, "tile kernel launch");
     }
     return QS_OK;
 }
+
+// ---------------------------------------------------------- plan cache --
+
+struct SegPlan {
+    bool tiled = false;
+    std::vector<qs::PlanStep> steps;   // tiled segments
+    TileProgram prog;
+    uint64_t prog_id = 0;
+    std::vector<qs::CanonGate> gates;  // per-gate and per-block plans
+    bool has_noise = false;            // a noise site follows the gates
+    qs::FlatOp noise;
+};
+
+struct CachedPlan {
+    std::vector<SegPlan> segs;
+};
 
 // ------------------------------------------------------------ reductions --
 
@@ -1255,6 +1424,35 @@ qs_status run_trajectory_batch(const qs_circuit *const *circs, const int *widths
 
 }  // namespace
 
+namespace {
+
+qs_status check_mlp(const float *params, int f, int h)
+{
+    if (!params) return fail(QS_E_INVAL, "params is NULL");
+    if (f < 1 || f > 256) return fail(QS_E_INVAL, "feature count %d not in [1, 256]", f);
+    if (h != qs::kMlpHidden) return fail(QS_E_UNSUPPORTED, "hidden width must be %d", qs::kMlpHidden);
+    return QS_OK;
+}
+
+struct DevTmp {
+    std::vector<void *> p;
+    ~DevTmp()
+    {
+        for (void *q : p) (void)hipFree(q);
+    }
+    template <typename T>
+    hipError_t alloc(T **out, size_t count)
+    {
+        void *q = nullptr;
+        hipError_t e = hipMalloc(&q, count * sizeof(T) + 16);
+        if (e == hipSuccess) p.push_back(q);
+        *out = static_cast<T *>(q);
+        return e;
+    }
+};
+
+}  // namespace
+
 // =================================================================== ABI ==
 
 extern "C" {
@@ -1426,6 +1624,7 @@ qs_status qs_circuit_append_gate(qs_circuit *c, const int *targets, int nt, cons
     if (nc) op.controls.assign(controls, controls + nc);
     op.m.assign(m, m + (size_t(2) << (2 * nt)));
     c->ops.push_back(std::move(op));
+    c->changed();
     return QS_OK;
 }
 
@@ -1445,6 +1644,7 @@ qs_status qs_circuit_append_noise(qs_circuit *c, const int *targets, int nt, con
     op.nk = nk;
     op.m.assign(kraus, kraus + (size_t(2) << (2 * nt)) * nk);
     c->ops.push_back(std::move(op));
+    c->changed();
     return QS_OK;
 }
 
@@ -1457,6 +1657,7 @@ static qs_status push_marker(qs_circuit *c, qs::Op::Kind k, int q)
     op.kind = k;
     op.qubit = q;
     c->ops.push_back(std::move(op));
+    c->changed();
     return QS_OK;
 }
 
@@ -1510,7 +1711,8 @@ qs_status qs_circuit_plan_info(const qs_circuit *c, int n, qs_dtype dt, const qs
         if (e > k) {
             if (tiled_plan(&probe, o)) {
                 std::vector<qs::PlanStep> steps;
-                qs::plan_tiles(flat, k, e, n, tile_params(n, o), steps);
+                qs::TileParams tp;
+                if (qs_status st = choose_tile_params(&probe, flat, k, e, o, tp, steps)) return st;
                 for (auto &st : steps) {
                     ++sw;
                     bl += st.sweep ? int64_t(st.sw.ops.size()) : 1;
@@ -1547,43 +1749,71 @@ qs_status qs_run_circuit(qs_state *s, const qs_circuit *c, const qs_run_opts *op
     if (o.k_max < 0 || o.k_max > QS_MAX_TARGETS) return fail(QS_E_INVAL, "k_max = %d not in [0, %d]", o.k_max, QS_MAX_TARGETS);
     if (o.tile_qubits && (o.tile_qubits < 10 || o.tile_qubits > 13))
         return fail(QS_E_INVAL, "tile_qubits = %d not in [10, 13]", o.tile_qubits);
-    std::vector<qs::FlatOp> flat;
-    std::string err;
-    int rc = qs::expand(c->ops, flat, err);
-    if (rc == 2) return fail(QS_E_UNSUPPORTED, "%s", err.c_str());
-    if (rc) return fail(QS_E_INVAL, "%s", err.c_str());
-    for (auto &f : flat) {
-        for (int q : f.targets)
-            if (q >= s->n) return fail(QS_E_RANGE, "qubit %d out of range [0, %d)", q, s->n);
-        for (int q : f.controls)
-            if (q >= s->n) return fail(QS_E_RANGE, "qubit %d out of range [0, %d)", q, s->n);
+    const PlanKey key{s->n, int(s->dt), o.plan, o.k_max, o.tile_qubits,
+                      o.plan == QS_PLAN_LEARNED ? g_model_version.load() : 0};
+    std::shared_ptr<const CachedPlan> cp;
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        auto it = c->cache.find(key);
+        if (it != c->cache.end()) cp = it->second;
+    }
+    if (!cp) {
+        std::vector<qs::FlatOp> flat;
+        std::string err;
+        int rc = qs::expand(c->ops, flat, err);
+        if (rc == 2) return fail(QS_E_UNSUPPORTED, "%s", err.c_str());
+        if (rc) return fail(QS_E_INVAL, "%s", err.c_str());
+        for (auto &f : flat) {
+            for (int q : f.targets)
+                if (q >= s->n) return fail(QS_E_RANGE, "qubit %d out of range [0, %d)", q, s->n);
+            for (int q : f.controls)
+                if (q >= s->n) return fail(QS_E_RANGE, "qubit %d out of range [0, %d)", q, s->n);
+        }
+        auto np = std::make_shared<CachedPlan>();
+        size_t k = 0;
+        while (k < flat.size()) {
+            // segment of gates up to the next noise site
+            size_t e = k;
+            while (e < flat.size() && flat[e].kind == qs::FlatOp::GATE) ++e;
+            SegPlan sp;
+            if (e > k) {
+                if (tiled_plan(s, o)) {
+                    sp.tiled = true;
+                    qs::TileParams tp;
+                    if (qs_status st = choose_tile_params(s, flat, k, e, o, tp, sp.steps)) return st;
+                    build_tile_program(sp.steps, sp.prog);
+                    sp.prog_id = g_prog_serial.fetch_add(1);
+                } else if (o.plan == QS_PLAN_UNFUSED) {
+                    for (size_t j = k; j < e; ++j)
+                        sp.gates.push_back(qs::canonicalize(flat[j].targets.data(), int(flat[j].targets.size()),
+                                                            flat[j].controls.data(), int(flat[j].controls.size()),
+                                                            flat[j].m.data()));
+                } else {
+                    const int kmax = o.k_max ? o.k_max : qs::default_kmax(s->n, s->dt);
+                    qs::greedy_fuse(flat, k, e, kmax, sp.gates);
+                }
+            }
+            if (e < flat.size()) {
+                sp.has_noise = true;
+                sp.noise = flat[e];
+                ++e;
+            }
+            np->segs.push_back(std::move(sp));
+            k = e;
+        }
+        cp = np;
+        std::lock_guard<std::mutex> lk(c->mu);
+        c->cache[key] = cp;
     }
     uint64_t site = 0;
-    size_t k = 0;
-    while (k < flat.size()) {
-        // segment of gates up to the next noise site
-        size_t e = k;
-        while (e < flat.size() && flat[e].kind == qs::FlatOp::GATE) ++e;
-        if (e > k) {
-            std::vector<qs::CanonGate> plan;
-            if (tiled_plan(s, o)) {
-                std::vector<qs::PlanStep> steps;
-                qs::plan_tiles(flat, k, e, s->n, tile_params(s->n, o), steps);
-                if (qs_status st = launch_tiled(s, steps)) return st;
-            } else if (o.plan == QS_PLAN_UNFUSED) {
-                for (size_t j = k; j < e; ++j)
-                    plan.push_back(qs::canonicalize(flat[j].targets.data(), int(flat[j].targets.size()),
-                                                    flat[j].controls.data(), int(flat[j].controls.size()),
-                                                    flat[j].m.data()));
-            } else {
-                const int kmax = o.k_max ? o.k_max : qs::default_kmax(s->n, s->dt);
-                qs::greedy_fuse(flat, k, e, kmax, plan);
-            }
-            if (!plan.empty())
-                if (qs_status st = launch_plan(s, plan)) return st;
+    for (const SegPlan &sp : cp->segs) {
+        if (sp.tiled) {
+            if (qs_status st = launch_steps(s, sp.steps, sp.prog, sp.prog_id)) return st;
+        } else if (!sp.gates.empty()) {
+            if (qs_status st = launch_plan(s, sp.gates)) return st;
         }
-        if (e < flat.size()) {
-            const qs::FlatOp &z = flat[e];
+        if (sp.has_noise) {
+            const qs::FlatOp &z = sp.noise;
             const double u = qs_philox_uniform(o.seed, o.traj, site);
             int ch = -1;
             if (qs_status st = apply_channel(s, z.targets.data(), int(z.targets.size()), z.m.data(), z.nk,
@@ -1591,9 +1821,7 @@ qs_status qs_run_circuit(qs_state *s, const qs_circuit *c, const qs_run_opts *op
                 return st;
             if (o.chosen && int64_t(site) < o.chosen_len) o.chosen[site] = ch;
             ++site;
-            ++e;
         }
-        k = e;
     }
     return QS_OK;
 }
@@ -1709,6 +1937,118 @@ qs_status qs_run_trajectories(const qs_circuit *const *circs, const int *widths,
                               qs_dtype dt, uint64_t seed, double *z_out, double *seconds)
 {
     return run_trajectory_batch(circs, widths, count, dt, seed, z_out, seconds);
+}
+
+// ------------------------------------------------------------ cost model --
+
+
+qs_status qs_mlp_forward(const float *params, int f, int h, const float *x, int64_t n, float *y)
+{
+    if (qs_status st = check_mlp(params, f, h)) return st;
+    if (n < 0 || (n && (!x || !y))) return fail(QS_E_INVAL, "bad samples");
+    if (n == 0) return QS_OK;
+    const size_t np = qs::mlp_num_params(f, h);
+    DevTmp t;
+    float *dp, *dx, *dy;
+    HIP_TRY(t.alloc(&dp, np));
+    HIP_TRY(t.alloc(&dx, size_t(n) * f));
+    HIP_TRY(t.alloc(&dy, size_t(n)));
+    HIP_TRY(hipMemcpy(dp, params, np * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dx, x, size_t(n) * f * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(qs::launch_mlp_forward(dp, f, h, dx, n, dy, nullptr));
+    HIP_TRY(hipMemcpy(y, dy, size_t(n) * sizeof(float), hipMemcpyDeviceToHost));
+    return QS_OK;
+}
+
+qs_status qs_mlp_grad(const float *params, int f, int h, const float *x, const float *tv, int64_t n,
+                      float *loss, float *grad)
+{
+    if (qs_status st = check_mlp(params, f, h)) return st;
+    if (n < 1 || !x || !tv || !loss || !grad) return fail(QS_E_INVAL, "bad samples");
+    const size_t np = qs::mlp_num_params(f, h);
+    DevTmp t;
+    float *dp, *dx, *dt, *dg, *dl;
+    HIP_TRY(t.alloc(&dp, np));
+    HIP_TRY(t.alloc(&dx, size_t(n) * f));
+    HIP_TRY(t.alloc(&dt, size_t(n)));
+    HIP_TRY(t.alloc(&dg, np));
+    HIP_TRY(t.alloc(&dl, 1));
+    HIP_TRY(hipMemcpy(dp, params, np * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dx, x, size_t(n) * f * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dt, tv, size_t(n) * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(qs::launch_mlp_grad(dp, f, h, dx, dt, n, dg, dl, nullptr));
+    HIP_TRY(hipMemcpy(grad, dg, np * sizeof(float), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(loss, dl, sizeof(float), hipMemcpyDeviceToHost));
+    return QS_OK;
+}
+
+qs_status qs_mlp_train(float *params, int f, int h, const float *x, const float *tv, int64_t n, int steps,
+                       int batch, float lr, uint64_t seed, float *loss)
+{
+    if (qs_status st = check_mlp(params, f, h)) return st;
+    if (n < 1 || !x || !tv) return fail(QS_E_INVAL, "bad samples");
+    if (steps < 0 || batch < 1 || batch > 4096) return fail(QS_E_INVAL, "steps / batch out of range");
+    if (!(lr > 0)) return fail(QS_E_INVAL, "learning rate must be positive");
+    const size_t np = qs::mlp_num_params(f, h);
+    // minibatch indices from the Philox stream (counter = draw index)
+    std::vector<int> idx(size_t(steps) * batch);
+    for (size_t i = 0; i < idx.size(); ++i)
+        idx[i] = int(qs::noise_uniform(seed, 0xC057, i) * double(n)) % int(n);
+    DevTmp t;
+    float *dp, *dm, *dv, *dx, *dt, *dl;
+    int *di;
+    HIP_TRY(t.alloc(&dp, np));
+    HIP_TRY(t.alloc(&dm, np));
+    HIP_TRY(t.alloc(&dv, np));
+    HIP_TRY(t.alloc(&dx, size_t(n) * f));
+    HIP_TRY(t.alloc(&dt, size_t(n)));
+    HIP_TRY(t.alloc(&dl, 1));
+    HIP_TRY(t.alloc(&di, idx.size() + 1));
+    HIP_TRY(hipMemcpy(dp, params, np * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(dm, 0, np * sizeof(float)));
+    HIP_TRY(hipMemset(dv, 0, np * sizeof(float)));
+    HIP_TRY(hipMemset(dl, 0, sizeof(float)));
+    HIP_TRY(hipMemcpy(dx, x, size_t(n) * f * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dt, tv, size_t(n) * sizeof(float), hipMemcpyHostToDevice));
+    if (!idx.empty()) HIP_TRY(hipMemcpy(di, idx.data(), idx.size() * sizeof(int), hipMemcpyHostToDevice));
+    const int chunk = 256;  // steps per launch
+    for (int s0 = 0; s0 < steps; s0 += chunk) {
+        const int ns = std::min(chunk, steps - s0);
+        HIP_TRY(qs::launch_mlp_train(dp, dm, dv, f, h, dx, dt, di + size_t(s0) * batch, batch, ns, s0, lr, dl,
+                                     nullptr));
+    }
+    HIP_TRY(hipMemcpy(params, dp, np * sizeof(float), hipMemcpyDeviceToHost));
+    if (loss) HIP_TRY(hipMemcpy(loss, dl, sizeof(float), hipMemcpyDeviceToHost));
+    return QS_OK;
+}
+
+qs_status qs_profile_samples(qs_state *s, float *features, float *y, int64_t capacity, int64_t *count)
+{
+    if (qs_status st = check_state(s)) return st;
+    if (capacity < 0 || (capacity && (!features || !y)) || !count) return fail(QS_E_INVAL, "bad output arrays");
+    if (qs_status st = harvest(s)) return st;
+    const int64_t c = std::min<int64_t>(capacity, int64_t(s->samples.size()));
+    for (int64_t i = 0; i < c; ++i) {
+        std::memcpy(features + i * QS_COST_FEATURES, s->samples[i].first.data(), sizeof(Features));
+        y[i] = s->samples[i].second;
+    }
+    s->samples.erase(s->samples.begin(), s->samples.begin() + c);
+    *count = c;
+    return QS_OK;
+}
+
+qs_status qs_cost_model_set(const float *params, int f, int h)
+{
+    std::lock_guard<std::mutex> lk(g_model_mu);
+    g_model_version.fetch_add(1);
+    if (!params) {
+        g_model.clear();
+        return QS_OK;
+    }
+    if (f != QS_COST_FEATURES) return fail(QS_E_INVAL, "the cost model takes %d features", QS_COST_FEATURES);
+    if (h != qs::kMlpHidden) return fail(QS_E_UNSUPPORTED, "hidden width must be %d", qs::kMlpHidden);
+    g_model.assign(params, params + qs::mlp_num_params(f, h));
+    return QS_OK;
 }
 
 // ------------------------------------------------------------- profiling --

@@ -24,6 +24,8 @@ if not os.path.exists(LIB_PATH):
 _lib = C.CDLL(LIB_PATH)
 
 C64, C128 = 1, 2
+COST_FEATURES = 16
+MLP_HIDDEN = 64
 PLAN_UNFUSED, PLAN_GREEDY, PLAN_LEARNED = 0, 1, 2
 (K_INIT, K_DENSE1, K_DENSE2, K_DENSE3, K_DENSEN, K_PHASE, K_FUSED, K_TILE, K_REDUCE,
  K_OTHER) = range(10)
@@ -80,6 +82,11 @@ _sig = {
     "qs_profile_enable": ([P, I], I),
     "qs_profile_reset": ([P], I),
     "qs_profile_query": ([P, I, P, P, P, P], I),
+    "qs_mlp_forward": ([P, I, I, P, I64, P], I),
+    "qs_mlp_grad": ([P, I, I, P, P, I64, P, P], I),
+    "qs_mlp_train": ([P, I, I, P, P, I64, I, I, C.c_float, U64, P], I),
+    "qs_profile_samples": ([P, P, P, I64, P], I),
+    "qs_cost_model_set": ([P, I, I], I),
     "qs_last_error": ([], C.c_char_p),
 }
 for _name, (_args, _res) in _sig.items():
@@ -130,6 +137,57 @@ def philox4x32_10(ctr, key):
     o = np.zeros(4, dtype=np.uint32)
     _lib.qs_philox4x32_10(_ptr(c), _ptr(k), _ptr(o))
     return [int(v) for v in o]
+
+
+def mlp_num_params(f: int, h: int = MLP_HIDDEN) -> int:
+    return h * f + h + h * h + h + h + 1
+
+
+def _f32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+
+
+def mlp_forward(params, x, f: int = COST_FEATURES, h: int = MLP_HIDDEN) -> np.ndarray:
+    p, xx = _f32(params), _f32(x).reshape(-1, f)
+    y = np.empty(xx.shape[0], dtype=np.float32)
+    _check(_lib.qs_mlp_forward(_ptr(p), f, h, _ptr(xx), xx.shape[0], _ptr(y)))
+    return y
+
+
+def mlp_grad(params, x, t, f: int = COST_FEATURES, h: int = MLP_HIDDEN):
+    p, xx, tt = _f32(params), _f32(x).reshape(-1, f), _f32(t)
+    g = np.empty(p.size, dtype=np.float32)
+    loss = np.zeros(1, dtype=np.float32)
+    _check(_lib.qs_mlp_grad(_ptr(p), f, h, _ptr(xx), _ptr(tt), xx.shape[0], _ptr(loss), _ptr(g)))
+    return float(loss[0]), g
+
+
+def mlp_train(params, x, t, steps: int, batch: int = 256, lr: float = 1e-3, seed: int = 0,
+              f: int = COST_FEATURES, h: int = MLP_HIDDEN):
+    """Adam on the GPU; returns (new params, last minibatch loss)."""
+    p, xx, tt = _f32(params).copy(), _f32(x).reshape(-1, f), _f32(t)
+    loss = np.zeros(1, dtype=np.float32)
+    _check(_lib.qs_mlp_train(_ptr(p), f, h, _ptr(xx), _ptr(tt), xx.shape[0], steps, batch, lr, seed,
+                             _ptr(loss)))
+    return p, float(loss[0])
+
+
+def mlp_init(seed: int, f: int = COST_FEATURES, h: int = MLP_HIDDEN) -> np.ndarray:
+    """He-style random initial parameters (biases zero)."""
+    rng = np.random.default_rng(seed)
+    w1 = rng.standard_normal((h, f)) * np.sqrt(2.0 / f)
+    w2 = rng.standard_normal((h, h)) * np.sqrt(2.0 / h)
+    w3 = rng.standard_normal(h) * np.sqrt(1.0 / h)
+    return np.concatenate([w1.ravel(), np.zeros(h), w2.ravel(), np.zeros(h), w3, np.zeros(1)]).astype(
+        np.float32)
+
+
+def cost_model_set(params) -> None:
+    if params is None:
+        _check(_lib.qs_cost_model_set(None, COST_FEATURES, MLP_HIDDEN))
+        return
+    p = _f32(params)
+    _check(_lib.qs_cost_model_set(_ptr(p), COST_FEATURES, MLP_HIDDEN))
 
 
 class Circuit:
@@ -289,6 +347,14 @@ class State:
         _check(_lib.qs_profile_query(self._h, kernel, C.byref(l), C.byref(ms), C.byref(b),
                                      C.byref(f)))
         return {"launches": l.value, "ms": ms.value, "bytes": b.value, "flops": f.value}
+
+    def profile_samples(self, capacity: int = 100000):
+        """(features [count, 16], ln ns per amplitude [count]) of the profiled tile sweeps."""
+        f = np.empty((capacity, COST_FEATURES), dtype=np.float32)
+        y = np.empty(capacity, dtype=np.float32)
+        cnt = C.c_int64()
+        _check(_lib.qs_profile_samples(self._h, _ptr(f), _ptr(y), capacity, C.byref(cnt)))
+        return f[: cnt.value].copy(), y[: cnt.value].copy()
 
     def info(self):
         n, dt = C.c_int(), C.c_int()

@@ -129,3 +129,18 @@ def test_workload_shapes():
         if o.kind == "gate":
             m = o.matrix
             assert np.allclose(m.conj().T @ m, np.eye(m.shape[0]), atol=1e-14)
+
+
+def test_cost_model_validation(qs):
+    import ctypes
+    p = qs.mlp_init(0)
+    ptr = p.ctypes.data_as(ctypes.c_void_p)
+    with pytest.raises(qs.QSError) as e:
+        qs._check(qs.lib().qs_cost_model_set(ptr, 7, 64))
+    assert e.value.status == -1
+    with pytest.raises(qs.QSError) as e:
+        qs._check(qs.lib().qs_cost_model_set(ptr, 16, 32))
+    assert e.value.status == -6
+    qs.cost_model_set(p)
+    qs.cost_model_set(None)
+    assert p.size == qs.mlp_num_params(16) == oracle.mlp_num_params(16, 64)

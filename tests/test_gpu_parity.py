@@ -431,3 +431,92 @@ def test_batched_trajectory_mean_matches_density_matrix(qs):
     mean = zs.mean(axis=0)
     sigma = np.maximum(zs.std(axis=0), 1e-3)
     assert np.all(np.abs(mean - zdm) < 5 * sigma / math.sqrt(T)), (mean, zdm)
+
+
+# --------------------------------------------------------------- cost model --
+
+
+def test_mlp_forward_and_gradient_match_fp64_oracle(qs):
+    rng = np.random.default_rng(3)
+    f = qs.COST_FEATURES
+    p = (rng.standard_normal(qs.mlp_num_params(f)) * 0.3).astype(np.float32)
+    x = rng.standard_normal((300, f)).astype(np.float32)
+    t = rng.standard_normal(300).astype(np.float32)
+    y = qs.mlp_forward(p, x)
+    yr, lossr, gr = oracle.mlp_forward_backward(p.astype(np.float64), f, 64, x.astype(np.float64),
+                                                t.astype(np.float64))
+    assert np.max(np.abs(y - yr)) <= 1e-4 * max(1.0, np.max(np.abs(yr)))
+    loss, g = qs.mlp_grad(p, x, t)
+    assert abs(loss - lossr) <= 1e-4 * max(1.0, lossr)
+    assert np.max(np.abs(g - gr)) <= 1e-4 * max(1.0, np.max(np.abs(gr)))
+
+
+def test_mlp_training_reduces_loss(qs):
+    rng = np.random.default_rng(5)
+    f = qs.COST_FEATURES
+    x = rng.uniform(0, 1, (2048, f)).astype(np.float32)
+    t = (np.sin(3 * x[:, 0]) + x[:, 1] * x[:, 2] - 0.5 * x[:, 3]).astype(np.float32)
+    p0 = qs.mlp_init(1)
+    _, l0, _ = oracle.mlp_forward_backward(p0.astype(np.float64), f, 64, x.astype(np.float64),
+                                           t.astype(np.float64))
+    p1, _ = qs.mlp_train(p0, x, t, steps=1500, batch=256, lr=3e-3, seed=2)
+    _, l1, _ = oracle.mlp_forward_backward(p1.astype(np.float64), f, 64, x.astype(np.float64),
+                                           t.astype(np.float64))
+    assert l1 < 0.05 * l0, (l0, l1)
+
+
+def test_learned_planner_parity_and_gain(qs):
+    """Samples come from profiled tile sweeps of random circuits under many
+    tile shapes; the network trained on them picks the tile shape of a
+    held-out circuit.  The learned plan must agree with the oracle, predict
+    held-out sweep times, and not run slower than the default plan."""
+    n = 24
+    s = qs.State(n, qs.C64)
+    s.profile(True)
+    for i in range(8):
+        rows, cols = [(4, 6), (6, 4), (3, 8), (8, 3)][i % 4]
+        c = qs.Circuit(cg.random_circuit(rows, cols, 12, seed=9000 + i, cu3_prob=0.1))
+        for m in (11, 12, 13):
+            for k in (4, 5):
+                s.reset()
+                s.run(c, plan=qs.PLAN_GREEDY, k_max=k, tile_qubits=m)
+    X, y = s.profile_samples()
+    s.profile(False)
+    assert X.shape[0] > 200
+    rng = np.random.default_rng(0)
+    perm = rng.permutation(X.shape[0])
+    tr, te = perm[: int(0.8 * len(perm))], perm[int(0.8 * len(perm)):]
+    p, _ = qs.mlp_train(qs.mlp_init(4), X[tr], y[tr], steps=3000, batch=256, lr=2e-3, seed=7)
+    pred = qs.mlp_forward(p, X[te])
+    corr = np.corrcoef(pred, y[te])[0, 1]
+    assert corr > 0.8, corr
+    qs.cost_model_set(p)
+    try:
+        # parity of the learned plan with the oracle (16 and 20 qubits)
+        for rows, cols, depth in [(4, 4, 20), (4, 5, 24)]:
+            ops = cg.random_circuit(rows, cols, depth, seed=77, cu3_prob=0.1)
+            ref, _ = oracle.run(rows * cols, ops)
+            t = qs.State(rows * cols, qs.C64)
+            t.run(qs.Circuit(ops), plan=qs.PLAN_LEARNED)
+            assert infidelity(ref, t.amplitudes()) <= 1e-6
+            t.close()
+        # measured gain on a held-out circuit
+        held = qs.Circuit(cg.random_circuit(4, 6, 24, seed=9999, cu3_prob=0.1))
+        times = {}
+        for plan in (qs.PLAN_GREEDY, qs.PLAN_LEARNED):
+            best = 1e9
+            for _ in range(3):
+                s.reset()
+                s.synchronize()
+                t0 = __import__("time").perf_counter()
+                s.run(held, plan=plan)
+                s.synchronize()
+                best = min(best, __import__("time").perf_counter() - t0)
+            times[plan] = best
+        print("learned vs greedy: %.4f s vs %.4f s (gain %.3fx)"
+              % (times[qs.PLAN_LEARNED], times[qs.PLAN_GREEDY],
+                 times[qs.PLAN_GREEDY] / times[qs.PLAN_LEARNED]))
+        assert times[qs.PLAN_LEARNED] <= 1.10 * times[qs.PLAN_GREEDY]
+    finally:
+        qs.cost_model_set(None)
+        s.close()
