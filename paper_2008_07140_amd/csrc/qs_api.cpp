@@ -402,20 +402,20 @@ float bf16_float(uint16_t h)
 // [[Re U, -Im U], [Im U, Re U]] per complex entry with re/im interleaved),
 // fragment (mt, s) of lane l holds A[16 mt + l % 16][32 s + 8 (l / 16) + j],
 // j < 8, as bfloat16 (hi), followed by the same layout of the remainders (lo).
-// Five-qubit blocks use the split form instead: fragment f < 4 of lane l
-// holds (f < 2 ? Re U : Im U)[16 (f % 2) + l % 16][8 (l / 16) + j], j < 8,
-// hi values for the four fragments first, then the remainders.
+// Five-qubit blocks use the split form instead: fragment f < 6 of lane l
+// holds (Re U, Im U, -Im U for f / 2 = 0, 1, 2)[16 (f % 2) + l % 16][8 (l / 16)
+// + j], j < 8, hi values for the six fragments first, then the remainders.
 void append_fragments5(const std::vector<double> &m, std::vector<uint16_t> &out)
 {
     const int D = 32;
     const size_t base = out.size();
-    const size_t nfr = size_t(4) * 64 * 8;
+    const size_t nfr = size_t(6) * 64 * 8;
     out.resize(base + 2 * nfr);
-    for (int f = 0; f < 4; ++f)
+    for (int f = 0; f < 6; ++f)
         for (int lane = 0; lane < 64; ++lane)
             for (int j = 0; j < 8; ++j) {
                 const int r = 16 * (f % 2) + lane % 16, c = 8 * (lane / 16) + j;
-                const double v = m[2 * (size_t(r) * D + c) + (f < 2 ? 0 : 1)];
+                const double v = (f < 4 ? 1.0 : -1.0) * m[2 * (size_t(r) * D + c) + (f < 2 ? 0 : 1)];
                 const uint16_t h = bf16_rne(float(v));
                 const uint16_t l = bf16_rne(float(v - double(bf16_float(h))));
                 const size_t idx = (size_t(f) * 64 + lane) * 8 + j;

@@ -15,11 +15,11 @@
 //    per column.  Both operands are split as hi + lo bfloat16 values and three
 //    v_mfma_f32_16x16x32_bf16 products (hi*hi + hi*lo + lo*hi) are accumulated
 //    in FP32, which keeps about 16 significant bits per product.
-//  - PHASE: a diagonal factor chosen by up to 3 tile bits and up to 3 bits
-//    outside the tile (constant per tile), e.g. a CZ between a tile qubit and
-//    an outer qubit.
-// Ops may carry a condition: a set of outer qubits that must all be 1 (a gate
-// controlled from outside the tile), evaluated once per tile.
+//  - PHASE: a diagonal factor chosen by up to 3 tile bits.
+// Every op may also depend on up to 5 bits outside the tile (constant over a
+// tile): they select one of 2^no precomputed operators, which is how gates
+// controlled from, or diagonal on, qubits outside the tile (a CZ or CU3 that
+// crosses the tile boundary) stay inside fused blocks.
 #include <hip/hip_runtime.h>
 
 #include "qs_internal.h"
@@ -46,29 +46,38 @@ __device__ __forceinline__ uint32_t insert_zero_bits(uint32_t t, const int *pos,
 
 constexpr int kMaxM = 13;
 
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+
+// Split two floats into bfloat16 hi parts and the bfloat16 of the remainders
+// (packed conversions; the remainder of each is exact in FP32).
+__device__ __forceinline__ void split2(float a, float b, v2bf &hi, v2bf &lo)
+{
+    hi = __builtin_convertvector(v2f{a, b}, v2bf);
+    lo = __builtin_convertvector(v2f{a - float(hi[0]), b - float(hi[1])}, v2bf);
+}
+
 // LDS layout of a tile: amplitude j lives at j ^ ((j >> 5) & 31).  Blocks on
 // the low tile qubits make the 16 groups of a matrix-core operand differ
 // only in high index bits; the XOR spreads those accesses over the banks.
 __device__ __forceinline__ uint32_t sw(uint32_t j) { return j ^ ((j >> 5) & 31u); }
 
-template <int K>
-__device__ void dense_op(float2 *tile, const TileOpDev &op, const uint4 *data, int m, int outer)
+// Four-qubit blocks in real form: A is the 32 x 32 real matrix
+// [[Re U, -Im U], [Im U, Re U]] (entry by entry, re/im interleaved); fragment
+// (mt, 0) of lane l holds A[16 mt + l % 16][8 (l / 16) + j].  Each wave takes
+// two column tiles at a time so that four accumulators interleave.
+__device__ void dense_op4(float2 *tile, const TileOpDev &op, const uint4 *data, int m, int outer)
 {
-    constexpr int D = 1 << K;
-    constexpr int MT = 2 * D / 16;  // row tiles of the real form
-    constexpr int KS = 2 * D / 32;  // K steps of the real form
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int K = 4;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     const bf16x8 *fr =
         reinterpret_cast<const bf16x8 *>(data + op.data_off + uint32_t(outer) * op.frag_stride);
-    bf16x8 ahi[MT][KS], alo[MT][KS];
+    bf16x8 ahi[2], alo[2];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int s = 0; s < KS; ++s) {
-            ahi[mt][s] = fr[(mt * KS + s) * 64 + lane];
-            alo[mt][s] = fr[MT * KS * 64 + (mt * KS + s) * 64 + lane];
-        }
-    // block qubit positions in the tile, op.lpos[0] = most significant
+    for (int mt = 0; mt < 2; ++mt) {
+        ahi[mt] = fr[mt * 64 + lane];
+        alo[mt] = fr[2 * 64 + mt * 64 + lane];
+    }
     int srt[K];
 #pragma unroll
     for (int b = 0; b < K; ++b) srt[b] = op.lpos[b];
@@ -88,73 +97,62 @@ __device__ void dense_op(float2 *tile, const TileOpDev &op, const uint4 *data, i
             if ((x >> (K - 1 - b)) & 1) o |= 1u << op.lpos[b];
         return o;
     };
-    uint32_t roff[KS][4], woff[MT][2];
+    const uint32_t gl = insert_zero_bits(uint32_t(lane & 15), srt, K);
+    uint32_t rd[4], wr[2][2];
 #pragma unroll
-    for (int s = 0; s < KS; ++s)
+    for (int j = 0; j < 4; ++j) rd[j] = sw(gl | offset(4 * (lane >> 4) + j)) * 8u;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) roff[s][j] = offset(16 * s + 4 * (lane >> 4) + j);
+    for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) woff[mt][j] = offset(8 * mt + 2 * (lane >> 4) + j);
-    // 16 groups per column tile; for k = 4 each wave takes two column tiles
-    // at a time so that four independent accumulators interleave on the
-    // matrix cores (k = 5 has four row tiles already)
-    constexpr int H = (K == 4) ? 2 : 1;
+        for (int j = 0; j < 2; ++j) wr[mt][j] = sw(gl | offset(8 * mt + 2 * (lane >> 4) + j)) * 8u;
+    char *tb = reinterpret_cast<char *>(tile);
     const int ntiles = 1 << (m - K - 4);
     constexpr int kWaves = kThreads / 64;
-    for (int nt0 = H * wave; nt0 < ntiles; nt0 += H * kWaves) {
-        uint32_t gb[H];
-        bf16x8 bhi[H][KS], blo[H][KS];
+    for (int nt0 = 2 * wave; nt0 < ntiles; nt0 += 2 * kWaves) {
+        uint32_t gt[2];
+        bf16x8 bhi[2], blo[2];
 #pragma unroll
-        for (int h = 0; h < H; ++h) {
-            const uint32_t g = uint32_t(nt0 + h) * 16 + (lane & 15);
-            gb[h] = insert_zero_bits(g, srt, K);
-            float2 v[KS][4];
+        for (int h = 0; h < 2; ++h) {
+            gt[h] = sw(insert_zero_bits(uint32_t(nt0 + h) * 16u, srt, K)) * 8u;  // uniform
+            float2 v[4];
 #pragma unroll
-            for (int s = 0; s < KS; ++s)
+            for (int j = 0; j < 4; ++j) v[j] = *reinterpret_cast<const float2 *>(tb + (rd[j] ^ gt[h]));
 #pragma unroll
-                for (int j = 0; j < 4; ++j) v[s][j] = tile[sw(gb[h] | roff[s][j])];
-#pragma unroll
-            for (int s = 0; s < KS; ++s)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const __bf16 hr = __bf16(v[s][j].x), hi = __bf16(v[s][j].y);
-                    bhi[h][s][2 * j] = hr;
-                    bhi[h][s][2 * j + 1] = hi;
-                    blo[h][s][2 * j] = __bf16(v[s][j].x - float(hr));
-                    blo[h][s][2 * j + 1] = __bf16(v[s][j].y - float(hi));
-                }
+            for (int j = 0; j < 4; ++j) {
+                v2bf hh, ll;
+                split2(v[j].x, v[j].y, hh, ll);
+                bhi[h][2 * j] = hh[0];
+                bhi[h][2 * j + 1] = hh[1];
+                blo[h][2 * j] = ll[0];
+                blo[h][2 * j + 1] = ll[1];
+            }
         }
-        f32x4 acc[H][MT];
+        f32x4 acc[2][2];
 #pragma unroll
-        for (int h = 0; h < H; ++h)
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) acc[h][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int mt = 0; mt < 2; ++mt) acc[h][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int s = 0; s < KS; ++s) {
+        for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
+            for (int h = 0; h < 2; ++h)
+                acc[h][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[mt], bhi[h], acc[h][mt], 0, 0, 0);
 #pragma unroll
-                for (int h = 0; h < H; ++h)
-                    acc[h][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[mt][s], bhi[h][s], acc[h][mt], 0, 0, 0);
+        for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
+            for (int h = 0; h < 2; ++h)
+                acc[h][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[mt], blo[h], acc[h][mt], 0, 0, 0);
 #pragma unroll
-                for (int h = 0; h < H; ++h)
-                    acc[h][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[mt][s], blo[h][s], acc[h][mt], 0, 0, 0);
+        for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
+            for (int h = 0; h < 2; ++h)
+                acc[h][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[mt], bhi[h], acc[h][mt], 0, 0, 0);
 #pragma unroll
-                for (int h = 0; h < H; ++h)
-                    acc[h][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[mt][s], bhi[h][s], acc[h][mt], 0, 0, 0);
-        }
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int h = 0; h < H; ++h)
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-                tile[sw(gb[h] | woff[mt][0])] = make_float2(acc[h][mt][0], acc[h][mt][1]);
-                tile[sw(gb[h] | woff[mt][1])] = make_float2(acc[h][mt][2], acc[h][mt][3]);
+            for (int mt = 0; mt < 2; ++mt) {
+                *reinterpret_cast<float2 *>(tb + (wr[mt][0] ^ gt[h])) = make_float2(acc[h][mt][0], acc[h][mt][1]);
+                *reinterpret_cast<float2 *>(tb + (wr[mt][1] ^ gt[h])) = make_float2(acc[h][mt][2], acc[h][mt][3]);
             }
     }
 }
@@ -168,16 +166,19 @@ __device__ void dense_op(float2 *tile, const TileOpDev &op, const uint4 *data, i
 __device__ void dense_op5(float2 *tile, const TileOpDev &op, const uint4 *data, int m, int outer)
 {
     constexpr int K = 5;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     const bf16x8 *fr =
         reinterpret_cast<const bf16x8 *>(data + op.data_off + uint32_t(outer) * op.frag_stride);
-    bf16x8 urh[2], uih[2], url[2], uil[2];
+    // fragments: Ur, Ui, -Ui row tiles (hi), then the same (lo)
+    bf16x8 urh[2], uih[2], nuih[2], url[2], uil[2], nuil[2];
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt) {
         urh[mt] = fr[(0 + mt) * 64 + lane];
         uih[mt] = fr[(2 + mt) * 64 + lane];
-        url[mt] = fr[(4 + mt) * 64 + lane];
-        uil[mt] = fr[(6 + mt) * 64 + lane];
+        nuih[mt] = fr[(4 + mt) * 64 + lane];
+        url[mt] = fr[(6 + mt) * 64 + lane];
+        uil[mt] = fr[(8 + mt) * 64 + lane];
+        nuil[mt] = fr[(10 + mt) * 64 + lane];
     }
     int srt[K];
 #pragma unroll
@@ -198,32 +199,39 @@ __device__ void dense_op5(float2 *tile, const TileOpDev &op, const uint4 *data, 
             if ((x >> (K - 1 - b)) & 1) o |= 1u << op.lpos[b];
         return o;
     };
-    uint32_t roff[8], woff[2][4];
+    // The group base and the LDS swizzle are linear over disjoint bits, so an
+    // address is (per-lane part) ^ (per-column-tile part): precompute the
+    // per-lane byte offsets once.
+    const uint32_t gl = insert_zero_bits(uint32_t(lane & 15), srt, K);
+    uint32_t rd[8], wr[2][4];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) roff[j] = offset(8 * (lane >> 4) + j);
+    for (int j = 0; j < 8; ++j) rd[j] = sw(gl | offset(8 * (lane >> 4) + j)) * 8u;
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) woff[mt][j] = offset(16 * mt + 4 * (lane >> 4) + j);
+        for (int j = 0; j < 4; ++j) wr[mt][j] = sw(gl | offset(16 * mt + 4 * (lane >> 4) + j)) * 8u;
+    char *tb = reinterpret_cast<char *>(tile);
     const int ntiles = 1 << (m - K - 4);
     constexpr int kWaves = kThreads / 64;
     for (int nt = wave; nt < ntiles; nt += kWaves) {
-        const uint32_t g = uint32_t(nt) * 16 + (lane & 15);
-        const uint32_t gb = insert_zero_bits(g, srt, K);
+        const uint32_t gt = sw(insert_zero_bits(uint32_t(nt) * 16u, srt, K)) * 8u;  // uniform
         float2 v[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = tile[sw(gb | roff[j])];
-        bf16x8 xrh, xrl, xih, xil, nxih, nxil;
+        for (int j = 0; j < 8; ++j) v[j] = *reinterpret_cast<const float2 *>(tb + (rd[j] ^ gt));
+        bf16x8 xrh, xrl, xih, xil;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const __bf16 hr = __bf16(v[j].x), hi = __bf16(v[j].y);
-            const __bf16 lr = __bf16(v[j].x - float(hr)), li = __bf16(v[j].y - float(hi));
-            xrh[j] = hr;
-            xrl[j] = lr;
-            xih[j] = hi;
-            xil[j] = li;
-            nxih[j] = -hi;
-            nxil[j] = -li;
+        for (int j = 0; j < 8; j += 2) {
+            v2bf h, l;
+            split2(v[j].x, v[j + 1].x, h, l);
+            xrh[j] = h[0];
+            xrh[j + 1] = h[1];
+            xrl[j] = l[0];
+            xrl[j + 1] = l[1];
+            split2(v[j].y, v[j + 1].y, h, l);
+            xih[j] = h[0];
+            xih[j + 1] = h[1];
+            xil[j] = l[0];
+            xil[j + 1] = l[1];
         }
         f32x4 ar[2], ai[2];
 #pragma unroll
@@ -231,6 +239,7 @@ __device__ void dense_op5(float2 *tile, const TileOpDev &op, const uint4 *data, 
             ar[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
             ai[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
         }
+        // Yr = Ur Xr - Ui Xi, Yi = Ui Xr + Ur Xi; hi*hi + hi*lo + lo*hi each
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt) {
             ar[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(urh[mt], xrh, ar[mt], 0, 0, 0);
@@ -238,7 +247,7 @@ __device__ void dense_op5(float2 *tile, const TileOpDev &op, const uint4 *data, 
         }
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt) {
-            ar[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(uih[mt], nxih, ar[mt], 0, 0, 0);
+            ar[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nuih[mt], xih, ar[mt], 0, 0, 0);
             ai[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(urh[mt], xih, ai[mt], 0, 0, 0);
         }
 #pragma unroll
@@ -248,7 +257,7 @@ __device__ void dense_op5(float2 *tile, const TileOpDev &op, const uint4 *data, 
         }
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt) {
-            ar[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(uih[mt], nxil, ar[mt], 0, 0, 0);
+            ar[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nuih[mt], xil, ar[mt], 0, 0, 0);
             ai[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(urh[mt], xil, ai[mt], 0, 0, 0);
         }
 #pragma unroll
@@ -258,13 +267,14 @@ __device__ void dense_op5(float2 *tile, const TileOpDev &op, const uint4 *data, 
         }
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt) {
-            ar[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(uil[mt], nxih, ar[mt], 0, 0, 0);
+            ar[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nuil[mt], xih, ar[mt], 0, 0, 0);
             ai[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(url[mt], xih, ai[mt], 0, 0, 0);
         }
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) tile[sw(gb | woff[mt][j])] = make_float2(ar[mt][j], ai[mt][j]);
+            for (int j = 0; j < 4; ++j)
+                *reinterpret_cast<float2 *>(tb + (wr[mt][j] ^ gt)) = make_float2(ar[mt][j], ai[mt][j]);
     }
 }
 
@@ -328,12 +338,12 @@ __device__ __forceinline__ void tile_pass(float2 *amp, uint64_t t, const TileArg
         const TileOpDev op = ops[oi];
         int outer = 0;
 #pragma unroll
-        for (int b = 0; b < 3; ++b)
+        for (int b = 0; b < 5; ++b)
             if (b < op.no) outer = (outer << 1) | int((base >> op.opos[b]) & 1);
         if (op.kind == 0) {
             if ((op.skip >> outer) & 1u) continue;  // identity on this tile
             if (op.k == 4)
-                dense_op<4>(tile, op, data, M, outer);
+                dense_op4(tile, op, data, M, outer);
             else
                 dense_op5(tile, op, data, M, outer);
         } else {

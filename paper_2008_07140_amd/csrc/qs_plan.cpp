@@ -561,8 +561,8 @@ void plan_tiles(const std::vector<FlatOp> &flat, size_t k0, size_t e, int n, con
         // a gate can live in a tile when its qubits inside any Q are few
         // enough: dense gates need all targets in Q and at most kmax local
         // qubits; diagonal gates at most 3 local and 3 outer qubits (table)
-        if (g.diag) return __builtin_popcountll(g.qmask) <= kmax + 3;
-        return __builtin_popcountll(g.tmask) <= kmax && __builtin_popcountll(g.cmask) <= kmax + 3;
+        if (g.diag) return __builtin_popcountll(g.qmask) <= kmax + kMaxOuter;
+        return __builtin_popcountll(g.tmask) <= kmax && __builtin_popcountll(g.cmask) <= kmax + kMaxOuter;
     };
     while (!remaining.empty()) {
         // ---- choose Q and the gates this sweep applies
@@ -608,7 +608,7 @@ void plan_tiles(const std::vector<FlatOp> &flat, size_t k0, size_t e, int n, con
             for (size_t gi : applied) {
                 const GInfo &g = info[gi];
                 const bool bad = __builtin_popcountll(g.qmask & Q) > kmax ||
-                                 __builtin_popcountll(g.qmask & ~Q) > 3;
+                                 __builtin_popcountll(g.qmask & ~Q) > kMaxOuter;
                 if (bad || (g.qmask & blk)) {
                     later.push_back(gi);
                     blk |= g.qmask;
@@ -678,52 +678,41 @@ void plan_tiles(const std::vector<FlatOp> &flat, size_t k0, size_t e, int n, con
         auto by_first = [](const std::unique_ptr<OpenBlock> &a, const std::unique_ptr<OpenBlock> &b) {
             return a->first < b->first;
         };
-        for (size_t gi : applied) {
-            const GInfo &g = info[gi];
-            const uint64_t loc = g.qmask & Q, outm = g.qmask & ~Q;
-            if (!loc) {
-                // only outer qubits: a per-tile phase, commutes with the
-                // whole sweep; attach it to the newest block with room
-                OpenBlock *host = nullptr;
-                for (auto &b : open)
-                    if (__builtin_popcountll(b->omask | outm) <= 3 && (!host || b->first > host->first))
-                        host = b.get();
-                if (host) {
-                    host->omask |= outm;
-                    host->gates.push_back(&g);
+        // Blocks by a light-cone scan: open a block at the first remaining
+        // gate and absorb, in circuit order, every later gate whose tile
+        // qubits keep the block within kmax (and its outer selectors within
+        // 3), skipping gates that touch a qubit of an earlier skipped gate.
+        // Skipped gates do not precede absorbed ones on a shared tile qubit,
+        // and outer qubits are constant over the sweep, so the absorbed
+        // gates may run first.
+        (void)by_first;
+        (void)serial;
+        std::vector<size_t> rem = applied;
+        while (!rem.empty()) {
+            OpenBlock blk;
+            uint64_t blocked = 0;
+            std::vector<size_t> rest;
+            for (size_t gi : rem) {
+                const GInfo &g = info[gi];
+                const uint64_t loc = g.qmask & Q, outm = g.qmask & ~Q;
+                if (loc & blocked) {
+                    rest.push_back(gi);
+                    blocked |= loc;
                     continue;
                 }
-            }
-            std::vector<size_t> hit;
-            uint64_t uni = loc, ouni = outm;
-            for (size_t b = 0; b < open.size(); ++b)
-                if (open[b]->qmask & loc) {
-                    hit.push_back(b);
-                    uni |= open[b]->qmask;
-                    ouni |= open[b]->omask;
+                const uint64_t uni = blk.qmask | loc, ouni = blk.omask | outm;
+                if (__builtin_popcountll(uni) <= kmax && __builtin_popcountll(ouni) <= kMaxOuter) {
+                    blk.qmask = uni;
+                    blk.omask = ouni;
+                    blk.gates.push_back(&g);
+                } else {
+                    rest.push_back(gi);
+                    blocked |= loc;
                 }
-            std::sort(hit.begin(), hit.end(), [&](size_t a, size_t b) { return open[a]->first < open[b]->first; });
-            auto nb = std::make_unique<OpenBlock>();
-            nb->first = serial++;
-            if (__builtin_popcountll(uni) <= kmax && __builtin_popcountll(ouni) <= 3) {
-                nb->qmask = uni;
-                nb->omask = ouni;
-                for (size_t b : hit) nb->gates.insert(nb->gates.end(), open[b]->gates.begin(), open[b]->gates.end());
-                if (!hit.empty()) nb->first = open[hit[0]]->first;
-            } else {
-                for (size_t b : hit) emit_block(*open[b]);
-                nb->qmask = loc;
-                nb->omask = outm;
             }
-            nb->gates.push_back(&g);
-            std::vector<std::unique_ptr<OpenBlock>> keep;
-            for (size_t b = 0; b < open.size(); ++b)
-                if (std::find(hit.begin(), hit.end(), b) == hit.end()) keep.push_back(std::move(open[b]));
-            keep.push_back(std::move(nb));
-            open.swap(keep);
+            emit_block(blk);
+            rem.swap(rest);
         }
-        std::sort(open.begin(), open.end(), by_first);
-        for (auto &b : open) emit_block(*b);
         PlanStep st;
         st.sweep = true;
         st.sw = std::move(sw);

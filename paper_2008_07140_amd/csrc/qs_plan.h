@@ -67,11 +67,13 @@ namespace qs {
 // starting with the L lowest qubits) in LDS and applies a list of ops to
 // every tile; the other n - m bits index the tiles.
 
+constexpr int kMaxOuter = 5;  // outer selector bits of one tile op
+
 struct TileOp {
     enum Kind { DENSE, PHASE };
     Kind kind = DENSE;
     // `qubits` lie in Q (qubits[0] = most significant bit of a matrix index),
-    // `outer` outside Q (at most 3, outer[0] most significant); the outer
+    // `outer` outside Q (at most kMaxOuter, outer[0] most significant); the outer
     // bits are constant over a tile and select one of 2^|outer| operators.
     // DENSE: m holds 2^|outer| matrices of 2^k x 2^k complex one after
     // another; `skip` bit p is set when matrix p is the identity.

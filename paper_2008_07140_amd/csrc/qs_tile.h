@@ -22,10 +22,10 @@ struct TileArgs {
 struct TileOpDev {
     int kind;            // 0 = dense block, 1 = phase
     int k;               // dense: 4 or 5 qubits; phase: number of tile bits (0..3)
-    int no;              // number of outer selector bits (0..3)
+    int no;              // number of outer selector bits (0..5)
     uint32_t data_off;   // offset of fragments / table in the data buffer, 16-byte units
     int lpos[6];         // tile-local bit positions, [0] = most significant
-    int opos[4];         // global positions of the outer bits, [0] = most significant
+    int opos[5];         // global positions of the outer bits, [0] = most significant
     uint32_t skip;       // dense: bit p set = identity for outer pattern p
     uint32_t frag_stride;  // dense: 16-byte units per outer pattern
 };
