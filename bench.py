@@ -54,6 +54,11 @@ def parse():
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 4 GiB device-to-device copy (5 times), the reference "
                         "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
+    p.add_argument("--no-by-target", action="store_true",
+                   help="skip the per-target / per-control bandwidth sweep of single gates")
+    p.add_argument("--summarize-profiles", metavar="DIR", default="",
+                   help="CPU only: read the rocprofv3 CSV output under DIR (see profiles/README.md) "
+                        "and write profiles/traffic.json plus the text summaries")
     return p.parse_args()
 
 
@@ -67,18 +72,195 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel_class: str):
-    """HBM bytes per launch measured by rocprofv3 counters for this kernel, if
-    the counters were taken on the current kernel sources."""
+def traffic_for(path_name: str, kernel_class: str):
+    """HBM bytes per launch measured by rocprofv3 counters for this kernel class
+    on this path, if the counters were taken on the current kernel sources."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         data = json.load(f)
-    rec = data.get(kernel_class)
+    rec = data.get("%s/%s" % (path_name, kernel_class))
     if not rec or rec.get("source_hash") != source_hash():
         return None
     return rec.get("bytes_per_launch")
+
+
+# --- rocprofv3 summaries ------------------------------------------------------
+# The counter passes, each a run of its own (rocprofv3 does not split counters
+# over passes), from the repository root on the GPU machine:
+PROFILE_RUNS = [
+    ("ktrace", "--kernel-trace --stats",
+     "--steps 2 --warmup 1 --no-cpu-baseline --trajectories 0 --no-by-target"),
+    ("pmc_fetch_fused_c64", "--pmc FETCH_SIZE",
+     "--steps 1 --warmup 0 --no-cpu-baseline --trajectories 0 --no-by-target --paths fused_c64"),
+    ("pmc_write_fused_c64", "--pmc WRITE_SIZE",
+     "--steps 1 --warmup 0 --no-cpu-baseline --trajectories 0 --no-by-target --paths fused_c64"),
+    ("pmc_fetch_plain_c128", "--pmc FETCH_SIZE",
+     "--steps 1 --warmup 0 --no-cpu-baseline --trajectories 0 --no-by-target --paths plain_c128"),
+    ("pmc_write_plain_c128", "--pmc WRITE_SIZE",
+     "--steps 1 --warmup 0 --no-cpu-baseline --trajectories 0 --no-by-target --paths plain_c128"),
+    ("pmc_fetch_copy", "--pmc FETCH_SIZE", "--copy-calibration"),
+    ("pmc_write_copy", "--pmc WRITE_SIZE", "--copy-calibration"),
+]
+
+
+def profile_command(sub, flags, bench_args):
+    return ("rocprofv3 %s -f csv -d gpurun_out/%s -o run -- python3 bench.py %s > gpurun_out/%s.log"
+            % (flags, sub, bench_args, sub))
+
+
+def kernel_class_of(name: str):
+    """Library kernel class of a rocprofv3 kernel name (None for other kernels)."""
+    import re
+    m = re.search(r"::(k_[A-Za-z0-9_]+)", name)
+    if not m:
+        return None
+    f = m.group(1)
+    if f == "k_tile":
+        return "tile"
+    if f.startswith("k_dense1"):
+        return "dense1"
+    table = {"k_dense_small": "dense_small", "k_denseN": "denseN", "k_phase": "phase", "k_init": "init",
+             "k_scale": "other"}
+    if f in table:
+        return table[f]
+    if f.startswith(("k_probs", "k_sum", "k_gather", "k_rdm", "k_zsum")):
+        return "reduce"
+    return None
+
+
+def short_kernel(name: str):
+    import re
+    m = re.search(r"::(k_[A-Za-z0-9_]+(<[^()]*>)?)\(", name)
+    return m.group(1) if m else name[:60]
+
+
+def _csv_rows(path):
+    import csv
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def _counter_means(d, sub):
+    """{kernel name: (dispatches, mean counter value in KiB)} of one --pmc pass."""
+    import glob
+    files = glob.glob(os.path.join(d, sub, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit("no counter CSV under %s" % os.path.join(d, sub))
+    acc = {}
+    for r in _csv_rows(files[0]):
+        k = r["Kernel_Name"]
+        v = float(r["Counter_Value"])
+        c, t = acc.get(k, (0, 0.0))
+        acc[k] = (c + 1, t + v)
+    return {k: (c, t / c) for k, (c, t) in acc.items()}
+
+
+def _last_json(path):
+    if not os.path.exists(path):
+        return None
+    last = None
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if line.startswith("{") and '"metric"' in line:
+                last = json.loads(line)
+    return last
+
+
+def summarize_profiles(d):
+    """Write profiles/traffic.json and the text summaries from rocprofv3 CSVs."""
+    import glob
+    prof = os.path.join(ROOT, "profiles")
+    os.makedirs(prof, exist_ok=True)
+    cmds = {sub: profile_command(sub, fl, ba) for sub, fl, ba in PROFILE_RUNS}
+    # copy calibration: a plain 4 GiB device copy reads and writes 4 GiB
+    copy_kib = float(4 << 30) / 1024.0
+    cf = [v for k, v in _counter_means(d, "pmc_fetch_copy").items() if "copyBuffer" in k or "copy" in k.lower()]
+    cw = [v for k, v in _counter_means(d, "pmc_write_copy").items() if "copyBuffer" in k or "copy" in k.lower()]
+    cf = max(cf, key=lambda x: x[1])
+    cw = max(cw, key=lambda x: x[1])
+    fetch_scale, write_scale = copy_kib / cf[1], copy_kib / cw[1]
+    src = source_hash()
+    bench_line = _last_json(os.path.join(d, "ktrace.log"))
+    traffic = {"_calibration": {"copy_bytes": 4 << 30, "fetch_kib": cf[1], "write_kib": cw[1],
+                                "fetch_scale": fetch_scale, "write_scale": write_scale,
+                                "commands": [cmds["pmc_fetch_copy"], cmds["pmc_write_copy"]]}}
+    lines = ["# HBM traffic per dispatch, 30-qubit depth-40 circuit (rqc30_d40)", "",
+             "FETCH_SIZE and WRITE_SIZE (KiB per dispatch, rocprofv3 `--pmc`, one counter per run),",
+             "scaled by what the same counters read for a plain 4 GiB device copy:",
+             "", "| copy counter | KiB per dispatch | true KiB | scale |", "|---|---|---|---|",
+             "| FETCH_SIZE | %.1f | %.1f | %.4f |" % (cf[1], copy_kib, fetch_scale),
+             "| WRITE_SIZE | %.1f | %.1f | %.4f |" % (cw[1], copy_kib, write_scale), "",
+             "| path | kernel | dispatches | FETCH KiB | WRITE KiB | scaled HBM bytes / dispatch | "
+             "algorithmic bytes / launch | ratio |", "|---|---|---|---|---|---|---|---|"]
+    for path in ("fused_c64", "plain_c128"):
+        fm = _counter_means(d, "pmc_fetch_%s" % path)
+        wm = _counter_means(d, "pmc_write_%s" % path)
+        alg = None
+        if bench_line and path in bench_line.get("paths", {}):
+            alg = bench_line["paths"][path]
+        by_class = {}
+        for k in fm:
+            cls = kernel_class_of(k)
+            if cls is None or k not in wm:
+                continue
+            nf, vf = fm[k]
+            nw, vw = wm[k]
+            b = (vf * fetch_scale + vw * write_scale) * 1024.0
+            c = by_class.setdefault(cls, [0, 0.0, 0.0, 0.0])
+            c[0] += nf
+            c[1] += vf * nf
+            c[2] += vw * nf
+            c[3] += b * nf
+            lines.append("| %s | %s | %d | %.0f | %.0f | %.4g | | |" % (path, short_kernel(k), nf, vf, vw, b))
+        for cls, (cnt, tf, tw, tb) in sorted(by_class.items()):
+            rec = {"source_hash": src, "dispatches": cnt, "fetch_kib_per_launch": tf / cnt,
+                   "write_kib_per_launch": tw / cnt, "bytes_per_launch": tb / cnt,
+                   "commands": [cmds["pmc_fetch_%s" % path], cmds["pmc_write_%s" % path]]}
+            ab = None
+            if alg and alg.get("dominant") == cls:
+                ab = alg["roofline"]["alg_bytes_per_launch"]
+                rec["alg_bytes_per_launch"] = ab
+                rec["ratio_to_algorithmic"] = rec["bytes_per_launch"] / ab
+            traffic["%s/%s" % (path, cls)] = rec
+            lines.append("| %s | **class %s** | %d | %.0f | %.0f | %.4g | %s | %s |"
+                         % (path, cls, cnt, tf / cnt, tw / cnt, tb / cnt,
+                            "%.4g" % ab if ab else "", "%.3f" % (tb / cnt / ab) if ab else ""))
+    lines += ["", "Commands (from the repository root, after `cd /tmp && export TMPDIR=/tmp` and with",
+              "paths taken from the root; each pass is its own process):", "", "```"]
+    lines += [cmds[k] for k in cmds if k.startswith("pmc_")]
+    lines += ["python3 bench.py --summarize-profiles gpurun_out", "```", "",
+              "Kernel sources hash: %s" % src]
+    with open(os.path.join(prof, "hbm_traffic_rqc30_d40.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    with open(os.path.join(prof, "traffic.json"), "w") as f:
+        json.dump(traffic, f, indent=1, sort_keys=True)
+        f.write("\n")
+    # kernel trace statistics
+    files = glob.glob(os.path.join(d, "ktrace", "**", "*kernel_stats.csv"), recursive=True)
+    rows = _csv_rows(files[0])
+    kl = ["# Kernel time, 30-qubit depth-40 circuit (rqc30_d40), fused c64 and plain c128 paths", "",
+          "`rocprofv3 --kernel-trace --stats` over warm-up 1 + 2 timed steps of each path.", "",
+          "| kernel | calls | total ms | average us | % |", "|---|---|---|---|---|"]
+    for r in rows[:20]:
+        kl.append("| %s | %s | %.1f | %.1f | %s |" % (short_kernel(r["Name"]), r["Calls"],
+                                                       float(r["TotalDurationNs"]) / 1e6,
+                                                       float(r["AverageNs"]) / 1e3, r["Percentage"]))
+    if bench_line:
+        kl += ["", "The same run's bench line measured, with HIP events on the state's stream:", ""]
+        for path, pr in bench_line.get("paths", {}).items():
+            rf = pr["roofline"]
+            kl.append("- %s: %.1f gates/s; dominant kernel class `%s` (%s), average launch %.1f us, "
+                      "%.0f GB/s on %.4g algorithmic bytes per launch"
+                      % (path, pr["gates_per_s"], pr["dominant"], rf["kernel"], rf["avg_launch_ms"] * 1e3,
+                         rf["achieved"], rf["alg_bytes_per_launch"]))
+    kl += ["", "Command (from the repository root):", "", "```", cmds["ktrace"], "```", "",
+           "Kernel sources hash: %s" % src]
+    with open(os.path.join(prof, "kernel_stats_rqc30_d40.md"), "w") as f:
+        f.write("\n".join(kl) + "\n")
+    print("wrote profiles/traffic.json, profiles/hbm_traffic_rqc30_d40.md, profiles/kernel_stats_rqc30_d40.md")
 
 
 def run_path(qs, torch, cg, name, n, circuit, gates, steps, warmup, kmax, plan, tile_qubits=0):
@@ -135,11 +317,55 @@ def run_path(qs, torch, cg, name, n, circuit, gates, steps, warmup, kmax, plan, 
                      "frac": achieved / HBM_PEAK_GBPS,
                      "alg_bytes_per_launch": d["bytes"] / d["launches"],
                      "avg_launch_ms": d["ms"] / d["launches"],
-                     "traffic": traffic_for(dom)},
+                     "traffic": traffic_for(name, dom)},
     }
     log("%s: %.1f gates/s, %.1f ms/step, path HBM fraction %.3f, dominant %s at %.0f GB/s"
         % (name, res["gates_per_s"], res["ms_per_step"], res["hbm_frac_path"], dom, achieved))
-    return res, st, buf
+    return res, st, buf, stream
+
+
+def gate_bandwidth_sweep(qs, torch, cg, st, stream, n, amp_bytes, reps=3):
+    """Effective GB/s of single gates on the resident state: a dense U3 on each
+    target bit k, and a controlled U3 for each control bit (target n-1, or 0
+    when the control is n-1).  Algorithmic bytes: 2 * 2^n * amp (dense),
+    2 * 2^(n-1) * amp (one control).  Timed with events on the state's stream."""
+    u = cg.u3(1.1, 0.7, -0.4)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(targets, controls, nbytes):
+        st.apply_gate(targets, controls, u)  # first touch / warm
+        ev0.record(stream)
+        for _ in range(reps):
+            st.apply_gate(targets, controls, u)
+        ev1.record(stream)
+        ev1.synchronize()
+        return nbytes * reps / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+
+    dense = [timed([k], [], 2.0 * (1 << n) * amp_bytes) for k in range(n)]
+    ctrl = [timed([n - 1 if c != n - 1 else 0], [c], 2.0 * (1 << (n - 1)) * amp_bytes) for c in range(n)]
+    log("single gates: dense U3 %.0f..%.0f GB/s over targets, CU3 %.0f..%.0f GB/s over controls"
+        % (min(dense), max(dense), min(ctrl), max(ctrl)))
+    return {"dense_u3_GBps_by_target": [round(x, 1) for x in dense],
+            "cu3_GBps_by_control": [round(x, 1) for x in ctrl]}
+
+
+def copy_ceiling(torch, nbytes=4 << 30, reps=5):
+    """Device-to-device copy bandwidth (read + write bytes / time), the
+    attainable HBM figure beside the nominal peak."""
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    ev1.record()
+    ev1.synchronize()
+    gbps = 2.0 * nbytes * reps / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    log("device copy: %.0f GB/s (read + write)" % gbps)
+    return gbps
 
 
 def trajectory_bench(qs, cg, count, seed=4001):
@@ -188,6 +414,9 @@ def cpu_baseline(cg, n, ops, seconds):
 
 def main():
     args = parse()
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU: the state-vector path here is single-GPU "
               "(multi-GPU sharding is described, not built); use --gpus 1", file=sys.stderr)
@@ -218,11 +447,15 @@ def main():
     paths = [p for p in args.paths.split(",") if p]
     out = {}
     states = {}
+    sweep_state = None
+    copy_gbps = copy_ceiling(torch)
     for p in paths:
-        res, st, buf = run_path(qs, torch, cg, p, n, circuit, gates, args.steps, args.warmup,
-                                args.kmax, args.plan, args.tile_qubits)
+        res, st, buf, stream = run_path(qs, torch, cg, p, n, circuit, gates, args.steps, args.warmup,
+                                        args.kmax, args.plan, args.tile_qubits)
         out[p] = res
         states[p] = (st, buf)
+        if p == "plain_c128" and not args.no_by_target:
+            sweep_state = (st, stream)
     acc = None
     if "fused_c64" in states and "plain_c128" in states:
         rng = np.random.default_rng(12345)
@@ -235,6 +468,10 @@ def main():
                "rel_l2": float(np.linalg.norm(a - b) / np.linalg.norm(a))}
         log("accuracy c64 vs c128 on %d sampled amplitudes: infidelity %.3e, max|d| %.3e"
             % (idx.size, acc["infidelity_c64_vs_c128"], acc["max_abs_diff"]))
+    by_target = None
+    if sweep_state is not None:
+        by_target = gate_bandwidth_sweep(qs, torch, cg, sweep_state[0], sweep_state[1], n, 16)
+        sweep_state = None
     for st, buf in states.values():
         st.close()
     del states
@@ -268,7 +505,9 @@ def main():
                    else "complex128 (FP64)"},
         "roofline": prim["roofline"],
         "hbm_frac_path": prim["hbm_frac_path"],
+        "copy_GBps": copy_gbps,
         "paths": out,
+        "single_gates_c128": by_target,
         "accuracy": acc,
         "trajectories": traj,
         "cpu_baseline": cpu,
