@@ -22,6 +22,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for all device code.
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
                 "-packed-fp32-ops"]
+HOST_FLAGS = ["-D__HIP_PLATFORM_AMD__", "-I", os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "include")]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result", "-Wno-unused-value",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
@@ -30,16 +31,25 @@ def sources():
     return [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
 
 
-def build(verbose: bool = True, jobs: int = 8) -> str:
-    """Compile every source to an object in _build/ and link libqs.so."""
+def build(verbose: bool = True, jobs: int = 8, incremental: bool = False) -> str:
+    """Compile every source to an object in _build/ and link libqs.so.
+    With `incremental`, objects newer than their source and every header are
+    kept."""
     bdir = os.path.join(ROOT, "_build")
     os.makedirs(bdir, exist_ok=True)
     objs, procs = [], []
+    hdr = max([os.path.getmtime(os.path.join(CSRC, h)) for h in HEADERS
+               if os.path.exists(os.path.join(CSRC, h))]
+              + [os.path.getmtime(os.path.join(ROOT, "include", "qs.h")), os.path.getmtime(__file__)])
     for src in sources():
         obj = os.path.join(bdir, os.path.basename(src) + ".o")
         objs.append(obj)
-        lang = ["-x", "hip"]
-        cmd = [HIPCC] + COMMON + DEVICE_FLAGS + lang + ["-c", src, "-o", obj]
+        if incremental and os.path.exists(obj) and os.path.getmtime(obj) > max(hdr, os.path.getmtime(src)):
+            continue
+        if src.endswith(".hip"):
+            cmd = [HIPCC] + COMMON + DEVICE_FLAGS + ["-x", "hip", "-c", src, "-o", obj]
+        else:  # host-only C++ against the HIP runtime API
+            cmd = [HIPCC] + COMMON + HOST_FLAGS + ["-x", "c++", "-c", src, "-o", obj]
         procs.append((src, cmd))
     t0 = time.time()
     running = []
@@ -74,4 +84,4 @@ def _wait_one(running):
 
 
 if __name__ == "__main__":
-    build()
+    build(incremental="--incremental" in sys.argv[1:])

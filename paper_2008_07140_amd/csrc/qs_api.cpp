@@ -11,10 +11,12 @@
 #include <complex>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "qs_internal.h"
@@ -397,39 +399,14 @@ float bf16_float(uint16_t h)
     return f;
 }
 
-// Matrix-core operand fragments of a dense 2^k block, in the order the tile
-// kernel's lanes read them: for the real form A (2D x 2D, D = 2^k, entries
-// [[Re U, -Im U], [Im U, Re U]] per complex entry with re/im interleaved),
-// fragment (mt, s) of lane l holds A[16 mt + l % 16][32 s + 8 (l / 16) + j],
-// j < 8, as bfloat16 (hi), followed by the same layout of the remainders (lo).
-// Five-qubit blocks use the split form instead: fragment f < 6 of lane l
-// holds (Re U, Im U, -Im U for f / 2 = 0, 1, 2)[16 (f % 2) + l % 16][8 (l / 16)
-// + j], j < 8, hi values for the six fragments first, then the remainders.
-void append_fragments5(const std::vector<double> &m, std::vector<uint16_t> &out)
-{
-    const int D = 32;
-    const size_t base = out.size();
-    const size_t nfr = size_t(6) * 64 * 8;
-    out.resize(base + 2 * nfr);
-    for (int f = 0; f < 6; ++f)
-        for (int lane = 0; lane < 64; ++lane)
-            for (int j = 0; j < 8; ++j) {
-                const int r = 16 * (f % 2) + lane % 16, c = 8 * (lane / 16) + j;
-                const double v = (f < 4 ? 1.0 : -1.0) * m[2 * (size_t(r) * D + c) + (f < 2 ? 0 : 1)];
-                const uint16_t h = bf16_rne(float(v));
-                const uint16_t l = bf16_rne(float(v - double(bf16_float(h))));
-                const size_t idx = (size_t(f) * 64 + lane) * 8 + j;
-                out[base + idx] = h;
-                out[base + nfr + idx] = l;
-            }
-}
-
+// Matrix-core operand fragments of a dense 2^k block (k = 4, 5), in the order
+// the tile kernel's lanes read them: for the real form A (2D x 2D, D = 2^k,
+// entries [[Re U, -Im U], [Im U, Re U]] per complex entry with re/im
+// interleaved), fragment (mt, s) of lane l holds
+// A[16 mt + l % 16][32 s + 8 (l / 16) + j], j < 8, as bfloat16 (hi),
+// followed by the same layout of the remainders (lo).
 void append_fragments(const std::vector<double> &m, int k, std::vector<uint16_t> &out)
 {
-    if (k == 5) {
-        append_fragments5(m, out);
-        return;
-    }
     const int D = 1 << k, MT = 2 * D / 16, KS = 2 * D / 32;
     const size_t base = out.size();
     const size_t nfr = size_t(MT) * KS * 64 * 8;
@@ -450,10 +427,29 @@ void append_fragments(const std::vector<double> &m, int k, std::vector<uint16_t>
                 }
 }
 
+// Host work spread over threads: f(i) for i < count, in any order.
+template <typename F>
+void parallel_for(size_t count, F &&f)
+{
+    const size_t hw = std::max(1u, std::thread::hardware_concurrency());
+    const size_t nt = std::min<size_t>({hw, 16, (count + 3) / 4});
+    if (nt <= 1) {
+        for (size_t i = 0; i < count; ++i) f(i);
+        return;
+    }
+    std::atomic<size_t> next{0};
+    std::vector<std::thread> pool;
+    for (size_t t = 0; t < nt; ++t)
+        pool.emplace_back([&] {
+            for (size_t i = next.fetch_add(1); i < count; i = next.fetch_add(1)) f(i);
+        });
+    for (auto &th : pool) th.join();
+}
+
 struct TileProgram {
     std::vector<qs::TileOpDev> ops;
-    std::vector<uint16_t> data;  // 16-byte aligned records
-    std::vector<size_t> first;   // first op of each sweep step
+    std::vector<uint16_t> data;     // 16-byte aligned records
+    std::vector<size_t> first;      // first op of each sweep step
 };
 
 void pad16(std::vector<uint16_t> &d)
@@ -461,54 +457,163 @@ void pad16(std::vector<uint16_t> &d)
     while (d.size() % 8) d.push_back(0);
 }
 
-void build_tile_program(const std::vector<qs::PlanStep> &steps, TileProgram &tp)
+// Matrix-core lane layout of a dense tile op.  The 32 lanes of one LDS read
+// vary in the 4 column bits and in the op qubit at lpos[k - 3]; the 16 lanes
+// of a write in the column bits only.  Tile bit p falls on LDS bank bit p mod 5
+// (the tile swizzle), so the accesses are conflict-free when those five tile
+// bits have distinct residues mod 5.  `pos` holds the tile bits of the op
+// qubits; returns the op qubit to place at lpos[k - 3] and the column bits.
+void choose_lane_layout(const std::vector<int> &pos, int m, int &lane_q, uint32_t &colmask)
 {
-    for (const auto &st : steps) {
-        tp.first.push_back(tp.ops.size());
-        if (!st.sweep) continue;
-        const auto &Q = st.sw.Q;
-        auto lpos = [&](int q) {
-            for (size_t b = 0; b < Q.size(); ++b)
-                if (Q[b] == q) return int(b);
-            return -1;
-        };
-        for (const auto &op : st.sw.ops) {
-            qs::TileOpDev d{};
-            pad16(tp.data);
-            d.data_off = uint32_t(tp.data.size() / 8);
-            d.k = int(op.qubits.size());
-            d.no = int(op.outer.size());
-            for (int b = 0; b < d.k; ++b) d.lpos[b] = lpos(op.qubits[b]);
-            for (int b = 0; b < d.no; ++b) d.opos[b] = op.outer[b];
-            if (op.kind == qs::TileOp::DENSE) {
-                d.kind = 0;
-                d.skip = op.skip;
-                const int D = 1 << d.k;
-                const size_t per = size_t(2) * D * D;
-                const size_t before = tp.data.size();
-                for (size_t p = 0; p < op.m.size() / per; ++p) {
-                    std::vector<double> mp(op.m.begin() + p * per, op.m.begin() + (p + 1) * per);
-                    append_fragments(mp, d.k, tp.data);
-                    if (p == 0) d.frag_stride = uint32_t((tp.data.size() - before) / 8);
+    uint32_t opm = 0;
+    for (int p : pos) opm |= 1u << p;
+    const uint32_t group = ((1u << m) - 1u) & ~opm;
+    for (size_t q = 0; q < pos.size(); ++q) {
+        uint32_t cm = 0;
+        int have = 1 << (pos[q] % 5);
+        for (int p = 0; p < m && __builtin_popcount(cm) < 4; ++p)
+            if ((group >> p & 1) && !(have >> (p % 5) & 1)) {
+                cm |= 1u << p;
+                have |= 1 << (p % 5);
+            }
+        if (__builtin_popcount(cm) == 4) {
+            lane_q = int(q);
+            colmask = cm;
+            return;
+        }
+    }
+    // no conflict-free choice: the lowest group bits (two-way conflicts)
+    lane_q = int(pos.size()) - 3;
+    colmask = 0;
+    for (int p = 0; p < m && __builtin_popcount(colmask) < 4; ++p)
+        if (group >> p & 1) colmask |= 1u << p;
+}
+
+// The matrix of a k-qubit op with its qubits reordered: new qubit b is old
+// qubit order[b] (index 0 = most significant bit).
+std::vector<double> permute_matrix(const double *m, int k, const std::vector<int> &order)
+{
+    const int D = 1 << k;
+    std::vector<int> idx(D);
+    for (int x = 0; x < D; ++x) {
+        int o = 0;
+        for (int b = 0; b < k; ++b)
+            if ((x >> (k - 1 - b)) & 1) o |= 1 << (k - 1 - order[b]);
+        idx[x] = o;
+    }
+    std::vector<double> out(size_t(2) * D * D);
+    for (int r = 0; r < D; ++r)
+        for (int c = 0; c < D; ++c) {
+            out[2 * (size_t(r) * D + c)] = m[2 * (size_t(idx[r]) * D + idx[c])];
+            out[2 * (size_t(r) * D + c) + 1] = m[2 * (size_t(idx[r]) * D + idx[c]) + 1];
+        }
+    return out;
+}
+
+// Device ops and operand data of one sweep; data_off counts from the start of
+// this sweep's data (16-byte units).
+void build_sweep_program(const qs::Sweep &sw, std::vector<qs::TileOpDev> &ops, std::vector<uint16_t> &data)
+{
+    const auto &Q = sw.Q;
+    auto lpos = [&](int q) {
+        for (size_t b = 0; b < Q.size(); ++b)
+            if (Q[b] == q) return int(b);
+        return -1;
+    };
+    for (const auto &op : sw.ops) {
+        qs::TileOpDev d{};
+        pad16(data);
+        d.data_off = uint32_t(data.size() / 8);
+        d.k = int(op.qubits.size());
+        d.no = int(op.outer.size());
+        for (int b = 0; b < d.k; ++b) d.lpos[b] = lpos(op.qubits[b]);
+        for (int b = 0; b < d.no; ++b) d.opos[b] = op.outer[b];
+        if (op.kind == qs::TileOp::DENSE) {
+            d.kind = 0;
+            d.skip = op.skip;
+            // lane layout: the chosen op qubit moves to lpos[k - 3]
+            std::vector<int> pos(d.lpos, d.lpos + d.k), order(d.k);
+            int lane_q = d.k - 3;
+            choose_lane_layout(pos, int(Q.size()), lane_q, d.colmask);
+            for (int b = 0, o = 0; b < d.k; ++b) {
+                if (b == d.k - 3) {
+                    order[b] = lane_q;
+                    continue;
                 }
-            } else {
-                d.kind = 1;
-                const size_t ent = op.m.size() / 2;
-                for (size_t x = 0; x < ent; ++x) {
-                    const float re = float(op.m[2 * x]), im = float(op.m[2 * x + 1]);
+                if (o == lane_q) ++o;
+                order[b] = o++;
+            }
+            for (int b = 0; b < d.k; ++b) d.lpos[b] = pos[order[b]];
+            // fragments of each distinct matrix once, then one copy per
+            // outer pattern in pattern order
+            const int D = 1 << d.k;
+            const size_t per = size_t(2) * D * D;
+            const size_t nd = op.m.size() / per;
+            std::vector<uint16_t> distinct;
+            for (size_t u = 0; u < nd; ++u)
+                append_fragments(permute_matrix(op.m.data() + u * per, d.k, order), d.k, distinct);
+            const size_t fs = distinct.size() / nd;  // uint16 per matrix, a multiple of 8
+            d.frag_stride = uint32_t(fs / 8);
+            const size_t P = size_t(1) << d.no;
+            const size_t before = data.size();
+            data.resize(before + P * fs);
+            for (size_t p = 0; p < P; ++p) {
+                const size_t u = op.pmap.empty() ? p : op.pmap[p];
+                std::memcpy(data.data() + before + p * fs, distinct.data() + u * fs, fs * sizeof(uint16_t));
+            }
+        } else {
+            // one table of 2^k complex64 entries per outer pattern, each
+            // padded to whole 16-byte units
+            d.kind = 1;
+            const size_t D = size_t(1) << d.k, P = size_t(1) << d.no;
+            const size_t per = std::max<size_t>(D, 2);
+            d.frag_stride = uint32_t(per / 2);
+            for (size_t p = 0; p < P; ++p)
+                for (size_t x = 0; x < per; ++x) {
+                    const size_t e = p * D + x;
+                    const float re = x < D ? float(op.m[2 * e]) : 0.f, im = x < D ? float(op.m[2 * e + 1]) : 0.f;
                     uint32_t ur, ui;
                     std::memcpy(&ur, &re, 4);
                     std::memcpy(&ui, &im, 4);
-                    tp.data.push_back(uint16_t(ur));
-                    tp.data.push_back(uint16_t(ur >> 16));
-                    tp.data.push_back(uint16_t(ui));
-                    tp.data.push_back(uint16_t(ui >> 16));
+                    data.push_back(uint16_t(ur));
+                    data.push_back(uint16_t(ur >> 16));
+                    data.push_back(uint16_t(ui));
+                    data.push_back(uint16_t(ui >> 16));
                 }
-            }
-            tp.ops.push_back(d);
         }
+        ops.push_back(d);
     }
-    pad16(tp.data);
+    pad16(data);
+}
+
+// Programs of all sweep steps (built in parallel), concatenated.
+void build_tile_program(const std::vector<qs::PlanStep> &steps, TileProgram &tp)
+{
+    const size_t ns = steps.size();
+    std::vector<std::vector<qs::TileOpDev>> pops(ns);
+    std::vector<std::vector<uint16_t>> pdata(ns);
+    parallel_for(ns, [&](size_t i) {
+        if (steps[i].sweep) build_sweep_program(steps[i].sw, pops[i], pdata[i]);
+    });
+    std::vector<size_t> dpos(ns);
+    size_t nops = 0, ndata = 0;
+    for (size_t i = 0; i < ns; ++i) {
+        tp.first.push_back(nops);
+        dpos[i] = ndata;
+        nops += pops[i].size();
+        ndata += pdata[i].size();
+    }
+    tp.ops.resize(nops);
+    tp.data.resize(ndata);
+    parallel_for(ns, [&](size_t i) {
+        const uint32_t base = uint32_t(dpos[i] / 8);
+        for (size_t j = 0; j < pops[i].size(); ++j) {
+            qs::TileOpDev d = pops[i][j];
+            d.data_off += base;
+            tp.ops[tp.first[i] + j] = d;
+        }
+        if (!pdata[i].empty()) std::memcpy(tp.data.data() + dpos[i], pdata[i].data(), pdata[i].size() * sizeof(uint16_t));
+    });
     if (tp.data.empty()) tp.data.resize(8, 0);
     if (tp.ops.empty()) tp.ops.resize(1);
 }
@@ -547,9 +652,9 @@ qs::TileArgs make_tile_args(const qs::Sweep &sw, int n)
     }
     uint64_t qm = 0;
     for (int q : Q) qm |= uint64_t(1) << q;
-    ta.nouter = 0;
-    for (int q = 0; q < n; ++q)
-        if (!(qm >> q & 1)) ta.outer[ta.nouter++] = uint8_t(q);
+    const uint64_t all = (n >= 64) ? ~uint64_t(0) : ((uint64_t(1) << n) - 1);
+    ta.omask = all & ~qm;
+    ta.nouter = __builtin_popcountll(ta.omask);
     return ta;
 }
 
@@ -1091,20 +1196,28 @@ struct Batch {
     }
 };
 
+// Trajectory gate lists are planned once per batch round and never reused:
+// four-qubit blocks and few outer selector bits keep their block matrices
+// and operand programs small (the states are small too).
+constexpr int kTrajKmax = 4;
+constexpr int kTrajMaxOuter = 2;
+
 // Apply a gate list to every listed trajectory: tiled complex64 plans run as
 // batched sweep rounds, everything else through the per-gate kernels.
 qs_status batch_gates(Batch &B, const std::vector<int> &who, std::vector<std::vector<qs::FlatOp>> &lists)
 {
     std::vector<std::vector<qs::PlanStep>> plans(who.size());
-    size_t rounds = 0;
-    for (size_t i = 0; i < who.size(); ++i) {
+    parallel_for(who.size(), [&](size_t i) {
         const int n = B.prep[who[i]].n;
         auto &fl = lists[i];
-        if (fl.empty()) continue;
+        if (fl.empty()) return;
         if (B.dt == QS_C64 && n >= 10) {
             qs_run_opts o{};
             o.plan = QS_PLAN_GREEDY;
-            qs::plan_tiles(fl, 0, fl.size(), n, tile_params(n, o), plans[i]);
+            qs::TileParams tp = tile_params(n, o);
+            tp.kmax = kTrajKmax;
+            tp.max_outer = kTrajMaxOuter;
+            qs::plan_tiles(fl, 0, fl.size(), n, tp, plans[i]);
         } else {
             for (auto &f : fl) {
                 qs::PlanStep st;
@@ -1114,8 +1227,9 @@ qs_status batch_gates(Batch &B, const std::vector<int> &who, std::vector<std::ve
                 if (st.gate.kind != qs::CanonGate::IDENTITY) plans[i].push_back(std::move(st));
             }
         }
-        rounds = std::max(rounds, plans[i].size());
-    }
+    });
+    size_t rounds = 0;
+    for (auto &pl : plans) rounds = std::max(rounds, pl.size());
     // flatten in (round, trajectory) order and build one device program
     std::vector<qs::PlanStep> all;
     struct Ref { size_t round; size_t who; };

@@ -35,17 +35,6 @@ typedef float vf4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
 
-__device__ __forceinline__ uint32_t insert_zero_bits(uint32_t t, const int *pos, int np)
-{
-    for (int b = 0; b < np; ++b) {
-        const uint32_t lo = t & ((1u << pos[b]) - 1u);
-        t = ((t ^ lo) << 1) | lo;
-    }
-    return t;
-}
-
-constexpr int kMaxM = 13;
-
 typedef float v2f __attribute__((ext_vector_type(2)));
 typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
 
@@ -57,39 +46,55 @@ __device__ __forceinline__ void split2(float a, float b, v2bf &hi, v2bf &lo)
     lo = __builtin_convertvector(v2f{a - float(hi[0]), b - float(hi[1])}, v2bf);
 }
 
-// LDS layout of a tile: amplitude j lives at j ^ ((j >> 5) & 31).  Blocks on
-// the low tile qubits make the 16 groups of a matrix-core operand differ
-// only in high index bits; the XOR spreads those accesses over the banks.
-__device__ __forceinline__ uint32_t sw(uint32_t j) { return j ^ ((j >> 5) & 31u); }
+// LDS layout of a tile: amplitude j lives at j ^ ((j >> 5) & 31) ^ (j >> 10)
+// (j < 2^13).  LDS banks see the 8-byte slot index mod 32, so tile bit p
+// lands on bank bit p mod 5: a 32-lane read is conflict-free when its five
+// lane bits sit on tile bits of distinct residues mod 5, and a 16-lane write
+// when its four do.  The host picks each op's column bits and its lane
+// qubit (lpos[1]) that way.
+__device__ __forceinline__ uint32_t sw(uint32_t j) { return j ^ ((j >> 5) & 31u) ^ (j >> 10); }
 
-// Four-qubit blocks in real form: A is the 32 x 32 real matrix
-// [[Re U, -Im U], [Im U, Re U]] (entry by entry, re/im interleaved); fragment
-// (mt, 0) of lane l holds A[16 mt + l % 16][8 (l / 16) + j].  Each wave takes
-// two column tiles at a time so that four accumulators interleave.
-__device__ void dense_op4(float2 *tile, const TileOpDev &op, const uint4 *data, int m, int outer)
+// Scatter the low bits of x onto the set bits of mask (ascending).
+__device__ __forceinline__ uint32_t deposit32(uint32_t x, uint32_t mask)
 {
-    constexpr int K = 4;
+    uint32_t r = 0;
+    for (uint32_t mm = mask; mm; mm &= mm - 1, x >>= 1)
+        if (x & 1) r |= mm & (~mm + 1);
+    return r;
+}
+
+// Dense k-qubit block (k = 4, 5) in real form: with D = 2^k, A is the
+// 2D x 2D real matrix [[Re U, -Im U], [Im U, Re U]] (entry by entry, re / im
+// interleaved) and a group of the tile is one column of X, so the re and im
+// parts of an output amplitude come out in adjacent accumulator registers.
+// Fragment (mt, s) of lane l holds A[16 mt + l % 16][32 s + 8 (l / 16) + j],
+// j < 8 (hi parts of all fragments, then the remainders).  `fr` points at the
+// fragments of this tile's outer pattern (global memory or LDS); NW waves
+// share the column tiles.
+//
+// Column c of a matrix-core tile sits on the 4 tile bits of op.colmask; the
+// column tile index on the other bits outside the op (blockmask).  A wave
+// walks its column tiles in Gray-code order, so the uniform part of the LDS
+// address changes by one precomputed XOR per step.
+template <int K, int NW>
+__device__ __forceinline__ void dense_op(float2 *tile, const TileOpDev &op, const bf16x8 *fr, int m)
+{
+    constexpr int D = 1 << K, MT = 2 * D / 16, KS = 2 * D / 32;
+    constexpr int H = K == 4 ? 2 : 1;  // column tiles per step: at least 4 accumulator chains
+    constexpr int LB = (H == 2 ? 1 : 0) + (NW == 8 ? 3 : NW == 4 ? 2 : NW == 2 ? 1 : 0);
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-    const bf16x8 *fr =
-        reinterpret_cast<const bf16x8 *>(data + op.data_off + uint32_t(outer) * op.frag_stride);
-    bf16x8 ahi[2], alo[2];
+    bf16x8 ahi[MT][KS], alo[MT][KS];
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt) {
-        ahi[mt] = fr[mt * 64 + lane];
-        alo[mt] = fr[2 * 64 + mt * 64 + lane];
-    }
-    int srt[K];
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int b = 0; b < K; ++b) srt[b] = op.lpos[b];
+        for (int s = 0; s < KS; ++s) {
+            ahi[mt][s] = fr[(mt * KS + s) * 64 + lane];
+            alo[mt][s] = fr[MT * KS * 64 + (mt * KS + s) * 64 + lane];
+        }
+    uint32_t opm = 0;
 #pragma unroll
-    for (int i = 1; i < K; ++i)
-#pragma unroll
-        for (int j = K - 1; j >= i; --j)
-            if (srt[j - 1] > srt[j]) {
-                const int t = srt[j];
-                srt[j] = srt[j - 1];
-                srt[j - 1] = t;
-            }
+    for (int b = 0; b < K; ++b) opm |= 1u << op.lpos[b];
+    const uint32_t blockmask = ((1u << m) - 1u) & ~opm & ~op.colmask;
     auto offset = [&](int x) {
         uint32_t o = 0;
 #pragma unroll
@@ -97,193 +102,105 @@ __device__ void dense_op4(float2 *tile, const TileOpDev &op, const uint4 *data, 
             if ((x >> (K - 1 - b)) & 1) o |= 1u << op.lpos[b];
         return o;
     };
-    const uint32_t gl = insert_zero_bits(uint32_t(lane & 15), srt, K);
-    uint32_t rd[4], wr[2][2];
+    // per-lane byte offsets: reads of amplitudes 16 s + 4 (l / 16) + jj,
+    // writes of amplitudes 8 mt + 2 (l / 16) + jj
+    const uint32_t gl = deposit32(uint32_t(lane & 15), op.colmask);
+    uint32_t rd[KS][4], wr[MT][2];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) rd[j] = sw(gl | offset(4 * (lane >> 4) + j)) * 8u;
+    for (int s = 0; s < KS; ++s)
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
+        for (int jj = 0; jj < 4; ++jj) rd[s][jj] = sw(gl | offset(16 * s + 4 * (lane >> 4) + jj)) << 3;
 #pragma unroll
-        for (int j = 0; j < 2; ++j) wr[mt][j] = sw(gl | offset(8 * mt + 2 * (lane >> 4) + j)) * 8u;
-    char *tb = reinterpret_cast<char *>(tile);
-    const int ntiles = 1 << (m - K - 4);
-    constexpr int kWaves = kThreads / 64;
-    for (int nt0 = 2 * wave; nt0 < ntiles; nt0 += 2 * kWaves) {
-        uint32_t gt[2];
-        bf16x8 bhi[2], blo[2];
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            gt[h] = sw(insert_zero_bits(uint32_t(nt0 + h) * 16u, srt, K)) * 8u;  // uniform
-            float2 v[4];
+        for (int jj = 0; jj < 2; ++jj) wr[mt][jj] = sw(gl | offset(8 * mt + 2 * (lane >> 4) + jj)) << 3;
+    // XOR images of the column-tile bits (uniform; at most 5 bits for
+    // m <= 13, so a wave takes at most 4 steps)
+    uint32_t img[LB + 2];
+    {
+        uint32_t mm = blockmask;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) v[j] = *reinterpret_cast<const float2 *>(tb + (rd[j] ^ gt[h]));
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                v2bf hh, ll;
-                split2(v[j].x, v[j].y, hh, ll);
-                bhi[h][2 * j] = hh[0];
-                bhi[h][2 * j + 1] = hh[1];
-                blo[h][2 * j] = ll[0];
-                blo[h][2 * j + 1] = ll[1];
-            }
+        for (int t = 0; t < LB + 2; ++t) {
+            img[t] = mm ? sw(mm & (~mm + 1)) << 3 : 0u;
+            mm &= mm - 1;
         }
-        f32x4 acc[2][2];
+    }
+    const int ntiles = 1 << (m - K - 4);
+    uint32_t gw = 0;  // first column tile of this wave: index H * wave
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+    for (int b = 0; b < LB; ++b)
+        if (((H * wave) >> b) & 1) gw ^= img[b];
+    const int steps = ntiles > H * NW ? ntiles / (H * NW) : 1;
+    char *tb = reinterpret_cast<char *>(tile);
+    uint32_t gi = 0;
+    for (int g = 0; g < steps; ++g) {
+        if (g) gi ^= (g & 1) ? img[LB] : img[LB + 1];  // Gray code: bit 0 on odd steps, bit 1 on step 2
+        const int i = g ^ (g >> 1);
+        if (H * wave + i * H * NW >= ntiles) break;
+        uint32_t gt[H];
+        gt[0] = __builtin_amdgcn_readfirstlane(gw ^ gi);
+        if (H == 2) gt[H - 1] = gt[0] ^ img[0];
+        bf16x8 bhi[H][KS], blo[H][KS];
 #pragma unroll
-            for (int mt = 0; mt < 2; ++mt) acc[h][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int h = 0; h < H; ++h)
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
+            for (int s = 0; s < KS; ++s) {
+                float2 v[4];
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
-                acc[h][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[mt], bhi[h], acc[h][mt], 0, 0, 0);
+                for (int jj = 0; jj < 4; ++jj) v[jj] = *reinterpret_cast<const float2 *>(tb + (rd[s][jj] ^ gt[h]));
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
+                for (int jj = 0; jj < 4; ++jj) {
+                    v2bf hh, ll;
+                    split2(v[jj].x, v[jj].y, hh, ll);
+                    bhi[h][s][2 * jj] = hh[0];
+                    bhi[h][s][2 * jj + 1] = hh[1];
+                    blo[h][s][2 * jj] = ll[0];
+                    blo[h][s][2 * jj + 1] = ll[1];
+                }
+            }
+        f32x4 acc[H][MT];
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
-                acc[h][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[mt], blo[h], acc[h][mt], 0, 0, 0);
+        for (int h = 0; h < H; ++h)
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
+            for (int mt = 0; mt < MT; ++mt) acc[h][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        // hi * hi, hi * lo, lo * hi, each over the k-steps
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
-                acc[h][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[mt], bhi[h], acc[h][mt], 0, 0, 0);
+        for (int s = 0; s < KS; ++s)
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+            for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-            for (int mt = 0; mt < 2; ++mt) {
+                for (int h = 0; h < H; ++h)
+                    acc[h][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[mt][s], bhi[h][s], acc[h][mt], 0, 0, 0);
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int h = 0; h < H; ++h)
+                    acc[h][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[mt][s], blo[h][s], acc[h][mt], 0, 0, 0);
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int h = 0; h < H; ++h)
+                    acc[h][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[mt][s], bhi[h][s], acc[h][mt], 0, 0, 0);
+#pragma unroll
+        for (int h = 0; h < H; ++h)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
                 *reinterpret_cast<float2 *>(tb + (wr[mt][0] ^ gt[h])) = make_float2(acc[h][mt][0], acc[h][mt][1]);
                 *reinterpret_cast<float2 *>(tb + (wr[mt][1] ^ gt[h])) = make_float2(acc[h][mt][2], acc[h][mt][3]);
             }
     }
 }
 
-// Five-qubit blocks in split form: with Ur = Re U and Ui = Im U (32 x 32
-// each) and the re / im parts of a group as separate columns,
-//   Yr = Ur Xr - Ui Xi,   Yi = Ui Xr + Ur Xi,
-// which needs half the operand registers of the real form at the same
-// number of matrix-core products.  Fragment order: Ur row tiles 0, 1, Ui row
-// tiles 0, 1 (hi), then the same four (lo).
-__device__ void dense_op5(float2 *tile, const TileOpDev &op, const uint4 *data, int m, int outer)
-{
-    constexpr int K = 5;
-    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-    const bf16x8 *fr =
-        reinterpret_cast<const bf16x8 *>(data + op.data_off + uint32_t(outer) * op.frag_stride);
-    // fragments: Ur, Ui, -Ui row tiles (hi), then the same (lo)
-    bf16x8 urh[2], uih[2], nuih[2], url[2], uil[2], nuil[2];
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt) {
-        urh[mt] = fr[(0 + mt) * 64 + lane];
-        uih[mt] = fr[(2 + mt) * 64 + lane];
-        nuih[mt] = fr[(4 + mt) * 64 + lane];
-        url[mt] = fr[(6 + mt) * 64 + lane];
-        uil[mt] = fr[(8 + mt) * 64 + lane];
-        nuil[mt] = fr[(10 + mt) * 64 + lane];
-    }
-    int srt[K];
-#pragma unroll
-    for (int b = 0; b < K; ++b) srt[b] = op.lpos[b];
-#pragma unroll
-    for (int i = 1; i < K; ++i)
-#pragma unroll
-        for (int j = K - 1; j >= i; --j)
-            if (srt[j - 1] > srt[j]) {
-                const int t = srt[j];
-                srt[j] = srt[j - 1];
-                srt[j - 1] = t;
-            }
-    auto offset = [&](int x) {
-        uint32_t o = 0;
-#pragma unroll
-        for (int b = 0; b < K; ++b)
-            if ((x >> (K - 1 - b)) & 1) o |= 1u << op.lpos[b];
-        return o;
-    };
-    // The group base and the LDS swizzle are linear over disjoint bits, so an
-    // address is (per-lane part) ^ (per-column-tile part): precompute the
-    // per-lane byte offsets once.
-    const uint32_t gl = insert_zero_bits(uint32_t(lane & 15), srt, K);
-    uint32_t rd[8], wr[2][4];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) rd[j] = sw(gl | offset(8 * (lane >> 4) + j)) * 8u;
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) wr[mt][j] = sw(gl | offset(16 * mt + 4 * (lane >> 4) + j)) * 8u;
-    char *tb = reinterpret_cast<char *>(tile);
-    const int ntiles = 1 << (m - K - 4);
-    constexpr int kWaves = kThreads / 64;
-    for (int nt = wave; nt < ntiles; nt += kWaves) {
-        const uint32_t gt = sw(insert_zero_bits(uint32_t(nt) * 16u, srt, K)) * 8u;  // uniform
-        float2 v[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = *reinterpret_cast<const float2 *>(tb + (rd[j] ^ gt));
-        bf16x8 xrh, xrl, xih, xil;
-#pragma unroll
-        for (int j = 0; j < 8; j += 2) {
-            v2bf h, l;
-            split2(v[j].x, v[j + 1].x, h, l);
-            xrh[j] = h[0];
-            xrh[j + 1] = h[1];
-            xrl[j] = l[0];
-            xrl[j + 1] = l[1];
-            split2(v[j].y, v[j + 1].y, h, l);
-            xih[j] = h[0];
-            xih[j + 1] = h[1];
-            xil[j] = l[0];
-            xil[j + 1] = l[1];
-        }
-        f32x4 ar[2], ai[2];
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt) {
-            ar[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-            ai[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-        }
-        // Yr = Ur Xr - Ui Xi, Yi = Ui Xr + Ur Xi; hi*hi + hi*lo + lo*hi each
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt) {
-            ar[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(urh[mt], xrh, ar[mt], 0, 0, 0);
-            ai[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(uih[mt], xrh, ai[mt], 0, 0, 0);
-        }
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt) {
-            ar[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nuih[mt], xih, ar[mt], 0, 0, 0);
-            ai[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(urh[mt], xih, ai[mt], 0, 0, 0);
-        }
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt) {
-            ar[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(urh[mt], xrl, ar[mt], 0, 0, 0);
-            ai[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(uih[mt], xrl, ai[mt], 0, 0, 0);
-        }
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt) {
-            ar[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nuih[mt], xil, ar[mt], 0, 0, 0);
-            ai[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(urh[mt], xil, ai[mt], 0, 0, 0);
-        }
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt) {
-            ar[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(url[mt], xrh, ar[mt], 0, 0, 0);
-            ai[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(uil[mt], xrh, ai[mt], 0, 0, 0);
-        }
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt) {
-            ar[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nuil[mt], xih, ar[mt], 0, 0, 0);
-            ai[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(url[mt], xih, ai[mt], 0, 0, 0);
-        }
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                *reinterpret_cast<float2 *>(tb + (wr[mt][j] ^ gt)) = make_float2(ar[mt][j], ai[mt][j]);
-    }
-}
-
 __device__ void phase_op(float2 *tile, float2 *ptab, const TileOpDev &op, const uint4 *data,
                          int outer, int m)
 {
-    const float2 *tab = reinterpret_cast<const float2 *>(data + op.data_off);
+    const float2 *tab = reinterpret_cast<const float2 *>(data + op.data_off + uint32_t(outer) * op.frag_stride);
     const int D = 1 << op.k;
-    if (int(threadIdx.x) < D) ptab[threadIdx.x] = tab[(outer << op.k) | threadIdx.x];
+    if (int(threadIdx.x) < D) ptab[threadIdx.x] = tab[threadIdx.x];
     __syncthreads();
     int active = 0;
     for (int x = 0; x < D; ++x)
@@ -309,6 +226,27 @@ __device__ void phase_op(float2 *tile, float2 *ptab, const TileOpDev &op, const 
     }
 }
 
+// Scatter the low bits of x onto the set bits of mask (ascending).
+__device__ __forceinline__ uint64_t deposit_bits(uint64_t x, uint64_t mask)
+{
+    uint64_t r = 0;
+    for (uint64_t mm = mask; mm; mm &= mm - 1, x >>= 1)
+        if (x & 1) r |= mm & (~mm + 1);
+    return r;
+}
+
+__device__ __forceinline__ uint64_t tile_base(uint64_t t, const TileArgs &ta) { return deposit_bits(t, ta.omask); }
+
+// Outer pattern of an op on the tile at `base` (opos[0] most significant).
+__device__ __forceinline__ int op_pattern(const TileOpDev &op, uint64_t base)
+{
+    int outer = 0;
+#pragma unroll
+    for (int b = 0; b < 5; ++b)
+        if (b < op.no) outer = (outer << 1) | int((base >> op.opos[b]) & 1);
+    return outer;
+}
+
 // One tile: load, apply ops, store.  `toff` is this thread's offset within
 // a tile (local index 2 * tid spread over the tile qubits).
 template <int M>
@@ -318,9 +256,7 @@ __device__ __forceinline__ void tile_pass(float2 *amp, uint64_t t, const TileArg
 {
     constexpr int PER = (1 << M) / (2 * kThreads);  // 16-byte slots (2 amplitudes) per thread
     // tile base: the tile index spread over the bits outside the tile
-    uint64_t base = 0;
-    for (int b = 0; b < ta.nouter; ++b)
-        if ((t >> b) & 1) base |= uint64_t(1) << ta.outer[b];
+    const uint64_t base = tile_base(t, ta);
     // ---- load (non-temporal: every amplitude is read once per sweep)
     vf4 buf[PER];
 #pragma unroll
@@ -336,16 +272,15 @@ __device__ __forceinline__ void tile_pass(float2 *amp, uint64_t t, const TileArg
     // ---- ops
     for (int oi = 0; oi < ta.nops; ++oi) {
         const TileOpDev op = ops[oi];
-        int outer = 0;
-#pragma unroll
-        for (int b = 0; b < 5; ++b)
-            if (b < op.no) outer = (outer << 1) | int((base >> op.opos[b]) & 1);
+        const int outer = op_pattern(op, base);
         if (op.kind == 0) {
             if ((op.skip >> outer) & 1u) continue;  // identity on this tile
+            const bf16x8 *fr =
+                reinterpret_cast<const bf16x8 *>(data + op.data_off + uint32_t(outer) * op.frag_stride);
             if (op.k == 4)
-                dense_op4(tile, op, data, M, outer);
+                dense_op<4, kThreads / 64>(tile, op, fr, M);
             else
-                dense_op5(tile, op, data, M, outer);
+                dense_op<5, kThreads / 64>(tile, op, fr, M);
         } else {
             phase_op(tile, ptab, op, data, outer, M);
         }
@@ -375,76 +310,54 @@ __device__ __forceinline__ uint64_t thread_offset(const TileArgs &ta)
 }
 
 template <int M>
-__global__ __launch_bounds__(kThreads) void k_tile(float2 *amp, uint64_t ntiles, TileArgs ta,
-                                                   const TileOpDev *ops, const uint4 *data)
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_tile(float2 *__restrict__ amp, uint64_t ntiles, TileArgs ta,
+                                                   const TileOpDev *__restrict__ ops, const uint4 *__restrict__ data)
 {
-    extern __shared__ float2 lds[];
-    float2 *ptab = lds + (size_t(1) << M);
+    __shared__ float2 lds[(1 << M) + 64];  // the tile, then a phase table
     const uint64_t toff = thread_offset(ta);
     for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x)
-        tile_pass<M>(amp, t, ta, toff, ops, data, lds, ptab);
+        tile_pass<M>(amp, t, ta, toff, ops, data, lds, lds + (1 << M));
 }
 
 // Batched form: workgroup b runs tile tasks[b].tile of the state described by
 // args[tasks[b].arg] (its own amplitudes, tile qubits and op list), so one
 // launch covers one sweep of many independent states.
 template <int M>
-__global__ __launch_bounds__(kThreads) void k_tile_multi(const TileTask *tasks, const TileArgsDev *args,
-                                                         const TileOpDev *ops, const uint4 *data)
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_tile_multi(const TileTask *__restrict__ tasks,
+                                                         const TileArgsDev *__restrict__ args,
+                                                         const TileOpDev *__restrict__ ops,
+                                                         const uint4 *__restrict__ data)
 {
-    extern __shared__ float2 lds[];
-    float2 *ptab = lds + (size_t(1) << M);
+    __shared__ float2 lds[(1 << M) + 64];
     const TileTask task = tasks[blockIdx.x];
     const TileArgsDev &ad = args[task.arg];
     const uint64_t toff = thread_offset(ad.ta);
-    tile_pass<M>(ad.amp, task.tile, ad.ta, toff, ops + ad.op_off, data, lds, ptab);
+    tile_pass<M>(ad.amp, task.tile, ad.ta, toff, ops + ad.op_off, data, lds, lds + (1 << M));
 }
 
 }  // namespace
 
-size_t tile_lds_bytes(int m) { return (size_t(8) << m) + 64 * sizeof(float2); }
-
-template <typename F>
-hipError_t set_lds_attr(F kernel)
-{
-    return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               int(tile_lds_bytes(13)));
-}
-
-hipError_t ensure_attrs()
-{
-    static bool done = false;
-    if (done) return hipSuccess;
-    hipError_t e = set_lds_attr(k_tile<13>);
-    if (e == hipSuccess) e = set_lds_attr(k_tile<12>);
-    if (e == hipSuccess) e = set_lds_attr(k_tile_multi<13>);
-    if (e == hipSuccess) e = set_lds_attr(k_tile_multi<12>);
-    if (e == hipSuccess) done = true;
-    return e;
-}
 
 hipError_t launch_tile(void *amp, int n, const TileArgs &ta, const TileOpDev *dev_ops,
                        const void *dev_data, hipStream_t st)
 {
     if (ta.m < 10 || ta.m > 13 || ta.m > n || ta.nouter != n - ta.m) return hipErrorInvalidValue;
-    const size_t lds = tile_lds_bytes(ta.m);
-    if (hipError_t e = ensure_attrs()) return e;
     const uint64_t ntiles = uint64_t(1) << (n - ta.m);
     const uint64_t grid = ntiles < (uint64_t(1) << 20) ? ntiles : (uint64_t(1) << 20);
     float2 *a = (float2 *)amp;
     const uint4 *d = (const uint4 *)dev_data;
     switch (ta.m) {
     case 10:
-        hipLaunchKernelGGL(k_tile<10>, dim3(unsigned(grid)), dim3(kThreads), lds, st, a, ntiles, ta, dev_ops, d);
+        hipLaunchKernelGGL(k_tile<10>, dim3(unsigned(grid)), dim3(kThreads), 0, st, a, ntiles, ta, dev_ops, d);
         break;
     case 11:
-        hipLaunchKernelGGL(k_tile<11>, dim3(unsigned(grid)), dim3(kThreads), lds, st, a, ntiles, ta, dev_ops, d);
+        hipLaunchKernelGGL(k_tile<11>, dim3(unsigned(grid)), dim3(kThreads), 0, st, a, ntiles, ta, dev_ops, d);
         break;
     case 12:
-        hipLaunchKernelGGL(k_tile<12>, dim3(unsigned(grid)), dim3(kThreads), lds, st, a, ntiles, ta, dev_ops, d);
+        hipLaunchKernelGGL(k_tile<12>, dim3(unsigned(grid)), dim3(kThreads), 0, st, a, ntiles, ta, dev_ops, d);
         break;
     default:
-        hipLaunchKernelGGL(k_tile<13>, dim3(unsigned(grid)), dim3(kThreads), lds, st, a, ntiles, ta, dev_ops, d);
+        hipLaunchKernelGGL(k_tile<13>, dim3(unsigned(grid)), dim3(kThreads), 0, st, a, ntiles, ta, dev_ops, d);
         break;
     }
     return hipGetLastError();
@@ -454,21 +367,19 @@ hipError_t launch_tile_multi(int m, uint32_t ntasks, const TileTask *tasks, cons
                              const TileOpDev *dev_ops, const void *dev_data, hipStream_t st)
 {
     if (m < 10 || m > 13 || ntasks == 0) return hipErrorInvalidValue;
-    const size_t lds = tile_lds_bytes(m);
-    if (hipError_t e = ensure_attrs()) return e;
     const uint4 *d = (const uint4 *)dev_data;
     switch (m) {
     case 10:
-        hipLaunchKernelGGL(k_tile_multi<10>, dim3(ntasks), dim3(kThreads), lds, st, tasks, args, dev_ops, d);
+        hipLaunchKernelGGL(k_tile_multi<10>, dim3(ntasks), dim3(kThreads), 0, st, tasks, args, dev_ops, d);
         break;
     case 11:
-        hipLaunchKernelGGL(k_tile_multi<11>, dim3(ntasks), dim3(kThreads), lds, st, tasks, args, dev_ops, d);
+        hipLaunchKernelGGL(k_tile_multi<11>, dim3(ntasks), dim3(kThreads), 0, st, tasks, args, dev_ops, d);
         break;
     case 12:
-        hipLaunchKernelGGL(k_tile_multi<12>, dim3(ntasks), dim3(kThreads), lds, st, tasks, args, dev_ops, d);
+        hipLaunchKernelGGL(k_tile_multi<12>, dim3(ntasks), dim3(kThreads), 0, st, tasks, args, dev_ops, d);
         break;
     default:
-        hipLaunchKernelGGL(k_tile_multi<13>, dim3(ntasks), dim3(kThreads), lds, st, tasks, args, dev_ops, d);
+        hipLaunchKernelGGL(k_tile_multi<13>, dim3(ntasks), dim3(kThreads), 0, st, tasks, args, dev_ops, d);
         break;
     }
     return hipGetLastError();

@@ -111,6 +111,8 @@ inline cd at(const std::vector<cd> &M, int d, int r, int c) { return M[size_t(r)
 
 // Apply a gate given on local bits to every column of the block matrix.
 // Local bit L of a block index corresponds to block qubit position L.
+// Complex products are written out (std::complex products go through the
+// C99 NaN-recovering multiply, which dominates planning time otherwise).
 void apply_local(std::vector<cd> &M, int k, const std::vector<int> &tbits,
                  const std::vector<int> &cbits, const std::vector<double> &m)
 {
@@ -120,25 +122,35 @@ void apply_local(std::vector<cd> &M, int k, const std::vector<int> &tbits,
     int tmask = 0, cmask = 0;
     for (int b : tbits) tmask |= 1 << b;
     for (int b : cbits) cmask |= 1 << b;
-    std::vector<int> off(g);
+    int off[64];
     for (int x = 0; x < g; ++x) {
         int o = 0;
         for (int b = 0; b < nt; ++b)
             if ((x >> (nt - 1 - b)) & 1) o |= 1 << tbits[b];
         off[x] = o;
     }
-    std::vector<cd> v(g), w(g);
-    for (int col = 0; col < D; ++col)
-        for (int i = 0; i < D; ++i) {
-            if ((i & tmask) || (i & cmask) != cmask) continue;
-            for (int x = 0; x < g; ++x) v[x] = M[size_t(i | off[x]) * D + col];
-            for (int r = 0; r < g; ++r) {
-                cd acc = 0;
-                for (int c = 0; c < g; ++c) acc += cd(m[2 * (r * g + c)], m[2 * (r * g + c) + 1]) * v[c];
-                w[r] = acc;
+    double v[128], w[128];
+    for (int i = 0; i < D; ++i) {
+        if ((i & tmask) || (i & cmask) != cmask) continue;
+        for (int col = 0; col < D; ++col) {
+            for (int x = 0; x < g; ++x) {
+                const cd a = M[size_t(i | off[x]) * D + col];
+                v[2 * x] = a.real();
+                v[2 * x + 1] = a.imag();
             }
-            for (int x = 0; x < g; ++x) M[size_t(i | off[x]) * D + col] = w[x];
+            for (int r = 0; r < g; ++r) {
+                double re = 0.0, im = 0.0;
+                const double *mr = m.data() + size_t(2) * r * g;
+                for (int c = 0; c < g; ++c) {
+                    re += mr[2 * c] * v[2 * c] - mr[2 * c + 1] * v[2 * c + 1];
+                    im += mr[2 * c] * v[2 * c + 1] + mr[2 * c + 1] * v[2 * c];
+                }
+                w[2 * r] = re;
+                w[2 * r + 1] = im;
+            }
+            for (int x = 0; x < g; ++x) M[size_t(i | off[x]) * D + col] = cd(w[2 * x], w[2 * x + 1]);
         }
+    }
 }
 
 struct Block {
@@ -395,57 +407,6 @@ std::vector<int> bits_desc(uint64_t m)
     return v;
 }
 
-// Matrix of a sequence of gates over the qubit list `qs` (qs[0] = MSB).
-std::vector<double> block_matrix(const std::vector<int> &qs, const std::vector<const GInfo *> &gates)
-{
-    const int k = int(qs.size());
-    const int D = 1 << k;
-    auto local = [&](int q) {
-        for (int i = 0; i < k; ++i)
-            if (qs[i] == q) return k - 1 - i;
-        return -1;
-    };
-    std::vector<cd> M(size_t(D) * D, cd(0));
-    for (int i = 0; i < D; ++i) M[size_t(i) * D + i] = 1;
-    for (const GInfo *g : gates) {
-        std::vector<int> tb, cb;
-        for (int q : g->c.targets) tb.push_back(local(q));
-        for (int q : g->c.controls) cb.push_back(local(q));
-        if (g->c.kind == CanonGate::PHASE) {
-            // diagonal: expand to a dense diagonal matrix on the targets
-            const int nt = int(g->c.targets.size());
-            const int d = 1 << nt;
-            std::vector<double> dm(size_t(2) * d * d, 0.0);
-            for (int x = 0; x < d; ++x) {
-                dm[2 * (x * d + x)] = g->c.m[2 * x];
-                dm[2 * (x * d + x) + 1] = g->c.m[2 * x + 1];
-            }
-            if (nt == 0) {
-                // scalar phase on the control pattern: a diagonal on the controls
-                std::vector<int> none;
-                std::vector<double> one = {g->c.m[0], g->c.m[1]};
-                // apply as a 1x1 "matrix": multiply the amplitudes whose control bits are set
-                int cm = 0;
-                for (int b : cb) cm |= 1 << b;
-                const cd f(one[0], one[1]);
-                for (int col = 0; col < D; ++col)
-                    for (int i = 0; i < D; ++i)
-                        if ((i & cm) == cm) M[size_t(i) * D + col] *= f;
-                continue;
-            }
-            apply_local(M, k, tb, cb, dm);
-        } else {
-            apply_local(M, k, tb, cb, g->c.m);
-        }
-    }
-    std::vector<double> out(size_t(2) * D * D);
-    for (int i = 0; i < D * D; ++i) {
-        out[2 * i] = M[i].real();
-        out[2 * i + 1] = M[i].imag();
-    }
-    return out;
-}
-
 bool is_diag_matrix(const std::vector<double> &m, int k)
 {
     const int D = 1 << k;
@@ -455,81 +416,189 @@ bool is_diag_matrix(const std::vector<double> &m, int k)
     return true;
 }
 
-// Diagonal factor of a canonical PHASE gate for a full assignment of the
-// qubits in `qs` (pattern bit (|qs|-1-b) = value of qs[b]).
-cd phase_factor(const CanonGate &g, const std::vector<int> &qs, int pattern)
-{
-    auto val = [&](int q) {
-        for (size_t b = 0; b < qs.size(); ++b)
-            if (qs[b] == q) return (pattern >> (qs.size() - 1 - b)) & 1;
-        return 0;
-    };
-    for (int c : g.controls)
-        if (!val(c)) return cd(1);
-    int x = 0;
-    for (int t : g.targets) x = (x << 1) | val(t);
-    return cd(g.m[2 * x], g.m[2 * x + 1]);
-}
-
 struct OpenBlock {
     uint64_t qmask = 0;  // qubits inside the tile
     uint64_t omask = 0;  // qubits outside the tile (constant per tile)
     std::vector<const GInfo *> gates;
-    size_t first = 0;
 };
 
-// Matrix over the tile qubits `qs` (qs[0] = MSB) of a gate sequence with the
-// outer qubits `os` fixed to `pattern` (bit |os|-1-b = value of os[b]).
-std::vector<double> block_matrix_outer(const std::vector<int> &qs, const std::vector<int> &os, int pattern,
-                                       const std::vector<const GInfo *> &gates)
+// A gate of a block in block-local terms.  Qubit sources are a local bit
+// (>= 0) or an outer selector slot s encoded as ~s.
+struct LocalGate {
+    bool diag = false;
+    int tmask = 0, cmask = 0;     // dense: local target / inner control masks
+    int g = 1;                    // dense: 2^targets
+    int off[64];                  // dense: local offset of target pattern x (targets[0] = MSB)
+    std::vector<int> octl;        // dense: outer slots that must be 1
+    std::vector<int> tsrc, csrc;  // diagonal: sources of the table index bits and of the controls
+    int reads = 0;                // outer slots the gate depends on (bit s)
+    const double *m = nullptr;    // dense matrix or diagonal table
+};
+
+// Left-multiply the block matrix M (D x D, row-major, interleaved complex)
+// by one block-local gate with the outer slots set to `oval`.
+void apply_local_gate(double *M, int D, const LocalGate &L, const int *oval)
 {
-    auto oval = [&](int q) {
-        for (size_t b = 0; b < os.size(); ++b)
-            if (os[b] == q) return (pattern >> (os.size() - 1 - b)) & 1;
-        return -1;
-    };
-    std::vector<GInfo> eff;
-    eff.reserve(gates.size());
-    for (const GInfo *g : gates) {
-        if (g->c.kind == CanonGate::DENSE) {
-            // outer qubits of a dense gate are controls: keep the gate only
-            // when they are all 1, with its inner controls
-            GInfo e = *g;
+    const size_t rs = size_t(2) * D;
+    if (L.diag) {
+        for (int i = 0; i < D; ++i) {
             bool on = true;
-            std::vector<int> cin;
-            for (int c : g->c.controls) {
-                const int v = oval(c);
-                if (v == 0) on = false;
-                if (v < 0) cin.push_back(c);
-            }
+            for (int s : L.csrc)
+                if (!(s >= 0 ? (i >> s) & 1 : oval[~s])) {
+                    on = false;
+                    break;
+                }
             if (!on) continue;
-            e.c.controls = cin;
-            eff.push_back(std::move(e));
+            int x = 0;
+            for (int s : L.tsrc) x = (x << 1) | (s >= 0 ? (i >> s) & 1 : oval[~s]);
+            const double fr = L.m[2 * x], fi = L.m[2 * x + 1];
+            if (fr == 1.0 && fi == 0.0) continue;
+            double *row = M + rs * i;
+            for (int c = 0; c < D; ++c) {
+                const double a = row[2 * c], b = row[2 * c + 1];
+                row[2 * c] = a * fr - b * fi;
+                row[2 * c + 1] = a * fi + b * fr;
+            }
+        }
+        return;
+    }
+    for (int s : L.octl)
+        if (!oval[s]) return;
+    const double *m = L.m;
+    if (L.g == 2) {
+        const double m00r = m[0], m00i = m[1], m01r = m[2], m01i = m[3];
+        const double m10r = m[4], m10i = m[5], m11r = m[6], m11i = m[7];
+        for (int i = 0; i < D; ++i) {
+            if ((i & L.tmask) || (i & L.cmask) != L.cmask) continue;
+            double *a = M + rs * i, *b = M + rs * (i | L.off[1]);
+            for (int c = 0; c < D; ++c) {
+                const double ar = a[2 * c], ai = a[2 * c + 1], br = b[2 * c], bi = b[2 * c + 1];
+                a[2 * c] = m00r * ar - m00i * ai + m01r * br - m01i * bi;
+                a[2 * c + 1] = m00r * ai + m00i * ar + m01r * bi + m01i * br;
+                b[2 * c] = m10r * ar - m10i * ai + m11r * br - m11i * bi;
+                b[2 * c + 1] = m10r * ai + m10i * ar + m11r * bi + m11i * br;
+            }
+        }
+        return;
+    }
+    double v[128], w[128];
+    for (int i = 0; i < D; ++i) {
+        if ((i & L.tmask) || (i & L.cmask) != L.cmask) continue;
+        for (int col = 0; col < D; ++col) {
+            for (int x = 0; x < L.g; ++x) {
+                const double *a = M + rs * (i | L.off[x]) + 2 * col;
+                v[2 * x] = a[0];
+                v[2 * x + 1] = a[1];
+            }
+            for (int r = 0; r < L.g; ++r) {
+                double re = 0.0, im = 0.0;
+                const double *mr = m + size_t(2) * r * L.g;
+                for (int c = 0; c < L.g; ++c) {
+                    re += mr[2 * c] * v[2 * c] - mr[2 * c + 1] * v[2 * c + 1];
+                    im += mr[2 * c] * v[2 * c + 1] + mr[2 * c + 1] * v[2 * c];
+                }
+                w[2 * r] = re;
+                w[2 * r + 1] = im;
+            }
+            for (int x = 0; x < L.g; ++x) {
+                double *a = M + rs * (i | L.off[x]) + 2 * col;
+                a[0] = w[2 * x];
+                a[1] = w[2 * x + 1];
+            }
+        }
+    }
+}
+
+// Block matrices over the tile qubits `qs` (qs[0] = MSB) for every assignment
+// p of the outer qubits `os` (bit |os|-1-b of p = value of os[b]):
+// mats[which[p]] is the matrix of pattern p.
+void block_matrices(const std::vector<int> &qs, const std::vector<int> &os,
+                    const std::vector<const GInfo *> &gates, std::vector<std::vector<double>> &mats,
+                    std::vector<int> &which)
+{
+    const int k = int(qs.size()), D = 1 << k, no = int(os.size()), P = 1 << no;
+    int lbit[64], oslot[64];
+    for (int q = 0; q < 64; ++q) lbit[q] = oslot[q] = -1;
+    for (int i = 0; i < k; ++i) lbit[qs[i]] = k - 1 - i;
+    for (int b = 0; b < no; ++b) oslot[os[b]] = b;
+    auto src = [&](int q) { return lbit[q] >= 0 ? lbit[q] : ~oslot[q]; };
+    std::vector<LocalGate> lg(gates.size());
+    for (size_t j = 0; j < gates.size(); ++j) {
+        const CanonGate &c = gates[j]->c;
+        LocalGate &L = lg[j];
+        L.m = c.m.data();
+        if (c.kind == CanonGate::PHASE) {
+            L.diag = true;
+            for (int q : c.targets) L.tsrc.push_back(src(q));
+            for (int q : c.controls) L.csrc.push_back(src(q));
+            for (int s : L.tsrc)
+                if (s < 0) L.reads |= 1 << ~s;
+            for (int s : L.csrc)
+                if (s < 0) L.reads |= 1 << ~s;
             continue;
         }
-        // diagonal: restrict the table to the inner qubits
-        std::vector<int> inner;
-        for (int q : g->c.targets)
-            if (oval(q) < 0) inner.push_back(q);
-        for (int q : g->c.controls)
-            if (oval(q) < 0) inner.push_back(q);
-        std::vector<int> all = os;
-        all.insert(all.end(), inner.begin(), inner.end());
-        GInfo e;
-        e.c.kind = CanonGate::PHASE;
-        e.c.targets = inner;
-        const int D = 1 << inner.size();
-        e.c.m.resize(size_t(2) * D);
-        for (int x = 0; x < D; ++x) {
-            const cd f = phase_factor(g->c, all, (pattern << inner.size()) | x);
-            e.c.m[2 * x] = f.real();
-            e.c.m[2 * x + 1] = f.imag();
+        const int nt = int(c.targets.size());
+        L.g = 1 << nt;
+        for (int q : c.targets) L.tmask |= 1 << lbit[q];
+        for (int x = 0; x < L.g; ++x) {
+            int o = 0;
+            for (int b = 0; b < nt; ++b)
+                if ((x >> (nt - 1 - b)) & 1) o |= 1 << lbit[c.targets[b]];
+            L.off[x] = o;
         }
-        eff.push_back(std::move(e));
+        for (int q : c.controls) {
+            if (lbit[q] >= 0) {
+                L.cmask |= 1 << lbit[q];
+            } else {
+                L.octl.push_back(oslot[q]);
+                L.reads |= 1 << oslot[q];
+            }
+        }
     }
-    std::vector<const GInfo *> ptrs;
-    for (auto &e : eff) ptrs.push_back(&e);
-    return block_matrix(qs, ptrs);
+    // Gates run in order on a list of partial products, one per assignment
+    // of the outer bits read so far; a gate that reads a new outer bit first
+    // splits every entry of the list.  Patterns differing only in bits no
+    // gate reads share a product.
+    struct Live {
+        int vals;  // values of the assigned outer slots (bit s)
+        std::vector<double> M;
+    };
+    std::vector<Live> live(1);
+    live[0].vals = 0;
+    live[0].M.assign(size_t(2) * D * D, 0.0);
+    for (int i = 0; i < D; ++i) live[0].M[2 * (size_t(i) * D + i)] = 1.0;
+    int assigned = 0;
+    int oval[64];
+    for (const LocalGate &L : lg) {
+        const int fresh = L.reads & ~assigned;
+        for (int b = 0; b < no; ++b) {
+            if (!(fresh >> b & 1)) continue;
+            const size_t cnt = live.size();
+            for (size_t u = 0; u < cnt; ++u) {
+                Live one = live[u];
+                one.vals |= 1 << b;
+                live.push_back(std::move(one));
+            }
+        }
+        assigned |= fresh;
+        for (Live &e : live) {
+            for (int b = 0; b < no; ++b) oval[b] = e.vals >> b & 1;
+            apply_local_gate(e.M.data(), D, L, oval);
+        }
+    }
+    mats.clear();
+    which.assign(P, 0);
+    for (int p = 0; p < P; ++p) {
+        int v = 0;
+        for (int b = 0; b < no; ++b) v |= ((p >> (no - 1 - b)) & 1) << b;
+        v &= assigned;
+        for (size_t u = 0; u < live.size(); ++u)
+            if (live[u].vals == v) {
+                which[p] = int(u);
+                break;
+            }
+    }
+    for (Live &e : live) mats.push_back(std::move(e.M));
 }
 
 }  // namespace
@@ -540,6 +609,7 @@ void plan_tiles(const std::vector<FlatOp> &flat, size_t k0, size_t e, int n, con
     const int m = std::min(tp.m, n);
     const int L = std::min(tp.L, m);
     const int kmax = std::min(tp.kmax, m);
+    const int mo = std::max(0, std::min(tp.max_outer, kMaxOuter));
     std::vector<GInfo> info;
     info.reserve(e - k0);
     for (size_t i = k0; i < e; ++i) {
@@ -561,8 +631,8 @@ void plan_tiles(const std::vector<FlatOp> &flat, size_t k0, size_t e, int n, con
         // a gate can live in a tile when its qubits inside any Q are few
         // enough: dense gates need all targets in Q and at most kmax local
         // qubits; diagonal gates at most 3 local and 3 outer qubits (table)
-        if (g.diag) return __builtin_popcountll(g.qmask) <= kmax + kMaxOuter;
-        return __builtin_popcountll(g.tmask) <= kmax && __builtin_popcountll(g.cmask) <= kmax + kMaxOuter;
+        if (g.diag) return __builtin_popcountll(g.qmask) <= kmax + mo;
+        return __builtin_popcountll(g.tmask) <= kmax && __builtin_popcountll(g.cmask) <= kmax + mo;
     };
     while (!remaining.empty()) {
         // ---- choose Q and the gates this sweep applies
@@ -577,6 +647,11 @@ void plan_tiles(const std::vector<FlatOp> &flat, size_t k0, size_t e, int n, con
                 continue;
             }
             if (g.diag) {
+                // at most `mo` of its qubits may stay outside the tile
+                int extra = __builtin_popcountll(g.qmask & ~Q) - mo;
+                if (extra > 0 && __builtin_popcountll(Q) + extra <= m) {
+                    for (uint64_t r = g.qmask & ~Q; extra > 0; r &= r - 1, --extra) Q |= r & (~r + 1);
+                }
                 applied.push_back(gi);
                 continue;
             }
@@ -599,7 +674,7 @@ void plan_tiles(const std::vector<FlatOp> &flat, size_t k0, size_t e, int n, con
             continue;
         }
         for (int q = 0; q < n && __builtin_popcountll(Q) < m; ++q) Q |= uint64_t(1) << q;
-        // diagonal gates with more than 3 qubits inside or outside the final Q
+        // gates with more than kmax qubits inside or `mo` outside the final Q
         // are left for a later step
         {
             std::vector<size_t> keep;
@@ -608,7 +683,7 @@ void plan_tiles(const std::vector<FlatOp> &flat, size_t k0, size_t e, int n, con
             for (size_t gi : applied) {
                 const GInfo &g = info[gi];
                 const bool bad = __builtin_popcountll(g.qmask & Q) > kmax ||
-                                 __builtin_popcountll(g.qmask & ~Q) > kMaxOuter;
+                                 __builtin_popcountll(g.qmask & ~Q) > mo;
                 if (bad || (g.qmask & blk)) {
                     later.push_back(gi);
                     blk |= g.qmask;
@@ -625,37 +700,48 @@ void plan_tiles(const std::vector<FlatOp> &flat, size_t k0, size_t e, int n, con
                 applied.swap(keep);
             }
         }
+        if (applied.empty()) {
+            // nothing left for this tile: the first gate goes on its own
+            PlanStep st;
+            st.sweep = false;
+            st.gate = info[remaining[0]].c;
+            out.push_back(std::move(st));
+            remaining.erase(remaining.begin());
+            continue;
+        }
         // ---- fuse the applied gates into tile ops
         Sweep sw;
         for (int q = 0; q < 64; ++q)
             if (Q >> q & 1) sw.Q.push_back(q);
         sw.gates = int(applied.size());
-        std::vector<std::unique_ptr<OpenBlock>> open;
-        size_t serial = 0;
+        std::vector<std::vector<double>> mats;
+        std::vector<int> which;
         auto emit_block = [&](OpenBlock &b) {
             const std::vector<int> os = bits_desc(b.omask);
             const int P = 1 << os.size();
-            std::vector<int> qs = bits_desc(b.qmask);
-            std::vector<std::vector<double>> mats(P);
-            bool all_diag = true;
-            for (int p = 0; p < P; ++p) {
-                mats[p] = block_matrix_outer(qs, os, p, b.gates);
-                all_diag = all_diag && is_diag_matrix(mats[p], int(qs.size()));
-            }
+            const std::vector<int> qs = bits_desc(b.qmask);
             TileOp op;
             op.outer = os;
-            if (all_diag && qs.size() <= 3) {
-                op.kind = TileOp::PHASE;
-                op.qubits = qs;
-                const int D = 1 << qs.size();
-                op.m.resize(size_t(2) * D * P);
-                for (int p = 0; p < P; ++p)
-                    for (int x = 0; x < D; ++x) {
-                        op.m[2 * (p * D + x)] = mats[p][2 * (x * D + x)];
-                        op.m[2 * (p * D + x) + 1] = mats[p][2 * (x * D + x) + 1];
+            if (qs.size() <= 3) {
+                // narrow blocks that are diagonal for every outer pattern
+                block_matrices(qs, os, b.gates, mats, which);
+                bool all_diag = true;
+                for (auto &mm : mats) all_diag = all_diag && is_diag_matrix(mm, int(qs.size()));
+                if (all_diag) {
+                    op.kind = TileOp::PHASE;
+                    op.qubits = qs;
+                    const int D = 1 << qs.size();
+                    op.m.resize(size_t(2) * D * P);
+                    for (int p = 0; p < P; ++p) {
+                        const std::vector<double> &mp = mats[which[p]];
+                        for (int x = 0; x < D; ++x) {
+                            op.m[2 * (p * D + x)] = mp[2 * (x * D + x)];
+                            op.m[2 * (p * D + x) + 1] = mp[2 * (x * D + x) + 1];
+                        }
                     }
-                sw.ops.push_back(std::move(op));
-                return;
+                    sw.ops.push_back(std::move(op));
+                    return;
+                }
             }
             uint64_t pm = b.qmask;
             // widen narrow blocks to the 4-qubit matrix-core shape with
@@ -667,26 +753,27 @@ void plan_tiles(const std::vector<FlatOp> &flat, size_t k0, size_t e, int n, con
             op.kind = TileOp::DENSE;
             op.qubits = bits_desc(pm);
             const int k = int(op.qubits.size());
+            block_matrices(op.qubits, os, b.gates, mats, which);
+            std::vector<char> ident(mats.size());
+            for (size_t u = 0; u < mats.size(); ++u) {
+                ident[u] = is_identity(mats[u], k);
+                op.m.insert(op.m.end(), mats[u].begin(), mats[u].end());
+            }
+            op.pmap.resize(P);
             for (int p = 0; p < P; ++p) {
-                std::vector<double> mp = (pm == b.qmask) ? std::move(mats[p])
-                                                         : block_matrix_outer(op.qubits, os, p, b.gates);
-                if (is_identity(mp, k)) op.skip |= 1u << p;
-                op.m.insert(op.m.end(), mp.begin(), mp.end());
+                op.pmap[p] = uint8_t(which[p]);
+                if (ident[which[p]]) op.skip |= 1u << p;
             }
             sw.ops.push_back(std::move(op));
-        };
-        auto by_first = [](const std::unique_ptr<OpenBlock> &a, const std::unique_ptr<OpenBlock> &b) {
-            return a->first < b->first;
         };
         // Blocks by a light-cone scan: open a block at the first remaining
         // gate and absorb, in circuit order, every later gate whose tile
         // qubits keep the block within kmax (and its outer selectors within
-        // 3), skipping gates that touch a qubit of an earlier skipped gate.
+        // max_outer), skipping gates that touch a qubit of an earlier skipped
+        // gate.
         // Skipped gates do not precede absorbed ones on a shared tile qubit,
         // and outer qubits are constant over the sweep, so the absorbed
         // gates may run first.
-        (void)by_first;
-        (void)serial;
         std::vector<size_t> rem = applied;
         while (!rem.empty()) {
             OpenBlock blk;
@@ -701,7 +788,7 @@ void plan_tiles(const std::vector<FlatOp> &flat, size_t k0, size_t e, int n, con
                     continue;
                 }
                 const uint64_t uni = blk.qmask | loc, ouni = blk.omask | outm;
-                if (__builtin_popcountll(uni) <= kmax && __builtin_popcountll(ouni) <= kMaxOuter) {
+                if (__builtin_popcountll(uni) <= kmax && __builtin_popcountll(ouni) <= mo) {
                     blk.qmask = uni;
                     blk.omask = ouni;
                     blk.gates.push_back(&g);

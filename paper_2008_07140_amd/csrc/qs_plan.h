@@ -75,13 +75,15 @@ struct TileOp {
     // `qubits` lie in Q (qubits[0] = most significant bit of a matrix index),
     // `outer` outside Q (at most kMaxOuter, outer[0] most significant); the outer
     // bits are constant over a tile and select one of 2^|outer| operators.
-    // DENSE: m holds 2^|outer| matrices of 2^k x 2^k complex one after
-    // another; `skip` bit p is set when matrix p is the identity.
+    // DENSE: m holds the distinct matrices (2^k x 2^k complex) one after
+    // another and pmap[p] is the matrix of outer pattern p; `skip` bit p is
+    // set when that matrix is the identity.
     // PHASE: m is the diagonal table, entry (outer pattern << k) | (qubit
     // pattern).
     std::vector<int> qubits;
     std::vector<int> outer;
     std::vector<double> m;
+    std::vector<uint8_t> pmap;
     uint32_t skip = 0;
 };
 
@@ -95,6 +97,7 @@ struct TileParams {
     int m = 12;     // tile qubits
     int L = 4;      // lowest qubits always in the tile
     int kmax = 5;   // widest dense block (4 or 5)
+    int max_outer = kMaxOuter;  // outer selector bits per op (0..kMaxOuter)
 };
 
 // One step of a tiled plan: a tile sweep, or a gate that does not fit a tile

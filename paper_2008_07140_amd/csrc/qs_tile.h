@@ -9,14 +9,16 @@
 
 namespace qs {
 
+// Tile t covers the amplitudes base(t) | (offsets over the tile qubits), where
+// base(t) deposits the bits of t on the qubits outside the tile (ascending).
 struct TileArgs {
     int m;               // tile qubits (10..13)
     int nops;
     int nouter;          // n - m
     int pad;
     uint64_t slot[16];   // global offset of local index 512 r (the r-th 16-byte slot of a thread)
+    uint64_t omask;      // qubits outside the tile
     uint16_t qlo[10];    // global positions of local bits 0..9
-    uint8_t outer[kMaxQ];  // positions of the bits outside the tile, ascending
 };
 
 struct TileOpDev {
@@ -28,6 +30,7 @@ struct TileOpDev {
     int opos[5];         // global positions of the outer bits, [0] = most significant
     uint32_t skip;       // dense: bit p set = identity for outer pattern p
     uint32_t frag_stride;  // dense: 16-byte units per outer pattern
+    uint32_t colmask;    // dense: the 4 tile bits that index the 16 columns of a matrix-core tile
 };
 
 // Batched sweeps: one entry per workgroup.
@@ -43,10 +46,9 @@ struct TileArgsDev {
     TileArgs ta;
 };
 
-size_t tile_lds_bytes(int m);
-hipError_t launch_tile_multi(int m, uint32_t ntasks, const TileTask *tasks, const TileArgsDev *args,
-                             const TileOpDev *dev_ops, const void *dev_data, hipStream_t st);
 hipError_t launch_tile(void *amp, int n, const TileArgs &ta, const TileOpDev *dev_ops,
                        const void *dev_data, hipStream_t st);
+hipError_t launch_tile_multi(int m, uint32_t ntasks, const TileTask *tasks, const TileArgsDev *args,
+                             const TileOpDev *dev_ops, const void *dev_data, hipStream_t st);
 
 }  // namespace qs

@@ -144,3 +144,16 @@ def test_cost_model_validation(qs):
     qs.cost_model_set(p)
     qs.cost_model_set(None)
     assert p.size == qs.mlp_num_params(16) == oracle.mlp_num_params(16, 64)
+
+
+def test_tile_planner_terminates_on_wide_diagonals(qs):
+    """Diagonal gates too wide for a tile op (more than k_max qubits inside
+    the tile, or more outer qubits than an op may select on) go on their own
+    instead of stalling the sweep planner."""
+    rng = np.random.default_rng(8)
+    d6 = np.diag(np.exp(1j * rng.uniform(0, 2 * np.pi, 64)))
+    for qubits in [(0, 1, 2, 3, 4, 5), (14, 15, 16, 17, 18, 19), (2, 9, 14, 15, 18, 19)]:
+        ops = [cg.Gate(qubits, (), d6), cg.Gate((0,), (), cg.H_GATE), cg.Gate(qubits[::-1], (), d6)]
+        for m, k in [(13, 5), (10, 4)]:
+            info = qs.Circuit(ops).plan_info(20, qs.C64, qs.PLAN_GREEDY, k_max=k, tile_qubits=m)
+            assert info["gates"] == 3 and 1 <= info["sweeps"] <= 3

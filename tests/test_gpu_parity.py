@@ -373,6 +373,26 @@ def test_tile_sweeps_rqc16_and_rqc20(qs, m):
         s.close()
 
 
+def test_tile_sweeps_wide_diagonals(qs):
+    """Diagonal gates wider than a tile op may be (more than k_max qubits
+    inside the tile, or outside qubits beyond the selector limit) run on
+    their own between sweeps."""
+    n = 20
+    rng = np.random.default_rng(9)
+    ops = []
+    for qubits in [(0, 1, 2, 3, 4, 5), (14, 15, 16, 17, 18, 19), (2, 9, 14, 15, 18, 19)]:
+        for q in range(n):
+            ops.append(cg.Gate((q,), (), cg.random_unitary(2, rng)))
+        ops.append(cg.Gate(qubits, (), np.diag(np.exp(1j * rng.uniform(0, 2 * np.pi, 64)))))
+    ref, _ = oracle.run(n, ops)
+    for m, k in [(13, 5), (10, 4)]:
+        s = qs.State(n, qs.C64)
+        s.run(qs.Circuit(ops), plan=1, k_max=k, tile_qubits=m)
+        got = s.amplitudes()
+        assert infidelity(ref, got) <= 1e-6, (m, k)
+        s.close()
+
+
 def test_tile_sweeps_with_noise_segments(qs):
     """Noise sites split the circuit into segments; each segment is tiled."""
     n = 10
@@ -419,7 +439,24 @@ def test_batched_trajectories_match_oracle_per_trajectory(qs, dtype):
         off += n
 
 
+def test_batched_trajectories_wider_than_a_tile(qs):
+    """States of 14..16 qubits span several 13-qubit tiles, so the batched
+    sweeps select operators on the qubits outside the tile; each trajectory
+    is still the oracle's run with the same draws."""
+    batch = _traj_batch(6, 14, 16, 4, 900, 0.05)
+    circs = [qs.Circuit(ops) for _, ops in batch]
+    widths = [n for n, _ in batch]
+    z, sec = qs.run_trajectories(circs, widths, dtype=qs.C64, seed=33)
+    off = 0
+    for t, (n, ops) in enumerate(batch):
+        psi, _ = oracle.run(n, ops, seed=33, traj=t)
+        assert np.max(np.abs(z[off:off + n] - oracle.expect_z(psi))) <= 1e-4, (t, n)
+        off += n
+
+
 def test_batched_trajectory_mean_matches_density_matrix(qs):
+    """Amplified rates (5e-2 everywhere), where a wrong branch weight or
+    Kraus product moves the mean well beyond the sampling error."""
     n = 10
     ops = cg.random_circuit(2, 5, 6, seed=4010, dep1=0.05, dep2=0.05, damping=0.05)
     rho = oracle.dm_run(n, ops)
@@ -431,6 +468,20 @@ def test_batched_trajectory_mean_matches_density_matrix(qs):
     mean = zs.mean(axis=0)
     sigma = np.maximum(zs.std(axis=0), 1e-3)
     assert np.all(np.abs(mean - zdm) < 5 * sigma / math.sqrt(T)), (mean, zdm)
+
+
+def test_batched_trajectory_mean_at_workload_rates(qs):
+    """The trajectory workload's own rates (depolarizing 1e-3 / 1e-2, damping
+    5e-4 per layer) on the 10-qubit depth-24 circuit: the mean of 4096
+    trajectories against the stored exact density-matrix values."""
+    n = 10
+    ops = cg.random_circuit(2, 5, 24, seed=4010, dep1=1e-3, dep2=1e-2, damping=5e-4)
+    zdm = np.loadtxt(os.path.join(GOLDEN, "dm_n10_d24_workload_rates.txt"))
+    T = 4096
+    z, sec = qs.run_trajectories([qs.Circuit(ops)] * T, [n] * T, dtype=qs.C64, seed=78)
+    zs = z.reshape(T, n)
+    sigma = np.maximum(zs.std(axis=0), 1e-3)
+    assert np.all(np.abs(zs.mean(axis=0) - zdm) < 5 * sigma / math.sqrt(T)), (zs.mean(axis=0), zdm)
 
 
 # --------------------------------------------------------------- cost model --
