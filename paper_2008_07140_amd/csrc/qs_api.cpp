@@ -489,6 +489,31 @@ void choose_lane_layout(const std::vector<int> &pos, int m, int &lane_q, uint32_
         if (group >> p & 1) colmask |= 1u << p;
 }
 
+// Per-lane LDS byte offsets of a dense tile op (layout in qs_tile.h).
+std::vector<uint32_t> lane_offsets(const qs::TileOpDev &d)
+{
+    const int k = d.k, D = 1 << k, MT = 2 * D / 16, KS = 2 * D / 32;
+    const int per = qs::tile_lane_offsets(k);
+    std::vector<uint32_t> out(size_t(64) * per);
+    auto offset = [&](int x) {
+        uint32_t o = 0;
+        for (int b = 0; b < k; ++b)
+            if ((x >> (k - 1 - b)) & 1) o |= 1u << d.lpos[b];
+        return o;
+    };
+    for (int lane = 0; lane < 64; ++lane) {
+        uint32_t gl = 0;
+        for (uint32_t mm = d.colmask, c = uint32_t(lane & 15); mm; mm &= mm - 1, c >>= 1)
+            if (c & 1) gl |= mm & (~mm + 1);
+        uint32_t *o = out.data() + size_t(lane) * per;
+        for (int s2 = 0; s2 < KS; ++s2)
+            for (int jj = 0; jj < 4; ++jj) *o++ = qs::tile_swizzle(gl | offset(16 * s2 + 4 * (lane >> 4) + jj)) << 3;
+        for (int mt = 0; mt < MT; ++mt)
+            for (int jj = 0; jj < 2; ++jj) *o++ = qs::tile_swizzle(gl | offset(8 * mt + 2 * (lane >> 4) + jj)) << 3;
+    }
+    return out;
+}
+
 // The matrix of a k-qubit op with its qubits reordered: new qubit b is old
 // qubit order[b] (index 0 = most significant bit).
 std::vector<double> permute_matrix(const double *m, int k, const std::vector<int> &order)
@@ -561,6 +586,7 @@ void build_sweep_program(const qs::Sweep &sw, std::vector<qs::TileOpDev> &ops, s
                 const size_t u = op.pmap.empty() ? p : op.pmap[p];
                 std::memcpy(data.data() + before + p * fs, distinct.data() + u * fs, fs * sizeof(uint16_t));
             }
+            // the per-lane offset table is shared program-wide (build_tile_program)
         } else {
             // one table of 2^k complex64 entries per outer pattern, each
             // padded to whole 16-byte units
@@ -614,6 +640,22 @@ void build_tile_program(const std::vector<qs::PlanStep> &steps, TileProgram &tp)
         }
         if (!pdata[i].empty()) std::memcpy(tp.data.data() + dpos[i], pdata[i].data(), pdata[i].size() * sizeof(uint16_t));
     });
+    // per-lane LDS offset tables: one per distinct lane layout of the program
+    std::map<std::array<uint32_t, 8>, uint32_t> tables;
+    for (auto &d : tp.ops) {
+        if (d.kind != 0) continue;
+        std::array<uint32_t, 8> key{uint32_t(d.k), d.colmask, 0, 0, 0, 0, 0, 0};
+        for (int b = 0; b < d.k; ++b) key[2 + b] = uint32_t(d.lpos[b]);
+        auto it = tables.find(key);
+        if (it == tables.end()) {
+            const std::vector<uint32_t> lo = lane_offsets(d);
+            const uint32_t off = uint32_t(tp.data.size() / 8);
+            tp.data.resize(tp.data.size() + lo.size() * 2);
+            std::memcpy(tp.data.data() + size_t(off) * 8, lo.data(), lo.size() * sizeof(uint32_t));
+            it = tables.emplace(key, off).first;
+        }
+        d.offs_off = it->second;
+    }
     if (tp.data.empty()) tp.data.resize(8, 0);
     if (tp.ops.empty()) tp.ops.resize(1);
 }

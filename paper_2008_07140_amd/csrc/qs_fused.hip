@@ -46,13 +46,7 @@ __device__ __forceinline__ void split2(float a, float b, v2bf &hi, v2bf &lo)
     lo = __builtin_convertvector(v2f{a - float(hi[0]), b - float(hi[1])}, v2bf);
 }
 
-// LDS layout of a tile: amplitude j lives at j ^ ((j >> 5) & 31) ^ (j >> 10)
-// (j < 2^13).  LDS banks see the 8-byte slot index mod 32, so tile bit p
-// lands on bank bit p mod 5: a 32-lane read is conflict-free when its five
-// lane bits sit on tile bits of distinct residues mod 5, and a 16-lane write
-// when its four do.  The host picks each op's column bits and its lane
-// qubit (lpos[1]) that way.
-__device__ __forceinline__ uint32_t sw(uint32_t j) { return j ^ ((j >> 5) & 31u) ^ (j >> 10); }
+__device__ __forceinline__ uint32_t sw(uint32_t j) { return tile_swizzle(j); }
 
 // Scatter the low bits of x onto the set bits of mask (ascending).
 __device__ __forceinline__ uint32_t deposit32(uint32_t x, uint32_t mask)
@@ -77,12 +71,17 @@ __device__ __forceinline__ uint32_t deposit32(uint32_t x, uint32_t mask)
 // walks its column tiles in Gray-code order, so the uniform part of the LDS
 // address changes by one precomputed XOR per step.
 template <int K, int NW>
-__device__ __forceinline__ void dense_op(float2 *tile, const TileOpDev &op, const bf16x8 *fr, int m)
+__device__ __forceinline__ void dense_op(float2 *tile, const TileOpDev &op, const bf16x8 *fr, const uint4 *offs,
+                                         int m)
 {
     constexpr int D = 1 << K, MT = 2 * D / 16, KS = 2 * D / 32;
     constexpr int H = K == 4 ? 2 : 1;  // column tiles per step: at least 4 accumulator chains
     constexpr int LB = (H == 2 ? 1 : 0) + (NW == 8 ? 3 : NW == 4 ? 2 : NW == 2 ? 1 : 0);
+    constexpr int NQ = tile_lane_offsets(K) / 4;
+    constexpr int MAXSTEPS = 4;  // at most 32 column tiles (m <= 13) over H * NW >= 8 per step
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const int ntiles = 1 << (m - K - 4);
+    if (H * wave >= ntiles) return;  // fewer column tiles than waves
     bf16x8 ahi[MT][KS], alo[MT][KS];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -91,73 +90,72 @@ __device__ __forceinline__ void dense_op(float2 *tile, const TileOpDev &op, cons
             ahi[mt][s] = fr[(mt * KS + s) * 64 + lane];
             alo[mt][s] = fr[MT * KS * 64 + (mt * KS + s) * 64 + lane];
         }
+    uint32_t ofs[4 * NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const uint4 o = offs[lane * NQ + q];
+        ofs[4 * q] = o.x;
+        ofs[4 * q + 1] = o.y;
+        ofs[4 * q + 2] = o.z;
+        ofs[4 * q + 3] = o.w;
+    }
+    const uint32_t *rd = ofs, *wr = ofs + KS * 4;
+    // XOR images of the column-tile bits (uniform): column tile index bits
+    // sit on the tile bits outside the op and its column bits
     uint32_t opm = 0;
 #pragma unroll
     for (int b = 0; b < K; ++b) opm |= 1u << op.lpos[b];
-    const uint32_t blockmask = ((1u << m) - 1u) & ~opm & ~op.colmask;
-    auto offset = [&](int x) {
-        uint32_t o = 0;
-#pragma unroll
-        for (int b = 0; b < K; ++b)
-            if ((x >> (K - 1 - b)) & 1) o |= 1u << op.lpos[b];
-        return o;
-    };
-    // per-lane byte offsets: reads of amplitudes 16 s + 4 (l / 16) + jj,
-    // writes of amplitudes 8 mt + 2 (l / 16) + jj
-    const uint32_t gl = deposit32(uint32_t(lane & 15), op.colmask);
-    uint32_t rd[KS][4], wr[MT][2];
-#pragma unroll
-    for (int s = 0; s < KS; ++s)
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) rd[s][jj] = sw(gl | offset(16 * s + 4 * (lane >> 4) + jj)) << 3;
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int jj = 0; jj < 2; ++jj) wr[mt][jj] = sw(gl | offset(8 * mt + 2 * (lane >> 4) + jj)) << 3;
-    // XOR images of the column-tile bits (uniform; at most 5 bits for
-    // m <= 13, so a wave takes at most 4 steps)
     uint32_t img[LB + 2];
     {
-        uint32_t mm = blockmask;
+        uint32_t mm = ((1u << m) - 1u) & ~opm & ~op.colmask;
 #pragma unroll
         for (int t = 0; t < LB + 2; ++t) {
             img[t] = mm ? sw(mm & (~mm + 1)) << 3 : 0u;
             mm &= mm - 1;
         }
     }
-    const int ntiles = 1 << (m - K - 4);
-    uint32_t gw = 0;  // first column tile of this wave: index H * wave
+    uint32_t gt = 0;  // first column tile of this wave: index H * wave
 #pragma unroll
     for (int b = 0; b < LB; ++b)
-        if (((H * wave) >> b) & 1) gw ^= img[b];
+        if (((H * wave) >> b) & 1) gt ^= img[b];
+    gt = __builtin_amdgcn_readfirstlane(gt);
     const int steps = ntiles > H * NW ? ntiles / (H * NW) : 1;
     char *tb = reinterpret_cast<char *>(tile);
-    uint32_t gi = 0;
-    for (int g = 0; g < steps; ++g) {
-        if (g) gi ^= (g & 1) ? img[LB] : img[LB + 1];  // Gray code: bit 0 on odd steps, bit 1 on step 2
-        const int i = g ^ (g >> 1);
-        if (H * wave + i * H * NW >= ntiles) break;
-        uint32_t gt[H];
-        gt[0] = __builtin_amdgcn_readfirstlane(gw ^ gi);
-        if (H == 2) gt[H - 1] = gt[0] ^ img[0];
+    // A wave walks its column tiles in Gray-code order (one XOR per step) and
+    // reads the next tile's amplitudes while the current one is multiplied.
+    float2 v[2][H][KS][4];
+    auto read_x = [&](float2 (&dst)[H][KS][4], uint32_t g0) {
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            const uint32_t gh = h ? g0 ^ img[0] : g0;
+#pragma unroll
+            for (int s = 0; s < KS; ++s)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj)
+                    dst[h][s][jj] = *reinterpret_cast<const float2 *>(tb + (rd[s * 4 + jj] ^ gh));
+        }
+    };
+    read_x(v[0], gt);
+#pragma unroll
+    for (int g = 0; g < MAXSTEPS; ++g) {
+        if (g >= steps) break;
+        const uint32_t gn = gt ^ (((g + 1) & 1) ? img[LB] : img[LB + 1]);
+        if (g + 1 < steps) read_x(v[(g + 1) & 1], gn);
+        float2 (&x)[H][KS][4] = v[g & 1];
         bf16x8 bhi[H][KS], blo[H][KS];
 #pragma unroll
         for (int h = 0; h < H; ++h)
 #pragma unroll
-            for (int s = 0; s < KS; ++s) {
-                float2 v[4];
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj) v[jj] = *reinterpret_cast<const float2 *>(tb + (rd[s][jj] ^ gt[h]));
+            for (int s = 0; s < KS; ++s)
 #pragma unroll
                 for (int jj = 0; jj < 4; ++jj) {
                     v2bf hh, ll;
-                    split2(v[jj].x, v[jj].y, hh, ll);
+                    split2(x[h][s][jj].x, x[h][s][jj].y, hh, ll);
                     bhi[h][s][2 * jj] = hh[0];
                     bhi[h][s][2 * jj + 1] = hh[1];
                     blo[h][s][2 * jj] = ll[0];
                     blo[h][s][2 * jj + 1] = ll[1];
                 }
-            }
         f32x4 acc[H][MT];
 #pragma unroll
         for (int h = 0; h < H; ++h)
@@ -186,12 +184,15 @@ __device__ __forceinline__ void dense_op(float2 *tile, const TileOpDev &op, cons
                 for (int h = 0; h < H; ++h)
                     acc[h][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[mt][s], bhi[h][s], acc[h][mt], 0, 0, 0);
 #pragma unroll
-        for (int h = 0; h < H; ++h)
+        for (int h = 0; h < H; ++h) {
+            const uint32_t gh = h ? gt ^ img[0] : gt;
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
-                *reinterpret_cast<float2 *>(tb + (wr[mt][0] ^ gt[h])) = make_float2(acc[h][mt][0], acc[h][mt][1]);
-                *reinterpret_cast<float2 *>(tb + (wr[mt][1] ^ gt[h])) = make_float2(acc[h][mt][2], acc[h][mt][3]);
+                *reinterpret_cast<float2 *>(tb + (wr[mt * 2] ^ gh)) = make_float2(acc[h][mt][0], acc[h][mt][1]);
+                *reinterpret_cast<float2 *>(tb + (wr[mt * 2 + 1] ^ gh)) = make_float2(acc[h][mt][2], acc[h][mt][3]);
             }
+        }
+        gt = gn;
     }
 }
 
@@ -278,9 +279,9 @@ __device__ __forceinline__ void tile_pass(float2 *amp, uint64_t t, const TileArg
             const bf16x8 *fr =
                 reinterpret_cast<const bf16x8 *>(data + op.data_off + uint32_t(outer) * op.frag_stride);
             if (op.k == 4)
-                dense_op<4, kThreads / 64>(tile, op, fr, M);
+                dense_op<4, kThreads / 64>(tile, op, fr, data + op.offs_off, M);
             else
-                dense_op<5, kThreads / 64>(tile, op, fr, M);
+                dense_op<5, kThreads / 64>(tile, op, fr, data + op.offs_off, M);
         } else {
             phase_op(tile, ptab, op, data, outer, M);
         }
@@ -310,7 +311,7 @@ __device__ __forceinline__ uint64_t thread_offset(const TileArgs &ta)
 }
 
 template <int M>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_tile(float2 *__restrict__ amp, uint64_t ntiles, TileArgs ta,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_tile(float2 *__restrict__ amp, uint64_t ntiles, TileArgs ta,
                                                    const TileOpDev *__restrict__ ops, const uint4 *__restrict__ data)
 {
     __shared__ float2 lds[(1 << M) + 64];  // the tile, then a phase table
@@ -323,7 +324,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 2))
 // args[tasks[b].arg] (its own amplitudes, tile qubits and op list), so one
 // launch covers one sweep of many independent states.
 template <int M>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_tile_multi(const TileTask *__restrict__ tasks,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_tile_multi(const TileTask *__restrict__ tasks,
                                                          const TileArgsDev *__restrict__ args,
                                                          const TileOpDev *__restrict__ ops,
                                                          const uint4 *__restrict__ data)

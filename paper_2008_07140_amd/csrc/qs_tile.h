@@ -31,7 +31,23 @@ struct TileOpDev {
     uint32_t skip;       // dense: bit p set = identity for outer pattern p
     uint32_t frag_stride;  // dense: 16-byte units per outer pattern
     uint32_t colmask;    // dense: the 4 tile bits that index the 16 columns of a matrix-core tile
+    uint32_t offs_off;   // dense: per-lane LDS byte offsets (tile_lane_offsets), 16-byte units
 };
+
+// LDS layout of a tile: amplitude j (j < 2^13) lives in 8-byte slot
+// j ^ ((j >> 5) & 31) ^ (j >> 10).  LDS banks see the slot index mod 32, so
+// tile bit p lands on bank bit p mod 5: a 32-lane read is conflict-free when
+// its five lane bits sit on tile bits of distinct residues mod 5, and a
+// 16-lane write when its four do.
+__host__ __device__ inline uint32_t tile_swizzle(uint32_t j) { return j ^ ((j >> 5) & 31u) ^ (j >> 10); }
+
+// Per-lane LDS byte offsets of a dense k-qubit tile op (k = 4, 5; D = 2^k,
+// MT = 2D / 16 row tiles, KS = 2D / 32 k-steps) relative to the column tile:
+// lane l reads amplitudes 16 s + 4 (l / 16) + jj (s < KS, jj < 4) and writes
+// amplitudes 8 mt + 2 (l / 16) + jj (mt < MT, jj < 2) of the group whose
+// column bits (colmask) hold l % 16.  Stored lane by lane: KS * 4 read
+// offsets, then MT * 2 write offsets, as uint32.
+constexpr int tile_lane_offsets(int k) { return (2 << k) / 32 * 4 + (2 << k) / 16 * 2; }
 
 // Batched sweeps: one entry per workgroup.
 struct TileTask {
