@@ -56,6 +56,9 @@ def parse():
                         "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
     p.add_argument("--no-by-target", action="store_true",
                    help="skip the per-target / per-control bandwidth sweep of single gates")
+    p.add_argument("--config5", action="store_true",
+                   help="34-qubit learned-planner comparison: complex128 reference on 2^20 sampled "
+                        "indices, then complex64 learned vs greedy vs unfused")
     p.add_argument("--summarize-profiles", metavar="DIR", default="",
                    help="CPU only: read the rocprofv3 CSV output under DIR (see profiles/README.md) "
                         "and write profiles/traffic.json plus the text summaries")
@@ -389,6 +392,85 @@ def trajectory_bench(qs, cg, count, seed=4001):
     return res
 
 
+def train_cost_model(qs, cg, n=28, circuits=8, log_fn=None):
+    """Train the planner's cost network on sweep timings that the simulator
+    records itself: random circuits on an n-qubit complex64 state, run under
+    every candidate tile shape, each sweep's features and measured time per
+    amplitude a sample; Adam on the GPU with the library's kernels."""
+    import numpy as np
+    s = qs.State(n, qs.C64)
+    s.profile(True)
+    shapes = [(r, n // r) for r in range(2, n // 2 + 1) if n % r == 0]
+    for i in range(circuits):
+        rows, cols = shapes[i % len(shapes)]
+        c = qs.Circuit(cg.random_circuit(rows, cols, 12, seed=9000 + i, cu3_prob=0.1))
+        for m in (11, 12, 13):
+            for k in (4, 5):
+                s.reset()
+                s.run(c, plan=qs.PLAN_GREEDY, k_max=k, tile_qubits=m)
+    X, y = s.profile_samples()
+    s.profile(False)
+    s.close()
+    p, loss = qs.mlp_train(qs.mlp_init(4), X, y, steps=3000, batch=256, lr=2e-3, seed=7)
+    if log_fn:
+        log_fn("cost model: %d sweep samples at %d qubits, final loss %.4f" % (X.shape[0], n, loss))
+    return p, int(X.shape[0])
+
+
+def config5(qs, cg, torch):
+    """34 qubits, 17 x 2 grid, depth 24: end-to-end gates/s of the complex64
+    path under the learned, greedy and unfused plans, and agreement with the
+    complex128 greedy-fused path (validated against the FP64 oracle at 30
+    qubits) on 2^20 indices sampled without replacement (seed 5002)."""
+    import numpy as np
+    n, ops = cg.workload("rqc34_d24")
+    gates = cg.count_gates(ops)
+    circuit = qs.Circuit(ops)
+    rng = np.random.default_rng(5002)
+    cand = np.unique(rng.integers(0, 1 << n, size=(1 << 20) + (1 << 16), dtype=np.uint64))
+    idx = np.sort(rng.permutation(cand)[: 1 << 20])
+    out = {"workload": "rqc34_d24: 34-qubit random circuit, 17 x 2 grid, depth 24, %d logical gates" % gates,
+           "sampled_indices": int(idx.size)}
+    log("config 5: complex128 reference (256 GiB) ...")
+    t0 = time.perf_counter()
+    ref = qs.State(n, qs.C128)
+    ref.run(circuit, plan=qs.PLAN_GREEDY, k_max=3)
+    ref.synchronize()
+    ref_s = time.perf_counter() - t0
+    a = ref.amplitudes(idx)
+    ref.close()
+    del ref
+    out["c128_greedy_k3"] = {"seconds": ref_s, "gates_per_s": gates / ref_s}
+    log("c128 reference: %.1f s" % ref_s)
+    p, nsamp = train_cost_model(qs, cg, log_fn=log)
+    out["cost_model_samples"] = nsamp
+    st = qs.State(n, qs.C64)
+    for name, plan in (("learned", qs.PLAN_LEARNED), ("greedy", qs.PLAN_GREEDY), ("unfused", qs.PLAN_UNFUSED)):
+        qs.cost_model_set(p if plan == qs.PLAN_LEARNED else None)
+        reps = 1 if plan == qs.PLAN_UNFUSED else 2
+        best = 1e30
+        for r in range(reps):
+            st.reset()
+            st.synchronize()
+            t0 = time.perf_counter()
+            st.run(circuit, plan=plan)
+            st.norm()
+            best = min(best, time.perf_counter() - t0)
+        b = st.amplitudes(idx)
+        ov = abs(np.vdot(a, b)) ** 2 / (np.vdot(a, a).real * np.vdot(b, b).real)
+        info = circuit.plan_info(n, qs.C64, plan)
+        out[name] = {"seconds": best, "gates_per_s": gates / best, "sweeps": info["sweeps"],
+                     "blocks": info["blocks"], "max_abs_diff": float(np.max(np.abs(a - b))),
+                     "rel_l2": float(np.linalg.norm(a - b) / np.linalg.norm(a)),
+                     "infidelity_sampled": float(1 - ov)}
+        log("%s: %.1f gates/s, max|d| %.2e" % (name, gates / best, out[name]["max_abs_diff"]))
+    qs.cost_model_set(None)
+    st.close()
+    out["learned_vs_greedy"] = out["greedy"]["seconds"] / out["learned"]["seconds"]
+    out["learned_vs_unfused"] = out["unfused"]["seconds"] / out["learned"]["seconds"]
+    print(json.dumps({"config5": out}), flush=True)
+
+
 def cpu_baseline(cg, n, ops, seconds):
     """The FP64 oracle on the host, on the first gates of the same circuit
     applied to the full 2^n state, for about `seconds` of gate work."""
@@ -440,6 +522,12 @@ def main():
     from paper_2008_07140_amd import circuits as cg
     from paper_2008_07140_amd import qs
 
+    if args.config5:
+        config5(qs, cg, torch)
+        return
+    if args.plan == "learned":
+        p, _ = train_cost_model(qs, cg, log_fn=log)
+        qs.cost_model_set(p)
     n, ops = cg.workload(args.workload)
     gates = cg.count_gates(ops)
     circuit = qs.Circuit(ops)
