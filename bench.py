@@ -46,7 +46,7 @@ def parse():
     p.add_argument("--paths", default="fused_c64,plain_c128")
     p.add_argument("--kmax", type=int, default=0, help="fused block width (0 = library default)")
     p.add_argument("--tile-qubits", type=int, default=0, help="qubits per LDS tile (0 = library default)")
-    p.add_argument("--plan", default="greedy", choices=["greedy", "learned"])
+    p.add_argument("--plan", default="greedy", choices=["greedy", "learned", "autotune"])
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--trajectories", type=int, default=512,
                    help="noisy trajectories in the batched-trajectory measurement (0 = skip)")
@@ -273,7 +273,10 @@ def run_path(qs, torch, cg, name, n, circuit, gates, steps, warmup, kmax, plan, 
     buf = torch.empty(1 << n, dtype=tdt, device="cuda")
     stream = torch.cuda.Stream()
     st = qs.State(n, dt, buffer=buf, stream=stream.cuda_stream)
-    plan_id = (qs.PLAN_LEARNED if plan == "learned" else qs.PLAN_GREEDY) if fused else qs.PLAN_UNFUSED
+    plan_id = ({"learned": qs.PLAN_LEARNED, "autotune": qs.PLAN_AUTOTUNE}.get(plan, qs.PLAN_GREEDY)
+               if fused else qs.PLAN_UNFUSED)
+    if plan_id == qs.PLAN_AUTOTUNE:  # every candidate runs once before the timed steps
+        warmup = max(warmup, circuit.autotune_result(n, dt)[1] + 1)
     pm = [n - 1, n // 2, 0]
 
     def step():
@@ -322,6 +325,9 @@ def run_path(qs, torch, cg, name, n, circuit, gates, steps, warmup, kmax, plan, 
                      "avg_launch_ms": d["ms"] / d["launches"],
                      "traffic": traffic_for(name, dom)},
     }
+    if plan_id == qs.PLAN_AUTOTUNE:
+        tr, nc, tq, km, sec = circuit.autotune_result(n, dt)
+        res["autotune"] = {"tried": tr, "candidates": nc, "tile_qubits": tq, "k_max": km, "seconds": sec}
     log("%s: %.1f gates/s, %.1f ms/step, path HBM fraction %.3f, dominant %s at %.0f GB/s"
         % (name, res["gates_per_s"], res["ms_per_step"], res["hbm_frac_path"], dom, achieved))
     return res, st, buf, stream

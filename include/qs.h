@@ -157,9 +157,10 @@ qs_status qs_circuit_counts(const qs_circuit *c, int64_t *gates, int64_t *noise_
                             int64_t *logical_gates);
 
 typedef enum {
-    QS_PLAN_UNFUSED = 0, /* one kernel launch per gate (Eq. 2 / Eq. 3 sweeps) */
-    QS_PLAN_GREEDY = 1,  /* gates fused into dense blocks of <= k_max qubits */
-    QS_PLAN_LEARNED = 2  /* fusion partition chosen with the trained cost model */
+    QS_PLAN_UNFUSED = 0,  /* one kernel launch per gate (Eq. 2 / Eq. 3 sweeps) */
+    QS_PLAN_GREEDY = 1,   /* gates fused into dense blocks of <= k_max qubits */
+    QS_PLAN_LEARNED = 2,  /* fusion partition chosen with the trained cost model */
+    QS_PLAN_AUTOTUNE = 3  /* fusion widths chosen by measurement (qs_circuit_autotune_result) */
 } qs_plan;
 
 typedef struct {
@@ -194,6 +195,21 @@ qs_status qs_circuit_plan_info(const qs_circuit *c, int n, qs_dtype dt, const qs
  * >= n), QS_E_UNSUPPORTED (noise inside a group, or a fused plan with noise
  * sites). */
 qs_status qs_run_circuit(qs_state *s, const qs_circuit *c, const qs_run_opts *opts);
+
+/* Autotuning (QS_PLAN_AUTOTUNE).  The candidates are the fused plans of the
+ * state's shape: tile_qubits in {11, 12, 13} (at most n) x k_max in {4, 5}
+ * for complex64 states of at least 11 qubits, k_max in {2, 3, 4} otherwise.
+ * Each of the first runs of a circuit on a state of a given (n, dtype) takes
+ * the next untried candidate and times its execution on the state's stream
+ * (planning and the upload of its operand program excluded; the call then
+ * synchronises); once every candidate has run, later runs use the fastest.
+ * Every run is a complete, exact execution of the circuit.  Tuning records
+ * belong to the circuit and are cleared when it changes.
+ * qs_circuit_autotune_result reports, for (n, dt): the number of candidates
+ * tried so far, the number of candidates, and the fastest one (tile_qubits = 0
+ * for per-block plans) with its time in seconds (all 0 before any run). */
+qs_status qs_circuit_autotune_result(const qs_circuit *c, int n, qs_dtype dt, int *tried, int *candidates,
+                                     int *tile_qubits, int *k_max, double *seconds);
 
 /* ------------------------------------------------------------- readout -- */
 

@@ -123,15 +123,29 @@ std::atomic<uint64_t> g_model_version{1};
 std::atomic<uint64_t> g_prog_serial{1};
 }  // namespace
 
+// Measured candidates of QS_PLAN_AUTOTUNE for one state shape.
+struct Tuning {
+    struct Cand {
+        int tile, kmax;
+        double seconds;  // < 0: not run yet
+    };
+    std::vector<Cand> cands;
+    size_t next = 0;
+    int best = -1;
+};
+
 struct qs_circuit {
     std::vector<qs::Op> ops;
-    // plans already made for this circuit (cleared when it changes)
+    // plans already made for this circuit and autotuning records (cleared
+    // when it changes)
     mutable std::mutex mu;
     mutable std::map<PlanKey, std::shared_ptr<const CachedPlan>> cache;
+    mutable std::map<std::pair<int, int>, Tuning> tuning;
     void changed()
     {
         std::lock_guard<std::mutex> lk(mu);
         cache.clear();
+        tuning.clear();
     }
 };
 
@@ -666,7 +680,7 @@ qs::TileParams tile_params(int n, const qs_run_opts &o)
     tp.m = o.tile_qubits ? o.tile_qubits : qs::default_tile_qubits(n);
     tp.m = std::min(tp.m, n);
     tp.L = 4;
-    tp.kmax = (o.k_max >= 4 && o.k_max <= 5) ? o.k_max : 5;
+    tp.kmax = (o.k_max >= 4 && o.k_max <= 5) ? o.k_max : 4;  // four-qubit blocks: cheapest per gate on the matrix cores
     return tp;
 }
 
@@ -1850,6 +1864,14 @@ qs_status qs_circuit_plan_info(const qs_circuit *c, int n, qs_dtype dt, const qs
     if (n < 1 || n > QS_MAX_QUBITS) return fail(QS_E_INVAL, "n = %d not in [1, %d]", n, QS_MAX_QUBITS);
     qs_run_opts o{};
     if (opts) o = *opts;
+    if (o.plan == QS_PLAN_AUTOTUNE) {
+        // the fastest candidate measured so far, else the greedy defaults
+        int tq = 0, km = 0;
+        qs_circuit_autotune_result(c, n, dt, nullptr, nullptr, &tq, &km, nullptr);
+        o.plan = QS_PLAN_GREEDY;
+        o.tile_qubits = tq;
+        o.k_max = km;
+    }
     std::vector<qs::FlatOp> flat;
     std::string err;
     if (int rc = qs::expand(c->ops, flat, err)) return fail(rc == 2 ? QS_E_UNSUPPORTED : QS_E_INVAL, "%s", err.c_str());
@@ -1895,19 +1917,140 @@ qs_status qs_circuit_plan_info(const qs_circuit *c, int n, qs_dtype dt, const qs
     return QS_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Candidate fused plans of a state shape for QS_PLAN_AUTOTUNE.
+std::vector<Tuning::Cand> autotune_candidates(int n, qs_dtype dt)
+{
+    std::vector<Tuning::Cand> c;
+    if (dt == QS_C64 && n >= 11) {
+        for (int m = 11; m <= 13 && m <= n; ++m)
+            for (int k = 4; k <= 5; ++k) c.push_back({m, k, -1.0});
+    } else {
+        for (int k = 2; k <= 4 && k <= n; ++k) c.push_back({0, k, -1.0});
+    }
+    return c;
+}
+
+qs_status plan_circuit(qs_state *s, const qs_circuit *c, const qs_run_opts &o,
+                       std::shared_ptr<const CachedPlan> &cp);
+qs_status execute_plan(qs_state *s, const CachedPlan &plan, qs_run_opts o);
+
+// One run under QS_PLAN_AUTOTUNE: the next untried candidate, timed, or the
+// fastest one.
+qs_status run_autotuned(qs_state *s, const qs_circuit *c, qs_run_opts o)
+{
+    int cand = -1;
+    Tuning::Cand pick{};
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        Tuning &t = c->tuning[{s->n, int(s->dt)}];
+        if (t.cands.empty()) t.cands = autotune_candidates(s->n, s->dt);
+        if (t.next < t.cands.size()) {
+            cand = int(t.next++);
+            pick = t.cands[cand];
+        } else {
+            pick = t.cands[t.best >= 0 ? t.best : 0];
+        }
+    }
+    o.plan = QS_PLAN_GREEDY;
+    o.k_max = pick.kmax;
+    o.tile_qubits = pick.tile;
+    std::shared_ptr<const CachedPlan> cp;
+    if (qs_status st = plan_circuit(s, c, o, cp)) return st;
+    if (cand < 0) return execute_plan(s, *cp, o);
+    // operand programs of a single tiled segment go up before the clock starts
+    size_t tiled = 0;
+    const SegPlan *only = nullptr;
+    for (const SegPlan &sp : cp->segs)
+        if (sp.tiled) ++tiled, only = &sp;
+    if (tiled == 1) {
+        size_t doff = 0;
+        if (qs_status st = upload_program(s, only->prog, only->prog_id, doff)) return st;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return fail(QS_E_DEVICE, "hipEventCreate failed");
+    }
+    qs_status st = QS_OK;
+    float ms = 0.f;
+    if (hipEventRecord(e0, s->stream) != hipSuccess) st = fail(QS_E_DEVICE, "hipEventRecord failed");
+    if (!st) st = execute_plan(s, *cp, o);
+    if (!st && (hipEventRecord(e1, s->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        st = fail(QS_E_DEVICE, "timing the autotuning run failed");
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st) return st;
+    std::lock_guard<std::mutex> lk(c->mu);
+    Tuning &t = c->tuning[{s->n, int(s->dt)}];
+    if (size_t(cand) < t.cands.size()) {
+        t.cands[cand].seconds = double(ms) * 1e-3;
+        if (t.best < 0 || t.cands[cand].seconds < t.cands[t.best].seconds) t.best = cand;
+    }
+    return QS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qs_status qs_circuit_autotune_result(const qs_circuit *c, int n, qs_dtype dt, int *tried, int *candidates,
+                                     int *tile_qubits, int *k_max, double *seconds)
+{
+    if (!c) return fail(QS_E_INVAL, "circuit is NULL");
+    if (n < 1 || n > QS_MAX_QUBITS) return fail(QS_E_INVAL, "n = %d not in [1, %d]", n, QS_MAX_QUBITS);
+    if (dt != QS_C64 && dt != QS_C128) return fail(QS_E_INVAL, "unknown dtype %d", int(dt));
+    std::lock_guard<std::mutex> lk(c->mu);
+    int tr = 0, nc = int(autotune_candidates(n, dt).size()), tq = 0, km = 0;
+    double sec = 0.0;
+    auto it = c->tuning.find({n, int(dt)});
+    if (it != c->tuning.end()) {
+        const Tuning &t = it->second;
+        for (const auto &cd : t.cands) tr += cd.seconds >= 0.0;
+        if (t.best >= 0) {
+            tq = t.cands[t.best].tile;
+            km = t.cands[t.best].kmax;
+            sec = t.cands[t.best].seconds;
+        }
+    }
+    if (tried) *tried = tr;
+    if (candidates) *candidates = nc;
+    if (tile_qubits) *tile_qubits = tq;
+    if (k_max) *k_max = km;
+    if (seconds) *seconds = sec;
+    return QS_OK;
+}
+
 qs_status qs_run_circuit(qs_state *s, const qs_circuit *c, const qs_run_opts *opts)
 {
     if (qs_status st = check_state(s)) return st;
     if (!c) return fail(QS_E_INVAL, "circuit is NULL");
     qs_run_opts o{};
     if (opts) o = *opts;
-    if (o.plan < QS_PLAN_UNFUSED || o.plan > QS_PLAN_LEARNED) return fail(QS_E_INVAL, "unknown plan %d", o.plan);
+    if (o.plan < QS_PLAN_UNFUSED || o.plan > QS_PLAN_AUTOTUNE) return fail(QS_E_INVAL, "unknown plan %d", o.plan);
     if (o.k_max < 0 || o.k_max > QS_MAX_TARGETS) return fail(QS_E_INVAL, "k_max = %d not in [0, %d]", o.k_max, QS_MAX_TARGETS);
     if (o.tile_qubits && (o.tile_qubits < 10 || o.tile_qubits > 13))
         return fail(QS_E_INVAL, "tile_qubits = %d not in [10, 13]", o.tile_qubits);
+    if (o.plan == QS_PLAN_AUTOTUNE) return run_autotuned(s, c, o);
+    std::shared_ptr<const CachedPlan> cp;
+    if (qs_status st = plan_circuit(s, c, o, cp)) return st;
+    return execute_plan(s, *cp, o);
+}
+
+namespace {
+
+// The cached plan of (state shape, options), made on first use.
+qs_status plan_circuit(qs_state *s, const qs_circuit *c, const qs_run_opts &o,
+                       std::shared_ptr<const CachedPlan> &cp)
+{
     const PlanKey key{s->n, int(s->dt), o.plan, o.k_max, o.tile_qubits,
                       o.plan == QS_PLAN_LEARNED ? g_model_version.load() : 0};
-    std::shared_ptr<const CachedPlan> cp;
+    cp.reset();
     {
         std::lock_guard<std::mutex> lk(c->mu);
         auto it = c->cache.find(key);
@@ -1961,8 +2104,13 @@ qs_status qs_run_circuit(qs_state *s, const qs_circuit *c, const qs_run_opts *op
         std::lock_guard<std::mutex> lk(c->mu);
         c->cache[key] = cp;
     }
+    return QS_OK;
+}
+
+qs_status execute_plan(qs_state *s, const CachedPlan &plan, qs_run_opts o)
+{
     uint64_t site = 0;
-    for (const SegPlan &sp : cp->segs) {
+    for (const SegPlan &sp : plan.segs) {
         if (sp.tiled) {
             if (qs_status st = launch_steps(s, sp.steps, sp.prog, sp.prog_id)) return st;
         } else if (!sp.gates.empty()) {
@@ -1981,6 +2129,8 @@ qs_status qs_run_circuit(qs_state *s, const qs_circuit *c, const qs_run_opts *op
     }
     return QS_OK;
 }
+
+}  // namespace
 
 // -------------------------------------------------------------- readout --
 

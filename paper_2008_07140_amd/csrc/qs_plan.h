@@ -96,7 +96,7 @@ struct Sweep {
 struct TileParams {
     int m = 12;     // tile qubits
     int L = 4;      // lowest qubits always in the tile
-    int kmax = 5;   // widest dense block (4 or 5)
+    int kmax = 4;   // widest dense block (4 or 5)
     int max_outer = kMaxOuter;  // outer selector bits per op (0..kMaxOuter)
 };
 

@@ -26,7 +26,7 @@ _lib = C.CDLL(LIB_PATH)
 C64, C128 = 1, 2
 COST_FEATURES = 16
 MLP_HIDDEN = 64
-PLAN_UNFUSED, PLAN_GREEDY, PLAN_LEARNED = 0, 1, 2
+PLAN_UNFUSED, PLAN_GREEDY, PLAN_LEARNED, PLAN_AUTOTUNE = 0, 1, 2, 3
 (K_INIT, K_DENSE1, K_DENSE2, K_DENSE3, K_DENSEN, K_PHASE, K_FUSED, K_TILE, K_REDUCE,
  K_OTHER) = range(10)
 KERNEL_NAMES = ["init", "dense1", "dense2", "dense3", "denseN", "phase", "fused", "tile",
@@ -87,6 +87,7 @@ _sig = {
     "qs_mlp_train": ([P, I, I, P, P, I64, I, I, C.c_float, U64, P], I),
     "qs_profile_samples": ([P, P, P, I64, P], I),
     "qs_cost_model_set": ([P, I, I], I),
+    "qs_circuit_autotune_result": ([P, I, I, P, P, P, P, P], I),
     "qs_last_error": ([], C.c_char_p),
 }
 for _name, (_args, _res) in _sig.items():
@@ -231,6 +232,14 @@ class Circuit:
         _check(_lib.qs_circuit_plan_info(self._h, n, dtype, C.byref(o), C.byref(sw), C.byref(bl),
                                          C.byref(lg)))
         return {"sweeps": sw.value, "blocks": bl.value, "gates": lg.value}
+
+    def autotune_result(self, n: int, dtype: int = C64):
+        """(tried, candidates, tile_qubits, k_max, seconds) of QS_PLAN_AUTOTUNE
+        for states of this shape."""
+        tr, nc, tq, km, sec = C.c_int(), C.c_int(), C.c_int(), C.c_int(), C.c_double()
+        _check(_lib.qs_circuit_autotune_result(self._h, n, dtype, C.byref(tr), C.byref(nc), C.byref(tq),
+                                               C.byref(km), C.byref(sec)))
+        return tr.value, nc.value, tq.value, km.value, sec.value
 
     def counts(self):
         g, z, l = C.c_int64(), C.c_int64(), C.c_int64()

@@ -157,3 +157,15 @@ def test_tile_planner_terminates_on_wide_diagonals(qs):
         for m, k in [(13, 5), (10, 4)]:
             info = qs.Circuit(ops).plan_info(20, qs.C64, qs.PLAN_GREEDY, k_max=k, tile_qubits=m)
             assert info["gates"] == 3 and 1 <= info["sweeps"] <= 3
+
+
+def test_autotune_result_before_any_run(qs):
+    c = qs.Circuit(cg.random_circuit(4, 5, 4, seed=3, cu3_prob=0.1))
+    assert c.autotune_result(20, qs.C64) == (0, 6, 0, 0, 0.0)
+    assert c.autotune_result(12, qs.C64)[:2] == (0, 4)  # tile sizes 11, 12
+    assert c.autotune_result(20, qs.C128)[:2] == (0, 3)  # block widths 2..4
+    with pytest.raises(qs.QSError) as e:
+        c.autotune_result(20, 9)
+    assert e.value.status == -1
+    # without measurements the plan is the greedy one
+    assert (c.plan_info(20, qs.C64, qs.PLAN_AUTOTUNE) == c.plan_info(20, qs.C64, qs.PLAN_GREEDY))

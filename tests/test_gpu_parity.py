@@ -484,6 +484,35 @@ def test_batched_trajectory_mean_at_workload_rates(qs):
     assert np.all(np.abs(zs.mean(axis=0) - zdm) < 5 * sigma / math.sqrt(T)), (zs.mean(axis=0), zdm)
 
 
+# ---------------------------------------------------------------- autotune --
+
+
+@pytest.mark.parametrize("dtype,ncand", [("c64", 6), ("c128", 3)])
+def test_autotune_runs_every_candidate_exactly(qs, dtype, ncand):
+    """Each autotuning run executes one candidate plan completely; every run,
+    and the tuned runs after it, agree with the oracle."""
+    rows, cols = (4, 5) if dtype == "c64" else (3, 5)
+    n = rows * cols
+    ops = cg.random_circuit(rows, cols, 16, seed=321, cu3_prob=0.1)
+    ref, _ = oracle.run(n, ops)
+    dt = qs.C64 if dtype == "c64" else qs.C128
+    c = qs.Circuit(ops)
+    s = qs.State(n, dt)
+    for r in range(ncand + 2):
+        s.reset()
+        s.run(c, plan=qs.PLAN_AUTOTUNE)
+        got = s.amplitudes()
+        if dtype == "c64":
+            assert infidelity(ref, got) <= 1e-6, r
+        else:
+            assert np.max(np.abs(got - ref)) <= TOL128, r
+        tried, cands, tq, km, sec = c.autotune_result(n, dt)
+        assert cands == ncand and tried == min(r + 1, ncand)
+        assert sec > 0
+    assert (tq in (11, 12, 13) and km in (4, 5)) if dtype == "c64" else (tq == 0 and km in (2, 3, 4))
+    s.close()
+
+
 # --------------------------------------------------------------- cost model --
 
 
