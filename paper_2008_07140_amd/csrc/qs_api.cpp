@@ -473,34 +473,61 @@ void pad16(std::vector<uint16_t> &d)
 
 // Matrix-core lane layout of a dense tile op.  The 32 lanes of one LDS read
 // vary in the 4 column bits and in the op qubit at lpos[k - 3]; the 16 lanes
-// of a write in the column bits only.  Tile bit p falls on LDS bank bit p mod 5
-// (the tile swizzle), so the accesses are conflict-free when those five tile
-// bits have distinct residues mod 5.  `pos` holds the tile bits of the op
-// qubits; returns the op qubit to place at lpos[k - 3] and the column bits.
-void choose_lane_layout(const std::vector<int> &pos, int m, int &lane_q, uint32_t &colmask)
+// of a write in the column bits only.  With image(p) the bank vector of tile
+// bit p under the tile swizzle, reads are conflict-free when the five images
+// have rank 5 and writes when the column images have rank 4 in their low four
+// bits (banks seen mod 16).  `pos` holds the tile bits of the op qubits;
+// returns the op qubit to place at lpos[k - 3] and the column bits.
+int gf2_rank(uint32_t *v, int n)
 {
+    int r = 0;
+    for (int bit = 0; bit < 5 && r < n; ++bit) {
+        int piv = -1;
+        for (int i = r; i < n; ++i)
+            if (v[i] >> bit & 1) {
+                piv = i;
+                break;
+            }
+        if (piv < 0) continue;
+        std::swap(v[r], v[piv]);
+        for (int i = 0; i < n; ++i)
+            if (i != r && (v[i] >> bit & 1)) v[i] ^= v[r];
+        ++r;
+    }
+    return r;
+}
+
+void search_lane_layout(const std::vector<int> &pos, int m, int &lane_q, uint32_t &colmask)
+{
+    auto image = [](int p) { return qs::tile_swizzle(1u << p) & 31u; };
     uint32_t opm = 0;
     for (int p : pos) opm |= 1u << p;
-    const uint32_t group = ((1u << m) - 1u) & ~opm;
-    for (size_t q = 0; q < pos.size(); ++q) {
-        uint32_t cm = 0;
-        int have = 1 << (pos[q] % 5);
-        for (int p = 0; p < m && __builtin_popcount(cm) < 4; ++p)
-            if ((group >> p & 1) && !(have >> (p % 5) & 1)) {
-                cm |= 1u << p;
-                have |= 1 << (p % 5);
-            }
-        if (__builtin_popcount(cm) == 4) {
-            lane_q = int(q);
-            colmask = cm;
-            return;
-        }
-    }
-    // no conflict-free choice: the lowest group bits (two-way conflicts)
-    lane_q = int(pos.size()) - 3;
-    colmask = 0;
-    for (int p = 0; p < m && __builtin_popcount(colmask) < 4; ++p)
-        if (group >> p & 1) colmask |= 1u << p;
+    std::vector<int> group;
+    for (int p = 0; p < m; ++p)
+        if (!(opm >> p & 1)) group.push_back(p);
+    const int ng = int(group.size());
+    int best = -1;
+    for (int a = 0; a < ng; ++a)
+        for (int b = a + 1; b < ng; ++b)
+            for (int c = b + 1; c < ng; ++c)
+                for (int d = c + 1; d < ng; ++d) {
+                    const int cols[4] = {group[a], group[b], group[c], group[d]};
+                    uint32_t w[4];
+                    for (int i = 0; i < 4; ++i) w[i] = image(cols[i]) & 15u;
+                    const bool wok = gf2_rank(w, 4) == 4;
+                    for (size_t q = 0; q < pos.size(); ++q) {
+                        uint32_t r[5];
+                        for (int i = 0; i < 4; ++i) r[i] = image(cols[i]);
+                        r[4] = image(pos[q]);
+                        const int score = (gf2_rank(r, 5) == 5) + 2 * wok;
+                        if (score > best) {
+                            best = score;
+                            lane_q = int(q);
+                            colmask = (1u << cols[0]) | (1u << cols[1]) | (1u << cols[2]) | (1u << cols[3]);
+                            if (score == 3) return;
+                        }
+                    }
+                }
 }
 
 // Per-lane LDS byte offsets of a dense tile op (layout in qs_tile.h).
@@ -526,6 +553,27 @@ std::vector<uint32_t> lane_offsets(const qs::TileOpDev &d)
             for (int jj = 0; jj < 2; ++jj) *o++ = qs::tile_swizzle(gl | offset(8 * mt + 2 * (lane >> 4) + jj)) << 3;
     }
     return out;
+}
+
+
+// The layout depends only on the op's tile bits and the tile size: searched
+// once per thread and remembered.
+void choose_lane_layout(const std::vector<int> &pos, int m, int &lane_q, uint32_t &colmask)
+{
+    thread_local std::map<uint64_t, std::pair<int, uint32_t>> memo;  // (tile-bit set, m) -> (lane bit, columns)
+    uint64_t key = uint64_t(m) << 32;
+    for (int p : pos) key |= uint64_t(1) << p;
+    auto it = memo.find(key);
+    if (it == memo.end()) {
+        std::vector<int> sorted(pos);
+        std::sort(sorted.begin(), sorted.end());
+        int q = int(sorted.size()) - 3;
+        uint32_t cm = 0;
+        search_lane_layout(sorted, m, q, cm);
+        it = memo.emplace(key, std::make_pair(sorted[q], cm)).first;
+    }
+    colmask = it->second.second;
+    lane_q = int(std::find(pos.begin(), pos.end(), it->second.first) - pos.begin());
 }
 
 // The matrix of a k-qubit op with its qubits reordered: new qubit b is old
@@ -583,6 +631,11 @@ void build_sweep_program(const qs::Sweep &sw, std::vector<qs::TileOpDev> &ops, s
                 order[b] = o++;
             }
             for (int b = 0; b < d.k; ++b) d.lpos[b] = pos[order[b]];
+            // column-tile index bits: the tile bits outside the op and its columns
+            uint32_t opm = 0;
+            for (int p : pos) opm |= 1u << p;
+            uint32_t bm = ((1u << Q.size()) - 1u) & ~opm & ~d.colmask;
+            for (int t = 0; t < 6; ++t, bm &= bm - 1) d.cimg[t] = bm ? qs::tile_swizzle(bm & (~bm + 1)) << 3 : 0u;
             // fragments of each distinct matrix once, then one copy per
             // outer pattern in pattern order
             const int D = 1 << d.k;

@@ -100,20 +100,11 @@ __device__ __forceinline__ void dense_op(float2 *tile, const TileOpDev &op, cons
         ofs[4 * q + 3] = o.w;
     }
     const uint32_t *rd = ofs, *wr = ofs + KS * 4;
-    // XOR images of the column-tile bits (uniform): column tile index bits
-    // sit on the tile bits outside the op and its column bits
-    uint32_t opm = 0;
-#pragma unroll
-    for (int b = 0; b < K; ++b) opm |= 1u << op.lpos[b];
+    // LDS byte offsets of the column-tile index bits (tile bits outside the
+    // op and its column bits), from the host
     uint32_t img[LB + 2];
-    {
-        uint32_t mm = ((1u << m) - 1u) & ~opm & ~op.colmask;
 #pragma unroll
-        for (int t = 0; t < LB + 2; ++t) {
-            img[t] = mm ? sw(mm & (~mm + 1)) << 3 : 0u;
-            mm &= mm - 1;
-        }
-    }
+    for (int t = 0; t < LB + 2; ++t) img[t] = t < 6 ? op.cimg[t] : 0u;
     uint32_t gt = 0;  // first column tile of this wave: index H * wave
 #pragma unroll
     for (int b = 0; b < LB; ++b)
@@ -213,16 +204,27 @@ __device__ void phase_op(float2 *tile, float2 *ptab, const TileOpDev &op, const 
         lp[b] = b < op.k ? op.lpos[b] : 0;
         sh[b] = b < op.k ? op.k - 1 - b : 0;
     }
-    const uint32_t n_amp = 1u << m;
-    for (uint32_t j = threadIdx.x; j < n_amp; j += kThreads) {
+    // rows j = tid + 256 i, i in Gray-code order: the swizzle is linear, so
+    // sw(j) = sw(tid) ^ sw(256 i) and one bit of i changes per step
+    const uint32_t st = sw(threadIdx.x);
+    const int rows = (1 << m) / kThreads;
+    uint32_t i = 0, su = 0;
+    for (int g = 0; g < rows; ++g) {
+        if (g) {
+            const int b = __builtin_ctz(uint32_t(g));
+            i ^= 1u << b;
+            su ^= sw(uint32_t(kThreads) << b);
+        }
+        const uint32_t j = i * kThreads + threadIdx.x;
         int x = 0;
 #pragma unroll
         for (int b = 0; b < 3; ++b)
             if (b < op.k) x |= int((j >> lp[b]) & 1) << sh[b];
         if ((active >> x) & 1) {
+            const uint32_t a = st ^ su;
             const float2 f = ptab[x];
-            const float2 v = tile[sw(j)];
-            tile[sw(j)] = make_float2(f.x * v.x - f.y * v.y, f.x * v.y + f.y * v.x);
+            const float2 v = tile[a];
+            tile[a] = make_float2(f.x * v.x - f.y * v.y, f.x * v.y + f.y * v.x);
         }
     }
 }
@@ -263,11 +265,15 @@ __device__ __forceinline__ void tile_pass(float2 *amp, uint64_t t, const TileArg
 #pragma unroll
     for (int r = 0; r < PER; ++r)
         buf[r] = __builtin_nontemporal_load(reinterpret_cast<const vf4 *>(amp + (base | toff | ta.slot[r])));
+    // amplitudes 2 t and 2 t + 1 of a thread share one 16-byte LDS unit
+    // (sw(j + 1) = sw(j) ^ 1 for even j): one 16-byte access each, halves
+    // swapped when sw(j) is odd
+    const uint32_t st = sw(2u * threadIdx.x);
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
-        const uint32_t j = 2u * (threadIdx.x + uint32_t(r) * kThreads);
-        tile[sw(j)] = make_float2(buf[r].x, buf[r].y);
-        tile[sw(j + 1)] = make_float2(buf[r].z, buf[r].w);
+        const uint32_t s0 = st ^ sw(2u * uint32_t(r) * kThreads);
+        vf4 *u = reinterpret_cast<vf4 *>(tile) + (s0 >> 1);
+        *u = (s0 & 1u) ? vf4{buf[r].z, buf[r].w, buf[r].x, buf[r].y} : buf[r];
     }
     __syncthreads();
     // ---- ops
@@ -290,9 +296,9 @@ __device__ __forceinline__ void tile_pass(float2 *amp, uint64_t t, const TileArg
     // ---- store
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
-        const uint32_t j = 2u * (threadIdx.x + uint32_t(r) * kThreads);
-        const float2 a0 = tile[sw(j)], a1 = tile[sw(j + 1)];
-        buf[r] = vf4{a0.x, a0.y, a1.x, a1.y};
+        const uint32_t s0 = st ^ sw(2u * uint32_t(r) * kThreads);
+        const vf4 u = reinterpret_cast<const vf4 *>(tile)[s0 >> 1];
+        buf[r] = (s0 & 1u) ? vf4{u.z, u.w, u.x, u.y} : u;
     }
 #pragma unroll
     for (int r = 0; r < PER; ++r)
@@ -314,7 +320,7 @@ template <int M>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_tile(float2 *__restrict__ amp, uint64_t ntiles, TileArgs ta,
                                                    const TileOpDev *__restrict__ ops, const uint4 *__restrict__ data)
 {
-    __shared__ float2 lds[(1 << M) + 64];  // the tile, then a phase table
+    __shared__ __attribute__((aligned(16))) float2 lds[(1 << M) + 64];  // the tile, then a phase table
     const uint64_t toff = thread_offset(ta);
     for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x)
         tile_pass<M>(amp, t, ta, toff, ops, data, lds, lds + (1 << M));
@@ -329,7 +335,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
                                                          const TileOpDev *__restrict__ ops,
                                                          const uint4 *__restrict__ data)
 {
-    __shared__ float2 lds[(1 << M) + 64];
+    __shared__ __attribute__((aligned(16))) float2 lds[(1 << M) + 64];
     const TileTask task = tasks[blockIdx.x];
     const TileArgsDev &ad = args[task.arg];
     const uint64_t toff = thread_offset(ad.ta);

@@ -32,14 +32,27 @@ struct TileOpDev {
     uint32_t frag_stride;  // dense: 16-byte units per outer pattern
     uint32_t colmask;    // dense: the 4 tile bits that index the 16 columns of a matrix-core tile
     uint32_t offs_off;   // dense: per-lane LDS byte offsets (tile_lane_offsets), 16-byte units
+    uint32_t cimg[6];    // dense: LDS byte offsets of the column-tile index bits (lowest first)
 };
 
 // LDS layout of a tile: amplitude j (j < 2^13) lives in 8-byte slot
-// j ^ ((j >> 5) & 31) ^ (j >> 10).  LDS banks see the slot index mod 32, so
-// tile bit p lands on bank bit p mod 5: a 32-lane read is conflict-free when
-// its five lane bits sit on tile bits of distinct residues mod 5, and a
-// 16-lane write when its four do.
-__host__ __device__ inline uint32_t tile_swizzle(uint32_t j) { return j ^ ((j >> 5) & 31u) ^ (j >> 10); }
+// j ^ g(j >> 5), where g XORs a fixed 5-bit image for each set bit among
+// tile bits 5..12 (a bijection: bits 5.. are kept).  LDS banks see slot mod
+// 32 for a 32-lane 8-byte read and slot mod 16 for a 16-lane 8-byte write,
+// so tile bit p lands on bank vector image(p) (e_p for p < 5).  The images of
+// bits 5..12 were searched so that almost every 4- or 5-qubit op has four
+// column bits whose images are independent mod 16 and a lane qubit that
+// completes them to rank 5: its reads and writes are then conflict-free.
+constexpr uint32_t kTileSwizzleImage[8] = {11, 31, 31, 21, 14, 28, 3, 28};
+
+__host__ __device__ inline uint32_t tile_swizzle(uint32_t j)
+{
+    uint32_t x = 0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+        if ((j >> (5 + b)) & 1u) x ^= kTileSwizzleImage[b];
+    return j ^ x;
+}
 
 // Per-lane LDS byte offsets of a dense k-qubit tile op (k = 4, 5; D = 2^k,
 // MT = 2D / 16 row tiles, KS = 2D / 32 k-steps) relative to the column tile:
