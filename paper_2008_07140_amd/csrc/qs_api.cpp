@@ -907,7 +907,12 @@ qs_status launch_steps(qs_state *s, const std::vector<qs::PlanStep> &steps, cons
                      std::ldexp(1.0, s->n);
         const Features feat = sweep_features(st.sw, s->n, s->dt);
         Timed t(s, QS_K_TILE, sweep_bytes, flops, &feat);
-        hipError_t e = qs::launch_tile(s->amp, s->n, ta, dops + tp.first[i], dev + doff, s->stream);
+        bool k5 = false;
+        for (size_t o = 0; o < st.sw.ops.size(); ++o) {
+            const qs::TileOpDev &d = tp.ops[tp.first[i] + o];
+            k5 = k5 || (d.kind == 0 && d.k == 5);
+        }
+        hipError_t e = qs::launch_tile(s->amp, s->n, ta, dops + tp.first[i], dev + doff, k5, s->stream);
         if (e != hipSuccess) return hip_fail(e, "tile kernel launch");
     }
     return QS_OK;
@@ -1398,6 +1403,8 @@ qs_status batch_gates(Batch &B, const std::vector<int> &who, std::vector<std::ve
     const void *ddata = dev + up(ob);
     const qs::TileArgsDev *dargs = reinterpret_cast<const qs::TileArgsDev *>(dev + up(ob) + up(db));
     const qs::TileTask *dtasks = reinterpret_cast<const qs::TileTask *>(dev + up(ob) + up(db) + up(ab));
+    bool k5 = false;  // any 5-qubit block selects the 256-thread kernel for every launch
+    for (const auto &d : tp.ops) k5 = k5 || (d.kind == 0 && d.k == 5);
     size_t k = 0;
     for (size_t r = 0; r < rounds; ++r) {
         // standalone gates of this round (different states: any order)
@@ -1411,7 +1418,7 @@ qs_status batch_gates(Batch &B, const std::vector<int> &who, std::vector<std::ve
             const auto &tl = tasks[r * 4 + mm];
             if (tl.empty()) continue;
             hipError_t e = qs::launch_tile_multi(10 + mm, uint32_t(tl.size()), dtasks + task_off[r * 4 + mm], dargs,
-                                                 dops, ddata, s->stream);
+                                                 dops, ddata, k5, s->stream);
             if (e != hipSuccess) return hip_fail(e, "batched tile launch");
         }
     }

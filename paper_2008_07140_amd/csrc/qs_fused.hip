@@ -33,7 +33,6 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float vf4 __attribute__((ext_vector_type(4)));
 
-constexpr int kThreads = 256;
 
 typedef float v2f __attribute__((ext_vector_type(2)));
 typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
@@ -47,15 +46,6 @@ __device__ __forceinline__ void split2(float a, float b, v2bf &hi, v2bf &lo)
 }
 
 __device__ __forceinline__ uint32_t sw(uint32_t j) { return tile_swizzle(j); }
-
-// Scatter the low bits of x onto the set bits of mask (ascending).
-__device__ __forceinline__ uint32_t deposit32(uint32_t x, uint32_t mask)
-{
-    uint32_t r = 0;
-    for (uint32_t mm = mask; mm; mm &= mm - 1, x >>= 1)
-        if (x & 1) r |= mm & (~mm + 1);
-    return r;
-}
 
 // Dense k-qubit block (k = 4, 5) in real form: with D = 2^k, A is the
 // 2D x 2D real matrix [[Re U, -Im U], [Im U, Re U]] (entry by entry, re / im
@@ -187,6 +177,7 @@ __device__ __forceinline__ void dense_op(float2 *tile, const TileOpDev &op, cons
     }
 }
 
+template <int NT>
 __device__ void phase_op(float2 *tile, float2 *ptab, const TileOpDev &op, const uint4 *data,
                          int outer, int m)
 {
@@ -204,18 +195,18 @@ __device__ void phase_op(float2 *tile, float2 *ptab, const TileOpDev &op, const 
         lp[b] = b < op.k ? op.lpos[b] : 0;
         sh[b] = b < op.k ? op.k - 1 - b : 0;
     }
-    // rows j = tid + 256 i, i in Gray-code order: the swizzle is linear, so
-    // sw(j) = sw(tid) ^ sw(256 i) and one bit of i changes per step
+    // rows j = tid + NT i, i in Gray-code order: the swizzle is linear, so
+    // sw(j) = sw(tid) ^ sw(NT i) and one bit of i changes per step
     const uint32_t st = sw(threadIdx.x);
-    const int rows = (1 << m) / kThreads;
+    const int rows = (1 << m) / NT;
     uint32_t i = 0, su = 0;
     for (int g = 0; g < rows; ++g) {
         if (g) {
             const int b = __builtin_ctz(uint32_t(g));
             i ^= 1u << b;
-            su ^= sw(uint32_t(kThreads) << b);
+            su ^= sw(uint32_t(NT) << b);
         }
-        const uint32_t j = i * kThreads + threadIdx.x;
+        const uint32_t j = i * NT + threadIdx.x;
         int x = 0;
 #pragma unroll
         for (int b = 0; b < 3; ++b)
@@ -250,28 +241,31 @@ __device__ __forceinline__ int op_pattern(const TileOpDev &op, uint64_t base)
     return outer;
 }
 
-// One tile: load, apply ops, store.  `toff` is this thread's offset within
-// a tile (local index 2 * tid spread over the tile qubits).
-template <int M>
+// One tile: load, apply ops, store, with NT threads; K5: the op list may
+// hold 5-qubit blocks.  `toff` is this thread's offset within a tile (local
+// index 2 * tid spread over the tile qubits); thread slot r adds the uniform
+// ta.slot[r * NT / 256] (local index 2 NT r).
+template <int M, int NT, bool K5>
 __device__ __forceinline__ void tile_pass(float2 *amp, uint64_t t, const TileArgs &ta, uint64_t toff,
                                           const TileOpDev *ops, const uint4 *data, float2 *tile,
                                           float2 *ptab)
 {
-    constexpr int PER = (1 << M) / (2 * kThreads);  // 16-byte slots (2 amplitudes) per thread
+    constexpr int PER = (1 << M) / (2 * NT);  // 16-byte slots (2 amplitudes) per thread
+    constexpr int SS = NT / 256;
     // tile base: the tile index spread over the bits outside the tile
     const uint64_t base = tile_base(t, ta);
     // ---- load (non-temporal: every amplitude is read once per sweep)
     vf4 buf[PER];
 #pragma unroll
     for (int r = 0; r < PER; ++r)
-        buf[r] = __builtin_nontemporal_load(reinterpret_cast<const vf4 *>(amp + (base | toff | ta.slot[r])));
+        buf[r] = __builtin_nontemporal_load(reinterpret_cast<const vf4 *>(amp + (base | toff | ta.slot[r * SS])));
     // amplitudes 2 t and 2 t + 1 of a thread share one 16-byte LDS unit
     // (sw(j + 1) = sw(j) ^ 1 for even j): one 16-byte access each, halves
     // swapped when sw(j) is odd
     const uint32_t st = sw(2u * threadIdx.x);
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
-        const uint32_t s0 = st ^ sw(2u * uint32_t(r) * kThreads);
+        const uint32_t s0 = st ^ sw(2u * uint32_t(r) * NT);
         vf4 *u = reinterpret_cast<vf4 *>(tile) + (s0 >> 1);
         *u = (s0 & 1u) ? vf4{buf[r].z, buf[r].w, buf[r].x, buf[r].y} : buf[r];
     }
@@ -284,110 +278,128 @@ __device__ __forceinline__ void tile_pass(float2 *amp, uint64_t t, const TileArg
             if ((op.skip >> outer) & 1u) continue;  // identity on this tile
             const bf16x8 *fr =
                 reinterpret_cast<const bf16x8 *>(data + op.data_off + uint32_t(outer) * op.frag_stride);
-            if (op.k == 4)
-                dense_op<4, kThreads / 64>(tile, op, fr, data + op.offs_off, M);
+            if (!K5 || op.k == 4)
+                dense_op<4, NT / 64>(tile, op, fr, data + op.offs_off, M);
             else
-                dense_op<5, kThreads / 64>(tile, op, fr, data + op.offs_off, M);
+                dense_op<5, NT / 64>(tile, op, fr, data + op.offs_off, M);
         } else {
-            phase_op(tile, ptab, op, data, outer, M);
+            phase_op<NT>(tile, ptab, op, data, outer, M);
         }
         __syncthreads();
     }
     // ---- store
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
-        const uint32_t s0 = st ^ sw(2u * uint32_t(r) * kThreads);
+        const uint32_t s0 = st ^ sw(2u * uint32_t(r) * NT);
         const vf4 u = reinterpret_cast<const vf4 *>(tile)[s0 >> 1];
         buf[r] = (s0 & 1u) ? vf4{u.z, u.w, u.x, u.y} : u;
     }
 #pragma unroll
     for (int r = 0; r < PER; ++r)
-        __builtin_nontemporal_store(buf[r], reinterpret_cast<vf4 *>(amp + (base | toff | ta.slot[r])));
+        __builtin_nontemporal_store(buf[r], reinterpret_cast<vf4 *>(amp + (base | toff | ta.slot[r * SS])));
     __syncthreads();
 }
 
+template <int NT>
 __device__ __forceinline__ uint64_t thread_offset(const TileArgs &ta)
 {
-    // local index 2 * tid (bits 1..8); slot r adds the uniform ta.slot[r]
+    // local index 2 * tid: bits 1 .. log2(2 NT) - 1
+    constexpr int TB = NT == 512 ? 10 : 9;
     uint64_t toff = 0;
 #pragma unroll
-    for (int b = 1; b < 9; ++b)
+    for (int b = 1; b < TB; ++b)
         if (((2u * threadIdx.x) >> b) & 1u) toff |= uint64_t(1) << ta.qlo[b];
     return toff;
 }
 
-template <int M>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_tile(float2 *__restrict__ amp, uint64_t ntiles, TileArgs ta,
-                                                   const TileOpDev *__restrict__ ops, const uint4 *__restrict__ data)
+// Workgroup shapes.  Op lists with 5-qubit blocks: 256 threads, two waves
+// per SIMD (their operand fragments need up to 256 registers).  Lists of
+// 4-qubit blocks and phase ops: at most 128 registers, four waves per SIMD,
+// so each wave's waits are better covered; 512 threads on tiles of 12 or 13
+// qubits (16 or 32 column tiles per 4-qubit block, enough for 8 waves), 256
+// threads on smaller tiles (four workgroups per compute unit).
+constexpr int tile_threads(int m, bool k5) { return k5 || m < 12 ? 256 : 512; }
+#define QS_TILE_ATTRS(NT, K5) __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(K5 ? 2 : 4, K5 ? 2 : 4)))
+
+template <int M, int NT, bool K5>
+__global__ QS_TILE_ATTRS(NT, K5) void k_tile(float2 *__restrict__ amp, uint64_t ntiles, TileArgs ta,
+                                         const TileOpDev *__restrict__ ops, const uint4 *__restrict__ data)
 {
     __shared__ __attribute__((aligned(16))) float2 lds[(1 << M) + 64];  // the tile, then a phase table
-    const uint64_t toff = thread_offset(ta);
+    const uint64_t toff = thread_offset<NT>(ta);
     for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x)
-        tile_pass<M>(amp, t, ta, toff, ops, data, lds, lds + (1 << M));
+        tile_pass<M, NT, K5>(amp, t, ta, toff, ops, data, lds, lds + (1 << M));
 }
 
 // Batched form: workgroup b runs tile tasks[b].tile of the state described by
 // args[tasks[b].arg] (its own amplitudes, tile qubits and op list), so one
 // launch covers one sweep of many independent states.
-template <int M>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_tile_multi(const TileTask *__restrict__ tasks,
-                                                         const TileArgsDev *__restrict__ args,
-                                                         const TileOpDev *__restrict__ ops,
-                                                         const uint4 *__restrict__ data)
+template <int M, int NT, bool K5>
+__global__ QS_TILE_ATTRS(NT, K5) void k_tile_multi(const TileTask *__restrict__ tasks,
+                                               const TileArgsDev *__restrict__ args,
+                                               const TileOpDev *__restrict__ ops,
+                                               const uint4 *__restrict__ data)
 {
     __shared__ __attribute__((aligned(16))) float2 lds[(1 << M) + 64];
     const TileTask task = tasks[blockIdx.x];
     const TileArgsDev &ad = args[task.arg];
-    const uint64_t toff = thread_offset(ad.ta);
-    tile_pass<M>(ad.amp, task.tile, ad.ta, toff, ops + ad.op_off, data, lds, lds + (1 << M));
+    const uint64_t toff = thread_offset<NT>(ad.ta);
+    tile_pass<M, NT, K5>(ad.amp, task.tile, ad.ta, toff, ops + ad.op_off, data, lds, lds + (1 << M));
+}
+
+template <int M, bool K5>
+void launch_m(float2 *a, uint64_t grid, uint64_t ntiles, const TileArgs &ta, const TileOpDev *ops,
+              const uint4 *d, hipStream_t st)
+{
+    constexpr int NT = tile_threads(M, K5);
+    hipLaunchKernelGGL((k_tile<M, NT, K5>), dim3(unsigned(grid)), dim3(NT), 0, st, a, ntiles, ta, ops, d);
+}
+
+template <int M, bool K5>
+void launch_multi_m(uint32_t ntasks, const TileTask *tasks, const TileArgsDev *args, const TileOpDev *ops,
+                    const uint4 *d, hipStream_t st)
+{
+    constexpr int NT = tile_threads(M, K5);
+    hipLaunchKernelGGL((k_tile_multi<M, NT, K5>), dim3(ntasks), dim3(NT), 0, st, tasks, args, ops, d);
 }
 
 }  // namespace
 
-
 hipError_t launch_tile(void *amp, int n, const TileArgs &ta, const TileOpDev *dev_ops,
-                       const void *dev_data, hipStream_t st)
+                       const void *dev_data, bool k5, hipStream_t st)
 {
     if (ta.m < 10 || ta.m > 13 || ta.m > n || ta.nouter != n - ta.m) return hipErrorInvalidValue;
     const uint64_t ntiles = uint64_t(1) << (n - ta.m);
     const uint64_t grid = ntiles < (uint64_t(1) << 20) ? ntiles : (uint64_t(1) << 20);
     float2 *a = (float2 *)amp;
     const uint4 *d = (const uint4 *)dev_data;
-    switch (ta.m) {
-    case 10:
-        hipLaunchKernelGGL(k_tile<10>, dim3(unsigned(grid)), dim3(kThreads), 0, st, a, ntiles, ta, dev_ops, d);
-        break;
-    case 11:
-        hipLaunchKernelGGL(k_tile<11>, dim3(unsigned(grid)), dim3(kThreads), 0, st, a, ntiles, ta, dev_ops, d);
-        break;
-    case 12:
-        hipLaunchKernelGGL(k_tile<12>, dim3(unsigned(grid)), dim3(kThreads), 0, st, a, ntiles, ta, dev_ops, d);
-        break;
-    default:
-        hipLaunchKernelGGL(k_tile<13>, dim3(unsigned(grid)), dim3(kThreads), 0, st, a, ntiles, ta, dev_ops, d);
-        break;
+    switch (ta.m * 2 + int(k5)) {
+    case 20: launch_m<10, false>(a, grid, ntiles, ta, dev_ops, d, st); break;
+    case 21: launch_m<10, true>(a, grid, ntiles, ta, dev_ops, d, st); break;
+    case 22: launch_m<11, false>(a, grid, ntiles, ta, dev_ops, d, st); break;
+    case 23: launch_m<11, true>(a, grid, ntiles, ta, dev_ops, d, st); break;
+    case 24: launch_m<12, false>(a, grid, ntiles, ta, dev_ops, d, st); break;
+    case 25: launch_m<12, true>(a, grid, ntiles, ta, dev_ops, d, st); break;
+    case 26: launch_m<13, false>(a, grid, ntiles, ta, dev_ops, d, st); break;
+    default: launch_m<13, true>(a, grid, ntiles, ta, dev_ops, d, st); break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_tile_multi(int m, uint32_t ntasks, const TileTask *tasks, const TileArgsDev *args,
-                             const TileOpDev *dev_ops, const void *dev_data, hipStream_t st)
+                             const TileOpDev *dev_ops, const void *dev_data, bool k5, hipStream_t st)
 {
     if (m < 10 || m > 13 || ntasks == 0) return hipErrorInvalidValue;
     const uint4 *d = (const uint4 *)dev_data;
-    switch (m) {
-    case 10:
-        hipLaunchKernelGGL(k_tile_multi<10>, dim3(ntasks), dim3(kThreads), 0, st, tasks, args, dev_ops, d);
-        break;
-    case 11:
-        hipLaunchKernelGGL(k_tile_multi<11>, dim3(ntasks), dim3(kThreads), 0, st, tasks, args, dev_ops, d);
-        break;
-    case 12:
-        hipLaunchKernelGGL(k_tile_multi<12>, dim3(ntasks), dim3(kThreads), 0, st, tasks, args, dev_ops, d);
-        break;
-    default:
-        hipLaunchKernelGGL(k_tile_multi<13>, dim3(ntasks), dim3(kThreads), 0, st, tasks, args, dev_ops, d);
-        break;
+    switch (m * 2 + int(k5)) {
+    case 20: launch_multi_m<10, false>(ntasks, tasks, args, dev_ops, d, st); break;
+    case 21: launch_multi_m<10, true>(ntasks, tasks, args, dev_ops, d, st); break;
+    case 22: launch_multi_m<11, false>(ntasks, tasks, args, dev_ops, d, st); break;
+    case 23: launch_multi_m<11, true>(ntasks, tasks, args, dev_ops, d, st); break;
+    case 24: launch_multi_m<12, false>(ntasks, tasks, args, dev_ops, d, st); break;
+    case 25: launch_multi_m<12, true>(ntasks, tasks, args, dev_ops, d, st); break;
+    case 26: launch_multi_m<13, false>(ntasks, tasks, args, dev_ops, d, st); break;
+    default: launch_multi_m<13, true>(ntasks, tasks, args, dev_ops, d, st); break;
     }
     return hipGetLastError();
 }

@@ -75,9 +75,10 @@ struct TileArgsDev {
     TileArgs ta;
 };
 
+// k5: the op list holds 5-qubit blocks (selects the kernel configuration).
 hipError_t launch_tile(void *amp, int n, const TileArgs &ta, const TileOpDev *dev_ops,
-                       const void *dev_data, hipStream_t st);
+                       const void *dev_data, bool k5, hipStream_t st);
 hipError_t launch_tile_multi(int m, uint32_t ntasks, const TileTask *tasks, const TileArgsDev *args,
-                             const TileOpDev *dev_ops, const void *dev_data, hipStream_t st);
+                             const TileOpDev *dev_ops, const void *dev_data, bool k5, hipStream_t st);
 
 }  // namespace qs
