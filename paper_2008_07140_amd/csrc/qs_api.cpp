@@ -751,14 +751,7 @@ qs::TileArgs make_tile_args(const qs::Sweep &sw, int n)
     ta.m = int(sw.Q.size());
     ta.nops = int(sw.ops.size());
     const auto &Q = sw.Q;
-    for (int b = 0; b < 10; ++b) ta.qlo[b] = uint16_t(b < ta.m ? Q[b] : 0);
-    for (int r = 0; r < 16; ++r) {
-        uint64_t off = 0;
-        const uint64_t j = uint64_t(r) * 512;  // local index of slot r (2 x 256 threads)
-        for (int b = 9; b < ta.m; ++b)
-            if ((j >> b) & 1) off |= uint64_t(1) << Q[b];
-        ta.slot[r] = off;
-    }
+    for (int b = 0; b < 16; ++b) ta.q[b] = uint8_t(b < ta.m ? Q[b] : 0);
     uint64_t qm = 0;
     for (int q : Q) qm |= uint64_t(1) << q;
     const uint64_t all = (n >= 64) ? ~uint64_t(0) : ((uint64_t(1) << n) - 1);

@@ -37,59 +37,93 @@ typedef float vf4 __attribute__((ext_vector_type(4)));
 typedef float v2f __attribute__((ext_vector_type(2)));
 typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
 
+// A bf16 pair with the given bits, held in a scalar register.  The pairs
+// (-1, 0) and (0, -1) feed the remainder dot products below; left visible, the
+// compiler encodes (-1, 0) as the inline constant -1.0, which the hardware
+// does not read as that pair (measured: wrong remainders), so the bits are
+// hidden behind an empty asm statement.
+__device__ __forceinline__ v2bf scalar_pair(uint32_t bits)
+{
+    asm("" : "+s"(bits));
+    return __builtin_bit_cast(v2bf, bits);
+}
+
 // Split two floats into bfloat16 hi parts and the bfloat16 of the remainders
-// (packed conversions; the remainder of each is exact in FP32).
-__device__ __forceinline__ void split2(float a, float b, v2bf &hi, v2bf &lo)
+// (packed conversions).  Each remainder a - hi[0] is a bf16 dot product of the
+// packed hi parts with m0 = (-1, 0) (m1 = (0, -1) for b) accumulated onto a:
+// one instruction, with no conversion of hi back to FP32, and exact (the
+// remainder fits in FP32).
+__device__ __forceinline__ void split2(float a, float b, v2bf m0, v2bf m1, v2bf &hi, v2bf &lo)
 {
     hi = __builtin_convertvector(v2f{a, b}, v2bf);
-    lo = __builtin_convertvector(v2f{a - float(hi[0]), b - float(hi[1])}, v2bf);
+    lo = __builtin_convertvector(
+        v2f{__builtin_amdgcn_fdot2_f32_bf16(hi, m0, a, false), __builtin_amdgcn_fdot2_f32_bf16(hi, m1, b, false)},
+        v2bf);
 }
 
 __device__ __forceinline__ uint32_t sw(uint32_t j) { return tile_swizzle(j); }
 
-// Dense k-qubit block (k = 4, 5) in real form: with D = 2^k, A is the
-// 2D x 2D real matrix [[Re U, -Im U], [Im U, Re U]] (entry by entry, re / im
-// interleaved) and a group of the tile is one column of X, so the re and im
-// parts of an output amplitude come out in adjacent accumulator registers.
-// Fragment (mt, s) of lane l holds A[16 mt + l % 16][32 s + 8 (l / 16) + j],
-// j < 8 (hi parts of all fragments, then the remainders).  `fr` points at the
-// fragments of this tile's outer pattern (global memory or LDS); NW waves
-// share the column tiles.
-//
-// Column c of a matrix-core tile sits on the 4 tile bits of op.colmask; the
-// column tile index on the other bits outside the op (blockmask).  A wave
-// walks its column tiles in Gray-code order, so the uniform part of the LDS
-// address changes by one precomputed XOR per step.
-template <int K, int NW>
-__device__ __forceinline__ void dense_op(float2 *tile, const TileOpDev &op, const bf16x8 *fr, const uint4 *offs,
-                                         int m)
-{
-    constexpr int D = 1 << K, MT = 2 * D / 16, KS = 2 * D / 32;
-    constexpr int H = K == 4 ? 2 : 1;  // column tiles per step: at least 4 accumulator chains
-    constexpr int LB = (H == 2 ? 1 : 0) + (NW == 8 ? 3 : NW == 4 ? 2 : NW == 2 ? 1 : 0);
-    constexpr int NQ = tile_lane_offsets(K) / 4;
-    constexpr int MAXSTEPS = 4;  // at most 32 column tiles (m <= 13) over H * NW >= 8 per step
-    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-    const int ntiles = 1 << (m - K - 4);
-    if (H * wave >= ntiles) return;  // fewer column tiles than waves
+// Operand fragments of a dense k-qubit block (k = 4, 5) for one outer pattern
+// and this lane's LDS offsets, in registers.  The block is applied in real
+// form: with D = 2^k, A is the 2D x 2D real matrix [[Re U, -Im U], [Im U, Re U]]
+// (entry by entry, re / im interleaved) and a group of the tile is one column
+// of X, so the re and im parts of an output amplitude come out in adjacent
+// accumulator registers.  Fragment (mt, s) of lane l holds
+// A[16 mt + l % 16][32 s + 8 (l / 16) + j], j < 8 (hi parts of all fragments,
+// then the remainders).
+template <int K>
+struct Frags {
+    static constexpr int D = 1 << K, MT = 2 * D / 16, KS = 2 * D / 32, NQ = tile_lane_offsets(K) / 4;
     bf16x8 ahi[MT][KS], alo[MT][KS];
+    uint32_t ofs[4 * NQ];  // KS * 4 read offsets, then MT * 2 write offsets
+};
+
+template <int K>
+__device__ __forceinline__ void load_frags(Frags<K> &f, const bf16x8 *fr, const uint4 *offs)
+{
+    constexpr int MT = Frags<K>::MT, KS = Frags<K>::KS, NQ = Frags<K>::NQ;
+    const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
-            ahi[mt][s] = fr[(mt * KS + s) * 64 + lane];
-            alo[mt][s] = fr[MT * KS * 64 + (mt * KS + s) * 64 + lane];
+            f.ahi[mt][s] = fr[(mt * KS + s) * 64 + lane];
+            f.alo[mt][s] = fr[MT * KS * 64 + (mt * KS + s) * 64 + lane];
         }
-    uint32_t ofs[4 * NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         const uint4 o = offs[lane * NQ + q];
-        ofs[4 * q] = o.x;
-        ofs[4 * q + 1] = o.y;
-        ofs[4 * q + 2] = o.z;
-        ofs[4 * q + 3] = o.w;
+        f.ofs[4 * q] = o.x;
+        f.ofs[4 * q + 1] = o.y;
+        f.ofs[4 * q + 2] = o.z;
+        f.ofs[4 * q + 3] = o.w;
     }
-    const uint32_t *rd = ofs, *wr = ofs + KS * 4;
+}
+
+// Apply one dense block to the tile with fragments f; NW waves share the
+// column tiles.  Column c of a matrix-core tile sits on the 4 tile bits of
+// op.colmask, the column tile index on the other bits outside the op.  A wave
+// walks its column tiles in Gray-code order, so the uniform part of the LDS
+// address changes by one precomputed XOR per step, and reads the next tile's
+// amplitudes while the current one is multiplied.  `prefetch` is called once
+// on every path, after the wave's last LDS read of the op (its input buffers
+// are then free): the caller loads the next op's fragments there, so their
+// latency overlaps the last multiplications, the write-back and the barrier.
+template <int K, int NW, class Prefetch>
+__device__ __forceinline__ void dense_op(float2 *tile, const TileOpDev &op, const Frags<K> &f, int m,
+                                         Prefetch &&prefetch)
+{
+    constexpr int MT = Frags<K>::MT, KS = Frags<K>::KS;
+    constexpr int H = K == 4 ? 2 : 1;  // column tiles per step: at least 4 accumulator chains
+    constexpr int LB = (H == 2 ? 1 : 0) + (NW == 8 ? 3 : NW == 4 ? 2 : NW == 2 ? 1 : 0);
+    constexpr int MAXSTEPS = 4;  // at most 32 column tiles (m <= 13) over H * NW >= 8 per step
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const int ntiles = 1 << (m - K - 4);
+    if (H * wave >= ntiles) {  // fewer column tiles than waves
+        prefetch();
+        return;
+    }
+    const uint32_t *rd = f.ofs, *wr = f.ofs + KS * 4;
     // LDS byte offsets of the column-tile index bits (tile bits outside the
     // op and its column bits), from the host
     uint32_t img[LB + 2];
@@ -102,8 +136,7 @@ __device__ __forceinline__ void dense_op(float2 *tile, const TileOpDev &op, cons
     gt = __builtin_amdgcn_readfirstlane(gt);
     const int steps = ntiles > H * NW ? ntiles / (H * NW) : 1;
     char *tb = reinterpret_cast<char *>(tile);
-    // A wave walks its column tiles in Gray-code order (one XOR per step) and
-    // reads the next tile's amplitudes while the current one is multiplied.
+    const v2bf m0 = scalar_pair(0x0000bf80u), m1 = scalar_pair(0xbf800000u);
     float2 v[2][H][KS][4];
     auto read_x = [&](float2 (&dst)[H][KS][4], uint32_t g0) {
 #pragma unroll
@@ -131,12 +164,13 @@ __device__ __forceinline__ void dense_op(float2 *tile, const TileOpDev &op, cons
 #pragma unroll
                 for (int jj = 0; jj < 4; ++jj) {
                     v2bf hh, ll;
-                    split2(x[h][s][jj].x, x[h][s][jj].y, hh, ll);
+                    split2(x[h][s][jj].x, x[h][s][jj].y, m0, m1, hh, ll);
                     bhi[h][s][2 * jj] = hh[0];
                     bhi[h][s][2 * jj + 1] = hh[1];
                     blo[h][s][2 * jj] = ll[0];
                     blo[h][s][2 * jj + 1] = ll[1];
                 }
+        if (g + 1 == steps) prefetch();
         f32x4 acc[H][MT];
 #pragma unroll
         for (int h = 0; h < H; ++h)
@@ -149,21 +183,21 @@ __device__ __forceinline__ void dense_op(float2 *tile, const TileOpDev &op, cons
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                 for (int h = 0; h < H; ++h)
-                    acc[h][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[mt][s], bhi[h][s], acc[h][mt], 0, 0, 0);
+                    acc[h][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.ahi[mt][s], bhi[h][s], acc[h][mt], 0, 0, 0);
 #pragma unroll
         for (int s = 0; s < KS; ++s)
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                 for (int h = 0; h < H; ++h)
-                    acc[h][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[mt][s], blo[h][s], acc[h][mt], 0, 0, 0);
+                    acc[h][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.ahi[mt][s], blo[h][s], acc[h][mt], 0, 0, 0);
 #pragma unroll
         for (int s = 0; s < KS; ++s)
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                 for (int h = 0; h < H; ++h)
-                    acc[h][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[mt][s], bhi[h][s], acc[h][mt], 0, 0, 0);
+                    acc[h][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.alo[mt][s], bhi[h][s], acc[h][mt], 0, 0, 0);
 #pragma unroll
         for (int h = 0; h < H; ++h) {
             const uint32_t gh = h ? gt ^ img[0] : gt;
@@ -241,24 +275,45 @@ __device__ __forceinline__ int op_pattern(const TileOpDev &op, uint64_t base)
     return outer;
 }
 
+// Global offset of local index r << TB (the r-th 16-byte slot of a thread,
+// TB = log2(2 NT)): bit i of r lands on tile qubit q[TB + i].  The positions
+// pass through an empty asm statement so the offsets are recomputed where
+// they are used (a few scalar instructions) instead of held in scalar
+// registers across the op loop.
+template <int TB, int PER>
+__device__ __forceinline__ uint64_t slot_offset(const TileArgs &ta, int r)
+{
+    static_assert(TB == 9 || TB == 10, "thread bits");
+    uint32_t w = uint32_t(ta.q[TB]) | uint32_t(ta.q[TB + 1]) << 8 | uint32_t(ta.q[TB + 2]) << 16 |
+                 (TB == 9 ? uint32_t(ta.q[TB + 3]) << 24 : 0u);
+    w = __builtin_amdgcn_readfirstlane(w);
+    asm("" : "+s"(w));
+    uint64_t off = 0;
+#pragma unroll
+    for (int i = 0; (1 << i) < PER; ++i)
+        if ((r >> i) & 1) off |= uint64_t(1) << ((w >> (8 * i)) & 63u);
+    return off;
+}
+
 // One tile: load, apply ops, store, with NT threads; K5: the op list may
 // hold 5-qubit blocks.  `toff` is this thread's offset within a tile (local
 // index 2 * tid spread over the tile qubits); thread slot r adds the uniform
-// ta.slot[r * NT / 256] (local index 2 NT r).
+// slot_offset (local index 2 NT r).
 template <int M, int NT, bool K5>
 __device__ __forceinline__ void tile_pass(float2 *amp, uint64_t t, const TileArgs &ta, uint64_t toff,
                                           const TileOpDev *ops, const uint4 *data, float2 *tile,
                                           float2 *ptab)
 {
     constexpr int PER = (1 << M) / (2 * NT);  // 16-byte slots (2 amplitudes) per thread
-    constexpr int SS = NT / 256;
+    constexpr int TB = NT == 512 ? 10 : 9;
     // tile base: the tile index spread over the bits outside the tile
     const uint64_t base = tile_base(t, ta);
     // ---- load (non-temporal: every amplitude is read once per sweep)
     vf4 buf[PER];
 #pragma unroll
     for (int r = 0; r < PER; ++r)
-        buf[r] = __builtin_nontemporal_load(reinterpret_cast<const vf4 *>(amp + (base | toff | ta.slot[r * SS])));
+        buf[r] = __builtin_nontemporal_load(
+            reinterpret_cast<const vf4 *>(amp + (base | toff | slot_offset<TB, PER>(ta, r))));
     // amplitudes 2 t and 2 t + 1 of a thread share one 16-byte LDS unit
     // (sw(j + 1) = sw(j) ^ 1 for even j): one 16-byte access each, halves
     // swapped when sw(j) is odd
@@ -270,22 +325,81 @@ __device__ __forceinline__ void tile_pass(float2 *amp, uint64_t t, const TileArg
         *u = (s0 & 1u) ? vf4{buf[r].z, buf[r].w, buf[r].x, buf[r].y} : buf[r];
     }
     __syncthreads();
-    // ---- ops
-    for (int oi = 0; oi < ta.nops; ++oi) {
-        const TileOpDev op = ops[oi];
-        const int outer = op_pattern(op, base);
-        if (op.kind == 0) {
-            if ((op.skip >> outer) & 1u) continue;  // identity on this tile
-            const bf16x8 *fr =
-                reinterpret_cast<const bf16x8 *>(data + op.data_off + uint32_t(outer) * op.frag_stride);
-            if (!K5 || op.k == 4)
-                dense_op<4, NT / 64>(tile, op, fr, data + op.offs_off, M);
-            else
-                dense_op<5, NT / 64>(tile, op, fr, data + op.offs_off, M);
-        } else {
-            phase_op<NT>(tile, ptab, op, data, outer, M);
+    // ---- ops (an op whose matrix is the identity on this tile's outer
+    // pattern is skipped, barrier included: the pattern is uniform)
+    if constexpr (K5) {
+        for (int oi = 0; oi < ta.nops; ++oi) {
+            const TileOpDev op = ops[oi];
+            const int outer = op_pattern(op, base);
+            if (op.kind == 0) {
+                if ((op.skip >> outer) & 1u) continue;
+                const bf16x8 *fr =
+                    reinterpret_cast<const bf16x8 *>(data + op.data_off + uint32_t(outer) * op.frag_stride);
+                if (op.k == 4) {
+                    Frags<4> f;
+                    load_frags<4>(f, fr, data + op.offs_off);
+                    dense_op<4, NT / 64>(tile, op, f, M, [] {});
+                } else {
+                    Frags<5> f;
+                    load_frags<5>(f, fr, data + op.offs_off);
+                    dense_op<5, NT / 64>(tile, op, f, M, [] {});
+                }
+            } else {
+                phase_op<NT>(tile, ptab, op, data, outer, M);
+            }
+            __syncthreads();
         }
-        __syncthreads();
+    } else {
+        // 4-qubit blocks only: the descriptor and fragments of op i + 1 load
+        // while op i finishes, into two register sets used in turn
+        // Descriptors are read where they are used, through a pointer the
+        // compiler cannot see through, so at most one and a few fields of the
+        // next stay in scalar registers.
+        auto desc = [&](int i) {
+            uint32_t ui = __builtin_amdgcn_readfirstlane(uint32_t(i));
+            asm("" : "+s"(ui));
+            return ops + ui;
+        };
+        Frags<4> fa, fb;
+        // (written on every path, so the previous contents of a set are dead)
+        auto fetch = [&](Frags<4> &f, const TileOpDev &o, int pat) {
+            if (o.kind == 0 && !((o.skip >> pat) & 1u))
+                load_frags<4>(f, reinterpret_cast<const bf16x8 *>(data + o.data_off + uint32_t(pat) * o.frag_stride),
+                              data + o.offs_off);
+            else
+                f = Frags<4>{};
+        };
+        if (ta.nops > 0) {
+            const TileOpDev *p0 = desc(0);
+            fetch(fa, *p0, op_pattern(*p0, base));
+        }
+        auto run = [&](int oi, const Frags<4> &cur, Frags<4> &nxt) {
+            const TileOpDev &op = *desc(oi);
+            const int outer = op_pattern(op, base);
+            auto prefetch = [&] {
+                if (oi + 1 < ta.nops) {
+                    const TileOpDev *pn = desc(oi + 1);
+                    fetch(nxt, *pn, op_pattern(*pn, base));
+                } else {
+                    nxt = Frags<4>{};
+                }
+            };
+            if (op.kind != 0) {
+                prefetch();
+                phase_op<NT>(tile, ptab, op, data, outer, M);
+                __syncthreads();
+            } else if ((op.skip >> outer) & 1u) {
+                prefetch();
+            } else {
+                dense_op<4, NT / 64>(tile, op, cur, M, prefetch);
+                __syncthreads();
+            }
+        };
+        for (int oi = 0; oi < ta.nops; oi += 2) {
+            run(oi, fa, fb);
+            if (oi + 1 >= ta.nops) break;
+            run(oi + 1, fb, fa);
+        }
     }
     // ---- store
 #pragma unroll
@@ -296,7 +410,8 @@ __device__ __forceinline__ void tile_pass(float2 *amp, uint64_t t, const TileArg
     }
 #pragma unroll
     for (int r = 0; r < PER; ++r)
-        __builtin_nontemporal_store(buf[r], reinterpret_cast<vf4 *>(amp + (base | toff | ta.slot[r * SS])));
+        __builtin_nontemporal_store(buf[r],
+                                    reinterpret_cast<vf4 *>(amp + (base | toff | slot_offset<TB, PER>(ta, r))));
     __syncthreads();
 }
 
@@ -308,7 +423,7 @@ __device__ __forceinline__ uint64_t thread_offset(const TileArgs &ta)
     uint64_t toff = 0;
 #pragma unroll
     for (int b = 1; b < TB; ++b)
-        if (((2u * threadIdx.x) >> b) & 1u) toff |= uint64_t(1) << ta.qlo[b];
+        if (((2u * threadIdx.x) >> b) & 1u) toff |= uint64_t(1) << ta.q[b];
     return toff;
 }
 
@@ -342,7 +457,7 @@ __global__ QS_TILE_ATTRS(NT, K5) void k_tile_multi(const TileTask *__restrict__ 
 {
     __shared__ __attribute__((aligned(16))) float2 lds[(1 << M) + 64];
     const TileTask task = tasks[blockIdx.x];
-    const TileArgsDev &ad = args[task.arg];
+    const TileArgsDev ad = args[task.arg];
     const uint64_t toff = thread_offset<NT>(ad.ta);
     tile_pass<M, NT, K5>(ad.amp, task.tile, ad.ta, toff, ops + ad.op_off, data, lds, lds + (1 << M));
 }

@@ -16,9 +16,8 @@ struct TileArgs {
     int nops;
     int nouter;          // n - m
     int pad;
-    uint64_t slot[16];   // global offset of local index 512 r (the r-th 16-byte slot of a thread)
     uint64_t omask;      // qubits outside the tile
-    uint16_t qlo[10];    // global positions of local bits 0..9
+    uint8_t q[16];       // global position of local bit b (b < m)
 };
 
 struct TileOpDev {
