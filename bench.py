@@ -245,7 +245,8 @@ def summarize_profiles(d):
     files = glob.glob(os.path.join(d, "ktrace", "**", "*kernel_stats.csv"), recursive=True)
     rows = _csv_rows(files[0])
     kl = ["# Kernel time, 30-qubit depth-40 circuit (rqc30_d40), fused c64 and plain c128 paths", "",
-          "`rocprofv3 --kernel-trace --stats` over warm-up 1 + 2 timed steps of each path.", "",
+          "`rocprofv3 --kernel-trace --stats` over the warm-up runs (plain c128: 1; fused c64: 5, four of"
+          " which time the candidate tile orders) and 2 timed steps of each path.", "",
           "| kernel | calls | total ms | average us | % |", "|---|---|---|---|---|"]
     for r in rows[:20]:
         kl.append("| %s | %s | %.1f | %.1f | %s |" % (short_kernel(r["Name"]), r["Calls"],
@@ -259,6 +260,22 @@ def summarize_profiles(d):
                       "%.0f GB/s on %.4g algorithmic bytes per launch"
                       % (path, pr["gates_per_s"], pr["dominant"], rf["kernel"], rf["avg_launch_ms"] * 1e3,
                          rf["achieved"], rf["alg_bytes_per_launch"]))
+    # the same trace per dispatch: the dominant kernel of each path over the
+    # timed steps only (the last steps x launches-per-step dispatches of its
+    # class), to set beside the bench line's event timing
+    tr = glob.glob(os.path.join(d, "ktrace", "**", "*kernel_trace.csv"), recursive=True)
+    if tr and bench_line:
+        trows = sorted(_csv_rows(tr[0]), key=lambda r: int(r["Start_Timestamp"]))
+        kl += ["", "Per dispatch (kernel trace), timed steps only:", ""]
+        for path, pr in bench_line.get("paths", {}).items():
+            dom = pr["dominant"]
+            nl = pr["kernels"][dom]["launches"] * bench_line.get("steps", 0)
+            durs = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in trows
+                    if kernel_class_of(r["Kernel_Name"]) == dom][-nl:] if nl else []
+            if durs:
+                kl.append("- %s: class `%s`, last %d dispatches, average %.1f us (HIP events: %.1f us)"
+                          % (path, dom, len(durs), sum(durs) / len(durs) / 1e3,
+                             pr["roofline"]["avg_launch_ms"] * 1e3))
     kl += ["", "Command (from the repository root):", "", "```", cmds["ktrace"], "```", "",
            "Kernel sources hash: %s" % src]
     with open(os.path.join(prof, "kernel_stats_rqc30_d40.md"), "w") as f:
@@ -275,8 +292,12 @@ def run_path(qs, torch, cg, name, n, circuit, gates, steps, warmup, kmax, plan, 
     st = qs.State(n, dt, buffer=buf, stream=stream.cuda_stream)
     plan_id = ({"learned": qs.PLAN_LEARNED, "autotune": qs.PLAN_AUTOTUNE}.get(plan, qs.PLAN_GREEDY)
                if fused else qs.PLAN_UNFUSED)
+    if fused and dt == qs.C64:
+        # the first runs of a plan time each candidate tile order per sweep
+        # (RunOpts.tile_order = 0): they are plan preparation, untimed
+        warmup = max(warmup, qs.TILE_ORDERS + 1)
     if plan_id == qs.PLAN_AUTOTUNE:  # every candidate runs once before the timed steps
-        warmup = max(warmup, circuit.autotune_result(n, dt)[1] + 1)
+        warmup = max(warmup, circuit.autotune_result(n, dt)[1] + qs.TILE_ORDERS + 1)
     pm = [n - 1, n // 2, 0]
 
     def step():

@@ -171,7 +171,16 @@ typedef struct {
     int64_t *chosen;    /* optional output: Kraus branch of every noise site */
     int64_t chosen_len; /* capacity of `chosen` */
     int tile_qubits;    /* complex64 fused plans: qubits per LDS tile, 10..13 (0 = default) */
+    int tile_order;     /* complex64 fused plans: order in which a sweep visits its tiles.
+                         * 0 = chosen per sweep by measurement: the first QS_TILE_ORDERS runs of
+                         * a plan each use one candidate order for every sweep, timed with HIP
+                         * events (those runs synchronise the stream at their end), and later
+                         * runs use each sweep's fastest; 1..QS_TILE_ORDERS = that candidate
+                         * for every sweep.  Results do not depend on the order. */
 } qs_run_opts;
+
+/* Candidate tile orders of a sweep (qs_run_opts.tile_order). */
+#define QS_TILE_ORDERS 4
 
 /* Shape of the plan qs_run_circuit would execute for this circuit on an
  * n-qubit state of dtype dt with these options (opts may be NULL): the number

@@ -880,20 +880,62 @@ qs_status upload_program(qs_state *s, const TileProgram &tp, uint64_t id, size_t
     return QS_OK;
 }
 
-qs_status launch_steps(qs_state *s, const std::vector<qs::PlanStep> &steps, const TileProgram &tp, uint64_t id)
+// Tile order of every sweep of one tiled segment (qs_run_opts.tile_order =
+// 0).  The first QS_TILE_ORDERS runs of the segment each time all its sweeps
+// under one candidate order; later runs take each sweep's fastest.  Shared by
+// every state that runs the cached plan.
+struct OrderTune {
+    std::mutex mu;
+    int next = 0;                                       // next candidate to time
+    int done = 0;                                       // candidates timed
+    std::vector<std::array<float, QS_TILE_ORDERS>> ms;  // per step
+    std::vector<uint8_t> best;                          // per step, once every candidate is timed
+};
+
+// Events bracketing the sweeps of one timing run.
+struct SweepEvents {
+    std::vector<hipEvent_t> ev;
+    ~SweepEvents()
+    {
+        for (hipEvent_t e : ev) hipEventDestroy(e);
+    }
+    hipError_t record(hipStream_t st)
+    {
+        hipEvent_t e = nullptr;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        ev.push_back(e);
+        return hipEventRecord(e, st);
+    }
+};
+
+qs_status launch_steps(qs_state *s, const std::vector<qs::PlanStep> &steps, const TileProgram &tp, uint64_t id,
+                       OrderTune *tune, int fixed_order)
 {
     size_t doff = 0;
     if (qs_status e = upload_program(s, tp, id, doff)) return e;
     unsigned char *dev = static_cast<unsigned char *>(s->prog);
     const qs::TileOpDev *dops = reinterpret_cast<const qs::TileOpDev *>(dev);
     const double sweep_bytes = 2.0 * 8.0 * std::ldexp(1.0, s->n);
+    int cand = -1;  // candidate order timed by this run
+    std::vector<uint8_t> best;
+    if (fixed_order == 0 && tune) {
+        std::lock_guard<std::mutex> lk(tune->mu);
+        if (tune->next < QS_TILE_ORDERS)
+            cand = tune->next++;
+        else
+            best = tune->best;  // empty while another run still times a candidate
+    }
+    SweepEvents sev;
+    std::vector<size_t> timed;  // steps bracketed by sev, in order
     for (size_t i = 0; i < steps.size(); ++i) {
         const qs::PlanStep &st = steps[i];
         if (!st.sweep) {
             if (qs_status e = launch_canon(s, st.gate)) return e;
             continue;
         }
-        const qs::TileArgs ta = make_tile_args(st.sw, s->n);
+        qs::TileArgs ta = make_tile_args(st.sw, s->n);
+        ta.order = fixed_order > 0 ? fixed_order - 1 : cand >= 0 ? cand : i < best.size() ? best[i] : 0;
         double flops = 0;
         for (const auto &op : st.sw.ops)
             flops += (op.kind == qs::TileOp::DENSE ? 8.0 * double(1 << op.qubits.size()) : 6.0) *
@@ -905,8 +947,31 @@ qs_status launch_steps(qs_state *s, const std::vector<qs::PlanStep> &steps, cons
             const qs::TileOpDev &d = tp.ops[tp.first[i] + o];
             k5 = k5 || (d.kind == 0 && d.k == 5);
         }
+        if (cand >= 0) {
+            if (hipError_t e = sev.record(s->stream)) return hip_fail(e, "timing a tile sweep");
+            timed.push_back(i);
+        }
         hipError_t e = qs::launch_tile(s->amp, s->n, ta, dops + tp.first[i], dev + doff, k5, s->stream);
         if (e != hipSuccess) return hip_fail(e, "tile kernel launch");
+        if (cand >= 0)
+            if (hipError_t e2 = sev.record(s->stream)) return hip_fail(e2, "timing a tile sweep");
+    }
+    if (cand < 0 || timed.empty()) return QS_OK;
+    // this run's candidate: read the sweep times and, after the last
+    // candidate, keep the fastest order of every sweep
+    if (hipError_t e = hipEventSynchronize(sev.ev.back())) return hip_fail(e, "timing a tile sweep");
+    std::vector<float> ms(timed.size());
+    for (size_t k = 0; k < timed.size(); ++k)
+        if (hipError_t e = hipEventElapsedTime(&ms[k], sev.ev[2 * k], sev.ev[2 * k + 1]))
+            return hip_fail(e, "timing a tile sweep");
+    std::lock_guard<std::mutex> lk(tune->mu);
+    if (tune->ms.size() < steps.size()) tune->ms.resize(steps.size());
+    for (size_t k = 0; k < timed.size(); ++k) tune->ms[timed[k]][cand] = ms[k];
+    if (++tune->done == QS_TILE_ORDERS) {
+        tune->best.assign(steps.size(), 0);
+        for (size_t i = 0; i < steps.size(); ++i)
+            for (int c = 1; c < QS_TILE_ORDERS; ++c)
+                if (tune->ms[i][c] < tune->ms[i][tune->best[i]]) tune->best[i] = uint8_t(c);
     }
     return QS_OK;
 }
@@ -918,6 +983,7 @@ struct SegPlan {
     std::vector<qs::PlanStep> steps;   // tiled segments
     TileProgram prog;
     uint64_t prog_id = 0;
+    std::shared_ptr<OrderTune> tune;   // tiled segments: measured tile orders
     std::vector<qs::CanonGate> gates;  // per-gate and per-block plans
     bool has_noise = false;            // a noise site follows the gates
     qs::FlatOp noise;
@@ -2089,6 +2155,8 @@ qs_status qs_run_circuit(qs_state *s, const qs_circuit *c, const qs_run_opts *op
     if (o.k_max < 0 || o.k_max > QS_MAX_TARGETS) return fail(QS_E_INVAL, "k_max = %d not in [0, %d]", o.k_max, QS_MAX_TARGETS);
     if (o.tile_qubits && (o.tile_qubits < 10 || o.tile_qubits > 13))
         return fail(QS_E_INVAL, "tile_qubits = %d not in [10, 13]", o.tile_qubits);
+    if (o.tile_order < 0 || o.tile_order > QS_TILE_ORDERS)
+        return fail(QS_E_INVAL, "tile_order = %d not in [0, %d]", o.tile_order, QS_TILE_ORDERS);
     if (o.plan == QS_PLAN_AUTOTUNE) return run_autotuned(s, c, o);
     std::shared_ptr<const CachedPlan> cp;
     if (qs_status st = plan_circuit(s, c, o, cp)) return st;
@@ -2135,6 +2203,7 @@ qs_status plan_circuit(qs_state *s, const qs_circuit *c, const qs_run_opts &o,
                     if (qs_status st = choose_tile_params(s, flat, k, e, o, tp, sp.steps)) return st;
                     build_tile_program(sp.steps, sp.prog);
                     sp.prog_id = g_prog_serial.fetch_add(1);
+                    sp.tune = std::make_shared<OrderTune>();
                 } else if (o.plan == QS_PLAN_UNFUSED) {
                     for (size_t j = k; j < e; ++j)
                         sp.gates.push_back(qs::canonicalize(flat[j].targets.data(), int(flat[j].targets.size()),
@@ -2165,7 +2234,8 @@ qs_status execute_plan(qs_state *s, const CachedPlan &plan, qs_run_opts o)
     uint64_t site = 0;
     for (const SegPlan &sp : plan.segs) {
         if (sp.tiled) {
-            if (qs_status st = launch_steps(s, sp.steps, sp.prog, sp.prog_id)) return st;
+            if (qs_status st = launch_steps(s, sp.steps, sp.prog, sp.prog_id, sp.tune.get(), o.tile_order))
+                return st;
         } else if (!sp.gates.empty()) {
             if (qs_status st = launch_plan(s, sp.gates)) return st;
         }

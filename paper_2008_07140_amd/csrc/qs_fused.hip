@@ -263,16 +263,40 @@ __device__ __forceinline__ uint64_t deposit_bits(uint64_t x, uint64_t mask)
     return r;
 }
 
-// Global base index of tile t.  Workgroups are dispatched to the eight XCDs
-// in turn, so bits 0..2 of t name the XCD that runs the tile: they select
-// the three highest qubits outside the tile, and the rest of t walks the
-// other outer qubits from the lowest.  Each XCD then streams its own eighth
-// of the state; on the 30-qubit circuit this measured 2.2% faster over all
-// sweeps than giving bits 0..2 to the lowest outer qubits.
+// Global base index of tile t under the sweep's tile order.  Tiles that
+// run at the same time share the low bits of t, and the order decides which
+// outer qubits those bits select, hence how the concurrent 128-byte runs of
+// a sweep spread over HBM; which order is fastest depends on the sweep's
+// tile qubits and is measured by the host.  Workgroups are dispatched to the
+// eight XCDs in turn, so bits 0..2 of t name the XCD running the tile.
+//   0: bits 0..2 select the three highest outer qubits (each XCD streams its
+//      own eighth of the state), the rest walk the others from the lowest;
+//   1: as 0, and bits 3..5 select the next three highest;
+//   2: t walks the outer qubits from the lowest;
+//   3: t walks the outer qubits from the highest.
+// Every order is a bijection of [0, 2^nouter).
 __device__ __forceinline__ uint64_t tile_base(uint64_t t, const TileArgs &ta)
 {
     const int no = ta.nouter;
-    if (no >= 3) t = (t >> 3) | ((t & 7) << (no - 3));
+    switch (ta.order) {
+    case 0:
+        if (no >= 3) t = (t >> 3) | ((t & 7) << (no - 3));
+        break;
+    case 1:
+        if (no >= 6)
+            t = (t >> 6) | (((t >> 3) & 7) << (no - 6)) | ((t & 7) << (no - 3));
+        else if (no >= 3)
+            t = (t >> 3) | ((t & 7) << (no - 3));
+        break;
+    case 3: {
+        uint64_t r = 0;
+        for (int b = 0; b < no; ++b) r |= ((t >> b) & 1) << (no - 1 - b);
+        t = r;
+        break;
+    }
+    default:
+        break;
+    }
     return deposit_bits(t, ta.omask);
 }
 

@@ -15,7 +15,7 @@ struct TileArgs {
     int m;               // tile qubits (10..13)
     int nops;
     int nouter;          // n - m
-    int pad;
+    int order;           // tile order of the sweep, 0 .. 3 (tile_base)
     uint64_t omask;      // qubits outside the tile
     uint8_t q[16];       // global position of local bit b (b < m)
 };

@@ -27,6 +27,7 @@ C64, C128 = 1, 2
 COST_FEATURES = 16
 MLP_HIDDEN = 64
 PLAN_UNFUSED, PLAN_GREEDY, PLAN_LEARNED, PLAN_AUTOTUNE = 0, 1, 2, 3
+TILE_ORDERS = 4  # candidate tile orders of a sweep (RunOpts.tile_order 1..TILE_ORDERS; 0 = measured)
 (K_INIT, K_DENSE1, K_DENSE2, K_DENSE3, K_DENSEN, K_PHASE, K_FUSED, K_TILE, K_REDUCE,
  K_OTHER) = range(10)
 KERNEL_NAMES = ["init", "dense1", "dense2", "dense3", "denseN", "phase", "fused", "tile",
@@ -45,7 +46,7 @@ class QSError(RuntimeError):
 class RunOpts(C.Structure):
     _fields_ = [("plan", C.c_int), ("k_max", C.c_int), ("seed", C.c_uint64),
                 ("traj", C.c_uint64), ("chosen", C.POINTER(C.c_int64)),
-                ("chosen_len", C.c_int64), ("tile_qubits", C.c_int)]
+                ("chosen_len", C.c_int64), ("tile_qubits", C.c_int), ("tile_order", C.c_int)]
 
 
 P, I, D, U64, I64, SZ = C.c_void_p, C.c_int, C.c_double, C.c_uint64, C.c_int64, C.c_size_t
@@ -305,8 +306,9 @@ class State:
         return ch.value, pc.value
 
     def run(self, circuit: Circuit, plan: int = PLAN_UNFUSED, k_max: int = 0, seed: int = 0,
-            traj: int = 0, nsites: int = 0, tile_qubits: int = 0):
-        o = RunOpts(plan=plan, k_max=k_max, seed=seed, traj=traj, tile_qubits=tile_qubits)
+            traj: int = 0, nsites: int = 0, tile_qubits: int = 0, tile_order: int = 0):
+        o = RunOpts(plan=plan, k_max=k_max, seed=seed, traj=traj, tile_qubits=tile_qubits,
+                    tile_order=tile_order)
         chosen = None
         if nsites:
             chosen = (C.c_int64 * nsites)()

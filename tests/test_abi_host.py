@@ -169,3 +169,22 @@ def test_autotune_result_before_any_run(qs):
     assert e.value.status == -1
     # without measurements the plan is the greedy one
     assert (c.plan_info(20, qs.C64, qs.PLAN_AUTOTUNE) == c.plan_info(20, qs.C64, qs.PLAN_GREEDY))
+
+
+def test_run_opts_layout_matches_header(qs, tmp_path):
+    """The binding's RunOpts mirrors qs_run_opts field by field (offsets and
+    size from a C program built against include/qs.h), and the candidate
+    count of tile orders agrees."""
+    import ctypes
+    import subprocess
+    fields = [f for f, _ in qs.RunOpts._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"qs.h\"\nint main(void) {\n"
+                   + "".join('printf("%%zu\\n", offsetof(qs_run_opts, %s));\n' % f for f in fields)
+                   + 'printf("%zu\\n%d\\n", sizeof(qs_run_opts), QS_TILE_ORDERS);\nreturn 0;\n}\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    want = [getattr(qs.RunOpts, f).offset for f in fields] + [ctypes.sizeof(qs.RunOpts), qs.TILE_ORDERS]
+    assert got == want

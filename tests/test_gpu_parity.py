@@ -373,6 +373,31 @@ def test_tile_sweeps_rqc16_and_rqc20(qs, m):
         s.close()
 
 
+@pytest.mark.parametrize("m", [10, 13])
+def test_tile_orders_give_identical_states(qs, m):
+    """The order in which a sweep visits its tiles changes no amplitude: every
+    fixed candidate order, and the measured per-sweep choice through its
+    timing runs and after them, give bit-identical states (each tile is
+    loaded, transformed and stored on its own), equal to the oracle."""
+    rows, cols, depth, seed = 4, 5, 12, 777
+    ops = cg.random_circuit(rows, cols, depth, seed, cu3_prob=0.1)
+    n = rows * cols
+    c = qs.Circuit(ops)
+    s = qs.State(n, qs.C64)
+    outs = []
+    for order in list(range(1, qs.TILE_ORDERS + 1)) + [0] * (qs.TILE_ORDERS + 2):
+        s.reset()
+        s.run(c, plan=qs.PLAN_GREEDY, k_max=4, tile_qubits=m, tile_order=order)
+        outs.append(s.amplitudes())
+    for i, o in enumerate(outs[1:], 1):
+        assert np.array_equal(o, outs[0]), i
+    ref, _ = oracle.run(n, ops)
+    assert infidelity(ref, outs[0]) <= 1e-6
+    with pytest.raises(qs.QSError):
+        s.run(c, plan=qs.PLAN_GREEDY, tile_order=qs.TILE_ORDERS + 1)
+    s.close()
+
+
 def test_tile_sweeps_wide_diagonals(qs):
     """Diagonal gates wider than a tile op may be (more than k_max qubits
     inside the tile, or outside qubits beyond the selector limit) run on
