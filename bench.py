@@ -60,7 +60,7 @@ def parse():
                    help="34-qubit learned-planner comparison: complex128 reference on 2^20 sampled "
                         "indices, then complex64 learned vs greedy vs unfused")
     p.add_argument("--summarize-profiles", metavar="DIR", default="",
-                   help="CPU only: read the rocprofv3 CSV output under DIR (see profiles/README.md) "
+                   help="CPU only: read the rocprofv3 CSV output under DIR (the runs in PROFILE_RUNS) "
                         "and write profiles/traffic.json plus the text summaries")
     return p.parse_args()
 
