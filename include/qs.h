@@ -247,7 +247,9 @@ qs_status qs_expect_z(const qs_state *s, double *out);
  * and key `seed` (noise sites drawn as in qs_run_circuit), then writes its
  * <Z_q> for q < widths[t] to z_out at offset sum_{t' < t} widths[t'].
  * States of all trajectories are batched on the device.  *seconds (may be
- * NULL) receives the device time of the batch.  Errors as qs_run_circuit. */
+ * NULL) receives the wall time of the whole call after argument checks:
+ * preparation of every trajectory, device allocation, all launches and the
+ * final reductions.  Errors as qs_run_circuit. */
 qs_status qs_run_trajectories(const qs_circuit *const *circs, const int *widths, int count,
                               qs_dtype dt, uint64_t seed, double *z_out, double *seconds);
 

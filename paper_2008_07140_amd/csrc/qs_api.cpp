@@ -26,7 +26,10 @@
 #include "qs_mlp.h"
 
 #include <array>
+#include <condition_variable>
+#include <functional>
 #include <mutex>
+#include <shared_mutex>
 #include <tuple>
 #include "qs_philox.h"
 
@@ -441,23 +444,98 @@ void append_fragments(const std::vector<double> &m, int k, std::vector<uint16_t>
                 }
 }
 
-// Host work spread over threads: f(i) for i < count, in any order.
+// Host work spread over threads: f(i) for i < count, in any order.  A fixed
+// set of worker threads, started on first use and kept for the life of the
+// process (intentionally never destroyed, so no thread outlives the objects
+// it waits on), takes items of the most recently published job.  The caller
+// works on its own job too and returns once every item is done, so nested
+// or concurrent calls cannot deadlock: at worst the caller does the work
+// itself.  A job lives on the heap, held by every thread that took it, so a
+// worker that wakes after the job is finished only sees an exhausted counter.
+class WorkerPool {
+public:
+    struct Job {
+        std::function<void(size_t)> fn;
+        size_t count = 0;
+        std::atomic<size_t> next{0}, done{0};
+        std::mutex mu;
+        std::condition_variable cv;
+    };
+
+    static WorkerPool &get()
+    {
+        static WorkerPool *pool = new WorkerPool();
+        return *pool;
+    }
+
+    size_t workers() const { return threads_.size(); }
+
+    void run(size_t count, std::function<void(size_t)> fn)
+    {
+        auto job = std::make_shared<Job>();
+        job->fn = std::move(fn);
+        job->count = count;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            cur_ = job;
+            ++serial_;
+        }
+        cv_.notify_all();
+        work(*job);
+        std::unique_lock<std::mutex> lk(job->mu);
+        job->cv.wait(lk, [&] { return job->done.load() == job->count; });
+    }
+
+private:
+    WorkerPool()
+    {
+        const size_t hw = std::max(1u, std::thread::hardware_concurrency());
+        const size_t nw = std::min<size_t>(hw, 16) - 1;
+        for (size_t t = 0; t < nw; ++t) threads_.emplace_back([this] { loop(); });
+        for (auto &th : threads_) th.detach();
+    }
+
+    static void work(Job &j)
+    {
+        for (size_t i = j.next.fetch_add(1); i < j.count; i = j.next.fetch_add(1)) {
+            j.fn(i);
+            if (j.done.fetch_add(1) + 1 == j.count) {
+                std::lock_guard<std::mutex> lk(j.mu);
+                j.cv.notify_all();
+            }
+        }
+    }
+
+    void loop()
+    {
+        uint64_t seen = 0;
+        for (;;) {
+            std::shared_ptr<Job> j;
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                cv_.wait(lk, [&] { return serial_ != seen; });
+                seen = serial_;
+                j = cur_;
+            }
+            if (j) work(*j);
+        }
+    }
+
+    std::mutex mu_;
+    std::condition_variable cv_;
+    std::shared_ptr<Job> cur_;
+    uint64_t serial_ = 0;
+    std::vector<std::thread> threads_;
+};
+
 template <typename F>
 void parallel_for(size_t count, F &&f)
 {
-    const size_t hw = std::max(1u, std::thread::hardware_concurrency());
-    const size_t nt = std::min<size_t>({hw, 16, (count + 3) / 4});
-    if (nt <= 1) {
+    if (count < 8 || WorkerPool::get().workers() == 0) {
         for (size_t i = 0; i < count; ++i) f(i);
         return;
     }
-    std::atomic<size_t> next{0};
-    std::vector<std::thread> pool;
-    for (size_t t = 0; t < nt; ++t)
-        pool.emplace_back([&] {
-            for (size_t i = next.fetch_add(1); i < count; i = next.fetch_add(1)) f(i);
-        });
-    for (auto &th : pool) th.join();
+    WorkerPool::get().run(count, [&f](size_t i) { f(i); });
 }
 
 struct TileProgram {
@@ -557,23 +635,35 @@ std::vector<uint32_t> lane_offsets(const qs::TileOpDev &d)
 
 
 // The layout depends only on the op's tile bits and the tile size: searched
-// once per thread and remembered.
+// once per process and remembered (a few thousand keys at most).
 void choose_lane_layout(const std::vector<int> &pos, int m, int &lane_q, uint32_t &colmask)
 {
-    thread_local std::map<uint64_t, std::pair<int, uint32_t>> memo;  // (tile-bit set, m) -> (lane bit, columns)
+    static std::shared_mutex mu;
+    static std::map<uint64_t, std::pair<int, uint32_t>> memo;  // (tile-bit set, m) -> (lane bit, columns)
     uint64_t key = uint64_t(m) << 32;
     for (int p : pos) key |= uint64_t(1) << p;
-    auto it = memo.find(key);
-    if (it == memo.end()) {
+    std::pair<int, uint32_t> v;
+    bool found = false;
+    {
+        std::shared_lock<std::shared_mutex> lk(mu);
+        auto it = memo.find(key);
+        if (it != memo.end()) {
+            v = it->second;
+            found = true;
+        }
+    }
+    if (!found) {
         std::vector<int> sorted(pos);
         std::sort(sorted.begin(), sorted.end());
         int q = int(sorted.size()) - 3;
         uint32_t cm = 0;
         search_lane_layout(sorted, m, q, cm);
-        it = memo.emplace(key, std::make_pair(sorted[q], cm)).first;
+        v = std::make_pair(sorted[q], cm);
+        std::unique_lock<std::shared_mutex> lk(mu);
+        memo.emplace(key, v);
     }
-    colmask = it->second.second;
-    lane_q = int(std::find(pos.begin(), pos.end(), it->second.first) - pos.begin());
+    colmask = v.second;
+    lane_q = int(std::find(pos.begin(), pos.end(), v.first) - pos.begin());
 }
 
 // The matrix of a k-qubit op with its qubits reordered: new qubit b is old
@@ -1503,7 +1593,7 @@ qs_status batch_run_sums(Batch &B, const std::vector<int> &who, const std::vecto
         a.J = int(qs_[i].size());
         for (int j = 0; j < a.J; ++j) {
             a.q[j] = uint8_t(qs_[i][j]);
-            a.a[j] = as_[i][j];
+            a.am1[j] = as_[i][j] - 1.0;
         }
         const uint32_t nch = uint32_t((a.n_amp + chunk - 1) / chunk);
         first[i] = uint32_t(tasks.size());
@@ -1528,7 +1618,9 @@ qs_status batch_run_sums(Batch &B, const std::vector<int> &who, const std::vecto
         double bytes = 0;
         for (int t : who) bytes += double(amp_bytes(B.dt)) * std::ldexp(1.0, B.prep[t].n);
         Timed tm(s, QS_K_REDUCE, bytes, bytes);
-        hipError_t e = qs::launch_run_sums(B.dt, uint32_t(tasks.size()), reinterpret_cast<qs::RunSumTask *>(dev + ab),
+        int nmax = 0;
+        for (int t : who) nmax = std::max(nmax, B.prep[t].n);
+        hipError_t e = qs::launch_run_sums(B.dt, nmax, uint32_t(tasks.size()), reinterpret_cast<qs::RunSumTask *>(dev + ab),
                                            reinterpret_cast<qs::RunSumArgs *>(dev), partials, s->stream);
         if (e == hipSuccess)
             e = qs::launch_run_sums_finish(partials, reinterpret_cast<uint32_t *>(dev + ab + tb),
@@ -1610,6 +1702,10 @@ qs_status run_trajectory_batch(const qs_circuit *const *circs, const int *widths
     if (!circs || !widths || !z_out || count < 0) return fail(QS_E_INVAL, "NULL argument or negative count");
     if (dt != QS_C64 && dt != QS_C128) return fail(QS_E_INVAL, "unknown dtype %d", int(dt));
     if (count == 0) return QS_OK;
+    // the reported time covers everything from here: preparation (group
+    // expansion, state-independent branches), allocation, every launch and
+    // the final reductions
+    const auto t0 = std::chrono::steady_clock::now();
     Batch B;
     B.dt = dt;
     B.prep.resize(count);
@@ -1617,8 +1713,18 @@ qs_status run_trajectory_batch(const qs_circuit *const *circs, const int *widths
     for (int t = 0; t < count; ++t) {
         if (!circs[t]) return fail(QS_E_INVAL, "circuit %d is NULL", t);
         if (widths[t] < 1 || widths[t] > qs::kRunMax) return fail(QS_E_INVAL, "width %d not in [1, %d]", widths[t], qs::kRunMax);
-        if (qs_status e = prepare_trajectory(circs[t], widths[t], seed, uint64_t(t), B.prep[t])) return e;
         total += amp_bytes(dt) << widths[t];
+    }
+    {
+        std::vector<qs_status> pst(count, QS_OK);
+        parallel_for(size_t(count), [&](size_t t) {
+            pst[t] = prepare_trajectory(circs[t], widths[t], seed, uint64_t(t), B.prep[t]);
+        });
+        for (int t = 0; t < count; ++t)
+            if (pst[t] != QS_OK) {  // again on this thread, which reports the error
+                B.prep[t] = TPrep();
+                return prepare_trajectory(circs[t], widths[t], seed, uint64_t(t), B.prep[t]);
+            }
     }
     const size_t lim = g_mem_limit.load();
     if (lim && total > lim) return fail(QS_E_NOMEM, "batch of %zu bytes exceeds the memory limit", total);
@@ -1633,7 +1739,6 @@ qs_status run_trajectory_batch(const qs_circuit *const *circs, const int *widths
         B.views.push_back(new View(B.master, B.amp.back(), widths[t]));
         off += amp_bytes(dt) << widths[t];
     }
-    const auto t0 = std::chrono::steady_clock::now();
     for (int t = 0; t < count; ++t)
         if (qs_status e = init_amplitudes(&B.views[t]->s)) return e;
     std::vector<size_t> cursor(count, 0);

@@ -17,7 +17,7 @@ struct RunSumArgs {
     uint64_t chunk_len;  // amplitudes per workgroup
     int J;               // number of sites in the run
     int pad;
-    double a[kRunMax];   // |K1_11|^2 of site j (1 for plain <Z> sums)
+    double am1[kRunMax]; // |K1_11|^2 - 1 of site j (0 for plain <Z> sums)
     uint8_t q[kRunMax];  // qubit of site j
 };
 
@@ -26,7 +26,9 @@ struct RunSumTask {
     uint32_t chunk;  // chunk of that state
 };
 
-hipError_t launch_run_sums(qs_dtype dt, uint32_t ntasks, const RunSumTask *tasks, const RunSumArgs *args,
+// nmax: the widest state of the launch (states of at most 32 qubits take a
+// kernel with 32-bit index arithmetic).
+hipError_t launch_run_sums(qs_dtype dt, int nmax, uint32_t ntasks, const RunSumTask *tasks, const RunSumArgs *args,
                            double *partials, hipStream_t st);
 hipError_t launch_run_sums_finish(const double *partials, const uint32_t *first, const uint32_t *count,
                                   int nstates, double *out, hipStream_t st);

@@ -25,29 +25,54 @@ __device__ __forceinline__ double wave_sum_d(double v)
     return v;
 }
 
-template <typename C>
-__global__ __launch_bounds__(kT) void k_run_sums(const RunSumTask *tasks, const RunSumArgs *args,
-                                                 double *partials)
+// WIDE: states of more than 32 qubits (64-bit index arithmetic).  A thread
+// holds the weights of NB amplitudes and walks the sites once per group, so
+// each site's qubit and a_j - 1 (uniform, scalar loads) serve NB amplitudes.
+// Per site the bit x_{q_j} enters as 0.0 / 1.0: S_j += x w and
+// w += w x (a_j - 1), two FMAs and a multiply, exact for x = 0 and one
+// rounding of w a_j for x = 1.
+template <typename C, bool WIDE>
+__global__ __launch_bounds__(kT) void k_run_sums(const RunSumTask *__restrict__ tasks,
+                                                 const RunSumArgs *__restrict__ args, double *partials)
 {
+    constexpr int NB = 8;
     const RunSumTask task = tasks[blockIdx.x];
     const RunSumArgs &d = args[task.arg];
     const C *a = reinterpret_cast<const C *>(d.amp);
+    const uint32_t *qw = reinterpret_cast<const uint32_t *>(d.q);  // four qubit bytes per word
     const uint64_t start = uint64_t(task.chunk) * d.chunk_len;
     uint64_t end = start + d.chunk_len;
     if (end > d.n_amp) end = d.n_amp;
     double z = 0.0, S[kRunMax];
 #pragma unroll
     for (int j = 0; j < kRunMax; ++j) S[j] = 0.0;
-    for (uint64_t i = start + threadIdx.x; i < end; i += kT) {
-        const auto v = a[i];
-        double w = double(v.x) * double(v.x) + double(v.y) * double(v.y);
-        z += w;
+    for (uint64_t i0 = start + threadIdx.x; i0 < end; i0 += uint64_t(NB) * kT) {
+        double w[NB];
+        uint32_t lo[NB], hi[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            const uint64_t i = i0 + uint64_t(k) * kT;
+            w[k] = 0.0;
+            if (i < end) {
+                const auto v = a[i];
+                w[k] = double(v.x) * double(v.x) + double(v.y) * double(v.y);
+            }
+            lo[k] = uint32_t(i);
+            hi[k] = WIDE ? uint32_t(i >> 32) : 0u;
+            z += w[k];
+        }
 #pragma unroll
         for (int j = 0; j < kRunMax; ++j)
             if (j < d.J) {
-                const bool bit = (i >> d.q[j]) & 1;
-                S[j] += bit ? w : 0.0;
-                w *= bit ? d.a[j] : 1.0;
+                const uint32_t q = (qw[j >> 2] >> (8 * (j & 3))) & 0xffu;
+                const double am1 = d.am1[j];
+#pragma unroll
+                for (int k = 0; k < NB; ++k) {
+                    const uint32_t bit = (WIDE && q >= 32) ? (hi[k] >> (q - 32)) & 1u : (lo[k] >> q) & 1u;
+                    const double x = double(bit);
+                    S[j] = fma(x, w[k], S[j]);
+                    w[k] = fma(w[k], x * am1, w[k]);
+                }
             }
     }
     __shared__ double lds[kT / 64];
@@ -85,14 +110,22 @@ __global__ __launch_bounds__(kT) void k_run_sums_finish(const double *partials, 
 
 }  // namespace
 
-hipError_t launch_run_sums(qs_dtype dt, uint32_t ntasks, const RunSumTask *tasks, const RunSumArgs *args,
+hipError_t launch_run_sums(qs_dtype dt, int nmax, uint32_t ntasks, const RunSumTask *tasks, const RunSumArgs *args,
                            double *partials, hipStream_t st)
 {
     if (ntasks == 0) return hipSuccess;
-    if (dt == QS_C128)
-        hipLaunchKernelGGL(k_run_sums<double2>, dim3(ntasks), dim3(kT), 0, st, tasks, args, partials);
-    else
-        hipLaunchKernelGGL(k_run_sums<float2>, dim3(ntasks), dim3(kT), 0, st, tasks, args, partials);
+    const bool wide = nmax > 32;
+    if (dt == QS_C128) {
+        if (wide)
+            hipLaunchKernelGGL((k_run_sums<double2, true>), dim3(ntasks), dim3(kT), 0, st, tasks, args, partials);
+        else
+            hipLaunchKernelGGL((k_run_sums<double2, false>), dim3(ntasks), dim3(kT), 0, st, tasks, args, partials);
+    } else {
+        if (wide)
+            hipLaunchKernelGGL((k_run_sums<float2, true>), dim3(ntasks), dim3(kT), 0, st, tasks, args, partials);
+        else
+            hipLaunchKernelGGL((k_run_sums<float2, false>), dim3(ntasks), dim3(kT), 0, st, tasks, args, partials);
+    }
     return hipGetLastError();
 }
 
