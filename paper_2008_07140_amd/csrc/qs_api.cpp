@@ -35,6 +35,7 @@
 
 #include <chrono>
 #include <map>
+#include <unordered_map>
 
 using cd = std::complex<double>;
 
@@ -786,33 +787,61 @@ void build_tile_program(const std::vector<qs::PlanStep> &steps, TileProgram &tp)
         nops += pops[i].size();
         ndata += pdata[i].size();
     }
+    // per-lane LDS offset tables: one per distinct lane layout of the program
+    // (block width, column bits and op bits packed into one key: 3 + 13 + 5 x 4
+    // bits), placed after the sweeps' data; the tables themselves are computed
+    // once per process
+    static std::shared_mutex memo_mu;
+    static std::unordered_map<uint64_t, std::vector<uint32_t>> memo;  // entries are never erased
+    std::unordered_map<uint64_t, uint32_t> slot_of;                    // key -> table slot
+    std::vector<const std::vector<uint32_t> *> table;                 // slot -> table
+    std::vector<uint32_t> table_at;                                    // slot -> offset, 16-byte units
+    std::vector<uint32_t> op_slot(nops, UINT32_MAX);
+    size_t dend = ndata;
+    for (size_t i = 0, o = 0; i < ns; ++i)
+        for (size_t j = 0; j < pops[i].size(); ++j, ++o) {
+            const qs::TileOpDev &d = pops[i][j];
+            if (d.kind != 0) continue;
+            uint64_t key = uint64_t(d.k) | uint64_t(d.colmask) << 3;
+            for (int b = 0; b < d.k; ++b) key |= uint64_t(d.lpos[b]) << (16 + 4 * b);
+            auto it = slot_of.find(key);
+            if (it == slot_of.end()) {
+                const std::vector<uint32_t> *lo = nullptr;
+                {
+                    std::shared_lock<std::shared_mutex> lk(memo_mu);
+                    auto m = memo.find(key);
+                    if (m != memo.end()) lo = &m->second;
+                }
+                if (!lo) {
+                    std::vector<uint32_t> v = lane_offsets(d);
+                    std::unique_lock<std::shared_mutex> lk(memo_mu);
+                    lo = &memo.emplace(key, std::move(v)).first->second;
+                }
+                it = slot_of.emplace(key, uint32_t(table.size())).first;
+                table.push_back(lo);
+                table_at.push_back(uint32_t(dend / 8));
+                dend += lo->size() * 2;  // uint32 entries in uint16 units (multiples of 8)
+            }
+            op_slot[o] = it->second;
+        }
     tp.ops.resize(nops);
-    tp.data.resize(ndata);
-    parallel_for(ns, [&](size_t i) {
+    tp.data.resize(dend);
+    parallel_for(ns + table.size(), [&](size_t i) {
+        if (i >= ns) {
+            const size_t t = i - ns;
+            std::memcpy(tp.data.data() + size_t(table_at[t]) * 8, table[t]->data(), table[t]->size() * sizeof(uint32_t));
+            return;
+        }
         const uint32_t base = uint32_t(dpos[i] / 8);
         for (size_t j = 0; j < pops[i].size(); ++j) {
+            const size_t o = tp.first[i] + j;
             qs::TileOpDev d = pops[i][j];
             d.data_off += base;
-            tp.ops[tp.first[i] + j] = d;
+            if (op_slot[o] != UINT32_MAX) d.offs_off = table_at[op_slot[o]];
+            tp.ops[o] = d;
         }
         if (!pdata[i].empty()) std::memcpy(tp.data.data() + dpos[i], pdata[i].data(), pdata[i].size() * sizeof(uint16_t));
     });
-    // per-lane LDS offset tables: one per distinct lane layout of the program
-    std::map<std::array<uint32_t, 8>, uint32_t> tables;
-    for (auto &d : tp.ops) {
-        if (d.kind != 0) continue;
-        std::array<uint32_t, 8> key{uint32_t(d.k), d.colmask, 0, 0, 0, 0, 0, 0};
-        for (int b = 0; b < d.k; ++b) key[2 + b] = uint32_t(d.lpos[b]);
-        auto it = tables.find(key);
-        if (it == tables.end()) {
-            const std::vector<uint32_t> lo = lane_offsets(d);
-            const uint32_t off = uint32_t(tp.data.size() / 8);
-            tp.data.resize(tp.data.size() + lo.size() * 2);
-            std::memcpy(tp.data.data() + size_t(off) * 8, lo.data(), lo.size() * sizeof(uint32_t));
-            it = tables.emplace(key, off).first;
-        }
-        d.offs_off = it->second;
-    }
     if (tp.data.empty()) tp.data.resize(8, 0);
     if (tp.ops.empty()) tp.ops.resize(1);
 }
@@ -1445,12 +1474,36 @@ struct DevBuf {
     }
 };
 
+// Pinned host memory for uploads, grown on demand.
+struct PinnedBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t bytes)
+    {
+        if (bytes <= cap) return hipSuccess;
+        if (p) {
+            hipError_t e = hipHostFree(p);
+            if (e != hipSuccess) return e;
+        }
+        p = nullptr;
+        cap = 0;
+        hipError_t e = hipHostMalloc(&p, bytes, hipHostMallocDefault);
+        if (e == hipSuccess) cap = bytes;
+        return e;
+    }
+    ~PinnedBuf()
+    {
+        if (p) (void)hipHostFree(p);
+    }
+};
+
 struct Batch {
     qs_state *master = nullptr;  // scratch and stream owner (a 1-qubit state)
     qs_dtype dt;
     std::vector<TPrep> prep;
     std::vector<void *> amp;
     DevBuf states, prog, red, outb;
+    PinnedBuf stage;  // program uploads (written only after the stream has drained)
     std::vector<View *> views;
     ~Batch()
     {
@@ -1500,7 +1553,7 @@ qs_status batch_gates(Batch &B, const std::vector<int> &who, std::vector<std::ve
     for (size_t r = 0; r < rounds; ++r)
         for (size_t i = 0; i < who.size(); ++i)
             if (r < plans[i].size()) {
-                all.push_back(plans[i][r]);
+                all.push_back(std::move(plans[i][r]));
                 refs.push_back({r, i});
             }
     if (all.empty()) return QS_OK;
@@ -1531,23 +1584,44 @@ qs_status batch_gates(Batch &B, const std::vector<int> &who, std::vector<std::ve
     auto up = [](size_t x) { return (x + 255) / 256 * 256; };
     const size_t total = up(ob) + up(db) + up(ab) + up(tb) + 256;
     qs_state *s = B.master;
+    // the previous round's upload and kernels are done before the staging
+    // buffer and the program buffer are rewritten
     HIP_TRY(hipStreamSynchronize(s->stream));
     HIP_TRY(B.prog.ensure(total));
+    HIP_TRY(B.stage.ensure(total));
     unsigned char *dev = static_cast<unsigned char *>(B.prog.p);
-    std::vector<unsigned char> host(total, 0);
-    std::memcpy(host.data(), tp.ops.data(), ob);
-    std::memcpy(host.data() + up(ob), tp.data.data(), db);
-    if (ab) std::memcpy(host.data() + up(ob) + up(db), args.data(), ab);
+    unsigned char *host = static_cast<unsigned char *>(B.stage.p);
     std::vector<size_t> task_off(tasks.size());
     size_t toff = 0;
     for (size_t k = 0; k < tasks.size(); ++k) {
         task_off[k] = toff;
-        if (!tasks[k].empty())
-            std::memcpy(host.data() + up(ob) + up(db) + up(ab) + toff * sizeof(qs::TileTask), tasks[k].data(),
-                        tasks[k].size() * sizeof(qs::TileTask));
         toff += tasks[k].size();
     }
-    HIP_TRY(hipMemcpy(dev, host.data(), total, hipMemcpyHostToDevice));
+    // the fragment data dominates: copied in parallel slices
+    const size_t slice = size_t(1) << 20;
+    const size_t nsl = (db + slice - 1) / slice;
+    parallel_for(nsl + 3 + tasks.size(), [&](size_t i) {
+        if (i < nsl) {
+            const size_t o = i * slice, len = std::min(slice, db - o);
+            std::memcpy(host + up(ob) + o, reinterpret_cast<const unsigned char *>(tp.data.data()) + o, len);
+        } else if (i == nsl) {
+            std::memcpy(host, tp.ops.data(), ob);
+        } else if (i == nsl + 1) {
+            if (ab) std::memcpy(host + up(ob) + up(db), args.data(), ab);
+        } else if (i == nsl + 2) {
+            // gaps between the sections stay zero
+            std::memset(host + ob, 0, up(ob) - ob);
+            std::memset(host + up(ob) + db, 0, up(db) - db);
+            std::memset(host + up(ob) + up(db) + ab, 0, up(ab) - ab);
+        } else {
+            const size_t k = i - nsl - 3;
+            if (!tasks[k].empty())
+                std::memcpy(host + up(ob) + up(db) + up(ab) + task_off[k] * sizeof(qs::TileTask), tasks[k].data(),
+                            tasks[k].size() * sizeof(qs::TileTask));
+        }
+    });
+    HIP_TRY(hipMemcpyAsync(dev, host, up(ob) + up(db) + up(ab) + ntask * sizeof(qs::TileTask), hipMemcpyHostToDevice,
+                           s->stream));
     const qs::TileOpDev *dops = reinterpret_cast<const qs::TileOpDev *>(dev);
     const void *ddata = dev + up(ob);
     const qs::TileArgsDev *dargs = reinterpret_cast<const qs::TileArgsDev *>(dev + up(ob) + up(db));
