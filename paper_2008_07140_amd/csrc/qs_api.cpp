@@ -1828,8 +1828,8 @@ qs_status run_trajectory_batch(const qs_circuit *const *circs, const int *widths
             for (int t : gate_who) {
                 std::vector<qs::FlatOp> l = std::move(B.prep[t].pending);
                 B.prep[t].pending.clear();
-                auto &g = B.prep[t].steps[cursor[t]].gates;
-                l.insert(l.end(), g.begin(), g.end());
+                auto &g = B.prep[t].steps[cursor[t]].gates;  // consumed here
+                l.insert(l.end(), std::make_move_iterator(g.begin()), std::make_move_iterator(g.end()));
                 lists.push_back(std::move(l));
                 ++cursor[t];
             }
