@@ -477,7 +477,8 @@ def config5(qs, cg, torch):
     st = qs.State(n, qs.C64)
     for name, plan in (("learned", qs.PLAN_LEARNED), ("greedy", qs.PLAN_GREEDY), ("unfused", qs.PLAN_UNFUSED)):
         qs.cost_model_set(p if plan == qs.PLAN_LEARNED else None)
-        reps = 1 if plan == qs.PLAN_UNFUSED else 2
+        # fused plans: the first runs of a plan time its candidate tile orders
+        reps = 1 if plan == qs.PLAN_UNFUSED else qs.TILE_ORDERS + 2
         best = 1e30
         for r in range(reps):
             st.reset()
