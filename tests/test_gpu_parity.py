@@ -479,6 +479,39 @@ def test_batched_trajectories_wider_than_a_tile(qs):
         off += n
 
 
+@pytest.mark.parametrize("n,T", [(12, 3), (33, 1)])
+def test_batched_trajectories_product_state_closed_form(qs, n, T):
+    """Ry(theta_q) on every qubit, then amplitude damping on every qubit in
+    ascending order (one run of n damping sites): the state stays a product
+    state, so each trajectory is n independent one-qubit Sec. 2.4 steps with
+    the same Philox draws (site q is the q-th damping site), done here per
+    qubit with the oracle's one-qubit noisy gate.  At 33 qubits (a 64 GiB
+    complex64 state) the run sums take their 64-bit-index kernel.  The batch
+    run twice gives bit-identical results."""
+    rng = np.random.default_rng(5150 + n)
+    theta = rng.uniform(0.0, np.pi, n)
+    gamma = rng.uniform(0.05, 0.6, n)
+    ops = [cg.Gate((q,), (), cg.ry(theta[q])) for q in range(n)]
+    for q in range(n):
+        ops.append(cg.Gate((q,), (), np.eye(2, dtype=np.complex128), "id"))
+        ops.append(cg.Noise((q,), cg.kraus_amplitude_damping(gamma[q]), "amplitude_damping"))
+    c = qs.Circuit(ops)
+    seed = 91
+    z, _ = qs.run_trajectories([c] * T, [n] * T, dtype=qs.C64, seed=seed)
+    for t in range(T):
+        want = np.empty(n)
+        for q in range(n):
+            psi = np.array([1.0, 0.0], dtype=np.complex128)
+            oracle.apply_noisy(psi, [0], cg.ry(theta[q]), cg.kraus_amplitude_damping(gamma[q]),
+                               oracle.uniform(seed, t, q))
+            p0, p1 = abs(psi[0]) ** 2, abs(psi[1]) ** 2
+            want[q] = (p0 - p1) / (p0 + p1)
+        assert np.max(np.abs(z[t * n:(t + 1) * n] - want)) <= 1e-4, t
+    if n <= 16:
+        z2, _ = qs.run_trajectories([c] * T, [n] * T, dtype=qs.C64, seed=seed)
+        assert np.array_equal(z, z2)
+
+
 def test_batched_trajectory_mean_matches_density_matrix(qs):
     """Amplified rates (5e-2 everywhere), where a wrong branch weight or
     Kraus product moves the mean well beyond the sampling error."""
