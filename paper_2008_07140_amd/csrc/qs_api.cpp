@@ -1533,6 +1533,7 @@ qs_status batch_gates(Batch &B, const std::vector<int> &who, std::vector<std::ve
             qs::TileParams tp = tile_params(n, o);
             tp.kmax = kTrajKmax;
             tp.max_outer = kTrajMaxOuter;
+            tp.search = false;  // planned every round for every trajectory: keep it cheap
             qs::plan_tiles(fl, 0, fl.size(), n, tp, plans[i]);
         } else {
             for (auto &f : fl) {

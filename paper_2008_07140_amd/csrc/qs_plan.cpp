@@ -674,6 +674,54 @@ void plan_tiles(const std::vector<FlatOp> &flat, size_t k0, size_t e, int n, con
             continue;
         }
         for (int q = 0; q < n && __builtin_popcountll(Q) < m; ++q) Q |= uint64_t(1) << q;
+        if (tp.search) {
+            // Local search over the tile qubits: the greedy set takes the
+            // qubits of the earliest pending gates, which on layered circuits
+            // leaves many of a sweep's gates blocked by a neighbour outside the
+            // tile.  Swap one qubit of Q (never the L lowest) for one outside
+            // whenever the sweep then applies more gates, until no swap helps.
+            // The count is the scan below with Q fixed, post-pass rules
+            // included, so the chosen Q's lists come from the same scan.
+            auto scan_fixed = [&](uint64_t Qf, std::vector<size_t> *app, std::vector<size_t> *def) {
+                uint64_t blk = 0;
+                int c = 0;
+                for (size_t gi : remaining) {
+                    const GInfo &g = info[gi];
+                    const bool ok = !(g.qmask & blk) && fits_tile(g) && (g.diag || !(g.tmask & ~Qf)) &&
+                                    __builtin_popcountll(g.qmask & Qf) <= kmax &&
+                                    __builtin_popcountll(g.qmask & ~Qf) <= mo;
+                    if (ok) {
+                        ++c;
+                        if (app) app->push_back(gi);
+                    } else {
+                        blk |= g.qmask;
+                        if (def) def->push_back(gi);
+                    }
+                }
+                return c;
+            };
+            int best = scan_fixed(Q, nullptr, nullptr);
+            for (bool improved = true; improved;) {
+                improved = false;
+                for (int a = L; a < n && !improved; ++a) {
+                    if (!(Q >> a & 1)) continue;
+                    for (int b = L; b < n; ++b) {
+                        if (Q >> b & 1) continue;
+                        const uint64_t Q2 = (Q & ~(uint64_t(1) << a)) | (uint64_t(1) << b);
+                        const int c2 = scan_fixed(Q2, nullptr, nullptr);
+                        if (c2 > best) {
+                            best = c2;
+                            Q = Q2;
+                            improved = true;
+                            break;
+                        }
+                    }
+                }
+            }
+            applied.clear();
+            deferred.clear();
+            scan_fixed(Q, &applied, &deferred);
+        }
         // gates with more than kmax qubits inside or `mo` outside the final Q
         // are left for a later step
         {
