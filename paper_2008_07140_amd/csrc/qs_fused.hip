@@ -411,13 +411,18 @@ __device__ __forceinline__ void tile_pass(float2 *amp, uint64_t t, const TileArg
         auto run = [&](int oi, const Frags<4> &cur, Frags<4> &nxt) {
             const TileOpDev &op = *desc(oi);
             const int outer = op_pattern(op, base);
+            // the next op's fields that locate its fragments are read now, so
+            // their scalar loads complete while this op runs
+            const bool has_next = oi + 1 < ta.nops;
+            const TileOpDev &nop = *desc(has_next ? oi + 1 : oi);
+            const int npat = op_pattern(nop, base);
+            const bool nload = has_next && nop.kind == 0 && !((nop.skip >> npat) & 1u);
+            const uint32_t nfr = nop.data_off + uint32_t(npat) * nop.frag_stride, noffs = nop.offs_off;
             auto prefetch = [&] {
-                if (oi + 1 < ta.nops) {
-                    const TileOpDev *pn = desc(oi + 1);
-                    fetch(nxt, *pn, op_pattern(*pn, base));
-                } else {
+                if (nload)
+                    load_frags<4>(nxt, reinterpret_cast<const bf16x8 *>(data + nfr), data + noffs);
+                else
                     nxt = Frags<4>{};
-                }
             };
             if (op.kind != 0) {
                 prefetch();
