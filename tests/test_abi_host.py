@@ -159,6 +159,21 @@ def test_tile_planner_terminates_on_wide_diagonals(qs):
             assert info["gates"] == 3 and 1 <= info["sweeps"] <= 3
 
 
+def test_tile_planner_sweep_counts_on_workload_circuits(qs):
+    """The greedy tile planner with its local search over tile qubits: on the
+    30-qubit depth-40 workload circuit it needs 31 sweeps of 13-qubit tiles
+    (41 with first-come tile qubits), and every logical gate is planned.  A
+    regression guard on the planner's quality, not a parity check."""
+    n, ops = cg.workload("rqc30_d40")
+    info = qs.Circuit(ops).plan_info(n, qs.C64, qs.PLAN_GREEDY)
+    assert info["gates"] == cg.count_gates(ops)
+    assert info["sweeps"] <= 32
+    assert info["blocks"] <= 200
+    n, ops = cg.workload("rqc34_d24")
+    info = qs.Circuit(ops).plan_info(n, qs.C64, qs.PLAN_GREEDY)
+    assert info["gates"] == cg.count_gates(ops) and info["sweeps"] <= 15
+
+
 def test_autotune_result_before_any_run(qs):
     c = qs.Circuit(cg.random_circuit(4, 5, 4, seed=3, cu3_prob=0.1))
     assert c.autotune_result(20, qs.C64) == (0, 6, 0, 0, 0.0)
