@@ -92,6 +92,7 @@ def traffic_for(path_name: str, kernel_class: str):
 # --- rocprofv3 summaries ------------------------------------------------------
 # The counter passes, each a run of its own (rocprofv3 does not split counters
 # over passes), from the repository root on the GPU machine:
+PROFILE_DIR = "rocprof_out"  # where the runs below write their CSVs and logs
 PROFILE_RUNS = [
     ("ktrace", "--kernel-trace --stats",
      "--steps 2 --warmup 1 --no-cpu-baseline --trajectories 0 --no-by-target"),
@@ -109,8 +110,8 @@ PROFILE_RUNS = [
 
 
 def profile_command(sub, flags, bench_args):
-    return ("rocprofv3 %s -f csv -d gpurun_out/%s -o run -- python3 bench.py %s > gpurun_out/%s.log"
-            % (flags, sub, bench_args, sub))
+    return ("rocprofv3 %s -f csv -d %s/%s -o run -- python3 bench.py %s > %s/%s.log"
+            % (flags, PROFILE_DIR, sub, bench_args, PROFILE_DIR, sub))
 
 
 def kernel_class_of(name: str):
@@ -234,7 +235,7 @@ def summarize_profiles(d):
     lines += ["", "Commands (from the repository root, after `cd /tmp && export TMPDIR=/tmp` and with",
               "paths taken from the root; each pass is its own process):", "", "```"]
     lines += [cmds[k] for k in cmds if k.startswith("pmc_")]
-    lines += ["python3 bench.py --summarize-profiles gpurun_out", "```", "",
+    lines += ["python3 bench.py --summarize-profiles %s" % PROFILE_DIR, "```", "",
               "Kernel sources hash: %s" % src]
     with open(os.path.join(prof, "hbm_traffic_rqc30_d40.md"), "w") as f:
         f.write("\n".join(lines) + "\n")

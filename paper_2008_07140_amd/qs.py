@@ -18,8 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqs.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError("libqs.so is not built: run `python -m paper_2008_07140_amd.build` "
-                      "(or __graft_entry__.build())")
+    raise ImportError("libqs.so is not built: run `python -m paper_2008_07140_amd.build`")
 
 _lib = C.CDLL(LIB_PATH)
 
