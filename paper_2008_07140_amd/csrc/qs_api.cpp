@@ -912,7 +912,8 @@ Features sweep_features(const qs::Sweep &sw, int n, qs_dtype dt)
 // Tile parameters for a segment.  Without a cost model: the defaults.  With
 // one (QS_PLAN_LEARNED): plan the segment for every candidate (tile qubits 11
 // to 13, block width 4 or 5), predict every sweep's time with the network on
-// the device and keep the cheapest candidate.
+// the device and keep the cheapest candidate, unless the defaults are
+// predicted within 3% of it.
 qs_status choose_tile_params(qs_state *s, const std::vector<qs::FlatOp> &flat, size_t k, size_t e,
                              const qs_run_opts &o, qs::TileParams &best, std::vector<qs::PlanStep> &best_steps)
 {
@@ -970,6 +971,11 @@ qs_status choose_tile_params(qs_state *s, const std::vector<qs::FlatOp> &flat, s
     size_t bi = 0;
     for (size_t c = 1; c < cand.size(); ++c)
         if (cost[c] < cost[bi]) bi = c;
+    // the default shape stands unless another is predicted clearly cheaper:
+    // the network's errors on whole plans are a few percent
+    constexpr double kMargin = 0.03;
+    for (size_t c = 0; c < cand.size(); ++c)
+        if (cand[c].m == best.m && cand[c].kmax == best.kmax && cost[bi] > (1.0 - kMargin) * cost[c]) bi = c;
     best = cand[bi];
     best_steps = std::move(plans[bi]);
     return QS_OK;
