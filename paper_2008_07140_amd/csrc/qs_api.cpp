@@ -861,9 +861,9 @@ bool tiled_plan(const qs_state *s, const qs_run_opts &o)
     return o.plan != QS_PLAN_UNFUSED && s->dt == QS_C64 && s->n >= 10;
 }
 
-// Kernel arguments of one sweep: slot r of a thread (local index 512 r) and
-// the local bits 0..8 of the thread offset mapped to their global qubits, and
-// the bits outside the tile that index the tiles.
+// Kernel arguments of one sweep: the global qubit of every local tile bit
+// (the kernel spreads a thread's local offsets over them), the bits outside
+// the tile that index the tiles, and tile order 0 (launch_steps may change it).
 qs::TileArgs make_tile_args(const qs::Sweep &sw, int n)
 {
     qs::TileArgs ta{};
