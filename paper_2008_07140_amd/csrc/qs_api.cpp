@@ -27,6 +27,7 @@
 
 #include <array>
 #include <condition_variable>
+#include <pthread.h>
 #include <functional>
 #include <mutex>
 #include <shared_mutex>
@@ -453,6 +454,10 @@ void append_fragments(const std::vector<double> &m, int k, std::vector<uint16_t>
 // or concurrent calls cannot deadlock: at worst the caller does the work
 // itself.  A job lives on the heap, held by every thread that took it, so a
 // worker that wakes after the job is finished only sees an exhausted counter.
+// A child process forked after the pool started inherits none of its threads
+// and possibly a locked mutex: there parallel_for runs serially.
+std::atomic<bool> g_pool_forked{false};
+
 class WorkerPool {
 public:
     struct Job {
@@ -490,6 +495,7 @@ public:
 private:
     WorkerPool()
     {
+        pthread_atfork(nullptr, nullptr, [] { g_pool_forked.store(true); });
         const size_t hw = std::max(1u, std::thread::hardware_concurrency());
         const size_t nw = std::min<size_t>(hw, 16) - 1;
         for (size_t t = 0; t < nw; ++t) threads_.emplace_back([this] { loop(); });
@@ -532,7 +538,7 @@ private:
 template <typename F>
 void parallel_for(size_t count, F &&f)
 {
-    if (count < 8 || WorkerPool::get().workers() == 0) {
+    if (count < 8 || g_pool_forked.load() || WorkerPool::get().workers() == 0) {
         for (size_t i = 0; i < count; ++i) f(i);
         return;
     }
