@@ -678,14 +678,19 @@ void plan_tiles(const std::vector<FlatOp> &flat, size_t k0, size_t e, int n, con
             // Local search over the tile qubits: the greedy set takes the
             // qubits of the earliest pending gates, which on layered circuits
             // leaves many of a sweep's gates blocked by a neighbour outside the
-            // tile.  Swap one qubit of Q (never the L lowest) for one outside
-            // whenever the sweep then applies more gates, until no swap helps.
-            // The count is the scan below with Q fixed, post-pass rules
+            // tile.  From the greedy set and from `restarts` random sets, swap
+            // one qubit of Q (never the L lowest) for one outside whenever the
+            // sweep then applies more gates, until no swap helps.  Among the
+            // local optima keep the one whose sweep plus the next sweep (its
+            // deferred gates, searched the same way from their greedy set)
+            // apply the most gates; ties keep the earliest candidate.  Counts
+            // come from the scan below with Q fixed, post-pass rules
             // included, so the chosen Q's lists come from the same scan.
-            auto scan_fixed = [&](uint64_t Qf, std::vector<size_t> *app, std::vector<size_t> *def) {
+            auto scan_on = [&](const std::vector<size_t> &rem, uint64_t Qf, std::vector<size_t> *app,
+                               std::vector<size_t> *def) {
                 uint64_t blk = 0;
                 int c = 0;
-                for (size_t gi : remaining) {
+                for (size_t gi : rem) {
                     const GInfo &g = info[gi];
                     const bool ok = !(g.qmask & blk) && fits_tile(g) && (g.diag || !(g.tmask & ~Qf)) &&
                                     __builtin_popcountll(g.qmask & Qf) <= kmax &&
@@ -700,27 +705,89 @@ void plan_tiles(const std::vector<FlatOp> &flat, size_t k0, size_t e, int n, con
                 }
                 return c;
             };
-            int best = scan_fixed(Q, nullptr, nullptr);
-            for (bool improved = true; improved;) {
-                improved = false;
-                for (int a = L; a < n && !improved; ++a) {
-                    if (!(Q >> a & 1)) continue;
-                    for (int b = L; b < n; ++b) {
-                        if (Q >> b & 1) continue;
-                        const uint64_t Q2 = (Q & ~(uint64_t(1) << a)) | (uint64_t(1) << b);
-                        const int c2 = scan_fixed(Q2, nullptr, nullptr);
-                        if (c2 > best) {
-                            best = c2;
-                            Q = Q2;
-                            improved = true;
-                            break;
+            auto climb = [&](const std::vector<size_t> &rem, uint64_t Qs, int &count) {
+                int best = scan_on(rem, Qs, nullptr, nullptr);
+                for (bool improved = true; improved;) {
+                    improved = false;
+                    for (int a = L; a < n && !improved; ++a) {
+                        if (!(Qs >> a & 1)) continue;
+                        for (int b = L; b < n; ++b) {
+                            if (Qs >> b & 1) continue;
+                            const uint64_t Q2 = (Qs & ~(uint64_t(1) << a)) | (uint64_t(1) << b);
+                            const int c2 = scan_on(rem, Q2, nullptr, nullptr);
+                            if (c2 > best) {
+                                best = c2;
+                                Qs = Q2;
+                                improved = true;
+                                break;
+                            }
                         }
                     }
                 }
+                count = best;
+                return Qs;
+            };
+            // first-come tile qubits of a gate list (the start of the next
+            // sweep's search)
+            auto greedy_q = [&](const std::vector<size_t> &rem) {
+                uint64_t Qg = low, blk = 0;
+                for (size_t gi : rem) {
+                    const GInfo &g = info[gi];
+                    if ((g.qmask & blk) || !fits_tile(g)) {
+                        blk |= g.qmask;
+                        continue;
+                    }
+                    if (g.diag) continue;
+                    const uint64_t need = g.tmask & ~Qg;
+                    if (!need || __builtin_popcountll(Qg | need) <= m)
+                        Qg |= need;
+                    else
+                        blk |= g.qmask;
+                }
+                for (int q = 0; q < n && __builtin_popcountll(Qg) < m; ++q) Qg |= uint64_t(1) << q;
+                return Qg;
+            };
+            std::vector<std::pair<uint64_t, int>> cands;
+            {
+                int c = 0;
+                const uint64_t q0 = climb(remaining, Q, c);
+                cands.push_back({q0, c});
             }
+            uint64_t rs = 0x9E3779B97F4A7C15ull ^ (uint64_t(out.size()) << 17);  // xorshift64, per sweep
+            for (int r = 0; r < tp.restarts && n - L > m - L; ++r) {
+                uint64_t Qr = low;
+                while (__builtin_popcountll(Qr) < m) {
+                    rs ^= rs << 13;
+                    rs ^= rs >> 7;
+                    rs ^= rs << 17;
+                    Qr |= uint64_t(1) << (L + int(rs % uint64_t(n - L)));
+                }
+                int c = 0;
+                const uint64_t qc = climb(remaining, Qr, c);
+                bool seen = false;
+                for (auto &x : cands) seen = seen || x.first == qc;
+                if (!seen) cands.push_back({qc, c});
+            }
+            size_t bi = 0;
+            int bscore = -1;
+            for (size_t ci = 0; ci < cands.size(); ++ci) {
+                int score = cands[ci].second;
+                if (cands.size() > 1) {
+                    std::vector<size_t> app, def;
+                    scan_on(remaining, cands[ci].first, &app, &def);
+                    int c2 = 0;
+                    if (!def.empty()) climb(def, greedy_q(def), c2);
+                    score += c2;
+                }
+                if (score > bscore) {
+                    bscore = score;
+                    bi = ci;
+                }
+            }
+            Q = cands[bi].first;
             applied.clear();
             deferred.clear();
-            scan_fixed(Q, &applied, &deferred);
+            scan_on(remaining, Q, &applied, &deferred);
         }
         // gates with more than kmax qubits inside or `mo` outside the final Q
         // are left for a later step

@@ -160,18 +160,20 @@ def test_tile_planner_terminates_on_wide_diagonals(qs):
 
 
 def test_tile_planner_sweep_counts_on_workload_circuits(qs):
-    """The greedy tile planner with its local search over tile qubits: on the
-    30-qubit depth-40 workload circuit it needs 31 sweeps of 13-qubit tiles
-    (41 with first-come tile qubits), and every logical gate is planned.  A
-    regression guard on the planner's quality, not a parity check."""
+    """The greedy tile planner with its search over tile qubits (local search
+    from the first-come set and from seeded random sets, two-sweep lookahead):
+    on the 30-qubit depth-40 workload circuit it needs 30 sweeps of 13-qubit
+    tiles (41 with first-come tile qubits), on the 34-qubit one 13 (20), and
+    every logical gate is planned.  A regression guard on the planner's
+    quality, not a parity check."""
     n, ops = cg.workload("rqc30_d40")
     info = qs.Circuit(ops).plan_info(n, qs.C64, qs.PLAN_GREEDY)
     assert info["gates"] == cg.count_gates(ops)
-    assert info["sweeps"] <= 32
+    assert info["sweeps"] <= 31
     assert info["blocks"] <= 200
     n, ops = cg.workload("rqc34_d24")
     info = qs.Circuit(ops).plan_info(n, qs.C64, qs.PLAN_GREEDY)
-    assert info["gates"] == cg.count_gates(ops) and info["sweeps"] <= 15
+    assert info["gates"] == cg.count_gates(ops) and info["sweeps"] <= 14
 
 
 def test_autotune_result_before_any_run(qs):
