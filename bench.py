@@ -66,12 +66,25 @@ def parse():
 
 
 def source_hash():
-    h = hashlib.sha256()
+    """Hash of the device code: every .hip source and the headers it includes
+    (transitively), so host-only changes (planner, executor) keep stored
+    counter readings valid."""
+    import re
     csrc = os.path.join(ROOT, "paper_2008_07140_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(fh.read())
+    files, todo = set(), [os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith(".hip")]
+    while todo:
+        f = os.path.normpath(todo.pop())
+        if f in files or not os.path.exists(f):
+            continue
+        files.add(f)
+        with open(f) as fh:
+            for inc in re.findall(r'#include\s+"([^"]+)"', fh.read()):
+                todo.append(os.path.join(os.path.dirname(f), inc))
+    h = hashlib.sha256()
+    for f in sorted(files):
+        h.update(os.path.relpath(f, ROOT).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
