@@ -56,6 +56,8 @@ def parse():
                         "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
     p.add_argument("--no-by-target", action="store_true",
                    help="skip the per-target / per-control bandwidth sweep of single gates")
+    p.add_argument("--remap", action="store_true",
+                   help="bandwidth of the qubit-remap pack / unpack on a 30-qubit shard (one JSON line)")
     p.add_argument("--config5", action="store_true",
                    help="34-qubit learned-planner comparison: complex128 reference on 2^20 sampled "
                         "indices, then complex64 learned vs greedy vs unfused")
@@ -117,6 +119,7 @@ PROFILE_RUNS = [
      "--steps 1 --warmup 0 --no-cpu-baseline --trajectories 0 --no-by-target --paths plain_c128"),
     ("pmc_write_plain_c128", "--pmc WRITE_SIZE",
      "--steps 1 --warmup 0 --no-cpu-baseline --trajectories 0 --no-by-target --paths plain_c128"),
+    ("remap", "--kernel-trace --stats", "--remap"),
     ("pmc_fetch_copy", "--pmc FETCH_SIZE", "--copy-calibration"),
     ("pmc_write_copy", "--pmc WRITE_SIZE", "--copy-calibration"),
 ]
@@ -184,6 +187,46 @@ def _last_json(path):
             if line.startswith("{") and '"metric"' in line:
                 last = json.loads(line)
     return last
+
+
+def summarize_remap(d, cmd, src):
+    """profiles/kernel_stats_remap_l30.md from the kernel trace of bench.py
+    --remap: per case and direction, the average of its timed dispatches (each
+    case runs one untimed and three timed calls per direction, in the order of
+    the run's JSON line) beside the run's own event timing."""
+    import glob
+    prof = os.path.join(ROOT, "profiles")
+    line = _last_json(os.path.join(d, "remap.log"))
+    tr = glob.glob(os.path.join(d, "remap", "**", "*kernel_trace.csv"), recursive=True)
+    if not line or not tr:
+        return
+    rows = sorted((r for r in _csv_rows(tr[0]) if "k_remap" in r["Kernel_Name"]),
+                  key=lambda r: int(r["Start_Timestamp"]))
+    L = line["shard_qubits"]
+    kl = ["# Kernel time, qubit-remap pack / unpack on a %d-qubit shard (g = %d)" % (L, line["g"]), "",
+          "`rocprofv3 --kernel-trace` of `bench.py --remap`; per case and direction the average of the",
+          "three timed dispatches. Algorithmic bytes per call: 2 * 2^%d * sizeof(amplitude) (34.36 GB for" % L,
+          "complex128, 17.18 GB for complex64).", "",
+          "| dtype | lq | direction | kernel | average us | GB/s (trace) | GB/s (HIP events, same run) |",
+          "|---|---|---|---|---|---|---|"]
+    per = 4
+    for ci, res in enumerate(line["results"]):
+        amp = 16 if res["dtype"] == "c128" else 8
+        nbytes = 2.0 * (1 << L) * amp
+        for di, name in enumerate(("pack", "unpack")):
+            grp = rows[(2 * ci + di) * per:(2 * ci + di + 1) * per]
+            if len(grp) < per:
+                continue
+            durs = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in grp[1:]]
+            avg = sum(durs) / len(durs)
+            kl.append("| %s | %s | %s | %s | %.1f | %.0f | %.0f |"
+                      % (res["dtype"], res["lq"], name, short_kernel(grp[0]["Kernel_Name"]), avg / 1e3,
+                         nbytes / avg, res[name + "_GBps"]))
+    kl += ["", "Command (from the repository root):", "", "```", cmd, "python3 bench.py --summarize-profiles %s"
+           % PROFILE_DIR, "```", "", "Kernel sources hash: %s" % src]
+    with open(os.path.join(prof, "kernel_stats_remap_l30.md"), "w") as f:
+        f.write("\n".join(kl) + "\n")
+    print("wrote profiles/kernel_stats_remap_l30.md")
 
 
 def summarize_profiles(d):
@@ -294,6 +337,8 @@ def summarize_profiles(d):
            "Kernel sources hash: %s" % src]
     with open(os.path.join(prof, "kernel_stats_rqc30_d40.md"), "w") as f:
         f.write("\n".join(kl) + "\n")
+    if os.path.isdir(os.path.join(d, "remap")):
+        summarize_remap(d, cmds["remap"], src)
     print("wrote profiles/traffic.json, profiles/hbm_traffic_rqc30_d40.md, profiles/kernel_stats_rqc30_d40.md")
 
 
@@ -413,6 +458,46 @@ def copy_ceiling(torch, nbytes=4 << 30, reps=5):
     torch.cuda.empty_cache()
     log("device copy: %.0f GB/s blit, %.0f GB/s elementwise (read + write)" % (res["blit"], res["elementwise"]))
     return max(res.values()), res
+
+
+def remap_bench(qs, torch, L=30, g=3, reps=3):
+    """Pack and unpack of the qubit-remap exchange (qs_remap_pack / _unpack) on
+    one shard at its real shape (L local qubits), for several local-qubit
+    sets: algorithmic bytes 2 * 2^L * amp per call (every amplitude read and
+    written once) / the average call time, from HIP events on the shard's
+    stream.  The all-to-all between the calls needs more than one GPU and is
+    not run."""
+    cases = [("c128", [L - 3, L - 2, L - 1]), ("c128", [20, 21, 22]), ("c128", [4, 5, 6]),
+             ("c128", [0, 13, L - 1]), ("c64", [4, 5, 6]), ("c64", [0, 13, L - 1])]
+    out = []
+    stream = torch.cuda.Stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for dtype, lq in cases:
+        lq = lq[:g]
+        dt = qs.C128 if dtype == "c128" else qs.C64
+        tdt = torch.complex128 if dt == qs.C128 else torch.complex64
+        t = torch.empty(1 << L, dtype=tdt, device="cuda")
+        buf = torch.empty_like(t)
+        st = qs.State(L, dt, buffer=t, stream=stream.cuda_stream)
+        nbytes = 2.0 * (1 << L) * t.element_size()
+        res = {"dtype": dtype, "lq": lq}
+        for name, fn in (("pack", lambda: st.remap_pack(lq, buf)), ("unpack", lambda: st.remap_unpack(lq, buf))):
+            fn()
+            ev0.record(stream)
+            for _ in range(reps):
+                fn()
+            ev1.record(stream)
+            ev1.synchronize()
+            res[name + "_GBps"] = round(nbytes * reps / (ev0.elapsed_time(ev1) * 1e-3) / 1e9, 1)
+        log("remap %s L=%d lq=%s: pack %.0f GB/s, unpack %.0f GB/s"
+            % (dtype, L, lq, res["pack_GBps"], res["unpack_GBps"]))
+        out.append(res)
+        st.close()
+        del t, buf
+        torch.cuda.empty_cache()
+    print(json.dumps({"metric": "qubit-remap pack / unpack bandwidth", "unit": "GB/s", "shard_qubits": L,
+                      "g": g, "bytes": "2 * 2^L * sizeof(amplitude) per call", "results": out}))
+    return out
 
 
 def trajectory_bench(qs, cg, count, seed=4001):
@@ -569,6 +654,9 @@ def main():
 
     if args.config5:
         config5(qs, cg, torch)
+        return
+    if args.remap:
+        remap_bench(qs, torch)
         return
     if args.plan == "learned":
         p, _ = train_cost_model(qs, cg, log_fn=log)

@@ -253,6 +253,38 @@ qs_status qs_expect_z(const qs_state *s, double *out);
 qs_status qs_run_trajectories(const qs_circuit *const *circs, const int *widths, int count,
                               qs_dtype dt, uint64_t seed, double *z_out, double *seconds);
 
+/* ------------------------------------------------------- sharded states -- */
+
+#define QS_REMAP_MAX_G 10
+
+/* Qubit-remap exchange, the device-local halves.  Sec. 2.1 divides the
+ * amplitudes of a state equally over the nodes, so the top g qubits of an
+ * (L + g)-qubit state name the node (here: the device) holding an
+ * amplitude, and each device keeps a shard of L local qubits in a qs_state.
+ * A gate on a global qubit needs partner amplitudes held elsewhere, the slow
+ * case of Sec. 3.1 / Fig. 4.  Instead of exchanging pairs per gate, the g
+ * global qubits swap places with g local qubits lq[0..g-1] (distinct, in
+ * [0, L)) in one all-to-all, which the caller runs between these calls
+ * (for example RCCL's all-to-all on the state's stream):
+ *  - qs_remap_pack writes the shard into `device_buf` as 2^g chunks of
+ *    2^(L-g) amplitudes, chunk d (at offset d * 2^(L-g) amplitudes) holding
+ *    the amplitudes whose bits lq read d (bit i of d = local qubit lq[i]),
+ *    in ascending order of the remaining local bits.  The shard is unchanged.
+ *  - chunk d of device r goes to slot r of device d's receive buffer;
+ *  - qs_remap_unpack overwrites the shard from such a buffer, slot r going
+ *    to the amplitudes whose bits lq read r.
+ * Afterwards local qubit lq[i] carries the former global qubit L + i and
+ * global qubit L + i the former local qubit lq[i]; with g = 0 both calls
+ * are plain copies.  `device_buf`: caller-owned device memory of at least
+ * 2^L amplitudes of the state's dtype, 16-byte aligned, not overlapping the
+ * state; only read by unpack, only written by pack.  Both calls are
+ * enqueued on the state's stream and return before the device finishes.
+ * Errors: QS_E_INVAL (null pointer, misaligned buffer, g outside
+ * [0, min(L, QS_REMAP_MAX_G)], buffer overlapping the state), QS_E_RANGE
+ * (lq repeated or outside [0, L)), QS_E_DEVICE. */
+qs_status qs_remap_pack(const qs_state *s, int g, const int *lq, void *device_buf);
+qs_status qs_remap_unpack(qs_state *s, int g, const int *lq, const void *device_buf);
+
 /* ------------------------------------------------------------------ misc -- */
 
 /* The uniform number used for noise site `site` of trajectory `traj`:

@@ -2447,6 +2447,49 @@ qs_status execute_plan(qs_state *s, const CachedPlan &plan, qs_run_opts o)
 
 }  // namespace
 
+// ------------------------------------------------------- sharded states --
+
+namespace {
+
+qs_status remap(qs_state *s, int g, const int *lq, const void *buf, bool pack)
+{
+    if (qs_status st = check_state(s)) return st;
+    const int L = s->n;
+    if (g < 0 || g > L || g > QS_REMAP_MAX_G)
+        return fail(QS_E_INVAL, "g = %d not in [0, %d]", g, L < QS_REMAP_MAX_G ? L : QS_REMAP_MAX_G);
+    if (g > 0 && !lq) return fail(QS_E_INVAL, "lq is NULL");
+    if (!buf) return fail(QS_E_INVAL, "device_buf is NULL");
+    if (reinterpret_cast<uintptr_t>(buf) % 16) return fail(QS_E_INVAL, "device_buf is not 16-byte aligned");
+    uint64_t seen = 0;
+    for (int i = 0; i < g; ++i) {
+        if (lq[i] < 0 || lq[i] >= L) return fail(QS_E_RANGE, "local qubit %d not in [0, %d)", lq[i], L);
+        if ((seen >> lq[i]) & 1) return fail(QS_E_RANGE, "local qubit %d repeated", lq[i]);
+        seen |= uint64_t(1) << lq[i];
+    }
+    const size_t bytes = amp_bytes(s->dt) << L;
+    const uintptr_t b0 = reinterpret_cast<uintptr_t>(buf), a0 = reinterpret_cast<uintptr_t>(s->amp);
+    if (b0 < a0 + bytes && a0 < b0 + bytes) return fail(QS_E_INVAL, "device_buf overlaps the state");
+    hipError_t e;
+    {
+        Timed t(s, QS_K_OTHER, 2.0 * double(bytes), 0.0);
+        e = qs::launch_remap(s->dt, s->amp, const_cast<void *>(buf), L, g, lq, pack, s->stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, pack ? "remap pack" : "remap unpack");
+    return QS_OK;
+}
+
+}  // namespace
+
+qs_status qs_remap_pack(const qs_state *s, int g, const int *lq, void *device_buf)
+{
+    return remap(const_cast<qs_state *>(s), g, lq, device_buf, true);
+}
+
+qs_status qs_remap_unpack(qs_state *s, int g, const int *lq, const void *device_buf)
+{
+    return remap(s, g, lq, device_buf, false);
+}
+
 // -------------------------------------------------------------- readout --
 
 qs_status qs_amplitudes(const qs_state *cs, const uint64_t *idx, size_t m, double *out)

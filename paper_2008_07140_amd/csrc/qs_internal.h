@@ -85,6 +85,12 @@ hipError_t launch_expect_z(qs_dtype dt, const void *amp, int n, double *scratch,
 // out[k] = alpha_{idx[k]} as double2
 hipError_t launch_gather(qs_dtype dt, const void *amp, const uint64_t *dev_idx, uint64_t m,
                          double *dev_out, hipStream_t st);
+// Qubit-remap exchange of a shard of L local qubits (qs_remap.hip): pack
+// (buf[b] = shard[remap(b)]) or unpack (shard[remap(b)] = buf[b]), where
+// remap spreads chunk number b >> (L - g) over the local qubits lq[0..g-1]
+// and the rest of b over the other local bits in ascending order.
+hipError_t launch_remap(qs_dtype dt, void *shard, void *buf, int L, int g, const int *lq, bool pack,
+                        hipStream_t st);
 // amp *= scale (real), used for renormalisation
 hipError_t launch_scale(qs_dtype dt, void *amp, uint64_t n_amp, double scale, hipStream_t st);
 

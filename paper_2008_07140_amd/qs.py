@@ -77,6 +77,8 @@ _sig = {
     "qs_norm": ([P, P], I),
     "qs_expect_z": ([P, P], I),
     "qs_run_trajectories": ([P, P, I, I, U64, P, P], I),
+    "qs_remap_pack": ([P, I, P, P], I),
+    "qs_remap_unpack": ([P, I, P, P], I),
     "qs_philox_uniform": ([U64, U64, U64], D),
     "qs_philox4x32_10": ([P, P, P], None),
     "qs_profile_enable": ([P, I], I),
@@ -315,6 +317,17 @@ class State:
             o.chosen_len = nsites
         _check(_lib.qs_run_circuit(self._h, circuit.handle, C.byref(o)))
         return np.array(chosen[:], dtype=np.int64) if chosen is not None else None
+
+    def remap_pack(self, lq: Sequence[int], buffer) -> None:
+        """qs_remap_pack into `buffer` (device memory exposing data_ptr(), e.g. a
+        torch tensor of 2^n amplitudes of the state's dtype)."""
+        q = _ints(lq)
+        _check(_lib.qs_remap_pack(self._h, len(q), _ptr(q), C.c_void_p(buffer.data_ptr())))
+
+    def remap_unpack(self, lq: Sequence[int], buffer) -> None:
+        """qs_remap_unpack from `buffer` (as remap_pack)."""
+        q = _ints(lq)
+        _check(_lib.qs_remap_unpack(self._h, len(q), _ptr(q), C.c_void_p(buffer.data_ptr())))
 
     def amplitudes(self, idx: Optional[np.ndarray] = None) -> np.ndarray:
         if idx is None:

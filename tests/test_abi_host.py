@@ -66,6 +66,13 @@ def test_create_validation_without_device(qs):
         qs.set_memory_limit(0)
 
 
+def test_remap_rejects_a_missing_state(qs):
+    lib = qs.lib()
+    assert lib.qs_remap_pack(None, 0, None, None) == -1
+    assert lib.qs_remap_unpack(None, 0, None, None) == -1
+    assert "state is NULL" in qs.last_error()
+
+
 def test_circuit_validation(qs):
     c = qs.Circuit()
     with pytest.raises(qs.QSError) as e:

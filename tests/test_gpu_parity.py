@@ -658,3 +658,143 @@ def test_learned_planner_parity_and_gain(qs):
     finally:
         qs.cost_model_set(None)
         s.close()
+
+
+# ------------------------------------------------ sharded states: remap --
+
+
+def _remap_index(b, L, lq):
+    """Shard index of element b of a packed remap buffer, as qs.h documents it:
+    the chunk number b >> (L - g) spread over the qubits lq (bit i at lq[i]),
+    the rest of b over the other local qubits in ascending order."""
+    g = len(lq)
+    d, x = b >> (L - g), b & ((1 << (L - g)) - 1)
+    idx = 0
+    for k, p in enumerate(p for p in range(L) if p not in lq):
+        idx |= ((x >> k) & 1) << p
+    for i, q in enumerate(lq):
+        idx |= ((d >> i) & 1) << q
+    return idx
+
+
+class _StateBuffer:
+    """Device memory for a remap buffer: the amplitude array of another state
+    (its initialisation finished before use), readable and writable through
+    that state's own calls."""
+
+    def __init__(self, qs, L, dt):
+        self.s = qs.State(L, dt)
+        self.s.synchronize()
+
+    def data_ptr(self):
+        return self.s.info()["device_ptr"]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("L,lq", [(9, []), (8, [3]), (10, [7, 0]), (12, [5, 1, 11]),
+                                  (11, [0, 1, 2]), (12, [11, 10, 9]), (6, [5, 0, 3, 1, 4, 2])])
+def test_remap_exchange_swaps_global_and_local_qubits(qs, dtype, L, lq):
+    """An (L + g)-qubit state split into 2^g shards of L qubits (one per
+    would-be device, all on this one): each packed buffer holds the layout
+    qs.h documents; after the all-to-all (chunk d of shard r to slot r of
+    shard d, done on the host here) and the unpacks, the shards equal the
+    oracle's state after SWAP(L + i, lq[i]) for every i, bit for bit (data
+    movement only)."""
+    g, n = len(lq), L + len(lq)
+    dt = qs.C128 if dtype == "c128" else qs.C64
+    psi = cg.random_state(n, 7000 + 31 * L + g)
+    if dt == qs.C64:
+        psi = psi.astype(np.complex64).astype(np.complex128)
+    ref = psi.copy()
+    for i, q in enumerate(lq):
+        oracle.apply(ref, (L + i, q), (), oracle.named_gate("SWAP"))
+    size, chunk = 1 << L, 1 << (L - g)
+    shards, sent = [], []
+    for r in range(1 << g):
+        s = qs.State(L, dt)
+        s.set_amplitudes(psi[r * size:(r + 1) * size])
+        b = _StateBuffer(qs, L, dt)
+        s.remap_pack(lq, b)
+        s.synchronize()
+        sent.append(b.s.amplitudes())
+        b.s.close()
+        shards.append(s)
+    layout = np.array([_remap_index(b, L, lq) for b in range(size)])
+    for r in range(1 << g):
+        assert np.array_equal(sent[r], psi[r * size + layout])
+    for d, s in enumerate(shards):
+        recv = np.concatenate([sent[r][d * chunk:(d + 1) * chunk] for r in range(1 << g)])
+        b = _StateBuffer(qs, L, dt)
+        b.s.set_amplitudes(recv)
+        s.remap_unpack(lq, b)
+        s.synchronize()
+        b.s.close()
+    got = np.concatenate([s.amplitudes() for s in shards])
+    assert np.array_equal(got, ref)
+    for s in shards:
+        s.close()
+
+
+@pytest.mark.parametrize("dtype,L,lq", [("c64", 27, [4, 17, 26]), ("c64", 26, [0, 25, 12]),
+                                        ("c128", 26, [9, 3, 25, 14])])
+def test_remap_large_shard_sampled_chunks_and_round_trip(qs, dtype, L, lq):
+    """At shard sizes of 0.5-1 GiB, on a state prepared by two layers of
+    random one-qubit gates with a CZ layer between them: 2^16 sampled entries
+    of the packed buffer equal the shard amplitudes the documented layout
+    names, and unpacking the buffer into a reset shard restores those
+    amplitudes exactly and the FP64 norm."""
+    dt = qs.C128 if dtype == "c128" else qs.C64
+    rng = np.random.default_rng(9000 + L)
+    s = qs.State(L, dt)
+    for q in range(L):
+        s.apply_gate((q,), (), cg.random_unitary(2, rng))
+    for q in range(0, L - 1, 2):
+        s.apply_gate((q, q + 1), (), np.diag([1, 1, 1, -1]))
+    for q in range(L):
+        s.apply_gate((q,), (), cg.random_unitary(2, rng))
+    bs = np.sort(rng.choice(1 << L, size=1 << 16, replace=False)).astype(np.uint64)
+    src = np.array([_remap_index(int(b), L, lq) for b in bs], dtype=np.uint64)
+    before = s.amplitudes(src)
+    norm_before = s.norm()
+    buf = _StateBuffer(qs, L, dt)
+    s.remap_pack(lq, buf)
+    s.synchronize()
+    assert np.array_equal(buf.s.amplitudes(bs), before)
+    s.reset()
+    s.remap_unpack(lq, buf)
+    assert np.array_equal(s.amplitudes(src), before)
+    assert abs(s.norm() - norm_before) < 1e-12
+    buf.s.close()
+    s.close()
+
+
+def test_remap_validation(qs):
+    s = qs.State(6, qs.C128)
+    buf = _StateBuffer(qs, 6, qs.C128)
+    for lq, status in [([6], -2), ([1, 1], -2), ([-1], -2), (list(range(7)), -1)]:
+        with pytest.raises(qs.QSError) as e:
+            s.remap_pack(lq, buf)
+        assert e.value.status == status
+
+    class Ptr:
+        def __init__(self, p):
+            self.p = p
+
+        def data_ptr(self):
+            return self.p
+
+    with pytest.raises(qs.QSError) as e:
+        s.remap_unpack([0], Ptr(buf.data_ptr() + 8))
+    assert e.value.status == -1 and "aligned" in qs.last_error()
+    with pytest.raises(qs.QSError) as e:
+        s.remap_pack([0], Ptr(0))
+    assert e.value.status == -1
+    with pytest.raises(qs.QSError) as e:
+        s.remap_pack([0], Ptr(s.info()["device_ptr"] + 128))
+    assert e.value.status == -1 and "overlaps" in qs.last_error()
+    big = qs.State(12, qs.C64)
+    with pytest.raises(qs.QSError) as e:
+        big.remap_pack(list(range(11)), Ptr(buf.data_ptr()))
+    assert e.value.status == -1
+    for x in (s, big, buf.s):
+        x.close()

@@ -156,6 +156,24 @@ def test_toffoli_and_cnot_are_basis_permutations():
         assert psi[y] == 1 and np.count_nonzero(psi) == 1
 
 
+def test_swap_exchanges_the_values_of_its_qubits():
+    """SWAP (App. A-1) on every basis state of 5 qubits and every ordered pair
+    moves the value of each qubit to the other: |x> -> |x with bits a, b
+    exchanged>, brute force."""
+    n = 5
+    for a in range(n):
+        for b in range(n):
+            if a == b:
+                continue
+            for x in range(1 << n):
+                psi = np.zeros(1 << n, dtype=complex)
+                psi[x] = 1
+                oracle.apply(psi, (a, b), (), oracle.named_gate("SWAP"))
+                ba, bb = (x >> a) & 1, (x >> b) & 1
+                y = x & ~((1 << a) | (1 << b)) | (ba << b) | (bb << a)
+                assert psi[y] == 1 and np.count_nonzero(psi) == 1
+
+
 def test_eq4_cz_decomposition():
     """CZ^{i,j} = P0^i (x) I^j + P1^i (x) Z^j (Eq. 4)."""
     n = 6
