@@ -189,6 +189,16 @@ def _last_json(path):
     return last
 
 
+def remap_label(name: str):
+    """k_remap<unit, shift, pack, walk-the-shard> with readable vector types."""
+    import re
+    m = re.search(r"k_remap<(.*?)>\(", name)
+    if not m:
+        return name[:60]
+    args = re.sub(r"(double|float) __vector\((\d)\)", r"\1\2", m.group(1))
+    return "`k_remap<%s>`" % args
+
+
 def summarize_remap(d, cmd, src):
     """profiles/kernel_stats_remap_l30.md from the kernel trace of bench.py
     --remap: per case and direction, the average of its timed dispatches (each
@@ -220,7 +230,7 @@ def summarize_remap(d, cmd, src):
             durs = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in grp[1:]]
             avg = sum(durs) / len(durs)
             kl.append("| %s | %s | %s | %s | %.1f | %.0f | %.0f |"
-                      % (res["dtype"], res["lq"], name, short_kernel(grp[0]["Kernel_Name"]), avg / 1e3,
+                      % (res["dtype"], res["lq"], name, remap_label(grp[0]["Kernel_Name"]), avg / 1e3,
                          nbytes / avg, res[name + "_GBps"]))
     kl += ["", "Command (from the repository root):", "", "```", cmd, "python3 bench.py --summarize-profiles %s"
            % PROFILE_DIR, "```", "", "Kernel sources hash: %s" % src]
