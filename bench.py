@@ -58,6 +58,8 @@ def parse():
                    help="skip the per-target / per-control bandwidth sweep of single gates")
     p.add_argument("--remap", action="store_true",
                    help="bandwidth of the qubit-remap pack / unpack on a 30-qubit shard (one JSON line)")
+    p.add_argument("--partial", action="store_true",
+                   help="partial-amplitude mode on a 40-qubit depth-8 circuit (one JSON line)")
     p.add_argument("--config5", action="store_true",
                    help="34-qubit learned-planner comparison: complex128 reference on 2^20 sampled "
                         "indices, then complex64 learned vs greedy vs unfused")
@@ -510,6 +512,39 @@ def remap_bench(qs, torch, L=30, g=3, reps=3):
     return out
 
 
+def partial_bench(qs, cg, rows=8, cols=5, depth=8, top_rows=4, m=1 << 20, seed=6001):
+    """Partial-amplitude mode (qs_partial_amplitudes) on a circuit no full state
+    of which fits one GPU: an 8 x 5 grid (40 qubits, 16 TiB as complex128) at
+    depth 8, divided between rows 3 and 4 (two 20-qubit parts, 10 CZ cut),
+    2^20 sampled output amplitudes.  Wall time of the whole call (cut
+    planning, 2^c branch words x 2 sub-circuits on the device, FP64
+    recombination)."""
+    import numpy as np
+    n = rows * cols
+    ops = cg.random_circuit(rows, cols, depth, seed=seed)
+    c = qs.Circuit(ops)
+    part_a = (1 << (top_rows * cols)) - 1
+    idx = np.random.default_rng(seed + 1).integers(0, 1 << n, size=m, dtype=np.uint64)
+    cuts = c.partial_cuts(n, part_a)
+    runs = []
+    for name, dt, plan in (("c128_unfused", qs.C128, qs.PLAN_UNFUSED), ("c128_greedy", qs.C128, qs.PLAN_GREEDY)):
+        t0 = time.perf_counter()
+        amps, _ = c.partial_amplitudes(n, part_a, idx, dtype=dt, plan=plan)
+        sec = time.perf_counter() - t0
+        p = np.abs(amps) ** 2
+        log("partial %s: %d qubits, %d cuts, %d sub-circuits, %d amplitudes in %.2f s (%.0f amplitudes/s); "
+            "mean |amp|^2 * 2^n = %.3f" % (name, n, cuts, 2 << cuts, m, sec, m / sec, p.mean() * 2.0 ** n))
+        runs.append({"path": name, "seconds": round(sec, 3), "amplitudes_per_s": round(m / sec, 1),
+                     "mean_prob_times_2n": round(float(p.mean() * 2.0 ** n), 4)})
+    print(json.dumps({"metric": "partial-amplitude mode: sampled amplitudes per second", "unit": "amplitudes/s",
+                      "value": max(r["amplitudes_per_s"] for r in runs), "workload":
+                      "%dx%d grid random circuit, %d qubits, depth %d, %d gates" % (rows, cols, n, depth,
+                                                                                  cg.count_gates(ops)),
+                      "parts": [top_rows * cols, n - top_rows * cols], "cuts": cuts, "sub_circuits": 2 << cuts,
+                      "amplitudes": m, "runs": runs}))
+    return runs
+
+
 def trajectory_bench(qs, cg, count, seed=4001):
     """Batched noisy trajectories: widths n ~ U{14..22}, depth 24, depolarizing
     1e-3 / 1e-2 (two-qubit, Kronecker form) and amplitude damping 5e-4 per
@@ -667,6 +702,9 @@ def main():
         return
     if args.remap:
         remap_bench(qs, torch)
+        return
+    if args.partial:
+        partial_bench(qs, cg)
         return
     if args.plan == "learned":
         p, _ = train_cost_model(qs, cg, log_fn=log)

@@ -47,6 +47,7 @@ extern "C" {
 #endif
 
 #define QS_MAX_QUBITS 36
+#define QS_MAX_CIRCUIT_QUBITS 62 /* qubit indices of a circuit: [0, 62) */
 #define QS_MAX_TARGETS 6
 #define QS_MAX_KRAUS 64
 
@@ -135,7 +136,10 @@ qs_status qs_apply_noisy_gate(qs_state *s, const int *targets, int nt, const int
  * qs_run_circuit.  Group markers must be balanced when the circuit is run.
  * DAGGER: the group is replaced by the conjugate transposes of its gates in
  * reverse order.  CONTROL q: every gate of the group gains control qubit q.
- * Groups nest.  Noise sites inside a group are QS_E_UNSUPPORTED. */
+ * Groups nest.  Noise sites inside a group are QS_E_UNSUPPORTED.  Gate,
+ * noise and CONTROL qubits lie in [0, QS_MAX_CIRCUIT_QUBITS) (QS_E_RANGE
+ * otherwise), so that circuits wider than any state can be cut by
+ * qs_partial_amplitudes; a run on an n-qubit state rejects qubits >= n. */
 qs_status qs_circuit_create(qs_circuit **out);
 qs_status qs_circuit_destroy(qs_circuit *c);
 qs_status qs_circuit_append_gate(qs_circuit *c, const int *targets, int nt, const int *controls,
@@ -284,6 +288,45 @@ qs_status qs_run_trajectories(const qs_circuit *const *circs, const int *widths,
  * (lq repeated or outside [0, L)), QS_E_DEVICE. */
 qs_status qs_remap_pack(const qs_state *s, int g, const int *lq, void *device_buf);
 qs_status qs_remap_unpack(qs_state *s, int g, const int *lq, const void *device_buf);
+
+/* ------------------------------------------------- partial-amplitude mode -- */
+
+#define QS_PARTIAL_MAX_CUTS 24
+
+/* Partial-amplitude mode (Sec. 2.2 (partial), Eq. 4, Fig. 1): amplitudes of
+ * an n-qubit circuit (2 <= n <= 62) from sub-circuits on two parts of the
+ * qubits, never holding a 2^n state.  Part A is the qubits whose bits are set
+ * in part_a, part B the others; each part is renumbered in ascending qubit
+ * order and may hold at most QS_MAX_QUBITS qubits.  Gates inside one part
+ * belong to that part's sub-circuit.  A gate crossing the dividing line is
+ * cut as Eq. 4 cuts CZ when, in canonical form (a target on which the matrix
+ * is the identity unless its bit is 1 becomes a control; diagonal matrices
+ * are phase gates), it is
+ *  - a dense gate whose targets lie in one part: its controls in the other
+ *    part (at most QS_MAX_TARGETS) become a projector there, onto all ones
+ *    (branch 1, the gate applied under its remaining controls) or onto the
+ *    rest (branch 0, no gate); CNOT, CU3 and Toffoli are cut this way;
+ *  - a phase gate with exactly one qubit in one part and at most
+ *    QS_MAX_TARGETS in the other: the projector P_0 or P_1 on that qubit and
+ *    the matching diagonal factor on the others (CZ, CR).
+ * Every cut doubles the circuits (Sec. 2.2 (partial), first step).  For each
+ * branch word w < 2^c (bit j = branch of cut j, cuts in circuit order) the
+ * two sub-circuits run from |0...0> on states of n_A and n_B qubits, as
+ * qs_run_circuit runs them with `opts` (NULL = unfused; QS_PLAN_AUTOTUNE is
+ * not accepted), and amp(x) = sum_w psiA_w(x_A) psiB_w(x_B), with x_A / x_B
+ * the bits of x in part A / B, accumulated in FP64 on the device (last
+ * step).  out[2k], out[2k+1] = amp(idx[k]) for k < m; *cuts (may be NULL)
+ * receives c.  Synchronous.  Errors: QS_E_INVAL (pointers, n, part_a, dt,
+ * opts), QS_E_RANGE (a gate qubit >= n, an index >= 2^n), QS_E_UNSUPPORTED
+ * (noise sites, a crossing gate of another form, more than
+ * QS_PARTIAL_MAX_CUTS cuts, a part wider than QS_MAX_QUBITS), QS_E_NOMEM,
+ * QS_E_DEVICE. */
+qs_status qs_partial_amplitudes(const qs_circuit *c, int n, qs_dtype dt, uint64_t part_a, const uint64_t *idx,
+                                size_t m, double *out, const qs_run_opts *opts, int *cuts);
+
+/* The number of cuts qs_partial_amplitudes makes for this circuit and
+ * division (host only, no device work); errors as qs_partial_amplitudes. */
+qs_status qs_partial_cuts(const qs_circuit *c, int n, uint64_t part_a, int *cuts);
 
 /* ------------------------------------------------------------------ misc -- */
 

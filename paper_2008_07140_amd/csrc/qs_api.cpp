@@ -2097,7 +2097,7 @@ qs_status qs_circuit_append_gate(qs_circuit *c, const int *targets, int nt, cons
                                  int nc, const double *m)
 {
     if (!c) return fail(QS_E_INVAL, "circuit is NULL");
-    if (qs_status st = check_qubits(QS_MAX_QUBITS, targets, nt, controls, nc, QS_MAX_TARGETS)) return st;
+    if (qs_status st = check_qubits(QS_MAX_CIRCUIT_QUBITS, targets, nt, controls, nc, QS_MAX_TARGETS)) return st;
     if (qs_status st = check_matrix(m, nt)) return st;
     qs::Op op;
     op.kind = qs::Op::GATE;
@@ -2112,7 +2112,7 @@ qs_status qs_circuit_append_gate(qs_circuit *c, const int *targets, int nt, cons
 qs_status qs_circuit_append_noise(qs_circuit *c, const int *targets, int nt, const double *kraus, int nk)
 {
     if (!c) return fail(QS_E_INVAL, "circuit is NULL");
-    if (qs_status st = check_qubits(QS_MAX_QUBITS, targets, nt, nullptr, 0, QS_MAX_TARGETS)) return st;
+    if (qs_status st = check_qubits(QS_MAX_CIRCUIT_QUBITS, targets, nt, nullptr, 0, QS_MAX_TARGETS)) return st;
     if (qs_status st = check_kraus(kraus, nk, nt)) return st;
     if (c->ops.empty() || c->ops.back().kind != qs::Op::GATE)
         return fail(QS_E_INVAL, "a noise site must follow a gate");
@@ -2132,7 +2132,7 @@ qs_status qs_circuit_append_noise(qs_circuit *c, const int *targets, int nt, con
 static qs_status push_marker(qs_circuit *c, qs::Op::Kind k, int q)
 {
     if (!c) return fail(QS_E_INVAL, "circuit is NULL");
-    if (k == qs::Op::BEGIN_CONTROL && (q < 0 || q >= QS_MAX_QUBITS))
+    if (k == qs::Op::BEGIN_CONTROL && (q < 0 || q >= QS_MAX_CIRCUIT_QUBITS))
         return fail(QS_E_RANGE, "control qubit %d out of range", q);
     qs::Op op;
     op.kind = k;
@@ -2186,6 +2186,12 @@ qs_status qs_circuit_plan_info(const qs_circuit *c, int n, qs_dtype dt, const qs
     std::vector<qs::FlatOp> flat;
     std::string err;
     if (int rc = qs::expand(c->ops, flat, err)) return fail(rc == 2 ? QS_E_UNSUPPORTED : QS_E_INVAL, "%s", err.c_str());
+    for (auto &f : flat) {
+        for (int q : f.targets)
+            if (q >= n) return fail(QS_E_RANGE, "qubit %d out of range [0, %d)", q, n);
+        for (int q : f.controls)
+            if (q >= n) return fail(QS_E_RANGE, "qubit %d out of range [0, %d)", q, n);
+    }
     int64_t sw = 0, bl = 0, lg = 0;
     qs_state probe;
     probe.n = n;
@@ -2488,6 +2494,290 @@ qs_status qs_remap_pack(const qs_state *s, int g, const int *lq, void *device_bu
 qs_status qs_remap_unpack(qs_state *s, int g, const int *lq, const void *device_buf)
 {
     return remap(s, g, lq, device_buf, false);
+}
+
+// ------------------------------------------------ partial-amplitude mode --
+
+namespace {
+
+// A gate of one part's sub-circuit, qubits in that part's numbering; the
+// matrix in the ABI layout (2^nt x 2^nt, row-major (re, im) pairs).
+struct PartGate {
+    std::vector<int> t, c;
+    std::vector<double> m;
+};
+
+// A crossing gate cut as in Eq. 4: on branch b, part `pside` receives the
+// diagonal projector proj[b] and the other part other[b] (when has[b]).
+struct PartCut {
+    int pside = 0;
+    PartGate proj[2], other[2];
+    bool has[2] = {false, false};
+};
+
+struct PartialPlan {
+    int n = 0, np[2] = {0, 0};
+    std::vector<int> side, pos;            // qubit -> part (0 = A, 1 = B), index in the part
+    std::vector<std::pair<int, PartGate>> items;  // (part, gate) or (2 + cut index, {})
+    std::vector<PartCut> cuts;
+};
+
+qs_status build_partial(const qs_circuit *c, int n, uint64_t part_a, PartialPlan &pp)
+{
+    // diagonal gate on `qs_` (qs_[0] = most significant bit of the index)
+    // with factors f(y), y < 2^|qs_|
+    auto diag_gate = [](const std::vector<int> &qs_, const std::function<cd(uint32_t)> &f) {
+        PartGate g;
+        g.t = qs_;
+        const size_t d = size_t(1) << qs_.size();
+        g.m.assign(2 * d * d, 0.0);
+        for (size_t y = 0; y < d; ++y) {
+            const cd v = f(uint32_t(y));
+            g.m[2 * (y * d + y)] = v.real();
+            g.m[2 * (y * d + y) + 1] = v.imag();
+        }
+        return g;
+    };
+    if (!c) return fail(QS_E_INVAL, "circuit is NULL");
+    if (n < 2 || n > 62) return fail(QS_E_INVAL, "n = %d not in [2, 62]", n);
+    const uint64_t all = (uint64_t(1) << n) - 1;
+    if (part_a & ~all) return fail(QS_E_INVAL, "part_a names qubits >= n = %d", n);
+    pp = PartialPlan{};
+    pp.n = n;
+    pp.side.resize(n);
+    pp.pos.resize(n);
+    for (int q = 0; q < n; ++q) {
+        pp.side[q] = (part_a >> q) & 1 ? 0 : 1;
+        pp.pos[q] = pp.np[pp.side[q]]++;
+    }
+    for (int p = 0; p < 2; ++p)
+        if (pp.np[p] < 1 || pp.np[p] > QS_MAX_QUBITS) {
+            const qs_status st = pp.np[p] < 1 ? QS_E_INVAL : QS_E_UNSUPPORTED;
+            return fail(st, "part %c has %d qubits (1 to %d)", p ? 'B' : 'A', pp.np[p], QS_MAX_QUBITS);
+        }
+    std::vector<qs::FlatOp> flat;
+    std::string err;
+    const int rc = qs::expand(c->ops, flat, err);
+    if (rc == 2) return fail(QS_E_UNSUPPORTED, "%s", err.c_str());
+    if (rc) return fail(QS_E_INVAL, "%s", err.c_str());
+    auto local = [&](const std::vector<int> &qs_) {
+        std::vector<int> r;
+        for (int q : qs_) r.push_back(pp.pos[q]);
+        return r;
+    };
+    for (auto &f : flat) {
+        if (f.kind == qs::FlatOp::NOISE)
+            return fail(QS_E_UNSUPPORTED, "noise sites in the partial-amplitude mode");
+        int seen = 0;
+        for (int q : f.targets) {
+            if (q >= n) return fail(QS_E_RANGE, "qubit %d out of range [0, %d)", q, n);
+            seen |= 1 << pp.side[q];
+        }
+        for (int q : f.controls) {
+            if (q >= n) return fail(QS_E_RANGE, "qubit %d out of range [0, %d)", q, n);
+            seen |= 1 << pp.side[q];
+        }
+        if (seen != 3) {
+            const int p = seen == 1 ? 0 : 1;
+            pp.items.push_back({p, PartGate{local(f.targets), local(f.controls), f.m}});
+            continue;
+        }
+        const qs::CanonGate g = qs::canonicalize(f.targets.data(), int(f.targets.size()), f.controls.data(),
+                                                 int(f.controls.size()), f.m.data());
+        if (g.kind == qs::CanonGate::IDENTITY) continue;
+        PartCut cut;
+        if (g.kind == qs::CanonGate::DENSE) {
+            // targets in one part S; the controls in the other part become
+            // the projector onto all ones (branch 1) or onto the rest
+            const int S = pp.side[g.targets[0]];
+            for (int q : g.targets)
+                if (pp.side[q] != S)
+                    return fail(QS_E_UNSUPPORTED, "a dense gate with targets on both sides of the dividing line");
+            std::vector<int> cs, cp;
+            for (int q : g.controls) (pp.side[q] == S ? cs : cp).push_back(q);
+            if (cp.size() > QS_MAX_TARGETS)
+                return fail(QS_E_UNSUPPORTED, "%zu controls across the dividing line", cp.size());
+            const uint32_t ones = (1u << cp.size()) - 1;
+            cut.pside = 1 - S;
+            cut.proj[1] = diag_gate(local(cp), [&](uint32_t y) { return cd(y == ones ? 1.0 : 0.0); });
+            cut.proj[0] = diag_gate(local(cp), [&](uint32_t y) { return cd(y == ones ? 0.0 : 1.0); });
+            cut.other[1] = PartGate{local(g.targets), local(cs), g.m};
+            cut.has[1] = true;
+        } else {
+            // a diagonal operator over Q = targets + controls: the factor of
+            // the target pattern where every control is 1, else 1
+            std::vector<int> Q = g.targets;
+            Q.insert(Q.end(), g.controls.begin(), g.controls.end());
+            int cnt[2] = {0, 0};
+            for (int q : Q) cnt[pp.side[q]]++;
+            const int ps = cnt[0] == 1 ? 0 : cnt[1] == 1 ? 1 : -1;
+            if (ps < 0)
+                return fail(QS_E_UNSUPPORTED, "a diagonal gate with more than one qubit on each side of the dividing line");
+            if (cnt[1 - ps] > QS_MAX_TARGETS)
+                return fail(QS_E_UNSUPPORTED, "a diagonal gate on more than %d qubits of one part", QS_MAX_TARGETS);
+            int pq = -1;
+            std::vector<int> rest;
+            for (int q : Q) {
+                if (pp.side[q] == ps)
+                    pq = q;
+                else
+                    rest.push_back(q);
+            }
+            const int nt = int(g.targets.size());
+            auto factor = [&](int pv, uint32_t y) {
+                // value of qubit Q[i]: pv for the projector qubit, else its bit of y
+                auto val = [&](int q) {
+                    if (q == pq) return pv;
+                    for (size_t i = 0; i < rest.size(); ++i)
+                        if (rest[i] == q) return int((y >> (rest.size() - 1 - i)) & 1);
+                    return 0;
+                };
+                for (int q : g.controls)
+                    if (!val(q)) return cd(1.0);
+                uint32_t x = 0;
+                for (int b = 0; b < nt; ++b) x |= uint32_t(val(g.targets[b])) << (nt - 1 - b);
+                return cd(g.m[2 * x], g.m[2 * x + 1]);
+            };
+            cut.pside = ps;
+            for (int v = 0; v < 2; ++v) {
+                cut.proj[v] = diag_gate({pp.pos[pq]}, [&](uint32_t y) { return cd(int(y) == v ? 1.0 : 0.0); });
+                PartGate o = diag_gate(local(rest), [&](uint32_t y) { return factor(v, y); });
+                bool ident = true;
+                const size_t d = size_t(1) << rest.size();
+                for (size_t y = 0; y < d; ++y)
+                    ident = ident && o.m[2 * (y * d + y)] == 1.0 && o.m[2 * (y * d + y) + 1] == 0.0;
+                cut.has[v] = !ident;
+                if (!ident) cut.other[v] = std::move(o);
+            }
+        }
+        pp.items.push_back({2 + int(pp.cuts.size()), PartGate{}});
+        pp.cuts.push_back(std::move(cut));
+    }
+    if (pp.cuts.size() > QS_PARTIAL_MAX_CUTS)
+        return fail(QS_E_UNSUPPORTED, "%zu gates cross the dividing line (at most %d)", pp.cuts.size(),
+                    QS_PARTIAL_MAX_CUTS);
+    return QS_OK;
+}
+
+// the sub-circuit of part p on branch word w
+void partial_circuit(const PartialPlan &pp, int p, uint64_t w, qs_circuit &out)
+{
+    out.ops.clear();
+    auto push = [&](const PartGate &g) {
+        qs::Op op;
+        op.kind = qs::Op::GATE;
+        op.targets = g.t;
+        op.controls = g.c;
+        op.m = g.m;
+        out.ops.push_back(std::move(op));
+    };
+    for (auto &it : pp.items) {
+        if (it.first < 2) {
+            if (it.first == p) push(it.second);
+            continue;
+        }
+        const int j = it.first - 2;
+        const PartCut &cut = pp.cuts[j];
+        const int b = int((w >> j) & 1);
+        if (cut.pside == p)
+            push(cut.proj[b]);
+        else if (cut.has[b])
+            push(cut.other[b]);
+    }
+    out.changed();
+}
+
+}  // namespace
+
+qs_status qs_partial_cuts(const qs_circuit *c, int n, uint64_t part_a, int *cuts)
+{
+    PartialPlan pp;
+    if (qs_status st = build_partial(c, n, part_a, pp)) return st;
+    if (cuts) *cuts = int(pp.cuts.size());
+    return QS_OK;
+}
+
+qs_status qs_partial_amplitudes(const qs_circuit *c, int n, qs_dtype dt, uint64_t part_a, const uint64_t *idx,
+                                size_t m, double *out, const qs_run_opts *opts, int *cuts)
+{
+    if (dt != QS_C64 && dt != QS_C128) return fail(QS_E_INVAL, "unknown dtype %d", int(dt));
+    if (m && (!idx || !out)) return fail(QS_E_INVAL, "idx or out is NULL");
+    qs_run_opts o{};
+    if (opts) o = *opts;
+    if (o.plan == QS_PLAN_AUTOTUNE)
+        return fail(QS_E_INVAL, "QS_PLAN_AUTOTUNE needs a circuit that runs repeatedly; every branch is a new one");
+    if (o.plan < QS_PLAN_UNFUSED || o.plan > QS_PLAN_AUTOTUNE) return fail(QS_E_INVAL, "unknown plan %d", o.plan);
+    PartialPlan pp;
+    if (qs_status st = build_partial(c, n, part_a, pp)) return st;
+    for (size_t k = 0; k < m; ++k)
+        if (idx[k] >> n) return fail(QS_E_RANGE, "index %llu >= 2^%d", (unsigned long long)idx[k], n);
+    if (cuts) *cuts = int(pp.cuts.size());
+    if (m == 0) return QS_OK;
+    // the bits of every index in part A and part B
+    std::vector<uint64_t> ix[2];
+    ix[0].resize(m);
+    ix[1].resize(m);
+    const size_t chunk = 1 << 14, nchunks = (m + chunk - 1) / chunk;
+    parallel_for(nchunks, [&](size_t ci) {
+        for (size_t k = ci * chunk; k < std::min(m, (ci + 1) * chunk); ++k) {
+            uint64_t v[2] = {0, 0};
+            for (int q = 0; q < n; ++q) v[pp.side[q]] |= ((idx[k] >> q) & 1) << pp.pos[q];
+            ix[0][k] = v[0];
+            ix[1][k] = v[1];
+        }
+    });
+    qs_state *st[2] = {nullptr, nullptr};
+    uint64_t *dix = nullptr;
+    double *acc = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    auto cleanup = [&](qs_status r) {
+        for (auto &s : st)
+            if (s) hipStreamSynchronize(s->stream);
+        for (auto &e : ev)
+            if (e) hipEventDestroy(e);
+        if (dix) hipFree(dix);
+        if (acc) hipFree(acc);
+        for (auto &s : st)
+            if (s) qs_destroy(s);
+        return r;
+    };
+    for (int p = 0; p < 2; ++p)
+        if (qs_status r = qs_create(pp.np[p], dt, &st[p])) return cleanup(r);
+    hipError_t e = hipMalloc(&dix, 2 * m * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMalloc(&acc, 2 * m * sizeof(double));
+    for (int p = 0; p < 2 && e == hipSuccess; ++p) e = hipEventCreateWithFlags(&ev[p], hipEventDisableTiming);
+    if (e != hipSuccess) {
+        const bool oom = e == hipErrorOutOfMemory;
+        return cleanup(oom ? fail(QS_E_NOMEM, "partial-amplitude buffers for %zu indices", m)
+                           : hip_fail(e, "partial-amplitude set-up"));
+    }
+    hipStream_t sa = st[0]->stream, sb = st[1]->stream;
+    e = hipMemcpyAsync(dix, ix[0].data(), m * sizeof(uint64_t), hipMemcpyHostToDevice, sa);
+    if (e == hipSuccess) e = hipMemcpyAsync(dix + m, ix[1].data(), m * sizeof(uint64_t), hipMemcpyHostToDevice, sa);
+    if (e == hipSuccess) e = hipMemsetAsync(acc, 0, 2 * m * sizeof(double), sa);
+    if (e == hipSuccess) e = hipStreamSynchronize(sa);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "partial-amplitude set-up"));
+    qs_circuit sub[2];
+    const uint64_t nw = uint64_t(1) << pp.cuts.size();
+    for (uint64_t w = 0; w < nw; ++w) {
+        // part B's state is rewritten only after the previous branch's
+        // recombination (on A's stream) has read it
+        if (w && (e = hipStreamWaitEvent(sb, ev[0], 0)) != hipSuccess) break;
+        for (int p = 1; p >= 0; --p) {
+            partial_circuit(pp, p, w, sub[p]);
+            if (qs_status r = qs_reset(st[p])) return cleanup(r);
+            if (qs_status r = qs_run_circuit(st[p], &sub[p], &o)) return cleanup(r);
+        }
+        if ((e = hipEventRecord(ev[1], sb)) != hipSuccess) break;
+        if ((e = hipStreamWaitEvent(sa, ev[1], 0)) != hipSuccess) break;
+        if ((e = qs::launch_partial_cmac(dt, st[0]->amp, st[1]->amp, dix, dix + m, m, acc, sa)) != hipSuccess) break;
+        if ((e = hipEventRecord(ev[0], sa)) != hipSuccess) break;
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(out, acc, 2 * m * sizeof(double), hipMemcpyDeviceToHost, sa);
+    if (e == hipSuccess) e = hipStreamSynchronize(sa);
+    if (e == hipSuccess) e = hipStreamSynchronize(sb);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "partial-amplitude branches"));
+    return cleanup(QS_OK);
 }
 
 // -------------------------------------------------------------- readout --

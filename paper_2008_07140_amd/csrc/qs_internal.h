@@ -91,6 +91,10 @@ hipError_t launch_gather(qs_dtype dt, const void *amp, const uint64_t *dev_idx, 
 // and the rest of b over the other local bits in ascending order.
 hipError_t launch_remap(qs_dtype dt, void *shard, void *buf, int L, int g, const int *lq, bool pack,
                         hipStream_t st);
+// acc[k] += a[ia[k]] * b[ib[k]] for k < m (complex, FP64 accumulators,
+// acc = m (re, im) doubles): one branch of the partial-amplitude recombination
+hipError_t launch_partial_cmac(qs_dtype dt, const void *a, const void *b, const uint64_t *ia,
+                               const uint64_t *ib, uint64_t m, double *acc, hipStream_t st);
 // amp *= scale (real), used for renormalisation
 hipError_t launch_scale(qs_dtype dt, void *amp, uint64_t n_amp, double scale, hipStream_t st);
 

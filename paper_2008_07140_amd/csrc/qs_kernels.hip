@@ -570,6 +570,25 @@ __global__ __launch_bounds__(kBlock) void k_gather(const typename Cpx<R>::T *a, 
     }
 }
 
+// Partial-amplitude recombination (Sec. 2.2 (partial), last step): one term
+// of acc[k] = sum_w psiA_w(ia[k]) psiB_w(ib[k]), added in FP64.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_partial_cmac(const typename Cpx<R>::T *a, const typename Cpx<R>::T *b,
+                                                         const uint64_t *ia, const uint64_t *ib, uint64_t m,
+                                                         double2 *acc)
+{
+    const uint64_t stride = uint64_t(gridDim.x) * kBlock;
+    for (uint64_t k = uint64_t(blockIdx.x) * kBlock + threadIdx.x; k < m; k += stride) {
+        const auto x = a[ia[k]];
+        const auto y = b[ib[k]];
+        const double xr = x.x, xi = x.y, yr = y.x, yi = y.y;
+        double2 r = acc[k];
+        r.x += xr * yr - xi * yi;
+        r.y += xr * yi + xi * yr;
+        acc[k] = r;
+    }
+}
+
 template <typename R>
 hipError_t dense1_impl(void *amp, int n, const IdxSpec &ix, int target, const double *m,
                        hipStream_t st)
@@ -901,6 +920,19 @@ hipError_t launch_expect_z(qs_dtype dt, const void *amp, int n, double *scratch,
     hipLaunchKernelGGL(k_sum_columns, dim3(1), dim3(kBlock), 0, st, scratch, int(grid), n + 1,
                        sums);
     hipLaunchKernelGGL(k_z_finish, dim3(1), dim3(64), 0, st, sums, n, dev_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_partial_cmac(qs_dtype dt, const void *a, const void *b, const uint64_t *ia,
+                               const uint64_t *ib, uint64_t m, double *acc, hipStream_t st)
+{
+    const uint64_t grid = grid_for(m, kBlock);
+    if (dt == QS_C128)
+        hipLaunchKernelGGL((k_partial_cmac<double>), dim3(unsigned(grid)), dim3(kBlock), 0, st,
+                           (const double2 *)a, (const double2 *)b, ia, ib, m, (double2 *)acc);
+    else
+        hipLaunchKernelGGL((k_partial_cmac<float>), dim3(unsigned(grid)), dim3(kBlock), 0, st,
+                           (const float2 *)a, (const float2 *)b, ia, ib, m, (double2 *)acc);
     return hipGetLastError();
 }
 

@@ -79,6 +79,8 @@ _sig = {
     "qs_run_trajectories": ([P, P, I, I, U64, P, P], I),
     "qs_remap_pack": ([P, I, P, P], I),
     "qs_remap_unpack": ([P, I, P, P], I),
+    "qs_partial_amplitudes": ([P, I, I, U64, P, SZ, P, C.POINTER(RunOpts), P], I),
+    "qs_partial_cuts": ([P, I, U64, P], I),
     "qs_philox_uniform": ([U64, U64, U64], D),
     "qs_philox4x32_10": ([P, P, P], None),
     "qs_profile_enable": ([P, I], I),
@@ -234,6 +236,24 @@ class Circuit:
         _check(_lib.qs_circuit_plan_info(self._h, n, dtype, C.byref(o), C.byref(sw), C.byref(bl),
                                          C.byref(lg)))
         return {"sweeps": sw.value, "blocks": bl.value, "gates": lg.value}
+
+    def partial_cuts(self, n: int, part_a: int) -> int:
+        """qs_partial_cuts: gates cut at the dividing line between the qubits of
+        the mask part_a and the rest."""
+        c = C.c_int()
+        _check(_lib.qs_partial_cuts(self._h, n, part_a, C.byref(c)))
+        return c.value
+
+    def partial_amplitudes(self, n: int, part_a: int, idx, dtype: int = C128, plan: int = PLAN_UNFUSED,
+                           k_max: int = 0, tile_qubits: int = 0):
+        """qs_partial_amplitudes: (complex128 amplitudes at idx, number of cuts)."""
+        ix = np.ascontiguousarray(np.asarray(idx, dtype=np.uint64))
+        out = np.empty(ix.size, dtype=np.complex128)
+        o = RunOpts(plan=plan, k_max=k_max, tile_qubits=tile_qubits)
+        c = C.c_int()
+        _check(_lib.qs_partial_amplitudes(self._h, n, dtype, part_a, _ptr(ix), ix.size,
+                                          _ptr(out.view(np.float64)), C.byref(o), C.byref(c)))
+        return out, c.value
 
     def autotune_result(self, n: int, dtype: int = C64):
         """(tried, candidates, tile_qubits, k_max, seconds) of QS_PLAN_AUTOTUNE

@@ -212,3 +212,61 @@ def test_run_opts_layout_matches_header(qs, tmp_path):
                                           text=True).stdout.split()]
     want = [getattr(qs.RunOpts, f).offset for f in fields] + [ctypes.sizeof(qs.RunOpts), qs.TILE_ORDERS]
     assert got == want
+
+
+def _crossing_gates(ops, part_a):
+    return sum(1 for o in ops if o.kind == "gate"
+               and {(part_a >> q) & 1 for q in tuple(o.targets) + tuple(o.controls)} == {0, 1})
+
+
+def test_partial_cut_counts_on_grid_circuits(qs):
+    """Partial-amplitude mode (Eq. 4): every CZ across the dividing line is one
+    cut.  An 8 x 5 grid (40 qubits) at depth 8 divided between rows 3 and 4 is
+    crossed by the vertical pairs at odd rows, in layers 3 and 7: 2 x 5 CZ.  A
+    6 x 5 grid at depth 8 divided between rows 2 and 3 is crossed in layers 1
+    and 5 (vertical pairs at even rows)."""
+    for rows, cols, depth, top_rows, want in [(8, 5, 8, 4, 10), (6, 5, 8, 3, 10), (6, 5, 12, 3, 15)]:
+        ops = cg.random_circuit(rows, cols, depth, seed=6001)
+        n, part_a = rows * cols, (1 << (top_rows * cols)) - 1
+        assert _crossing_gates(ops, part_a) == want
+        assert qs.Circuit(ops).partial_cuts(n, part_a) == want
+
+
+def test_partial_cut_forms_and_rejections(qs):
+    """Crossing gates that are cut (controlled gates with their targets on one
+    side, diagonal gates with one qubit on one side, CONTROL groups) and the
+    ones that are rejected (SWAP, a diagonal with two qubits on each side,
+    noise, more than QS_PARTIAL_MAX_CUTS cuts)."""
+    n, A = 6, 0b000111
+    rng = np.random.default_rng(3)
+    X = cg.PX
+    d3 = np.diag(np.exp(1j * rng.uniform(0, 6.28, 8)))
+    d4 = np.diag(np.exp(1j * rng.uniform(0, 6.28, 16)))
+    swap = np.eye(4)[[0, 2, 1, 3]]
+    ok = [([cg.Gate((4,), (1,), X)], 1), ([cg.Gate((1,), (4,), X)], 1),
+          ([cg.Gate((0, 5), (), cg.CZ_GATE)], 1), ([cg.Gate((3,), (0, 1), X)], 1),
+          ([cg.Gate((3,), (0, 4), X)], 1), ([cg.Gate((2, 3, 4), (), d3)], 1),
+          ([cg.Gate((0, 3), (), np.eye(4))], 0),
+          ([cg.Marker("control", 0), cg.Gate((3,), (), cg.H_GATE), cg.Gate((4,), (), cg.T_GATE),
+            cg.Marker("endcontrol")], 2)]
+    for ops, want in ok:
+        assert qs.Circuit(ops).partial_cuts(n, A) == want
+    bad = [[cg.Gate((0, 3), (), swap)], [cg.Gate((0, 1, 3, 4), (), d4)],
+           [cg.Gate((0,), (), cg.H_GATE), cg.Noise((0,), cg.kraus_depolarizing(0.1))],
+           [cg.Gate((0, 5), (), cg.CZ_GATE)] * 25]
+    for ops in bad:
+        with pytest.raises(qs.QSError) as e:
+            qs.Circuit(ops).partial_cuts(n, A)
+        assert e.value.status == -6
+    c = qs.Circuit([cg.Gate((7,), (), cg.H_GATE)])
+    with pytest.raises(qs.QSError) as e:
+        c.partial_cuts(n, A)
+    assert e.value.status == -2
+    c = qs.Circuit([cg.Gate((0,), (), cg.H_GATE)])
+    for nn, part in [(n, 0), (n, 0b111111), (n, 1 << 6), (1, 1), (63, 1)]:
+        with pytest.raises(qs.QSError) as e:
+            c.partial_cuts(nn, part)
+        assert e.value.status == -1
+    with pytest.raises(qs.QSError) as e:
+        c.partial_cuts(40, (1 << 38) - 1)  # part A of 38 qubits
+    assert e.value.status == -6

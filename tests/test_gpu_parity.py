@@ -798,3 +798,92 @@ def test_remap_validation(qs):
     assert e.value.status == -1
     for x in (s, big, buf.s):
         x.close()
+
+
+# ------------------------------------------------ partial-amplitude mode --
+
+
+def _partial_circuit():
+    """12 qubits (4 x 3 grid, depth 4: the CZ layer 3 crosses rows 1 | 2 with
+    3 gates) plus one crossing gate of every supported form: CNOT both ways,
+    CR, Toffoli with both controls across, CU3, a 3-qubit diagonal with one
+    qubit in part A, and a CONTROL group from part A around a part-B gate."""
+    rng = np.random.default_rng(77)
+    ops = list(cg.random_circuit(4, 3, 4, seed=7001, cu3_prob=0.0))
+    d3 = np.diag(np.exp(1j * rng.uniform(0, 2 * np.pi, 8)))
+    cr = np.diag([1, np.exp(0.7j)])
+    extra = [cg.Gate((7,), (1,), cg.PX), cg.Gate((2,), (8,), cg.PX), cg.Gate((9,), (3,), cr),
+             cg.Gate((10,), (0, 4), cg.PX), cg.Gate((0,), (11,), cg.u3(0.4, 1.1, -0.3)),
+             cg.Gate((5, 6, 11), (), d3), cg.Marker("control", 2), cg.Gate((8,), (), cg.H_GATE),
+             cg.Marker("endcontrol")]
+    return ops[:20] + extra[:3] + ops[20:40] + extra[3:] + ops[40:]
+
+
+@pytest.mark.parametrize("dtype,plan", [("c128", "unfused"), ("c128", "greedy"), ("c64", "unfused"),
+                                        ("c64", "greedy")])
+def test_partial_amplitudes_match_oracle_full_state(qs, dtype, plan):
+    """Partial-amplitude mode (Sec. 2.2 (partial), Eq. 4): every amplitude of a
+    12-qubit circuit cut between qubits 0-5 and 6-11 (10 cuts, 1024 branch
+    words, 2048 six-qubit sub-circuits) equals the oracle's full-amplitude
+    state: complex128 within 1e-12, complex64 within infidelity 1e-6."""
+    ops = _partial_circuit()
+    n, part_a = 12, (1 << 6) - 1
+    ref, _ = oracle.run(n, ops)
+    c = qs.Circuit(ops)
+    dt = qs.C128 if dtype == "c128" else qs.C64
+    pl = qs.PLAN_UNFUSED if plan == "unfused" else qs.PLAN_GREEDY
+    got, cuts = c.partial_amplitudes(n, part_a, np.arange(1 << n), dtype=dt, plan=pl)
+    assert cuts == 10 == c.partial_cuts(n, part_a)
+    if dt == qs.C128:
+        assert np.max(np.abs(got - ref)) <= TOL128
+    else:
+        assert infidelity(ref, got) <= 1e-6
+        assert np.max(np.abs(got - ref)) <= 2e-5
+
+
+def test_partial_amplitudes_other_division_and_sampled_order(qs):
+    """The same circuit divided into an interleaved part A (even qubits):
+    CZ layers, CU3 and every extra gate cross differently; amplitudes asked in
+    a shuffled order with repeats come back in that order (complex128)."""
+    ops = _partial_circuit()[:30]
+    n, part_a = 12, 0b010101010101
+    ref, _ = oracle.run(n, ops)
+    c = qs.Circuit(ops)
+    cuts = c.partial_cuts(n, part_a)
+    assert 1 <= cuts <= 14
+    idx = np.random.default_rng(5).integers(0, 1 << n, size=3000)
+    got, cc = c.partial_amplitudes(n, part_a, idx)
+    assert cc == cuts
+    assert np.max(np.abs(got - ref[idx])) <= TOL128
+
+
+def test_partial_amplitudes_30_qubits_against_full_state(qs):
+    """At 30 qubits (6 x 5 grid, depth 8, divided between rows 2 and 3: 10
+    cuts, two 15-qubit parts), 4096 sampled amplitudes equal those of the
+    complex128 full-amplitude path (which the tests above pin to the oracle)."""
+    n, part_a = 30, (1 << 15) - 1
+    ops = cg.random_circuit(6, 5, 8, seed=7002)
+    c = qs.Circuit(ops)
+    s = qs.State(n, qs.C128)
+    s.run(c)
+    idx = np.random.default_rng(6).choice(1 << n, size=4096, replace=False)
+    full = s.amplitudes(idx)
+    s.close()
+    got, cuts = c.partial_amplitudes(n, part_a, idx)
+    assert cuts == 10
+    assert np.max(np.abs(got - full)) <= 1e-13
+
+
+def test_partial_amplitudes_validation(qs):
+    c = qs.Circuit([cg.Gate((0,), (), cg.H_GATE), cg.Gate((0, 5), (), cg.CZ_GATE)])
+    with pytest.raises(qs.QSError) as e:
+        c.partial_amplitudes(6, 0b111, [64])
+    assert e.value.status == -2
+    with pytest.raises(qs.QSError) as e:
+        c.partial_amplitudes(6, 0b111, [1], plan=qs.PLAN_AUTOTUNE)
+    assert e.value.status == -1
+    with pytest.raises(qs.QSError) as e:
+        c.partial_amplitudes(6, 0b111, [1], dtype=9)
+    assert e.value.status == -1
+    got, cuts = c.partial_amplitudes(6, 0b111, [])
+    assert got.size == 0 and cuts == 1
