@@ -315,7 +315,12 @@ qs_status qs_remap_unpack(qs_state *s, int g, const int *lq, const void *device_
  * qs_run_circuit runs them with `opts` (NULL = unfused; QS_PLAN_AUTOTUNE is
  * not accepted), and amp(x) = sum_w psiA_w(x_A) psiB_w(x_B), with x_A / x_B
  * the bits of x in part A / B, accumulated in FP64 on the device (last
- * step).  out[2k], out[2k+1] = amp(idx[k]) for k < m; *cuts (may be NULL)
+ * step).  The gates of a part between two cuts do not depend on later
+ * branches, so when c + 1 states of each part fit in 32 GiB (and in the
+ * qs_set_memory_limit bound) the branch words are walked depth first and
+ * each segment between cuts runs once per prefix, from a copy of the state
+ * before it; otherwise each branch word runs both sub-circuits in full.
+ * out[2k], out[2k+1] = amp(idx[k]) for k < m; *cuts (may be NULL)
  * receives c.  Synchronous.  Errors: QS_E_INVAL (pointers, n, part_a, dt,
  * opts), QS_E_RANGE (a gate qubit >= n, an index >= 2^n), QS_E_UNSUPPORTED
  * (noise sites, a crossing gate of another form, more than

@@ -2500,6 +2500,10 @@ qs_status qs_remap_unpack(qs_state *s, int g, const int *lq, const void *device_
 
 namespace {
 
+// Device memory up to which the partial mode keeps one state per level of
+// the cut tree (partial_tree) instead of rerunning each branch word in full.
+constexpr double kPartialTreeBytes = 32.0 * (1ull << 30);
+
 // A gate of one part's sub-circuit, qubits in that part's numbering; the
 // matrix in the ABI layout (2^nt x 2^nt, row-major (re, im) pairs).
 struct PartGate {
@@ -2687,6 +2691,126 @@ void partial_circuit(const PartialPlan &pp, int p, uint64_t w, qs_circuit &out)
     out.changed();
 }
 
+
+// Device states of one run of the partial mode: `count` states of n qubits
+// in buffers of their own, all enqueued on `strm`.
+struct PartStates {
+    std::vector<void *> bufs;
+    std::vector<qs_state *> st;
+    hipStream_t strm = nullptr;
+    ~PartStates()
+    {
+        if (strm) hipStreamSynchronize(strm);  // nothing queued may still use them
+        for (auto *s : st) qs_destroy(s);
+        for (void *b : bufs) hipFree(b);
+    }
+    qs_status make(int n, qs_dtype dt, hipStream_t stream)
+    {
+        strm = stream;
+        const size_t bytes = amp_bytes(dt) << n;
+        void *b = nullptr;
+        hipError_t e = hipMalloc(&b, bytes);
+        if (e != hipSuccess)
+            return e == hipErrorOutOfMemory ? fail(QS_E_NOMEM, "partial-amplitude state of %d qubits", n)
+                                            : hip_fail(e, "hipMalloc");
+        bufs.push_back(b);
+        qs_state *s = nullptr;
+        if (qs_status r = qs_create_from_buffer(n, dt, b, bytes, strm, &s)) return r;
+        st.push_back(s);
+        return QS_OK;
+    }
+};
+
+qs_status apply_part_gate(qs_state *s, const PartGate &g)
+{
+    return qs_apply_gate(s, g.t.data(), int(g.t.size()), g.c.empty() ? nullptr : g.c.data(), int(g.c.size()),
+                         g.m.data());
+}
+
+// Every branch word in turn: both sub-circuits from |0...0>, then one
+// recombination term (memory: one state per part).
+qs_status partial_branches(const PartialPlan &pp, qs_dtype dt, const qs_run_opts &o, const uint64_t *dix, size_t m,
+                           double *acc, hipStream_t strm)
+{
+    PartStates ps;
+    for (int p = 0; p < 2; ++p)
+        if (qs_status r = ps.make(pp.np[p], dt, strm)) return r;
+    qs_circuit sub[2];
+    const uint64_t nw = uint64_t(1) << pp.cuts.size();
+    for (uint64_t w = 0; w < nw; ++w) {
+        for (int p = 0; p < 2; ++p) {
+            partial_circuit(pp, p, w, sub[p]);
+            if (qs_status r = qs_reset(ps.st[p])) return r;
+            if (qs_status r = qs_run_circuit(ps.st[p], &sub[p], &o)) return r;
+        }
+        hipError_t e = qs::launch_partial_cmac(dt, ps.st[0]->amp, ps.st[1]->amp, dix, dix + m, m, acc, strm);
+        if (e != hipSuccess) return hip_fail(e, "partial-amplitude recombination");
+    }
+    hipError_t e = hipStreamSynchronize(strm);
+    return e == hipSuccess ? QS_OK : hip_fail(e, "partial-amplitude branches");
+}
+
+// Depth-first walk of the tree of cuts.  The gates of a part between cut
+// j - 1 and cut j (segment j) do not depend on later branches, so the state
+// after segment j is computed once per prefix of branch bits: level j + 1
+// starts as a copy of level j, receives cut j's operator for branch b and
+// runs segment j + 1.  Each segment is one circuit whose plan is made once.
+// Memory: c + 1 states per part.
+qs_status partial_tree(const PartialPlan &pp, qs_dtype dt, const qs_run_opts &o, const uint64_t *dix, size_t m,
+                       double *acc, hipStream_t strm)
+{
+    const int c = int(pp.cuts.size());
+    std::vector<std::unique_ptr<qs_circuit>> seg[2];
+    for (int p = 0; p < 2; ++p)
+        for (int k = 0; k <= c; ++k) seg[p].emplace_back(new qs_circuit);
+    int k = 0;
+    for (auto &it : pp.items) {
+        if (it.first >= 2) {
+            k = it.first - 1;  // after cut j: segment j + 1
+            continue;
+        }
+        qs::Op op;
+        op.kind = qs::Op::GATE;
+        op.targets = it.second.t;
+        op.controls = it.second.c;
+        op.m = it.second.m;
+        seg[it.first][k]->ops.push_back(std::move(op));
+    }
+    PartStates ps[2];
+    for (int p = 0; p < 2; ++p)
+        for (int l = 0; l <= c; ++l)
+            if (qs_status r = ps[p].make(pp.np[p], dt, strm)) return r;
+    const size_t bytes[2] = {amp_bytes(dt) << pp.np[0], amp_bytes(dt) << pp.np[1]};
+    for (int p = 0; p < 2; ++p)
+        if (!seg[p][0]->ops.empty())
+            if (qs_status r = qs_run_circuit(ps[p].st[0], seg[p][0].get(), &o)) return r;
+    std::function<qs_status(int)> walk = [&](int j) -> qs_status {
+        if (j == c) {
+            hipError_t e = qs::launch_partial_cmac(dt, ps[0].st[c]->amp, ps[1].st[c]->amp, dix, dix + m, m, acc, strm);
+            return e == hipSuccess ? QS_OK : hip_fail(e, "partial-amplitude recombination");
+        }
+        const PartCut &cut = pp.cuts[j];
+        for (int b = 0; b < 2; ++b) {
+            for (int p = 0; p < 2; ++p) {
+                qs_state *dst = ps[p].st[j + 1];
+                hipError_t e = hipMemcpyAsync(dst->amp, ps[p].st[j]->amp, bytes[p], hipMemcpyDeviceToDevice, strm);
+                if (e != hipSuccess) return hip_fail(e, "partial-amplitude state copy");
+                const PartGate *g = cut.pside == p ? &cut.proj[b] : cut.has[b] ? &cut.other[b] : nullptr;
+                if (g)
+                    if (qs_status r = apply_part_gate(dst, *g)) return r;
+                if (!seg[p][j + 1]->ops.empty())
+                    if (qs_status r = qs_run_circuit(dst, seg[p][j + 1].get(), &o)) return r;
+            }
+            if (qs_status r = walk(j + 1)) return r;
+        }
+        return QS_OK;
+    };
+    qs_status r = walk(0);
+    hipError_t e = hipStreamSynchronize(strm);
+    if (r) return r;
+    return e == hipSuccess ? QS_OK : hip_fail(e, "partial-amplitude tree");
+}
+
 }  // namespace
 
 qs_status qs_partial_cuts(const qs_circuit *c, int n, uint64_t part_a, int *cuts)
@@ -2726,56 +2850,40 @@ qs_status qs_partial_amplitudes(const qs_circuit *c, int n, qs_dtype dt, uint64_
             ix[1][k] = v[1];
         }
     });
-    qs_state *st[2] = {nullptr, nullptr};
+    // every state, copy and recombination runs in order on one stream
+    hipStream_t strm = nullptr;
     uint64_t *dix = nullptr;
     double *acc = nullptr;
-    hipEvent_t ev[2] = {nullptr, nullptr};
     auto cleanup = [&](qs_status r) {
-        for (auto &s : st)
-            if (s) hipStreamSynchronize(s->stream);
-        for (auto &e : ev)
-            if (e) hipEventDestroy(e);
+        if (strm) hipStreamSynchronize(strm);
         if (dix) hipFree(dix);
         if (acc) hipFree(acc);
-        for (auto &s : st)
-            if (s) qs_destroy(s);
+        if (strm) hipStreamDestroy(strm);
         return r;
     };
-    for (int p = 0; p < 2; ++p)
-        if (qs_status r = qs_create(pp.np[p], dt, &st[p])) return cleanup(r);
-    hipError_t e = hipMalloc(&dix, 2 * m * sizeof(uint64_t));
-    if (e == hipSuccess) e = hipMalloc(&acc, 2 * m * sizeof(double));
-    for (int p = 0; p < 2 && e == hipSuccess; ++p) e = hipEventCreateWithFlags(&ev[p], hipEventDisableTiming);
+    hipError_t e = hipStreamCreateWithFlags(&strm, hipStreamNonBlocking);
     if (e != hipSuccess) {
-        const bool oom = e == hipErrorOutOfMemory;
-        return cleanup(oom ? fail(QS_E_NOMEM, "partial-amplitude buffers for %zu indices", m)
-                           : hip_fail(e, "partial-amplitude set-up"));
+        strm = nullptr;
+        return hip_fail(e, "stream creation");
     }
-    hipStream_t sa = st[0]->stream, sb = st[1]->stream;
-    e = hipMemcpyAsync(dix, ix[0].data(), m * sizeof(uint64_t), hipMemcpyHostToDevice, sa);
-    if (e == hipSuccess) e = hipMemcpyAsync(dix + m, ix[1].data(), m * sizeof(uint64_t), hipMemcpyHostToDevice, sa);
-    if (e == hipSuccess) e = hipMemsetAsync(acc, 0, 2 * m * sizeof(double), sa);
-    if (e == hipSuccess) e = hipStreamSynchronize(sa);
+    e = hipMalloc(&dix, 2 * m * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMalloc(&acc, 2 * m * sizeof(double));
+    if (e != hipSuccess)
+        return cleanup(e == hipErrorOutOfMemory ? fail(QS_E_NOMEM, "partial-amplitude buffers for %zu indices", m)
+                                                : hip_fail(e, "partial-amplitude set-up"));
+    e = hipMemcpyAsync(dix, ix[0].data(), m * sizeof(uint64_t), hipMemcpyHostToDevice, strm);
+    if (e == hipSuccess) e = hipMemcpyAsync(dix + m, ix[1].data(), m * sizeof(uint64_t), hipMemcpyHostToDevice, strm);
+    if (e == hipSuccess) e = hipMemsetAsync(acc, 0, 2 * m * sizeof(double), strm);
+    if (e == hipSuccess) e = hipStreamSynchronize(strm);
     if (e != hipSuccess) return cleanup(hip_fail(e, "partial-amplitude set-up"));
-    qs_circuit sub[2];
-    const uint64_t nw = uint64_t(1) << pp.cuts.size();
-    for (uint64_t w = 0; w < nw; ++w) {
-        // part B's state is rewritten only after the previous branch's
-        // recombination (on A's stream) has read it
-        if (w && (e = hipStreamWaitEvent(sb, ev[0], 0)) != hipSuccess) break;
-        for (int p = 1; p >= 0; --p) {
-            partial_circuit(pp, p, w, sub[p]);
-            if (qs_status r = qs_reset(st[p])) return cleanup(r);
-            if (qs_status r = qs_run_circuit(st[p], &sub[p], &o)) return cleanup(r);
-        }
-        if ((e = hipEventRecord(ev[1], sb)) != hipSuccess) break;
-        if ((e = hipStreamWaitEvent(sa, ev[1], 0)) != hipSuccess) break;
-        if ((e = qs::launch_partial_cmac(dt, st[0]->amp, st[1]->amp, dix, dix + m, m, acc, sa)) != hipSuccess) break;
-        if ((e = hipEventRecord(ev[0], sa)) != hipSuccess) break;
-    }
-    if (e == hipSuccess) e = hipMemcpyAsync(out, acc, 2 * m * sizeof(double), hipMemcpyDeviceToHost, sa);
-    if (e == hipSuccess) e = hipStreamSynchronize(sa);
-    if (e == hipSuccess) e = hipStreamSynchronize(sb);
+    const size_t bytes[2] = {amp_bytes(dt) << pp.np[0], amp_bytes(dt) << pp.np[1]};
+    const double tree_bytes = double(pp.cuts.size() + 1) * double(bytes[0] + bytes[1]);
+    const size_t lim = g_mem_limit.load();
+    const bool tree = tree_bytes <= kPartialTreeBytes && (lim == 0 || tree_bytes <= double(lim));
+    qs_status r = tree ? partial_tree(pp, dt, o, dix, m, acc, strm) : partial_branches(pp, dt, o, dix, m, acc, strm);
+    if (r) return cleanup(r);
+    e = hipMemcpyAsync(out, acc, 2 * m * sizeof(double), hipMemcpyDeviceToHost, strm);
+    if (e == hipSuccess) e = hipStreamSynchronize(strm);
     if (e != hipSuccess) return cleanup(hip_fail(e, "partial-amplitude branches"));
     return cleanup(QS_OK);
 }

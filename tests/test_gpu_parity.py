@@ -857,6 +857,23 @@ def test_partial_amplitudes_other_division_and_sampled_order(qs):
     assert np.max(np.abs(got - ref[idx])) <= TOL128
 
 
+def test_partial_amplitudes_per_branch_path_matches_tree_walk(qs):
+    """With a memory limit below the c + 1 states per part that the
+    depth-first walk keeps, every branch word runs its sub-circuits in full;
+    both ways give the oracle's amplitudes (complex128)."""
+    ops = _partial_circuit()
+    n, part_a = 12, (1 << 6) - 1
+    ref, _ = oracle.run(n, ops)
+    c = qs.Circuit(ops)
+    qs.set_memory_limit(4 << 10)  # 2 x 64 x 16 B per level fit, 11 levels do not
+    try:
+        got, cuts = c.partial_amplitudes(n, part_a, np.arange(1 << n))
+    finally:
+        qs.set_memory_limit(0)
+    assert cuts == 10
+    assert np.max(np.abs(got - ref)) <= TOL128
+
+
 def test_partial_amplitudes_30_qubits_against_full_state(qs):
     """At 30 qubits (6 x 5 grid, depth 8, divided between rows 2 and 3: 10
     cuts, two 15-qubit parts), 4096 sampled amplitudes equal those of the
