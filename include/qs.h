@@ -333,6 +333,52 @@ qs_status qs_partial_amplitudes(const qs_circuit *c, int n, qs_dtype dt, uint64_
  * division (host only, no device work); errors as qs_partial_amplitudes. */
 qs_status qs_partial_cuts(const qs_circuit *c, int n, uint64_t part_a, int *cuts);
 
+/* --------------------------------------------------------------- scripts -- */
+
+/* Input scripts in the instruction set of App. A-1, one instruction per line
+ * (names case-insensitive, arguments separated by commas, angle arguments
+ * optionally in double quotes as App. A-2 prints them: a number, pi, or an
+ * expression of them with + - * / and parentheses; '#' starts a comment and
+ * lines starting with '%' are section labels):
+ *   QINIT n | CREG m | H/X/Y/Z/S/T i | RX/RY/RZ i, theta | U4 i, a, b, c, d
+ *   (the angle form) | CNOT/CZ i, j | CR i, j, theta | SWAP/ISWAP i, j |
+ *   TOFFOLI i, j, k | DAGGER ... ENDDAGGER | CONTROL i ... ENDCONTROL [i] |
+ *   MEASURE i, $j | PMEASURE i, j, ..., k
+ * with the matrices of App. A-1 (controlled gates act on the last listed
+ * qubit when the others are 1).  MEASURE i, $j is a projective measurement
+ * of qubit i in the computational basis: a noise site with the Kraus set
+ * {|0><0|, |1><1|} after an identity gate, so the outcome b is drawn as in
+ * Sec. 2.4 (p_b = ||P_b psi||^2 in FP64, the run's Philox draw, the state
+ * renormalised) and stored in classical register j.  PMEASURE changes no
+ * state and must come after every other operation; at most one per script.
+ * QINIT comes first; qubit and register numbers are checked against it and
+ * CREG.  qs_script_parse builds a new circuit (freed by the caller with
+ * qs_circuit_destroy) and fills `info`; it needs no device.  Errors name the
+ * line: QS_E_INVAL (syntax, unknown instruction, missing QINIT, unbalanced
+ * groups, PMEASURE not last), QS_E_RANGE (qubit or register numbers),
+ * QS_E_UNSUPPORTED (MEASURE inside a DAGGER / CONTROL group). */
+typedef struct {
+    int n;            /* QINIT */
+    int creg;         /* CREG (0 when absent) */
+    int measures;     /* MEASURE instructions */
+    int pmeasure_n;   /* qubits listed by PMEASURE (0 when absent) */
+    int pmeasure[QS_MAX_QUBITS];
+} qs_script_info;
+
+qs_status qs_script_parse(const char *text, qs_circuit **circuit, qs_script_info *info);
+
+/* Parse and run a script on a new n-qubit state of dtype dt, from |0...0>
+ * (QINIT), with Philox key `seed` and trajectory 0 for the MEASURE draws,
+ * per-gate launches when it measures, else `plan` (a qs_plan value; not
+ * QS_PLAN_AUTOTUNE).  creg[j] (creg_len >= CREG entries) receives the last
+ * outcome stored in register j (0 if none); probs (probs_len >= 2^pmeasure_n
+ * doubles) the PMEASURE probabilities in the order of qs_probabilities.
+ * Either output may be NULL when the script has no such instruction; info
+ * may be NULL.  Synchronous.  Errors as qs_script_parse and qs_run_circuit,
+ * QS_E_INVAL for short outputs. */
+qs_status qs_script_run(const char *text, qs_dtype dt, uint64_t seed, int plan, int *creg, int creg_len,
+                        double *probs, size_t probs_len, qs_script_info *info);
+
 /* ------------------------------------------------------------------ misc -- */
 
 /* The uniform number used for noise site `site` of trajectory `traj`:

@@ -48,6 +48,11 @@ class RunOpts(C.Structure):
                 ("chosen_len", C.c_int64), ("tile_qubits", C.c_int), ("tile_order", C.c_int)]
 
 
+class ScriptInfo(C.Structure):
+    _fields_ = [("n", C.c_int), ("creg", C.c_int), ("measures", C.c_int), ("pmeasure_n", C.c_int),
+                ("pmeasure", C.c_int * 36)]
+
+
 P, I, D, U64, I64, SZ = C.c_void_p, C.c_int, C.c_double, C.c_uint64, C.c_int64, C.c_size_t
 PP = C.POINTER(C.c_void_p)
 _sig = {
@@ -81,6 +86,8 @@ _sig = {
     "qs_remap_unpack": ([P, I, P, P], I),
     "qs_partial_amplitudes": ([P, I, I, U64, P, SZ, P, C.POINTER(RunOpts), P], I),
     "qs_partial_cuts": ([P, I, U64, P], I),
+    "qs_script_parse": ([C.c_char_p, PP, C.POINTER(ScriptInfo)], I),
+    "qs_script_run": ([C.c_char_p, I, U64, I, P, I, P, SZ, C.POINTER(ScriptInfo)], I),
     "qs_philox_uniform": ([U64, U64, U64], D),
     "qs_philox4x32_10": ([P, P, P], None),
     "qs_profile_enable": ([P, I], I),
@@ -278,6 +285,32 @@ class Circuit:
             self.close()
         except Exception:
             pass
+
+
+def _info_dict(info: ScriptInfo) -> dict:
+    return {"n": info.n, "creg": info.creg, "measures": info.measures,
+            "pmeasure": [info.pmeasure[k] for k in range(info.pmeasure_n)]}
+
+
+def script_parse(text: str):
+    """qs_script_parse: (Circuit, info) for an App. A-1 script."""
+    h, info = C.c_void_p(), ScriptInfo()
+    _check(_lib.qs_script_parse(text.encode(), C.byref(h), C.byref(info)))
+    c = Circuit.__new__(Circuit)
+    c._h = h
+    return c, _info_dict(info)
+
+
+def script_run(text: str, dtype: int = C128, seed: int = 0, plan: int = PLAN_UNFUSED):
+    """qs_script_run: (classical registers, PMEASURE probabilities, info)."""
+    h, info = C.c_void_p(), ScriptInfo()
+    _check(_lib.qs_script_parse(text.encode(), C.byref(h), C.byref(info)))
+    _lib.qs_circuit_destroy(h)
+    creg = (C.c_int * max(info.creg, 1))()
+    probs = np.zeros(1 << info.pmeasure_n if info.pmeasure_n else 1)
+    _check(_lib.qs_script_run(text.encode(), dtype, seed, plan, creg, info.creg, _ptr(probs), probs.size,
+                              C.byref(info)))
+    return ([creg[j] for j in range(info.creg)], probs if info.pmeasure_n else None, _info_dict(info))
 
 
 class State:

@@ -270,3 +270,81 @@ def test_partial_cut_forms_and_rejections(qs):
     with pytest.raises(qs.QSError) as e:
         c.partial_cuts(40, (1 << 38) - 1)  # part A of 38 qubits
     assert e.value.status == -6
+
+
+# --------------------------------------------------------------- scripts --
+
+SCRIPT_ALL = """# every App. A-1 instruction
+QINIT 4
+CREG 2
+H 0
+X 1
+Y 2
+Z 3
+S 0
+T 1
+RX 2, "pi/3"
+RY 3, "-pi/4"
+RZ 0, "3*pi/4"
+U4 1, "0.1, (1+1)*pi/8, -0.7, 1e-1"
+CNOT 0, 2
+CZ 1, 3
+CR 2, 0, "pi/2"
+SWAP 1, 2
+ISWAP 0, 3
+TOFFOLI 0, 1, 3
+DAGGER
+H 2
+CR 2, 3, "pi/5"
+DAGGER
+T 0
+ENDDAGGER
+ENDDAGGER
+CONTROL 3
+RY 0, "0.3"
+CONTROL 2
+X 1
+ENDCONTROL 2
+ENDCONTROL 3
+H 0
+H 1
+H 2
+H 3
+"""
+
+
+def _golden_script():
+    with open(os.path.join(ROOT, "tests", "golden", "appA2_example.txt")) as f:
+        text = f.read()
+    return text, text.split("%Output")[0]
+
+
+def test_script_parse_counts_and_info(qs):
+    """The App. A-1 parser builds the circuit the test-side reader builds for
+    the App. A-2 example (same gate counts after DAGGER expansion) and
+    reports QINIT, CREG and the PMEASURE qubits."""
+    from tests import appa_script
+    full, text = _golden_script()
+    n, ops, pm, _ = appa_script.parse(full, oracle.named_gate)
+    c, info = qs.script_parse(text)
+    assert info == {"n": n, "creg": 3, "measures": 0, "pmeasure": pm}
+    assert c.counts() == qs.Circuit(ops).counts()
+    c, info = qs.script_parse(SCRIPT_ALL)
+    n, ops, _, _ = appa_script.parse(SCRIPT_ALL, oracle.named_gate)
+    assert info["n"] == n == 4 and info["pmeasure"] == []
+    assert c.counts() == qs.Circuit(ops).counts() == (25, 0, 25)
+
+
+def test_script_errors_name_the_line(qs):
+    cases = [("QINIT 2\nH 0\nFOO 1\n", -1, "line 3"), ("QINIT 2\nH 2\n", -2, "line 2"),
+             ("H 0\n", -1, "line 1"), ("QINIT 2\nRX 0, \"pi/\"\n", -1, "line 2"),
+             ("QINIT 2\nCREG 1\nDAGGER\nMEASURE 0, $0\nENDDAGGER\n", -6, "line 4"),
+             ("QINIT 2\nPMEASURE 0\nH 1\n", -1, "line 3"), ("QINIT 2\nCREG 1\nMEASURE 0, $1\n", -2, "line 3"),
+             ("QINIT 3\nCONTROL 0\nH 1\nENDCONTROL 2\n", -1, "line 4"), ("QINIT 2\nDAGGER\nH 0\n", -1, "line 2"),
+             ("QINIT 2\nCNOT 0\n", -1, "line 2"), ("QINIT 2\nMEASURE 0, 0\n", -1, "line 2"),
+             ("QINIT 2\nPMEASURE 1, 1\n", -2, "line 2"), ("QINIT 40\n", -1, "line 1")]
+    for text, status, where in cases:
+        with pytest.raises(qs.QSError) as e:
+            qs.script_parse(text)
+        assert e.value.status == status, text
+        assert qs.last_error().startswith(where + ":"), (text, qs.last_error())

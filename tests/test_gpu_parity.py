@@ -904,3 +904,69 @@ def test_partial_amplitudes_validation(qs):
     assert e.value.status == -1
     got, cuts = c.partial_amplitudes(6, 0b111, [])
     assert got.size == 0 and cuts == 1
+
+
+# --------------------------------------------------------------- scripts --
+
+
+def test_script_run_reproduces_the_printed_appA2_output(qs):
+    """The App. A-2 example through the library's own script reader: the
+    PMEASURE probabilities equal the printed output within 1e-6 and the
+    oracle's (run on the test-side reading of the same script) within 1e-12."""
+    with open(os.path.join(GOLDEN, "appA2_example.txt")) as f:
+        full = f.read()
+    n, ops, pm, printed = appa_script.parse(full, oracle.named_gate)
+    ref, _ = oracle.run(n, ops)
+    want = oracle.probabilities(ref, pm)
+    creg, probs, info = qs.script_run(full.split("%Output")[0])
+    assert info["pmeasure"] == pm and creg == [0, 0, 0]
+    assert np.max(np.abs(probs - printed)) <= 1e-6
+    assert np.max(np.abs(probs - want)) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_script_gate_table_matches_oracle(qs, dtype):
+    """Every App. A-1 instruction (angle expressions, nested DAGGER and
+    CONTROL groups) parsed by the library and run on a state gives the
+    oracle's amplitudes for the test-side reading with the oracle's gate
+    table."""
+    from tests.test_abi_host import SCRIPT_ALL
+    n, ops, _, _ = appa_script.parse(SCRIPT_ALL, oracle.named_gate)
+    ref, _ = oracle.run(n, ops)
+    c, info = qs.script_parse(SCRIPT_ALL)
+    dt = qs.C128 if dtype == "c128" else qs.C64
+    s = qs.State(n, dt)
+    s.run(c)
+    got = s.amplitudes()
+    s.close()
+    tol = TOL128 if dt == qs.C128 else 1e-6
+    assert np.max(np.abs(got - ref)) <= tol
+
+
+def _measure_ops(qubits):
+    p0, p1 = np.diag([1.0, 0.0]).astype(complex), np.diag([0.0, 1.0]).astype(complex)
+    out = []
+    for q in qubits:
+        out += [cg.Gate((q,), (), np.eye(2)), cg.Noise((q,), np.stack([p0, p1]))]
+    return out
+
+
+def test_script_measure_outcomes_match_oracle_draws(qs):
+    """MEASURE i, $j is the Sec. 2.4 noise site with Kraus {P0, P1}: over 24
+    seeds the outcomes equal the oracle's branch choices for the same Philox
+    draws, a Bell pair measures equal bits, an X-flipped qubit measures 1,
+    and a measured qubit stays collapsed (PMEASURE is then one-hot)."""
+    script = "QINIT 4\nCREG 4\nH 0\nCNOT 0, 1\nX 2\nRY 3, \"1.1\"\nMEASURE 0, $0\nMEASURE 1, $1\n" \
+             "MEASURE 2, $2\nMEASURE 3, $3\nPMEASURE 3\n"
+    ops = [cg.Gate((0,), (), oracle.named_gate("H")), cg.Gate((1,), (0,), oracle.named_gate("X")),
+           cg.Gate((2,), (), oracle.named_gate("X")), cg.Gate((3,), (), oracle.named_gate("RY", (1.1,)))]
+    ops += _measure_ops([0, 1, 2, 3])
+    seen = set()
+    for seed in range(24):
+        creg, probs, info = qs.script_run(script, seed=seed)
+        _, chosen = oracle.run(4, ops, seed=seed)
+        assert creg == list(chosen), seed
+        assert creg[0] == creg[1] and creg[2] == 1
+        assert probs[creg[3]] == pytest.approx(1.0, abs=1e-12) and info["measures"] == 4
+        seen.add(creg[0])
+    assert seen == {0, 1}
