@@ -603,8 +603,10 @@ void block_matrices(const std::vector<int> &qs, const std::vector<int> &os,
 
 }  // namespace
 
-void plan_tiles(const std::vector<FlatOp> &flat, size_t k0, size_t e, int n, const TileParams &tp,
-                std::vector<PlanStep> &out)
+namespace {
+
+void plan_tiles_once(const std::vector<FlatOp> &flat, size_t k0, size_t e, int n, const TileParams &tp,
+                     std::vector<PlanStep> &out)
 {
     const int m = std::min(tp.m, n);
     const int L = std::min(tp.L, m);
@@ -921,6 +923,48 @@ void plan_tiles(const std::vector<FlatOp> &flat, size_t k0, size_t e, int n, con
         out.push_back(std::move(st));
         remaining.swap(deferred);
     }
+}
+
+// Relative cost of a tiled plan: a sweep costs its memory pass (1) plus
+// 0.15 per dense block beyond the two that hide under that pass, a gate
+// applied on its own one pass.  The ratio is the per-op time of the tile
+// kernel beyond the second op over its memory time (0.37 over 3.75 ms on the
+// microbenchmark, about 0.15 in whole plans of 30- and 34-qubit circuits).
+double plan_cost(const std::vector<PlanStep> &steps)
+{
+    double c = 0;
+    for (const PlanStep &st : steps) {
+        if (!st.sweep) {
+            c += 1;
+            continue;
+        }
+        int dense = 0;
+        for (const TileOp &op : st.sw.ops) dense += op.kind == TileOp::DENSE;
+        c += 1 + 0.15 * std::max(0, dense - 2);
+    }
+    return c;
+}
+
+}  // namespace
+
+// With the tile-qubit search on, whole plans made with half and with all of
+// the random restarts are compared by plan_cost: more restarts find sweeps
+// that apply more gates, which is not always the cheaper plan (fewer sweeps
+// carrying more blocks).
+void plan_tiles(const std::vector<FlatOp> &flat, size_t k0, size_t e, int n, const TileParams &tp,
+                std::vector<PlanStep> &out)
+{
+    if (!tp.search || tp.restarts < 2) {
+        plan_tiles_once(flat, k0, e, n, tp, out);
+        return;
+    }
+    TileParams half = tp;
+    half.restarts = tp.restarts / 2;
+    std::vector<PlanStep> a, b;
+    plan_tiles_once(flat, k0, e, n, half, a);
+    plan_tiles_once(flat, k0, e, n, tp, b);
+    std::vector<PlanStep> &best = plan_cost(b) < plan_cost(a) ? b : a;
+    out.insert(out.end(), std::make_move_iterator(best.begin()), std::make_move_iterator(best.end()));
 }
 
 }  // namespace qs

@@ -99,7 +99,7 @@ struct TileParams {
     int kmax = 4;   // widest dense block (4 or 5)
     int max_outer = kMaxOuter;  // outer selector bits per op (0..kMaxOuter)
     bool search = true;  // improve each sweep's tile qubits by local search
-    int restarts = 16;   // extra random starting sets for that search
+    int restarts = 32;   // extra random starting sets for that search
 };
 
 // One step of a tiled plan: a tile sweep, or a gate that does not fit a tile

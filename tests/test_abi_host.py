@@ -168,19 +168,20 @@ def test_tile_planner_terminates_on_wide_diagonals(qs):
 
 def test_tile_planner_sweep_counts_on_workload_circuits(qs):
     """The greedy tile planner with its search over tile qubits (local search
-    from the first-come set and from seeded random sets, two-sweep lookahead):
-    on the 30-qubit depth-40 workload circuit it needs 30 sweeps of 13-qubit
-    tiles (41 with first-come tile qubits), on the 34-qubit one 13 (20), and
+    from the first-come set and from seeded random sets, two-sweep lookahead,
+    the cheaper of the plans with 16 and 32 restarts): on the 30-qubit
+    depth-40 workload circuit it needs 28 sweeps of 13-qubit tiles (41 with
+    first-come tile qubits), on the 34-qubit one 13 (20) with 88 blocks, and
     every logical gate is planned.  A regression guard on the planner's
     quality, not a parity check."""
     n, ops = cg.workload("rqc30_d40")
     info = qs.Circuit(ops).plan_info(n, qs.C64, qs.PLAN_GREEDY)
     assert info["gates"] == cg.count_gates(ops)
-    assert info["sweeps"] <= 31
+    assert info["sweeps"] <= 29
     assert info["blocks"] <= 200
     n, ops = cg.workload("rqc34_d24")
     info = qs.Circuit(ops).plan_info(n, qs.C64, qs.PLAN_GREEDY)
-    assert info["gates"] == cg.count_gates(ops) and info["sweeps"] <= 14
+    assert info["gates"] == cg.count_gates(ops) and info["sweeps"] <= 13 and info["blocks"] <= 92
 
 
 def test_autotune_result_before_any_run(qs):
