@@ -190,6 +190,42 @@ def test_eq4_cz_decomposition():
         assert np.allclose(a, b + c, atol=1e-15)
 
 
+def test_eq4_generalised_to_controlled_and_diagonal_gates():
+    """The cut rule of the partial-amplitude mode, checked on the oracle: a
+    gate U on targets T with controls C' on the other side equals
+    P_rest(C') (x) I + P_ones(C') (x) U (Eq. 4 with the all-ones projector,
+    for CNOT, CU3 and a Toffoli with both controls across), and a diagonal D
+    with one qubit p on one side equals P_0(p) (x) D_0 + P_1(p) (x) D_1 with
+    D_v the diagonal restricted to p = v."""
+    n = 6
+    rng = np.random.default_rng(12)
+    X = oracle.named_gate("X")
+    for tgt, ctl, u in [((4,), (1,), X), ((0,), (5,), cg.u3(0.4, 1.1, -0.3)), ((3,), (0, 1), X)]:
+        psi = cg.random_state(n, int(rng.integers(1 << 30)))
+        a = psi.copy()
+        oracle.apply(a, tgt, ctl, u)
+        k = len(ctl)
+        ones = np.zeros(1 << k)
+        ones[-1] = 1
+        b = psi.copy()
+        oracle.apply(b, ctl, (), np.diag(1 - ones))
+        c = psi.copy()
+        oracle.apply(c, ctl, (), np.diag(ones))
+        oracle.apply(c, tgt, (), u)
+        assert np.allclose(a, b + c, atol=1e-14)
+    d = np.exp(1j * rng.uniform(0, 2 * np.pi, 8))  # on (p, q1, q2), p the high bit
+    psi = cg.random_state(n, 99)
+    a = psi.copy()
+    oracle.apply(a, (2, 3, 4), (), np.diag(d))
+    total = np.zeros_like(psi)
+    for v in (0, 1):
+        t = psi.copy()
+        oracle.apply(t, (2,), (), P1 if v else P0)
+        oracle.apply(t, (3, 4), (), np.diag(d[4 * v:4 * v + 4]))
+        total += t
+    assert np.allclose(a, total, atol=1e-14)
+
+
 # ----------------------------------------------- dense operators, n <= 10 --
 
 
