@@ -891,6 +891,25 @@ def test_partial_amplitudes_30_qubits_against_full_state(qs):
     assert np.max(np.abs(got - full)) <= 1e-13
 
 
+def test_partial_amplitudes_40_qubits_two_divisions_agree(qs):
+    """At 40 qubits (8 x 5 grid, depth 6), where no full state fits one GPU,
+    two dividing lines give entirely different sub-circuits: rows 0-3 | 4-7
+    (20 + 20 qubits, 5 cuts) and columns 0-1 | 2-4 (16 + 24 qubits, 8 cuts).
+    Their amplitudes at 4096 sampled indices agree to 1e-13 (complex128), and
+    the mean of |amp|^2 * 2^40 over the sample is near 1."""
+    rows, cols, n = 8, 5, 40
+    ops = cg.random_circuit(rows, cols, 6, seed=6003)
+    c = qs.Circuit(ops)
+    top = (1 << 20) - 1
+    left = sum(1 << (r * cols + k) for r in range(rows) for k in range(2))
+    idx = np.random.default_rng(8).integers(0, 1 << n, size=4096, dtype=np.uint64)
+    a, ca = c.partial_amplitudes(n, top, idx, plan=qs.PLAN_GREEDY)
+    b, cb = c.partial_amplitudes(n, left, idx, plan=qs.PLAN_GREEDY)
+    assert (ca, cb) == (5, 8)
+    assert np.max(np.abs(a - b)) <= 1e-13
+    assert abs(np.mean(np.abs(a) ** 2) * 2.0 ** n - 1) < 0.25
+
+
 def test_partial_amplitudes_validation(qs):
     c = qs.Circuit([cg.Gate((0,), (), cg.H_GATE), cg.Gate((0, 5), (), cg.CZ_GATE)])
     with pytest.raises(qs.QSError) as e:
