@@ -382,14 +382,27 @@ __global__ __launch_bounds__(kBlock) void k_probs_reg(const typename Cpx<R>::T *
     double acc[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[b] = 0.0;
+    // four amplitudes per lane and step, loaded before any is summed, so
+    // that enough loads are in flight to keep HBM busy on complex64 states
+    constexpr int U = 4;
     const uint64_t stride = uint64_t(gridDim.x) * kBlock;
-    for (uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x; i < n_amp; i += stride) {
-        const auto v = a[i];
-        const double p = double(v.x) * double(v.x) + double(v.y) * double(v.y);
-        int x = 0;
-        for (int b = 0; b < nq; ++b) x = (x << 1) | int((i >> q.pos[b]) & 1);
+    for (uint64_t i0 = uint64_t(blockIdx.x) * kBlock + threadIdx.x; i0 < n_amp; i0 += U * stride) {
+        typename Cpx<R>::T v[U];
 #pragma unroll
-        for (int b = 0; b < NB; ++b) acc[b] += (x == b) ? p : 0.0;
+        for (int u = 0; u < U; ++u) {
+            const uint64_t i = i0 + u * stride;
+            if (i < n_amp) v[u] = a[i];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t i = i0 + u * stride;
+            if (i >= n_amp) break;
+            const double p = double(v[u].x) * double(v[u].x) + double(v[u].y) * double(v[u].y);
+            int x = 0;
+            for (int b = 0; b < nq; ++b) x = (x << 1) | int((i >> q.pos[b]) & 1);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) acc[b] += (x == b) ? p : 0.0;
+        }
     }
     __shared__ double lds[kBlock / 64];
 #pragma unroll
