@@ -51,6 +51,8 @@ def parse():
     p.add_argument("--trajectories", type=int, default=512,
                    help="noisy trajectories in the batched-trajectory measurement (0 = skip)")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--no-extras", action="store_true",
+                   help="skip the partial-amplitude and qubit-remap measurements that follow the main paths")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 4 GiB device-to-device copy (5 times), the reference "
                         "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
@@ -112,15 +114,15 @@ def traffic_for(path_name: str, kernel_class: str):
 PROFILE_DIR = "rocprof_out"  # where the runs below write their CSVs and logs
 PROFILE_RUNS = [
     ("ktrace", "--kernel-trace --stats",
-     "--steps 2 --warmup 1 --no-cpu-baseline --trajectories 0 --no-by-target"),
+     "--steps 2 --warmup 1 --no-cpu-baseline --trajectories 0 --no-by-target --no-extras"),
     ("pmc_fetch_fused_c64", "--pmc FETCH_SIZE",
-     "--steps 1 --warmup 0 --no-cpu-baseline --trajectories 0 --no-by-target --paths fused_c64"),
+     "--steps 1 --warmup 0 --no-cpu-baseline --trajectories 0 --no-by-target --no-extras --paths fused_c64"),
     ("pmc_write_fused_c64", "--pmc WRITE_SIZE",
-     "--steps 1 --warmup 0 --no-cpu-baseline --trajectories 0 --no-by-target --paths fused_c64"),
+     "--steps 1 --warmup 0 --no-cpu-baseline --trajectories 0 --no-by-target --no-extras --paths fused_c64"),
     ("pmc_fetch_plain_c128", "--pmc FETCH_SIZE",
-     "--steps 1 --warmup 0 --no-cpu-baseline --trajectories 0 --no-by-target --paths plain_c128"),
+     "--steps 1 --warmup 0 --no-cpu-baseline --trajectories 0 --no-by-target --no-extras --paths plain_c128"),
     ("pmc_write_plain_c128", "--pmc WRITE_SIZE",
-     "--steps 1 --warmup 0 --no-cpu-baseline --trajectories 0 --no-by-target --paths plain_c128"),
+     "--steps 1 --warmup 0 --no-cpu-baseline --trajectories 0 --no-by-target --no-extras --paths plain_c128"),
     ("remap", "--kernel-trace --stats", "--remap"),
     ("pmc_fetch_copy", "--pmc FETCH_SIZE", "--copy-calibration"),
     ("pmc_write_copy", "--pmc WRITE_SIZE", "--copy-calibration"),
@@ -472,7 +474,7 @@ def copy_ceiling(torch, nbytes=4 << 30, reps=5):
     return max(res.values()), res
 
 
-def remap_bench(qs, torch, L=30, g=3, reps=3):
+def remap_bench(qs, torch, L=30, g=3, reps=3, emit=True):
     """Pack and unpack of the qubit-remap exchange (qs_remap_pack / _unpack) on
     one shard at its real shape (L local qubits), for several local-qubit
     sets: algorithmic bytes 2 * 2^L * amp per call (every amplitude read and
@@ -507,12 +509,14 @@ def remap_bench(qs, torch, L=30, g=3, reps=3):
         st.close()
         del t, buf
         torch.cuda.empty_cache()
-    print(json.dumps({"metric": "qubit-remap pack / unpack bandwidth", "unit": "GB/s", "shard_qubits": L,
-                      "g": g, "bytes": "2 * 2^L * sizeof(amplitude) per call", "results": out}))
-    return out
+    rec = {"metric": "qubit-remap pack / unpack bandwidth", "unit": "GB/s", "shard_qubits": L, "g": g,
+           "bytes": "2 * 2^L * sizeof(amplitude) per call", "results": out}
+    if emit:
+        print(json.dumps(rec))
+    return rec
 
 
-def partial_bench(qs, cg, rows=8, cols=5, depth=8, top_rows=4, m=1 << 20, seed=6001):
+def partial_bench(qs, cg, rows=8, cols=5, depth=8, top_rows=4, m=1 << 20, seed=6001, emit=True):
     """Partial-amplitude mode (qs_partial_amplitudes) on a circuit no full state
     of which fits one GPU: an 8 x 5 grid (40 qubits, 16 TiB as complex128) at
     depth 8, divided between rows 3 and 4 (two 20-qubit parts, 10 CZ cut),
@@ -536,13 +540,15 @@ def partial_bench(qs, cg, rows=8, cols=5, depth=8, top_rows=4, m=1 << 20, seed=6
             "mean |amp|^2 * 2^n = %.3f" % (name, n, cuts, 2 << cuts, m, sec, m / sec, p.mean() * 2.0 ** n))
         runs.append({"path": name, "seconds": round(sec, 3), "amplitudes_per_s": round(m / sec, 1),
                      "mean_prob_times_2n": round(float(p.mean() * 2.0 ** n), 4)})
-    print(json.dumps({"metric": "partial-amplitude mode: sampled amplitudes per second", "unit": "amplitudes/s",
-                      "value": max(r["amplitudes_per_s"] for r in runs), "workload":
-                      "%dx%d grid random circuit, %d qubits, depth %d, %d gates" % (rows, cols, n, depth,
-                                                                                  cg.count_gates(ops)),
-                      "parts": [top_rows * cols, n - top_rows * cols], "cuts": cuts, "sub_circuits": 2 << cuts,
-                      "amplitudes": m, "runs": runs}))
-    return runs
+    rec = {"metric": "partial-amplitude mode: sampled amplitudes per second", "unit": "amplitudes/s",
+           "value": max(r["amplitudes_per_s"] for r in runs),
+           "workload": "%dx%d grid random circuit, %d qubits, depth %d, %d gates" % (rows, cols, n, depth,
+                                                                                   cg.count_gates(ops)),
+           "parts": [top_rows * cols, n - top_rows * cols], "cuts": cuts, "sub_circuits": 2 << cuts,
+           "amplitudes": m, "runs": runs}
+    if emit:
+        print(json.dumps(rec))
+    return rec
 
 
 def trajectory_bench(qs, cg, count, seed=4001):
@@ -746,6 +752,16 @@ def main():
     del states
     torch.cuda.empty_cache()
     traj = trajectory_bench(qs, cg, args.trajectories) if args.trajectories > 0 else None
+    # the widened paths, measured after (and apart from) the timed steps
+    extras = {}
+    if not args.no_extras:
+        for key, fn in (("partial_mode", lambda: partial_bench(qs, cg, emit=False)),
+                        ("remap", lambda: remap_bench(qs, torch, emit=False))):
+            try:
+                extras[key] = fn()
+            except Exception as e:  # reported, never fatal to the headline
+                log("%s measurement failed: %s" % (key, e))
+                extras[key] = {"error": str(e)}
     primary = "fused_c64" if "fused_c64" in out else paths[0]
     prim = out[primary]
     cpu = None
@@ -782,6 +798,7 @@ def main():
         "trajectories": traj,
         "cpu_baseline": cpu,
     }
+    line.update(extras)
     if "plain_c128" in out and primary != "plain_c128":
         line["speedup_vs_plain_c128"] = prim["gates_per_s"] / out["plain_c128"]["gates_per_s"]
     print(json.dumps(line), flush=True)
