@@ -8,6 +8,8 @@
 #include <complex>
 #include <cstdio>
 #include <cstdlib>
+#include <exception>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -353,6 +355,12 @@ qs_status qs_script_parse(const char *text, qs_circuit **circuit, qs_script_info
     } catch (const ScriptError &e) {
         qs_circuit_destroy(P.c);
         return qs::set_error(e.st, e.msg.c_str());
+    } catch (const std::bad_alloc &) {
+        qs_circuit_destroy(P.c);
+        return qs::set_error(QS_E_NOMEM, "host allocation failed while reading the script");
+    } catch (const std::exception &e) {  // nothing may unwind through the C ABI
+        qs_circuit_destroy(P.c);
+        return qs::set_error(QS_E_INVAL, e.what());
     }
     *circuit = P.c;
     if (info) *info = P.info;
@@ -370,6 +378,12 @@ qs_status qs_script_run(const char *text, qs_dtype dt, uint64_t seed, int plan, 
     } catch (const ScriptError &e) {
         qs_circuit_destroy(P.c);
         return qs::set_error(e.st, e.msg.c_str());
+    } catch (const std::bad_alloc &) {
+        qs_circuit_destroy(P.c);
+        return qs::set_error(QS_E_NOMEM, "host allocation failed while reading the script");
+    } catch (const std::exception &e) {  // nothing may unwind through the C ABI
+        qs_circuit_destroy(P.c);
+        return qs::set_error(QS_E_INVAL, e.what());
     }
     const qs_script_info &I = P.info;
     qs_status st = QS_OK;
