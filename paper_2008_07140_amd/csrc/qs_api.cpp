@@ -2814,16 +2814,18 @@ qs_status partial_tree(const PartialPlan &pp, qs_dtype dt, const qs_run_opts &o,
 }  // namespace
 
 qs_status qs_partial_cuts(const qs_circuit *c, int n, uint64_t part_a, int *cuts)
-{
+try {
     PartialPlan pp;
     if (qs_status st = build_partial(c, n, part_a, pp)) return st;
     if (cuts) *cuts = int(pp.cuts.size());
     return QS_OK;
+} catch (const std::bad_alloc &) {
+    return fail(QS_E_NOMEM, "host allocation failed while cutting the circuit");
 }
 
 qs_status qs_partial_amplitudes(const qs_circuit *c, int n, qs_dtype dt, uint64_t part_a, const uint64_t *idx,
                                 size_t m, double *out, const qs_run_opts *opts, int *cuts)
-{
+try {
     if (dt != QS_C64 && dt != QS_C128) return fail(QS_E_INVAL, "unknown dtype %d", int(dt));
     if (m && (!idx || !out)) return fail(QS_E_INVAL, "idx or out is NULL");
     qs_run_opts o{};
@@ -2880,12 +2882,19 @@ qs_status qs_partial_amplitudes(const qs_circuit *c, int n, qs_dtype dt, uint64_
     const double tree_bytes = double(pp.cuts.size() + 1) * double(bytes[0] + bytes[1]);
     const size_t lim = g_mem_limit.load();
     const bool tree = tree_bytes <= kPartialTreeBytes && (lim == 0 || tree_bytes <= double(lim));
-    qs_status r = tree ? partial_tree(pp, dt, o, dix, m, acc, strm) : partial_branches(pp, dt, o, dix, m, acc, strm);
+    qs_status r;
+    try {
+        r = tree ? partial_tree(pp, dt, o, dix, m, acc, strm) : partial_branches(pp, dt, o, dix, m, acc, strm);
+    } catch (const std::bad_alloc &) {  // the buffers above are released before reporting
+        r = fail(QS_E_NOMEM, "host allocation failed in the partial-amplitude mode");
+    }
     if (r) return cleanup(r);
     e = hipMemcpyAsync(out, acc, 2 * m * sizeof(double), hipMemcpyDeviceToHost, strm);
     if (e == hipSuccess) e = hipStreamSynchronize(strm);
     if (e != hipSuccess) return cleanup(hip_fail(e, "partial-amplitude branches"));
     return cleanup(QS_OK);
+} catch (const std::bad_alloc &) {
+    return fail(QS_E_NOMEM, "host allocation failed in the partial-amplitude mode");
 }
 
 // -------------------------------------------------------------- readout --
