@@ -2752,10 +2752,11 @@ qs_status partial_branches(const PartialPlan &pp, qs_dtype dt, const qs_run_opts
 
 // Depth-first walk of the tree of cuts.  The gates of a part between cut
 // j - 1 and cut j (segment j) do not depend on later branches, so the state
-// after segment j is computed once per prefix of branch bits: level j + 1
-// starts as a copy of level j, receives cut j's operator for branch b and
-// runs segment j + 1.  Each segment is one circuit whose plan is made once.
-// Memory: c + 1 states per part.
+// after segment j is computed once per prefix of branch bits: a child starts
+// from its parent's state (a copy for branch 0, the state itself for branch
+// 1), receives cut j's operator for its branch and runs segment j + 1.  Each
+// segment is one circuit whose plan is made once.  Memory: c + 1 states per
+// part.
 qs_status partial_tree(const PartialPlan &pp, qs_dtype dt, const qs_run_opts &o, const uint64_t *dix, size_t m,
                        double *acc, hipStream_t strm)
 {
@@ -2784,28 +2785,35 @@ qs_status partial_tree(const PartialPlan &pp, qs_dtype dt, const qs_run_opts &o,
     for (int p = 0; p < 2; ++p)
         if (!seg[p][0]->ops.empty())
             if (qs_status r = qs_run_circuit(ps[p].st[0], seg[p][0].get(), &o)) return r;
-    std::function<qs_status(int)> walk = [&](int j) -> qs_status {
+    // walk(j, k): state slot k of each part holds the state after segment j
+    // for the current prefix.  Branch 0 continues in a copy (slot k + 1);
+    // branch 1 is the slot's last use, so it continues in place.  Slots stay
+    // below c + 1: only branch-0 steps go one deeper.
+    std::function<qs_status(int, int)> walk = [&](int j, int k) -> qs_status {
         if (j == c) {
-            hipError_t e = qs::launch_partial_cmac(dt, ps[0].st[c]->amp, ps[1].st[c]->amp, dix, dix + m, m, acc, strm);
+            hipError_t e = qs::launch_partial_cmac(dt, ps[0].st[k]->amp, ps[1].st[k]->amp, dix, dix + m, m, acc, strm);
             return e == hipSuccess ? QS_OK : hip_fail(e, "partial-amplitude recombination");
         }
         const PartCut &cut = pp.cuts[j];
         for (int b = 0; b < 2; ++b) {
+            const int kk = b == 0 ? k + 1 : k;
             for (int p = 0; p < 2; ++p) {
-                qs_state *dst = ps[p].st[j + 1];
-                hipError_t e = hipMemcpyAsync(dst->amp, ps[p].st[j]->amp, bytes[p], hipMemcpyDeviceToDevice, strm);
-                if (e != hipSuccess) return hip_fail(e, "partial-amplitude state copy");
+                qs_state *dst = ps[p].st[kk];
+                if (kk != k) {
+                    hipError_t e = hipMemcpyAsync(dst->amp, ps[p].st[k]->amp, bytes[p], hipMemcpyDeviceToDevice, strm);
+                    if (e != hipSuccess) return hip_fail(e, "partial-amplitude state copy");
+                }
                 const PartGate *g = cut.pside == p ? &cut.proj[b] : cut.has[b] ? &cut.other[b] : nullptr;
                 if (g)
                     if (qs_status r = apply_part_gate(dst, *g)) return r;
                 if (!seg[p][j + 1]->ops.empty())
                     if (qs_status r = qs_run_circuit(dst, seg[p][j + 1].get(), &o)) return r;
             }
-            if (qs_status r = walk(j + 1)) return r;
+            if (qs_status r = walk(j + 1, kk)) return r;
         }
         return QS_OK;
     };
-    qs_status r = walk(0);
+    qs_status r = walk(0, 0);
     hipError_t e = hipStreamSynchronize(strm);
     if (r) return r;
     return e == hipSuccess ? QS_OK : hip_fail(e, "partial-amplitude tree");
