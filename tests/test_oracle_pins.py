@@ -131,6 +131,68 @@ def test_u4_angles_equal_phase_times_rz_ry_rz():
         assert np.allclose(u, np.exp(1j * al) * rzb @ ryg @ rzd, atol=1e-14)
 
 
+def test_rotation_gates_are_exponentials_of_paulis():
+    """RX, RY, RZ (App. A-1) are rotations about the x, y, z axes,
+    exp(-i theta P / 2), with P built from gates pinned elsewhere: X (a basis
+    permutation), Z = H X H and Y = i X Z.  A sign error in the printed
+    off-diagonal of RX or RY, or in the phases of RZ, fails here."""
+    from scipy.linalg import expm
+    h, x = oracle.named_gate("H"), oracle.named_gate("X")
+    z = h @ x @ h
+    y = 1j * x @ z
+    assert np.allclose(oracle.named_gate("Z"), z, atol=1e-15)
+    assert np.allclose(oracle.named_gate("Y"), y, atol=1e-15)
+    for theta in (0.3, -1.7, 2.9, math.pi):
+        for name, p in (("RX", x), ("RY", y), ("RZ", z)):
+            assert np.allclose(oracle.named_gate(name, (theta,)), expm(-0.5j * theta * p), atol=1e-14), (name, theta)
+        # the same rotations related to each other by the basis change H
+        assert np.allclose(oracle.named_gate("RX", (theta,)),
+                           h @ oracle.named_gate("RZ", (theta,)) @ h, atol=1e-14)
+
+
+def test_phase_gate_powers():
+    """T^2 = S and S^2 = Z: T is the fourth root of Z with the phase e^{+i pi/4}
+    on |1> that App. A-1 prints, and S = T^2 its square root."""
+    t, s, z = (oracle.named_gate(g) for g in ("T", "S", "Z"))
+    assert np.allclose(t @ t, s, atol=1e-15)
+    assert np.allclose(s @ s, z, atol=1e-15)
+    # and T is diagonal with |1> picking up a phase of +pi/4 (not -pi/4)
+    assert abs(t[1, 1] - np.exp(0.25j * math.pi)) < 1e-15 and t[0, 0] == 1
+
+
+def test_u4_reduces_to_rz_for_zero_gamma():
+    """U4(0, theta, 0, 0) = RZ(theta): with gamma = 0 the angle form of App. A-1
+    is the z rotation by beta (RZ pinned above as exp(-i theta Z / 2))."""
+    for theta in (0.4, -2.2):
+        assert np.allclose(oracle.named_gate("U4", (0.0, theta, 0.0, 0.0)),
+                           oracle.named_gate("RZ", (theta,)), atol=1e-15)
+
+
+def test_iswap_as_printed():
+    """iSWAP of App. A-1 exchanges |01> and |10> with a factor -i (the printed
+    matrix; first listed qubit = most significant bit): on qubits (a, b),
+    |a=0, b=1> -> -i |a=1, b=0>, and it equals exp(-i pi/4 (X X + Y Y)) built
+    from the pinned Paulis, the sign the paper prints."""
+    from scipy.linalg import expm
+    h, x = oracle.named_gate("H"), oracle.named_gate("X")
+    y = 1j * x @ (h @ x @ h)
+    u = oracle.named_gate("ISWAP")
+    assert np.allclose(u, expm(-0.25j * math.pi * (np.kron(x, x) + np.kron(y, y))), atol=1e-14)
+    n, a, b = 3, 2, 0
+    psi = np.zeros(1 << n, dtype=complex)
+    psi[1 << b] = 1  # qubit a = 0, qubit b = 1
+    oracle.apply(psi, (a, b), (), u)
+    want = np.zeros(1 << n, dtype=complex)
+    want[1 << a] = -1j
+    assert np.allclose(psi, want, atol=1e-15)
+    # |00> and |11> are unchanged
+    for x0 in (0, (1 << a) | (1 << b)):
+        psi = np.zeros(1 << n, dtype=complex)
+        psi[x0] = 1
+        oracle.apply(psi, (a, b), (), u)
+        assert psi[x0] == 1 and np.count_nonzero(psi) == 1
+
+
 def test_named_gates_are_unitary():
     for name, params in [("H", ()), ("X", ()), ("Y", ()), ("Z", ()), ("S", ()), ("T", ()),
                          ("RX", (0.3,)), ("RY", (1.1,)), ("RZ", (-2.0,)),
