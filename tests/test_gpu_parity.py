@@ -273,40 +273,100 @@ def test_rqc30_depth40_c128_full_size_properties(qs):
     s.close()
 
 
+def _product_circuit(half_a, half_b, nh):
+    """Two independent nh-qubit circuits placed on the even and the odd qubits
+    of a 2*nh-qubit register, interleaved gate by gate."""
+    def remap(ops, f):
+        return [cg.Gate(tuple(f(q) for q in o.targets), tuple(f(q) for q in o.controls),
+                        o.matrix, o.name) for o in ops]
+
+    ev = remap(half_a, lambda q: 2 * q)
+    od = remap(half_b, lambda q: 2 * q + 1)
+    return [g for pair in zip(ev, od) for g in pair] + ev[len(od):] + od[len(ev):]
+
+
+def _product_expected(half_a, half_b, nh, idx):
+    """Each amplitude of the product state is a_even(bits 0,2,4..) times
+    a_odd(bits 1,3,5..), both from the oracle on nh qubits."""
+    a_ev, _ = oracle.run(nh, half_a)
+    a_od, _ = oracle.run(nh, half_b)
+    ev_idx = np.zeros(idx.size, dtype=np.int64)
+    od_idx = np.zeros(idx.size, dtype=np.int64)
+    for b in range(nh):
+        ev_idx |= ((idx >> np.uint64(2 * b)) & np.uint64(1)).astype(np.int64) << b
+        od_idx |= ((idx >> np.uint64(2 * b + 1)) & np.uint64(1)).astype(np.int64) << b
+    return a_ev[ev_idx] * a_od[od_idx]
+
+
+def _sample_indices(n, count, seed, forced):
+    rng = np.random.default_rng(seed)
+    idx = rng.choice(1 << n, count, replace=False).astype(np.uint64)
+    idx[: len(forced)] = np.array(forced, dtype=np.uint64)
+    return idx
+
+
+def _check_c64_sample(got, want):
+    """complex64 bar on a sample: infidelity of the sampled sub-vector
+    <= 1e-5 (the bound on the whole state) and every error small against
+    the sample's RMS amplitude."""
+    assert infidelity(want, got) <= 1e-5
+    rms = math.sqrt(float(np.mean(np.abs(want) ** 2)))
+    assert np.max(np.abs(got - want)) <= 1e-2 * rms
+
+
 def test_rqc30_product_circuit_sampled_amplitudes(qs):
     """A 30-qubit circuit made of two independent 15-qubit random circuits on
     the even and the odd qubits: each amplitude is the product of two oracle
     amplitudes, so 2^16 sampled outputs of the full-size launch are checked."""
     half = cg.random_circuit(5, 3, 12, seed=909, cu3_prob=0.1)
     half2 = cg.random_circuit(3, 5, 12, seed=910, cu3_prob=0.1)
-
-    def remap(ops, f):
-        out = []
-        for o in ops:
-            out.append(cg.Gate(tuple(f(q) for q in o.targets), tuple(f(q) for q in o.controls),
-                               o.matrix, o.name))
-        return out
-
-    ev = remap(half, lambda q: 2 * q)
-    od = remap(half2, lambda q: 2 * q + 1)
-    ops = [g for pair in zip(ev, od) for g in pair]
-    a_ev, _ = oracle.run(15, half)
-    a_od, _ = oracle.run(15, half2)
-    rng = np.random.default_rng(1)
-    idx = rng.choice(1 << 30, 1 << 16, replace=False).astype(np.uint64)
-    idx[:4] = [0, 1, (1 << 30) - 1, 1 << 29]
-    ev_idx = np.zeros(idx.size, dtype=np.int64)
-    od_idx = np.zeros(idx.size, dtype=np.int64)
-    for b in range(15):
-        ev_idx |= ((idx >> np.uint64(2 * b)) & np.uint64(1)).astype(np.int64) << b
-        od_idx |= ((idx >> np.uint64(2 * b + 1)) & np.uint64(1)).astype(np.int64) << b
-    want = a_ev[ev_idx] * a_od[od_idx]
+    ops = _product_circuit(half, half2, 15)
+    idx = _sample_indices(30, 1 << 16, 1, [0, 1, (1 << 30) - 1, 1 << 29])
+    want = _product_expected(half, half2, 15, idx)
     for dt, plan, kmax, tol in [(qs.C128, 0, 0, TOL128), (qs.C64, 1, 5, 2e-6), (qs.C128, 1, 3, TOL128)]:
         s = qs.State(30, dt)
         s.run(qs.Circuit(ops), plan=plan, k_max=kmax)
         got = s.amplitudes(idx)
         assert np.max(np.abs(got - want)) <= tol
         s.close()
+
+
+@pytest.mark.parametrize("nh,grid", [(16, (4, 4)), (17, (17, 1))])
+def test_product_circuit_above_30_qubits_sampled_amplitudes(qs, nh, grid):
+    """32 and 34 qubits (states of 32 and 128 GiB as complex64) through the
+    tile path in the benchmark's launch configuration (13-qubit tiles, 4-qubit
+    blocks, greedy plan): at 34 qubits there are 2^21 tiles, more than the
+    launch grid, so each workgroup walks several tiles; indices at and above
+    2^32 are forced into the 2^16-index sample.  The expected values are
+    products of two oracle amplitudes on nh qubits.  At 32 qubits the plain
+    complex128 path is checked as well (64 GiB)."""
+    n = 2 * nh
+    half = cg.random_circuit(grid[0], grid[1], 12, seed=950 + nh, cu3_prob=0.1)
+    half2 = cg.random_circuit(grid[0], grid[1], 12, seed=970 + nh, cu3_prob=0.1)
+    ops = _product_circuit(half, half2, nh)
+    top = (1 << n) - 1
+    forced = [0, 1, top, 1 << 31, (1 << 32) - 1, 1 << 32, (1 << 32) + 1, top ^ (1 << 32),
+              (1 << (n - 1)) | 5, top >> 1, top ^ (1 << 31)]
+    forced = sorted(set(f for f in forced if f <= top))
+    idx = _sample_indices(n, 1 << 16, 3 + nh, forced)
+    want = _product_expected(half, half2, nh, idx)
+    print("[product] n=%d c64 greedy tile_qubits=13 k_max=4" % n, flush=True)
+    s = qs.State(n, qs.C64)
+    c = qs.Circuit(ops)
+    info = c.plan_info(n, qs.C64, qs.PLAN_GREEDY, k_max=4, tile_qubits=13)
+    assert info["sweeps"] > 1
+    s.run(c, plan=qs.PLAN_GREEDY, k_max=4, tile_qubits=13)
+    got = s.amplitudes(idx)
+    assert abs(s.norm() - 1) < 1e-5
+    s.close()
+    _check_c64_sample(got, want)
+    if n == 32:
+        print("[product] n=32 c128 unfused", flush=True)
+        s = qs.State(n, qs.C128)
+        s.run(c, plan=qs.PLAN_UNFUSED)
+        got = s.amplitudes(idx)
+        s.close()
+        assert np.max(np.abs(got - want)) <= TOL128
 
 
 # ------------------------------------------------------------ tile sweeps --
