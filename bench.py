@@ -95,16 +95,24 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_for(path_name: str, kernel_class: str):
+def traffic_key(workload: str, n: int, path_name: str, kernel_class: str) -> str:
+    return "%s/n%d/%s/%s" % (workload, n, path_name, kernel_class)
+
+
+def traffic_for(workload: str, n: int, path_name: str, kernel_class: str, plan: str = "greedy"):
     """HBM bytes per launch measured by rocprofv3 counters for this kernel class
-    on this path, if the counters were taken on the current kernel sources."""
+    on this path of this workload, if the counters were taken on the current
+    kernel sources (and, for fused paths, under the same plan); None when no
+    reading matches exactly."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         data = json.load(f)
-    rec = data.get("%s/%s" % (path_name, kernel_class))
+    rec = data.get(traffic_key(workload, n, path_name, kernel_class))
     if not rec or rec.get("source_hash") != source_hash():
+        return None
+    if path_name.startswith("fused") and rec.get("plan", "greedy") != plan:
         return None
     return rec.get("bytes_per_launch")
 
@@ -291,7 +299,7 @@ def summarize_profiles(d):
             c[3] += b * nf
             lines.append("| %s | %s | %d | %.0f | %.0f | %.4g | | |" % (path, short_kernel(k), nf, vf, vw, b))
         for cls, (cnt, tf, tw, tb) in sorted(by_class.items()):
-            rec = {"source_hash": src, "dispatches": cnt, "fetch_kib_per_launch": tf / cnt,
+            rec = {"source_hash": src, "plan": "greedy", "dispatches": cnt, "fetch_kib_per_launch": tf / cnt,
                    "write_kib_per_launch": tw / cnt, "bytes_per_launch": tb / cnt,
                    "commands": [cmds["pmc_fetch_%s" % path], cmds["pmc_write_%s" % path]]}
             ab = None
@@ -299,7 +307,7 @@ def summarize_profiles(d):
                 ab = alg["roofline"]["alg_bytes_per_launch"]
                 rec["alg_bytes_per_launch"] = ab
                 rec["ratio_to_algorithmic"] = rec["bytes_per_launch"] / ab
-            traffic["%s/%s" % (path, cls)] = rec
+            traffic[traffic_key("rqc30_d40", 30, path, cls)] = rec
             lines.append("| %s | **class %s** | %d | %.0f | %.0f | %.4g | %s | %s |"
                          % (path, cls, cnt, tf / cnt, tw / cnt, tb / cnt,
                             "%.4g" % ab if ab else "", "%.3f" % (tb / cnt / ab) if ab else ""))
@@ -357,7 +365,8 @@ def summarize_profiles(d):
     print("wrote profiles/traffic.json, profiles/hbm_traffic_rqc30_d40.md, profiles/kernel_stats_rqc30_d40.md")
 
 
-def run_path(qs, torch, cg, name, n, circuit, gates, steps, warmup, kmax, plan, tile_qubits=0):
+def run_path(qs, torch, cg, name, n, circuit, gates, steps, warmup, kmax, plan, tile_qubits=0,
+             workload="rqc30_d40"):
     dt = qs.C64 if name.endswith("c64") else qs.C128
     fused = name.startswith("fused")
     tdt = torch.complex64 if dt == qs.C64 else torch.complex128
@@ -418,7 +427,7 @@ def run_path(qs, torch, cg, name, n, circuit, gates, steps, warmup, kmax, plan, 
                      "frac": achieved / HBM_PEAK_GBPS,
                      "alg_bytes_per_launch": d["bytes"] / d["launches"],
                      "avg_launch_ms": d["ms"] / d["launches"],
-                     "traffic": traffic_for(name, dom)},
+                     "traffic": traffic_for(workload, n, name, dom, plan)},
     }
     if dom == "tile" and d["flops"]:
         # the same launches seen from the matrix cores: the fused blocks'
@@ -737,7 +746,7 @@ def main():
     copy_gbps, copy_detail = copy_ceiling(torch)
     for p in paths:
         res, st, buf, stream = run_path(qs, torch, cg, p, n, circuit, gates, args.steps, args.warmup,
-                                        args.kmax, args.plan, args.tile_qubits)
+                                        args.kmax, args.plan, args.tile_qubits, args.workload)
         out[p] = res
         states[p] = (st, buf)
         if p == "plain_c128" and not args.no_by_target:
