@@ -63,6 +63,8 @@ def parse():
                    help="bandwidth of the qubit-remap pack / unpack on a 30-qubit shard (one JSON line)")
     p.add_argument("--partial", action="store_true",
                    help="partial-amplitude mode on a 40-qubit depth-8 circuit (one JSON line)")
+    p.add_argument("--single", action="store_true",
+                   help="single-amplitude mode on a 60-qubit depth-14 circuit (one JSON line)")
     p.add_argument("--config5", action="store_true",
                    help="34-qubit learned-planner comparison: complex128 reference on 2^20 sampled "
                         "indices, then complex64 learned vs greedy vs unfused")
@@ -571,24 +573,101 @@ def partial_bench(qs, cg, rows=8, cols=5, depth=8, top_rows=4, m=1 << 20, seed=6
     return rec
 
 
-def trajectory_bench(qs, cg, count, seed=4001):
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 (vector and matrix alike)
+
+
+def single_bench(qs, cg, rows=6, cols=10, depth=14, words=8, seed=6201, emit=True):
+    """Single-amplitude mode (qs_single_amplitudes) on a circuit far wider than
+    any state vector: a 6 x 10 grid (60 qubits) at depth 14, `words` random
+    bitstrings per call.  Wall time of the whole call (graph construction,
+    elimination order, placement and contraction of every bitstring on the
+    device); the merges' algorithmic FP64 flops (8 per complex
+    multiply-add) over that time, against the FP64 peak."""
+    import numpy as np
+    n = rows * cols
+    ops = cg.random_circuit(rows, cols, depth, seed=seed)
+    c = qs.Circuit(ops)
+    bits = np.random.default_rng(seed + 1).integers(0, 1 << n, size=words, dtype=np.uint64)
+    plan = c.single_plan(n)
+    c.single_amplitudes(n, bits[:1])  # warm-up (first launches of the kernels)
+    t0 = time.perf_counter()
+    amps, info = c.single_amplitudes(n, bits)
+    sec = time.perf_counter() - t0
+    tf = plan["flops"] * words / sec / 1e12
+    rec = {"metric": "single-amplitude mode: amplitudes per second", "unit": "amplitudes/s",
+           "value": round(words / sec, 2),
+           "workload": "%dx%d grid random circuit, %d qubits, depth %d, %d gates" % (rows, cols, n, depth,
+                                                                                   cg.count_gates(ops)),
+           "bitstrings": words, "seconds": round(sec, 4), "vertices": plan["vertices"], "merges": plan["merges"],
+           "max_rank": plan["max_rank"], "flops_per_amplitude": plan["flops"],
+           "peak_bytes_per_bitstring": plan["peak_bytes"], "batch": info["batch"],
+           "roofline": {"bound": "fp64", "achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": tf / FP64_PEAK_TFLOPS},
+           "mean_prob_times_2n": float(np.mean(np.abs(amps) ** 2) * 2.0 ** n)}
+    log("single-amplitude: %d qubits depth %d, %d amplitudes in %.3f s (%.1f /s), %.2f TFLOP/s FP64, "
+        "max rank %d" % (n, depth, words, sec, words / sec, tf, plan["max_rank"]))
+    if emit:
+        print(json.dumps(rec))
+    return rec
+
+
+def trajectory_bench(qs, cg, count, seed=4001, reps=3):
     """Batched noisy trajectories: widths n ~ U{14..22}, depth 24, depolarizing
     1e-3 / 1e-2 (two-qubit, Kronecker form) and amplitude damping 5e-4 per
-    layer, complex64 states, one batch."""
+    layer, complex64 states, one batch per call.  The autotuner's calls (one
+    per candidate width set) run first as warm-up; the timed calls use the
+    fastest.  Also: the mean <Z_q> of 4096 trajectories of the 10-qubit
+    depth-24 circuit at the same rates against the exact density-matrix
+    values (tests/golden/dm_n10_d24_workload_rates.txt, written by the
+    oracle)."""
+    import numpy as np
     t0 = time.perf_counter()
     batch = cg.trajectory_batch(count, seed=seed)
     circs = [qs.Circuit(ops) for _, ops in batch]
     widths = [n for n, _ in batch]
     gen = time.perf_counter() - t0
-    qs.run_trajectories(circs[:8], widths[:8], dtype=qs.C64, seed=seed)  # warm-up
-    z, sec = qs.run_trajectories(circs, widths, dtype=qs.C64, seed=seed)
+    tuning = []
+    for _ in range(16):
+        _, info = qs.run_trajectories(circs, widths, dtype=qs.C64, seed=seed, plan=qs.PLAN_AUTOTUNE)
+        tuning.append({"tile_qubits": info["tile_qubits"], "k_max": info["k_max"], "max_outer": info["max_outer"],
+                       "seconds": round(info["seconds"], 4)})
+        if info["autotune_tried"] >= info["autotune_candidates"]:
+            break
+    runs = []
+    for _ in range(reps):
+        _, info = qs.run_trajectories(circs, widths, dtype=qs.C64, seed=seed, plan=qs.PLAN_AUTOTUNE)
+        runs.append(info)
+    best = min(runs, key=lambda r: r["seconds"])
+    _, direct = qs.run_trajectories(circs, widths, dtype=qs.C64, seed=seed, plan=qs.PLAN_AUTOTUNE,
+                                    direct_launch=True)
     sites = sum(sum(1 for o in ops if o.kind == "noise") for _, ops in batch)
     gates = sum(cg.count_gates(ops) for _, ops in batch)
-    res = {"count": count, "seconds": sec, "traj_per_s": count / sec,
+    res = {"count": count, "seconds": best["seconds"], "traj_per_s": count / best["seconds"],
            "widths": [min(widths), max(widths)], "mean_width": sum(widths) / count,
            "logical_gates": gates, "noise_sites": sites, "generation_s": gen,
-           "dtype": "c64 state, FP64 branch weights"}
-    log("trajectories: %d in %.3f s -> %.1f traj/s" % (count, sec, count / sec))
+           "dtype": "c64 state, FP64 run sums and branch weights, Kraus branches drawn on the device",
+           "passes": best["passes"], "jumps": best["jumps"], "launches": best["launches"],
+           "graph": bool(best["graph"]), "host_s": best["host_seconds"], "device_s": best["device_seconds"],
+           "widths_chosen": {"tile_qubits": best["tile_qubits"], "k_max": best["k_max"],
+                             "max_outer": best["max_outer"]},
+           "autotune_calls": tuning, "direct_launch_s": direct["seconds"]}
+    log("trajectories: %d in %.3f s -> %.1f traj/s (%d passes, %d jumps, device %.3f s, host %.3f s; "
+        "widths %s; direct launches %.3f s)" % (count, best["seconds"], count / best["seconds"], best["passes"],
+                                               best["jumps"], best["device_seconds"], best["host_seconds"],
+                                               res["widths_chosen"], direct["seconds"]))
+    # accuracy of the trajectory mean at n = 10 (BASELINE config 4's check)
+    n, T = 10, 4096
+    ops = cg.random_circuit(2, 5, 24, seed=4010, dep1=1e-3, dep2=1e-2, damping=5e-4)
+    zdm = np.loadtxt(os.path.join(ROOT, "tests", "golden", "dm_n10_d24_workload_rates.txt"))
+    z, _ = qs.run_trajectories([qs.Circuit(ops)] * T, [n] * T, dtype=qs.C64, seed=78)
+    zs = z.reshape(T, n)
+    dev = np.abs(zs.mean(axis=0) - zdm)
+    se = zs.std(axis=0) / math.sqrt(T)
+    res["dm_check_n10"] = {"trajectories": T, "max_abs_dev_mean_z": float(dev.max()),
+                           "max_dev_in_std_errors": float((dev / np.maximum(se, 1e-12)).max()),
+                           "reference": "exact density matrix (FP64 oracle), tests/golden/dm_n10_d24_workload_rates.txt"}
+    log("trajectory mean at n=10: max |<Z> - rho| = %.2e (%.2f standard errors)"
+        % (dev.max(), res["dm_check_n10"]["max_dev_in_std_errors"]))
     return res
 
 
@@ -672,27 +751,57 @@ def config5(qs, cg, torch):
     print(json.dumps({"config5": out}), flush=True)
 
 
-def cpu_baseline(cg, n, ops, seconds):
-    """The FP64 oracle on the host, on the first gates of the same circuit
-    applied to the full 2^n state, for about `seconds` of gate work."""
-    import numpy as np
+def _host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
+
+def cpu_baseline(cg, n, ops, seconds, seconds_1t=12.0):
+    """The FP64 oracle on the host, as it stands, on the full 2^n complex128
+    state: a sample of the circuit's own gates taken evenly over the whole
+    circuit (bit-reversed order of the gate index, so any prefix mixes
+    one-qubit gates, CU3 and CZ in about their proportions), applied for
+    about `seconds` with every host thread and for about `seconds_1t` with
+    one.  Gates/s of each; state initialisation excluded."""
     import oracle
-    psi = oracle.zero_state(n)
     gl = [o for o in ops if o.kind == "gate"]
-    t0 = time.perf_counter()
-    done = 0
-    while done < len(gl) and (time.perf_counter() - t0 < seconds or done < 2):
-        g = gl[done]
-        oracle.apply(psi, g.targets, g.controls, g.matrix)
-        done += 1
-    el = time.perf_counter() - t0
+    bits = max(1, (len(gl) - 1).bit_length())
+    order = sorted(range(len(gl)), key=lambda i: int(format(i, "0%db" % bits)[::-1], 2))
+    full = oracle.num_threads()
+    psi = oracle.zero_state(n)
+
+    def timed(budget, threads, start):
+        oracle.set_threads(threads)
+        t0 = time.perf_counter()
+        done = 0
+        kinds = {}
+        while start + done < len(order) and (time.perf_counter() - t0 < budget or done < 2):
+            g = gl[order[start + done]]
+            oracle.apply(psi, g.targets, g.controls, g.matrix)
+            kinds[g.name] = kinds.get(g.name, 0) + 1
+            done += 1
+        return done / (time.perf_counter() - t0), done, kinds
+
+    rate, done, kinds = timed(seconds, full, 0)
+    rate1, done1, _ = timed(seconds_1t, 1, done)
+    oracle.set_threads(full)
     del psi
-    return {"value": done / el, "unit": "gates/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": "first %d gates of the %d-qubit circuit on the full 2^%d complex128 state "
-                      "(FP64, OpenMP over the amplitude loop), %.1f s; state initialisation "
-                      "excluded" % (done, n, n, el)}
+    mix = {"cz": kinds.get("cz", 0), "cu3": kinds.get("cu3", 0),
+           "one_qubit": sum(v for k, v in kinds.items() if k not in ("cz", "cu3"))}
+    circ = {"cz": sum(1 for g in gl if g.name == "cz"), "cu3": sum(1 for g in gl if g.name == "cu3")}
+    circ["one_qubit"] = len(gl) - circ["cz"] - circ["cu3"]
+    return {"value": rate, "unit": "gates/s", "cores": full, "kind": "oracle",
+            "value_1_thread": rate1, "cpu_model": _host_cpu_model(),
+            "sample": "%d gates of the %d-qubit circuit spread over all of it (one-qubit %d, CU3 %d, CZ %d; "
+                      "circuit: %d / %d / %d) on the full 2^%d complex128 state, FP64, %d threads; then %d more "
+                      "gates on 1 thread" % (done, n, mix["one_qubit"], mix["cu3"], mix["cz"], circ["one_qubit"],
+                                             circ["cu3"], circ["cz"], n, full, done1)}
 
 
 def main():
@@ -732,6 +841,9 @@ def main():
     if args.partial:
         partial_bench(qs, cg)
         return
+    if args.single:
+        single_bench(qs, cg)
+        return
     if args.plan == "learned":
         p, _ = train_cost_model(qs, cg, log_fn=log)
         qs.cost_model_set(p)
@@ -751,6 +863,33 @@ def main():
         states[p] = (st, buf)
         if p == "plain_c128" and not args.no_by_target:
             sweep_state = (st, stream)
+    learned = None
+    if "fused_c64" in out and args.plan == "greedy" and not args.no_extras:
+        # the learned planner on the same circuit (spec comparison):
+        # the cost network trained on the simulator's own sweep timings
+        t0 = time.perf_counter()
+        p, nsamp = train_cost_model(qs, cg, log_fn=log)
+        train_s = time.perf_counter() - t0
+        qs.cost_model_set(p)
+        try:
+            res_l, st_l, _, _ = run_path(qs, torch, cg, "fused_c64", n, circuit, gates, args.steps, args.warmup,
+                                         args.kmax, "learned", args.tile_qubits, args.workload)
+            st_l.close()
+            info_l = circuit.plan_info(n, qs.C64, qs.PLAN_LEARNED, k_max=args.kmax, tile_qubits=args.tile_qubits)
+        finally:
+            qs.cost_model_set(None)
+        info_g = circuit.plan_info(n, qs.C64, qs.PLAN_GREEDY, k_max=args.kmax, tile_qubits=args.tile_qubits)
+        learned = {"gates_per_s": res_l["gates_per_s"], "ms_per_step": res_l["ms_per_step"],
+                   "sweeps": info_l["sweeps"], "blocks": info_l["blocks"],
+                   "greedy_sweeps": info_g["sweeps"], "greedy_blocks": info_g["blocks"],
+                   "same_plan_as_greedy": info_l == info_g,
+                   "learned_over_greedy": res_l["gates_per_s"] / out["fused_c64"]["gates_per_s"],
+                   "training_samples": nsamp, "training_s": train_s}
+        if "plain_c128" in out:
+            learned["learned_over_plain_c128"] = res_l["gates_per_s"] / out["plain_c128"]["gates_per_s"]
+        log("learned plan: %.1f gates/s (%d sweeps, %d blocks; greedy %d / %d), learned/greedy %.3f"
+            % (res_l["gates_per_s"], info_l["sweeps"], info_l["blocks"], info_g["sweeps"], info_g["blocks"],
+               learned["learned_over_greedy"]))
     acc = None
     if "fused_c64" in states and "plain_c128" in states:
         rng = np.random.default_rng(12345)
@@ -776,6 +915,7 @@ def main():
     extras = {}
     if not args.no_extras:
         for key, fn in (("partial_mode", lambda: partial_bench(qs, cg, emit=False)),
+                        ("single_amplitude_mode", lambda: single_bench(qs, cg, emit=False)),
                         ("remap", lambda: remap_bench(qs, torch, emit=False))):
             try:
                 extras[key] = fn()
@@ -800,14 +940,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if primary.endswith("c64") else "f64",
+        "dtype": "f32+bf16x3" if primary.endswith("c64") else "f64",
         "data": "synthetic",
         "config": {"workload": "%s: %d-qubit random circuit, depth %d, %d logical gates"
                                % (args.workload, n, cg.WORKLOADS[args.workload][2], gates),
-                   "path": primary, "plan": args.plan, "k_max": args.kmax,
-                   "tile_qubits": args.tile_qubits,
-                   "state": "complex64 (FP32), FP64 reductions" if primary.endswith("c64")
-                   else "complex128 (FP64)"},
+                   "path": primary, "plan": args.plan,
+                   "k_max": (args.kmax or 4) if primary.endswith("c64") else (args.kmax or 0),
+                   "tile_qubits": (args.tile_qubits or min(13, n)) if primary.endswith("c64") else 0,
+                   "arithmetic": "complex64 state (FP32); fused blocks on the matrix cores as split-bf16 "
+                                 "products (hi*hi + hi*lo + lo*hi, about 16 significant bits per block) with "
+                                 "FP32 accumulation; FP64 norm and probability reductions"
+                   if primary.endswith("c64") else "complex128 (FP64) per-gate kernels"},
         "roofline": prim["roofline"],
         "hbm_frac_path": prim["hbm_frac_path"],
         "copy_GBps": copy_gbps,
@@ -816,6 +959,7 @@ def main():
         "single_gates_c128": by_target,
         "accuracy": acc,
         "trajectories": traj,
+        "learned_plan": learned,
         "cpu_baseline": cpu,
     }
     line.update(extras)

@@ -181,6 +181,8 @@ typedef struct {
                          * events (those runs synchronise the stream at their end), and later
                          * runs use each sweep's fastest; 1..QS_TILE_ORDERS = that candidate
                          * for every sweep.  Results do not depend on the order. */
+    int direct_launch;  /* qs_run_trajectories: 0 = each device-sampled pass runs as one captured
+                         * HIP graph; 1 = the same launches enqueued one by one */
 } qs_run_opts;
 
 /* Candidate tile orders of a sweep (qs_run_opts.tile_order). */
@@ -203,10 +205,12 @@ qs_status qs_circuit_plan_info(const qs_circuit *c, int n, qs_dtype dt, const qs
  * tile of 2^tile_qubits amplitudes in LDS receives a run of fused 4- and
  * 5-qubit blocks on the matrix cores, with split-bfloat16 operands and FP32
  * accumulation, keeping about 16 significant bits per block); on complex128
- * states as one FP64 sweep per fused block.  Synchronises only when the circuit has noise
- * sites.  Errors: QS_E_INVAL (unbalanced groups, k_max), QS_E_RANGE (a qubit
- * >= n), QS_E_UNSUPPORTED (noise inside a group, or a fused plan with noise
- * sites). */
+ * states as one FP64 sweep per fused block.  Noise sites split the circuit
+ * into segments: the gates between two sites are planned and fused as one
+ * segment, and each site is sampled on the state that the segments before it
+ * left (Sec. 2.4).  Synchronises only when the circuit has noise sites.
+ * Errors: QS_E_INVAL (unbalanced groups, k_max), QS_E_RANGE (a qubit >= n),
+ * QS_E_UNSUPPORTED (noise inside a group). */
 qs_status qs_run_circuit(qs_state *s, const qs_circuit *c, const qs_run_opts *opts);
 
 /* Autotuning (QS_PLAN_AUTOTUNE).  The candidates are the fused plans of the
@@ -246,16 +250,63 @@ qs_status qs_expect_z(const qs_state *s, double *out);
 
 /* ----------------------------------------------------- noisy trajectories -- */
 
-/* Run `count` independent noisy trajectories: trajectory t evolves a state of
- * widths[t] qubits from |0...0> under circs[t] with Philox trajectory index t
- * and key `seed` (noise sites drawn as in qs_run_circuit), then writes its
- * <Z_q> for q < widths[t] to z_out at offset sum_{t' < t} widths[t'].
- * States of all trajectories are batched on the device.  *seconds (may be
- * NULL) receives the wall time of the whole call after argument checks:
- * preparation of every trajectory, device allocation, all launches and the
- * final reductions.  Errors as qs_run_circuit. */
+/* Run `count` independent noisy trajectories (Sec. 2.4): trajectory t
+ * evolves a state of widths[t] qubits (1..36) from |0...0> under circs[t]
+ * with Philox trajectory index t and key `seed` (noise sites drawn as in
+ * qs_run_circuit), then writes its <Z_q> for q < widths[t] to z_out at
+ * offset sum_{t' < t} widths[t'].  Noise sites must have state-independent
+ * branch weights (every K_b^dagger K_b a multiple of I: flips,
+ * depolarizing; drawn on the host before any launch) or be damping-type
+ * one-qubit channels (K1 = diag(1, k), K2 nonzero only in column 1:
+ * amplitude and phase damping), whose weights come from FP64 prefix sums
+ * of the state.  All states live in one device allocation.
+ * Complex64 states of at least 10 qubits run in device-sampled passes: all
+ * remaining steps of all trajectories are planned as tile sweeps, uploaded
+ * once and executed as one captured HIP graph (opts->direct_launch = 0) of
+ * batched sweeps, batched FP64 run sums and a sampling kernel that draws
+ * each damping site's uniform on the device and picks its branch.  A
+ * trajectory whose site takes K2 stops there for the pass; the host
+ * rewrites its remaining steps (K1 of the earlier sites of the run, K2,
+ * renormalisation, the rest of the run) and runs such trajectories in the
+ * next pass.  Complex128 states, narrower states and plans with gates too
+ * wide for a tile take the host-sampled path (one batched step at a time,
+ * sums read back and sampled on the host); so does every state with
+ * opts->plan = QS_PLAN_UNFUSED.  opts (may be NULL): plan QS_PLAN_GREEDY
+ * (default widths: 13-qubit tiles, 4-qubit blocks, 2 outer selector bits per
+ * op) or QS_PLAN_AUTOTUNE (each of the first calls for a batch of the same
+ * dtype, size and widths runs the next untried candidate width set and
+ * times the whole call; later calls use the fastest: qs_trajectory_stats
+ * reports the choice), k_max (4 or 5; 0 = default), tile_qubits (10..13;
+ * 0 = default), direct_launch.  The branch choices do not depend on any of
+ * these.  *traj_per_s (may be NULL) receives count / the wall time of the
+ * whole call after argument checks: preparation of every trajectory,
+ * planning, device allocation, uploads, all launches and the final
+ * reductions.  Synchronous.  Errors: QS_E_INVAL (arguments, widths),
+ * QS_E_RANGE (a qubit >= the trajectory's width), QS_E_UNSUPPORTED (noise
+ * inside a group, or a channel of another form), QS_E_ZERO_NORM,
+ * QS_E_NOMEM, QS_E_DEVICE. */
 qs_status qs_run_trajectories(const qs_circuit *const *circs, const int *widths, int count,
-                              qs_dtype dt, uint64_t seed, double *z_out, double *seconds);
+                              qs_dtype dt, uint64_t seed, const qs_run_opts *opts, double *z_out,
+                              double *traj_per_s);
+
+/* Statistics of the last qs_run_trajectories call on the calling thread. */
+typedef struct {
+    int passes;             /* device-sampled passes (each one HIP graph or one set of launches) */
+    int host_sampled;       /* trajectories that took the host-sampled path */
+    int64_t jumps;          /* K2 branches taken */
+    int64_t launches;       /* kernel launches enqueued (inside graphs included) */
+    int graph;              /* 1 when the passes ran as captured HIP graphs */
+    int tile_qubits;        /* widths used: qubits per tile (at most the state's width), */
+    int k_max;              /*   widest fused block, */
+    int max_outer;          /*   outer selector bits per tile op */
+    int autotune_tried;     /* QS_PLAN_AUTOTUNE: candidates measured so far for this batch shape */
+    int autotune_candidates;
+    double seconds;         /* wall time of the call */
+    double host_seconds;    /* of which: planning, program build and upload of the passes (host) */
+    double device_seconds;  /* device time of the passes (HIP events around each) */
+} qs_traj_stats;
+
+qs_status qs_trajectory_stats(qs_traj_stats *out);
 
 /* ------------------------------------------------------- sharded states -- */
 
@@ -332,6 +383,56 @@ qs_status qs_partial_amplitudes(const qs_circuit *c, int n, qs_dtype dt, uint64_
 /* The number of cuts qs_partial_amplitudes makes for this circuit and
  * division (host only, no device work); errors as qs_partial_amplitudes. */
 qs_status qs_partial_cuts(const qs_circuit *c, int n, uint64_t part_a, int *cuts);
+
+/* ------------------------------------------------- single-amplitude mode -- */
+
+#define QS_SINGLE_MAX_SLICES 16
+
+/* Shape of a single-amplitude contraction (Sec. 2.3). */
+typedef struct {
+    int vertices;       /* Boolean variables of the graphical model (Fig. 2): one per qubit at the
+                         * start and one per target of every gate that is not diagonal */
+    int tensors;        /* edges: one per non-identity gate, plus a vector of ones for every vertex
+                         * that ends up on a single edge */
+    int fixed;          /* vertices fixed: initial state, measured bits, slices */
+    int sliced;         /* vertices fixed by slicing: 2^sliced graphs per amplitude */
+    int merges;         /* pairwise tensor merges (one device launch each) */
+    int max_rank;       /* indices of the largest merged tensor */
+    double flops;       /* real FP64 flops of the merges for one amplitude (all slices) */
+    double peak_bytes;  /* device arena of the tensors (qs_single_plan: one bitstring) */
+    int batch;          /* graphs contracted side by side per launch (bitstrings x slices) */
+} qs_single_info;
+
+/* Single-amplitude mode (Sec. 2.3, Figs. 2-3): amplitudes <x|C|0...0> of an
+ * n-qubit unitary circuit (1 <= n <= 62), never holding a 2^n state.  The
+ * circuit is mapped to an undirected graphical model: a vertex per Boolean
+ * variable, an edge (tensor) per gate; a diagonal gate keeps its qubits'
+ * vertices, any other gate gives each target a new vertex (controls are kept),
+ * and a gate's tensor over (new target vertices, old target vertices,
+ * controls) holds U[new, old] where every control is 1 and delta(new, old)
+ * elsewhere.  Each qubit's first vertex is fixed to 0 and its last to bit q
+ * of x; the nslice free vertices on the most edges are fixed to every
+ * combination of values, giving 2^nslice graphs (differential elimination).
+ * All other vertices are eliminated one by one, the next chosen as the one
+ * whose merged tensor is smallest: the tensors on it are merged in order of
+ * rank and the vertex summed out with the last merge (integral
+ * elimination).  The merges run on the device as batched complex FP64
+ * contractions (all bitstrings of a chunk and all slices side by side); the
+ * product of the remaining scalars, summed over the slices, is the
+ * amplitude.  bits[k] holds x for k < m (bit q = measured value of qubit q);
+ * out[2k], out[2k+1] = the amplitude.  nslice in [0, QS_SINGLE_MAX_SLICES]
+ * does not change the result (up to rounding).  info (may be NULL) receives
+ * the shape.  Bitstrings are processed in chunks whose tensors fit 64 GiB
+ * (and the qs_set_memory_limit bound).  Synchronous.  Errors: QS_E_INVAL
+ * (pointers, n, nslice), QS_E_RANGE (a gate qubit >= n, a bitstring with a
+ * bit >= n), QS_E_UNSUPPORTED (noise sites), QS_E_NOMEM (one bitstring's
+ * tensors do not fit), QS_E_DEVICE. */
+qs_status qs_single_amplitudes(const qs_circuit *c, int n, const uint64_t *bits, size_t m, int nslice,
+                               double *out, qs_single_info *info);
+
+/* The shape qs_single_amplitudes would contract for one bitstring (host only,
+ * no device work); errors as qs_single_amplitudes. */
+qs_status qs_single_plan(const qs_circuit *c, int n, int nslice, qs_single_info *info);
 
 /* --------------------------------------------------------------- scripts -- */
 

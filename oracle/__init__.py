@@ -43,6 +43,7 @@ def lib():
             i, d, u64 = C.c_int, C.c_double, C.c_uint64
             L.or_num_threads.argtypes = []
             L.or_num_threads.restype = i
+            L.or_set_threads.argtypes = [i]
             L.or_init.argtypes = [P, i]
             L.or_norm2.argtypes = [P, i]
             L.or_norm2.restype = d
@@ -80,6 +81,11 @@ def _cmat(m):
 
 def num_threads() -> int:
     return int(lib().or_num_threads())
+
+
+def set_threads(k: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on (timing only)."""
+    lib().or_set_threads(int(k))
 
 
 def zero_state(n: int) -> np.ndarray:

@@ -50,6 +50,12 @@ typedef double complex cplx;
 /* Threads the OpenMP loops of the oracle use. */
 int or_num_threads(void) { return omp_get_max_threads(); }
 
+/* Set that number (k >= 1), for timing the oracle on fewer host threads. */
+void or_set_threads(int k)
+{
+    if (k >= 1) omp_set_num_threads(k);
+}
+
 /* ------------------------------------------------------------------ */
 /* State                                                               */
 /* ------------------------------------------------------------------ */

@@ -67,6 +67,22 @@ qs_status hip_fail(hipError_t e, const char *what)
         if (e_ != hipSuccess) return hip_fail(e_, #expr); \
     } while (0)
 
+// Handlers of the function-try-block around every C ABI entry: no C++
+// exception crosses the ABI (host allocation failures report QS_E_NOMEM).
+#define QS_ABI_CATCH                                                              \
+    catch (const std::bad_alloc &)                                                \
+    {                                                                             \
+        return fail(QS_E_NOMEM, "host allocation failed");                        \
+    }                                                                             \
+    catch (const std::exception &ex_)                                             \
+    {                                                                             \
+        return fail(QS_E_INVAL, "unexpected host exception: %s", ex_.what());     \
+    }                                                                             \
+    catch (...)                                                                   \
+    {                                                                             \
+        return fail(QS_E_INVAL, "unexpected host exception");                     \
+    }
+
 size_t amp_bytes(qs_dtype dt) { return dt == QS_C128 ? 16 : 8; }
 
 struct ProfRec {
@@ -916,10 +932,12 @@ Features sweep_features(const qs::Sweep &sw, int n, qs_dtype dt)
 }
 
 // Tile parameters for a segment.  Without a cost model: the defaults.  With
-// one (QS_PLAN_LEARNED): plan the segment for every candidate (tile qubits 11
-// to 13, block width 4 or 5), predict every sweep's time with the network on
-// the device and keep the cheapest candidate, unless the defaults are
-// predicted within 3% of it.
+// one (QS_PLAN_LEARNED): plan the segment for every candidate shape (tile
+// qubits 11 to 13, block width 4 or 5), each with the whole plans of the
+// tile-qubit search at half and at all of its restarts, predict every
+// sweep's time with the network on the device and keep the cheapest plan,
+// unless the greedy plan (default shape, the plan the fixed estimate
+// prefers) is predicted within 3% of it.
 qs_status choose_tile_params(qs_state *s, const std::vector<qs::FlatOp> &flat, size_t k, size_t e,
                              const qs_run_opts &o, qs::TileParams &best, std::vector<qs::PlanStep> &best_steps)
 {
@@ -933,19 +951,32 @@ qs_status choose_tile_params(qs_state *s, const std::vector<qs::FlatOp> &flat, s
         qs::plan_tiles(flat, k, e, s->n, best, best_steps);
         return QS_OK;
     }
-    std::vector<qs::TileParams> cand;
+    // every shape's whole plans from the restart search (half and all of the
+    // restarts): the network chooses among all of them
+    std::vector<qs::TileParams> shapes;
     for (int m = 11; m <= 13; ++m)
         for (int km = 4; km <= 5; ++km) {
             qs::TileParams tp;
             tp.m = std::min(m, s->n);
             tp.kmax = km;
-            cand.push_back(tp);
+            shapes.push_back(tp);
         }
-    std::vector<std::vector<qs::PlanStep>> plans(cand.size());
+    std::vector<std::vector<std::vector<qs::PlanStep>>> var(shapes.size());
+    parallel_for(shapes.size(), [&](size_t i) { qs::plan_tiles_variants(flat, k, e, s->n, shapes[i], var[i]); });
+    std::vector<qs::TileParams> cand;
+    std::vector<std::vector<qs::PlanStep>> plans;
+    size_t dflt = SIZE_MAX;  // the plan the fixed estimate picks at the default shape
+    for (size_t i = 0; i < shapes.size(); ++i)
+        for (auto &pl : var[i]) {
+            const bool is_default = shapes[i].m == best.m && shapes[i].kmax == best.kmax;
+            if (is_default && (dflt == SIZE_MAX || qs::plan_cost(pl) < qs::plan_cost(plans[dflt])))
+                dflt = plans.size();
+            cand.push_back(shapes[i]);
+            plans.push_back(std::move(pl));
+        }
     std::vector<float> feats;
     std::vector<std::pair<int, int>> owner;  // (candidate, standalone?)
     for (size_t c = 0; c < cand.size(); ++c) {
-        qs::plan_tiles(flat, k, e, s->n, cand[c], plans[c]);
         for (auto &st : plans[c]) {
             qs::Sweep sw = st.sweep ? st.sw : qs::Sweep{};
             if (!st.sweep) {  // a per-gate launch: scored as a sweep with one op
@@ -977,11 +1008,10 @@ qs_status choose_tile_params(qs_state *s, const std::vector<qs::FlatOp> &flat, s
     size_t bi = 0;
     for (size_t c = 1; c < cand.size(); ++c)
         if (cost[c] < cost[bi]) bi = c;
-    // the default shape stands unless another is predicted clearly cheaper:
+    // the greedy plan stands unless another is predicted clearly cheaper:
     // the network's errors on whole plans are a few percent
     constexpr double kMargin = 0.03;
-    for (size_t c = 0; c < cand.size(); ++c)
-        if (cand[c].m == best.m && cand[c].kmax == best.kmax && cost[bi] > (1.0 - kMargin) * cost[c]) bi = c;
+    if (dflt != SIZE_MAX && cost[bi] > (1.0 - kMargin) * cost[dflt]) bi = dflt;
     best = cand[bi];
     best_steps = std::move(plans[bi]);
     return QS_OK;
@@ -1276,37 +1306,51 @@ qs_status create_common(int n, qs_dtype dt, qs_state **out)
 // =============================================================== batches ==
 //
 // Noisy trajectories (Sec. 2.4), many states at once.  Per trajectory the
-// circuit is cut into steps:
+// circuit is cut into steps that alternate GATES, RUN, GATES, ..., GATES:
 //  - GATES: gates, with every noise site whose branch weights do not depend
 //    on the state (all K_b^dagger K_b = c_b I, e.g. depolarizing) already
 //    sampled on the host from its Philox draw and replaced by K_b / sqrt(c_b);
+//    a GATES step that follows a RUN begins with the RUN's K1 factors, the
+//    operators of the path on which no site of the run jumps;
 //  - RUN: consecutive one-qubit sites on distinct qubits whose first Kraus
-//    operator is diag(1, k) (amplitude and phase damping), sampled together
-//    from one FP64 reduction pass (qs_traj.hip).
-// Steps of all trajectories are executed together: one batched tile launch
-// per sweep round (complex64), one batched reduction and one host
-// synchronisation per RUN step for the whole batch.
+//    operator is K1 = diag(1, k) (amplitude and phase damping), sampled
+//    together from the prefix sums of one FP64 reduction pass (qs_traj.hip).
+// Branch weights are ratios of those sums, so the K1 factors are applied
+// without renormalising; a jump (K2) renormalises the state.
+//
+// Complex64 states of at least 10 qubits run in device-sampled passes: every
+// remaining step of every trajectory is planned on the host, uploaded once,
+// and executed as one captured HIP graph of batched tile sweeps, batched run
+// sums and a sampling kernel that draws each site's Philox uniform on the
+// device.  A trajectory whose run takes K2 at some site is frozen there (its
+// later launches exit at once); after the pass the host rewrites its steps
+// from the jump on (K1 of the earlier sites, K2, renormalisation, the rest
+// of the run) and runs the frozen trajectories in the next pass.  Other
+// states (complex128, fewer qubits, gates too wide for a tile) take the
+// host-sampled path: one batched step at a time, run sums read back and
+// sampled on the host.
 
 namespace {
 
 struct RunSite {
     int q;
     uint64_t site;
-    std::vector<double> kraus;  // nk 2x2 matrices
+    std::vector<double> kraus;  // nk 2x2 matrices (K1 first)
     int nk;
     double a;                   // |K1_11|^2
 };
 
 struct TStep {
     bool run = false;
-    std::vector<qs::FlatOp> gates;
-    std::vector<RunSite> sites;
+    std::vector<qs::FlatOp> gates;  // GATES: the first k1_lead are the K1 factors of the RUN before it
+    int k1_lead = 0;
+    std::vector<RunSite> sites;     // RUN
 };
 
 struct TPrep {
     int n = 0;
     std::vector<TStep> steps;
-    std::vector<qs::FlatOp> pending;  // diagonal factors left by the last RUN
+    size_t cur = 0;  // next step to execute
 };
 
 bool scalar_channel(const std::vector<double> &kr, int nk, int nt, std::vector<double> &c)
@@ -1370,6 +1414,7 @@ qs_status prepare_trajectory(const qs_circuit *c, int n, uint64_t seed, uint64_t
     int rc = qs::expand(c->ops, flat, err);
     if (rc) return fail(rc == 2 ? QS_E_UNSUPPORTED : QS_E_INVAL, "%s", err.c_str());
     tp.n = n;
+    tp.cur = 0;
     TStep cur;
     bool since_run_only_identity = false;  // no non-identity gate since the open RUN
     uint64_t site = 0;
@@ -1380,7 +1425,7 @@ qs_status prepare_trajectory(const qs_circuit *c, int n, uint64_t seed, uint64_t
             if (q >= n) return fail(QS_E_RANGE, "qubit %d out of range [0, %d)", q, n);
         if (f.kind == qs::FlatOp::GATE) {
             if (!qs::is_identity(f.m, int(f.targets.size()))) since_run_only_identity = false;
-            cur.gates.push_back(f);
+            cur.gates.push_back(std::move(f));
             continue;
         }
         const int nt = int(f.targets.size());
@@ -1409,6 +1454,7 @@ qs_status prepare_trajectory(const qs_circuit *c, int n, uint64_t seed, uint64_t
                 since_run_only_identity = false;
             }
         } else if (damping_channel(f.m, f.nk, nt, a)) {
+            qs::FlatOp k1 = one_qubit(f.targets[0], f.m.data());
             RunSite rs{f.targets[0], site, f.m, f.nk, a};
             TStep *last = tp.steps.empty() ? nullptr : &tp.steps.back();
             bool join = last && last->run && since_run_only_identity && int(last->sites.size()) < qs::kRunMax;
@@ -1416,7 +1462,7 @@ qs_status prepare_trajectory(const qs_circuit *c, int n, uint64_t seed, uint64_t
                 for (auto &o : last->sites)
                     if (o.q == rs.q) join = false;
             if (join) {
-                cur.gates.clear();  // identity carriers only
+                cur.gates.resize(size_t(cur.k1_lead));  // identity carriers only besides the run's K1 factors
                 last->sites.push_back(std::move(rs));
             } else {
                 tp.steps.push_back(std::move(cur));
@@ -1426,6 +1472,8 @@ qs_status prepare_trajectory(const qs_circuit *c, int n, uint64_t seed, uint64_t
                 r.sites.push_back(std::move(rs));
                 tp.steps.push_back(std::move(r));
             }
+            cur.gates.push_back(std::move(k1));
+            ++cur.k1_lead;
             since_run_only_identity = true;
         } else {
             return fail(QS_E_UNSUPPORTED, "batched trajectories support noise channels with state-independent "
@@ -1435,6 +1483,33 @@ qs_status prepare_trajectory(const qs_circuit *c, int n, uint64_t seed, uint64_t
     }
     tp.steps.push_back(std::move(cur));
     return QS_OK;
+}
+
+// Site j of the RUN step r took K2 with branch weight nrm2 (the squared norm
+// after K1 on sites 0..j-1 and K2 on site j): step r becomes the GATES step
+// {K1 of sites < j, K2 of site j, 1/sqrt(nrm2)}, followed by a RUN of the
+// sites after j (if any); the GATES step after the run loses the K1 factors
+// of sites 0..j.  The trajectory continues at step r.
+void jump_continuation(TPrep &tp, size_t r, size_t j, double nrm2)
+{
+    TStep g;
+    TStep rest;
+    rest.run = true;
+    {
+        const TStep &R = tp.steps[r];
+        for (size_t i = 0; i < j; ++i) g.gates.push_back(one_qubit(R.sites[i].q, R.sites[i].kraus.data()));
+        g.gates.push_back(one_qubit(R.sites[j].q, R.sites[j].kraus.data() + 8));
+        const double sc = 1.0 / std::sqrt(nrm2);
+        const double m2[8] = {sc, 0, 0, 0, 0, 0, sc, 0};
+        g.gates.push_back(one_qubit(R.sites[j].q, m2));
+        rest.sites.assign(R.sites.begin() + long(j) + 1, R.sites.end());
+    }
+    TStep &N = tp.steps[r + 1];  // the GATES step after a RUN always exists
+    N.gates.erase(N.gates.begin(), N.gates.begin() + long(j) + 1);
+    N.k1_lead -= int(j) + 1;
+    tp.steps[r] = std::move(g);
+    if (!rest.sites.empty()) tp.steps.insert(tp.steps.begin() + long(r) + 1, std::move(rest));
+    tp.cur = r;
 }
 
 // A lightweight view of one trajectory's amplitudes that borrows the
@@ -1509,14 +1584,27 @@ struct PinnedBuf {
     }
 };
 
+// Tile planning of a trajectory's gate lists (planned once, never reused).
+struct TrajParams {
+    int m_cap = 13;     // qubits per tile (at most the state's width)
+    int kmax = 4;       // widest dense block
+    int max_outer = 2;  // outer selector bits per op
+};
+
 struct Batch {
     qs_state *master = nullptr;  // scratch and stream owner (a 1-qubit state)
     qs_dtype dt;
+    TrajParams par;
+    bool graph = true;           // device-sampled passes run as captured HIP graphs
+    uint64_t seed = 0;
     std::vector<TPrep> prep;
     std::vector<void *> amp;
-    DevBuf states, prog, red, outb;
-    PinnedBuf stage;  // program uploads (written only after the stream has drained)
+    std::vector<size_t> zoff;    // offset of each trajectory's <Z_q> in the output
+    double *z_out = nullptr;
+    DevBuf states, prog, red, work;
+    PinnedBuf stage, back;       // uploads (written only after the stream has drained), read-backs
     std::vector<View *> views;
+    qs_traj_stats st{};
     ~Batch()
     {
         for (auto *v : views) delete v;
@@ -1524,39 +1612,43 @@ struct Batch {
     }
 };
 
-// Trajectory gate lists are planned once per batch round and never reused:
-// four-qubit blocks and few outer selector bits keep their block matrices
-// and operand programs small (the states are small too).
-constexpr int kTrajKmax = 4;
-constexpr int kTrajMaxOuter = 2;
+bool device_sampled(const Batch &B, int t) { return B.dt == QS_C64 && B.prep[t].n >= 10; }
 
-// Apply a gate list to every listed trajectory: tiled complex64 plans run as
+// Plan one gate list of a trajectory: tile sweeps for complex64 states of at
+// least 10 qubits (gates wider than a tile block stay per-gate steps), the
+// per-gate kernels otherwise.
+void plan_gate_list(const Batch &B, int n, const std::vector<qs::FlatOp> &fl, std::vector<qs::PlanStep> &out)
+{
+    if (fl.empty()) return;
+    if (B.dt == QS_C64 && n >= 10) {
+        qs::TileParams tp;
+        tp.m = std::min(B.par.m_cap, n);
+        tp.L = 4;
+        tp.kmax = B.par.kmax;
+        tp.max_outer = B.par.max_outer;
+        tp.search = false;  // planned once per trajectory step: keep it cheap
+        qs::plan_tiles(fl, 0, fl.size(), n, tp, out);
+        return;
+    }
+    for (auto &f : fl) {
+        qs::PlanStep st;
+        st.sweep = false;
+        st.gate = qs::canonicalize(f.targets.data(), int(f.targets.size()), f.controls.data(), int(f.controls.size()),
+                                   f.m.data());
+        if (st.gate.kind != qs::CanonGate::IDENTITY) out.push_back(std::move(st));
+    }
+}
+
+constexpr size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// ------------------------------------------------------ host-sampled path --
+
+// Apply one gate list to each listed trajectory: tiled complex64 plans run as
 // batched sweep rounds, everything else through the per-gate kernels.
-qs_status batch_gates(Batch &B, const std::vector<int> &who, std::vector<std::vector<qs::FlatOp>> &lists)
+qs_status batch_gates(Batch &B, const std::vector<int> &who, const std::vector<const std::vector<qs::FlatOp> *> &lists)
 {
     std::vector<std::vector<qs::PlanStep>> plans(who.size());
-    parallel_for(who.size(), [&](size_t i) {
-        const int n = B.prep[who[i]].n;
-        auto &fl = lists[i];
-        if (fl.empty()) return;
-        if (B.dt == QS_C64 && n >= 10) {
-            qs_run_opts o{};
-            o.plan = QS_PLAN_GREEDY;
-            qs::TileParams tp = tile_params(n, o);
-            tp.kmax = kTrajKmax;
-            tp.max_outer = kTrajMaxOuter;
-            tp.search = false;  // planned every round for every trajectory: keep it cheap
-            qs::plan_tiles(fl, 0, fl.size(), n, tp, plans[i]);
-        } else {
-            for (auto &f : fl) {
-                qs::PlanStep st;
-                st.sweep = false;
-                st.gate = qs::canonicalize(f.targets.data(), int(f.targets.size()), f.controls.data(),
-                                           int(f.controls.size()), f.m.data());
-                if (st.gate.kind != qs::CanonGate::IDENTITY) plans[i].push_back(std::move(st));
-            }
-        }
-    });
+    parallel_for(who.size(), [&](size_t i) { plan_gate_list(B, B.prep[who[i]].n, *lists[i], plans[i]); });
     size_t rounds = 0;
     for (auto &pl : plans) rounds = std::max(rounds, pl.size());
     // flatten in (round, trajectory) order and build one device program
@@ -1574,7 +1666,6 @@ qs_status batch_gates(Batch &B, const std::vector<int> &who, std::vector<std::ve
     build_tile_program(all, tp);
     std::vector<qs::TileArgsDev> args;
     std::vector<std::vector<qs::TileTask>> tasks(rounds * 4);  // per round, per m - 10
-    std::vector<size_t> arg_index(all.size(), SIZE_MAX);
     for (size_t k = 0; k < all.size(); ++k) {
         if (!all[k].sweep) continue;
         const int t = who[refs[k].who];
@@ -1582,7 +1673,6 @@ qs_status batch_gates(Batch &B, const std::vector<int> &who, std::vector<std::ve
         ad.amp = static_cast<float2 *>(B.amp[t]);
         ad.op_off = uint32_t(tp.first[k]);
         ad.ta = make_tile_args(all[k].sw, B.prep[t].n);
-        arg_index[k] = args.size();
         args.push_back(ad);
         const uint32_t ntiles = uint32_t(1) << (B.prep[t].n - ad.ta.m);
         auto &tl = tasks[refs[k].round * 4 + (ad.ta.m - 10)];
@@ -1593,9 +1683,7 @@ qs_status batch_gates(Batch &B, const std::vector<int> &who, std::vector<std::ve
     const size_t ob = tp.ops.size() * sizeof(qs::TileOpDev);
     const size_t db = tp.data.size() * sizeof(uint16_t);
     const size_t ab = args.size() * sizeof(qs::TileArgsDev);
-    const size_t tb = ntask * sizeof(qs::TileTask);
-    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
-    const size_t total = up(ob) + up(db) + up(ab) + up(tb) + 256;
+    const size_t total = align256(ob) + align256(db) + align256(ab) + align256(ntask * sizeof(qs::TileTask)) + 256;
     qs_state *s = B.master;
     // the previous round's upload and kernels are done before the staging
     // buffer and the program buffer are rewritten
@@ -1610,35 +1698,18 @@ qs_status batch_gates(Batch &B, const std::vector<int> &who, std::vector<std::ve
         task_off[k] = toff;
         toff += tasks[k].size();
     }
-    // the fragment data dominates: copied in parallel slices
-    const size_t slice = size_t(1) << 20;
-    const size_t nsl = (db + slice - 1) / slice;
-    parallel_for(nsl + 3 + tasks.size(), [&](size_t i) {
-        if (i < nsl) {
-            const size_t o = i * slice, len = std::min(slice, db - o);
-            std::memcpy(host + up(ob) + o, reinterpret_cast<const unsigned char *>(tp.data.data()) + o, len);
-        } else if (i == nsl) {
-            std::memcpy(host, tp.ops.data(), ob);
-        } else if (i == nsl + 1) {
-            if (ab) std::memcpy(host + up(ob) + up(db), args.data(), ab);
-        } else if (i == nsl + 2) {
-            // gaps between the sections stay zero
-            std::memset(host + ob, 0, up(ob) - ob);
-            std::memset(host + up(ob) + db, 0, up(db) - db);
-            std::memset(host + up(ob) + up(db) + ab, 0, up(ab) - ab);
-        } else {
-            const size_t k = i - nsl - 3;
-            if (!tasks[k].empty())
-                std::memcpy(host + up(ob) + up(db) + up(ab) + task_off[k] * sizeof(qs::TileTask), tasks[k].data(),
-                            tasks[k].size() * sizeof(qs::TileTask));
-        }
-    });
-    HIP_TRY(hipMemcpyAsync(dev, host, up(ob) + up(db) + up(ab) + ntask * sizeof(qs::TileTask), hipMemcpyHostToDevice,
-                           s->stream));
+    const size_t o_data = align256(ob), o_args = o_data + align256(db), o_tasks = o_args + align256(ab);
+    std::memcpy(host, tp.ops.data(), ob);
+    std::memcpy(host + o_data, tp.data.data(), db);
+    if (ab) std::memcpy(host + o_args, args.data(), ab);
+    for (size_t k = 0; k < tasks.size(); ++k)
+        if (!tasks[k].empty())
+            std::memcpy(host + o_tasks + task_off[k] * sizeof(qs::TileTask), tasks[k].data(),
+                        tasks[k].size() * sizeof(qs::TileTask));
+    HIP_TRY(hipMemcpyAsync(dev, host, o_tasks + ntask * sizeof(qs::TileTask), hipMemcpyHostToDevice, s->stream));
     const qs::TileOpDev *dops = reinterpret_cast<const qs::TileOpDev *>(dev);
-    const void *ddata = dev + up(ob);
-    const qs::TileArgsDev *dargs = reinterpret_cast<const qs::TileArgsDev *>(dev + up(ob) + up(db));
-    const qs::TileTask *dtasks = reinterpret_cast<const qs::TileTask *>(dev + up(ob) + up(db) + up(ab));
+    const qs::TileArgsDev *dargs = reinterpret_cast<const qs::TileArgsDev *>(dev + o_args);
+    const qs::TileTask *dtasks = reinterpret_cast<const qs::TileTask *>(dev + o_tasks);
     bool k5 = false;  // any 5-qubit block selects the 256-thread kernel for every launch
     for (const auto &d : tp.ops) k5 = k5 || (d.kind == 0 && d.k == 5);
     size_t k = 0;
@@ -1654,15 +1725,16 @@ qs_status batch_gates(Batch &B, const std::vector<int> &who, std::vector<std::ve
             const auto &tl = tasks[r * 4 + mm];
             if (tl.empty()) continue;
             hipError_t e = qs::launch_tile_multi(10 + mm, uint32_t(tl.size()), dtasks + task_off[r * 4 + mm], dargs,
-                                                 dops, ddata, k5, s->stream);
+                                                 dops, dev + o_data, k5, nullptr, s->stream);
             if (e != hipSuccess) return hip_fail(e, "batched tile launch");
+            ++B.st.launches;
         }
     }
     return QS_OK;
 }
 
-// Sums S_j / Z for runs of sites (qs_traj.hip) of several trajectories.
-// sums[i] receives kRunMax + 1 doubles: Z, S_0, S_1, ...
+// Run sums (qs_traj.hip) of several trajectories, read back: sums[i]
+// receives kRunMax + 1 doubles: Z, S_0, S_1, ...
 qs_status batch_run_sums(Batch &B, const std::vector<int> &who, const std::vector<std::vector<int>> &qs_,
                          const std::vector<std::vector<double>> &as_, std::vector<std::vector<double>> &sums)
 {
@@ -1688,10 +1760,9 @@ qs_status batch_run_sums(Batch &B, const std::vector<int> &who, const std::vecto
         for (uint32_t c = 0; c < nch; ++c) tasks.push_back({uint32_t(i), c});
     }
     const int w = qs::kRunMax + 1;
-    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
-    const size_t ab = up(args.size() * sizeof(qs::RunSumArgs)), tb = up(tasks.size() * sizeof(qs::RunSumTask));
-    const size_t fb = up(who.size() * 4);
-    const size_t pb = up(tasks.size() * w * sizeof(double)), ob = up(who.size() * w * sizeof(double));
+    const size_t ab = align256(args.size() * sizeof(qs::RunSumArgs)), tb = align256(tasks.size() * sizeof(qs::RunSumTask));
+    const size_t fb = align256(who.size() * 4);
+    const size_t pb = align256(tasks.size() * w * sizeof(double)), ob = align256(who.size() * w * sizeof(double));
     HIP_TRY(hipStreamSynchronize(s->stream));
     HIP_TRY(B.red.ensure(ab + tb + 2 * fb + pb + ob));
     unsigned char *dev = static_cast<unsigned char *>(B.red.p);
@@ -1708,12 +1779,13 @@ qs_status batch_run_sums(Batch &B, const std::vector<int> &who, const std::vecto
         int nmax = 0;
         for (int t : who) nmax = std::max(nmax, B.prep[t].n);
         hipError_t e = qs::launch_run_sums(B.dt, nmax, uint32_t(tasks.size()), reinterpret_cast<qs::RunSumTask *>(dev + ab),
-                                           reinterpret_cast<qs::RunSumArgs *>(dev), partials, s->stream);
+                                           reinterpret_cast<qs::RunSumArgs *>(dev), partials, nullptr, s->stream);
         if (e == hipSuccess)
             e = qs::launch_run_sums_finish(partials, reinterpret_cast<uint32_t *>(dev + ab + tb),
                                            reinterpret_cast<uint32_t *>(dev + ab + tb + fb), int(who.size()), out,
                                            s->stream);
         if (e != hipSuccess) return hip_fail(e, "trajectory reductions");
+        B.st.launches += 2;
     }
     std::vector<double> host(who.size() * w);
     HIP_TRY(hipMemcpyAsync(host.data(), out, host.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
@@ -1723,78 +1795,475 @@ qs_status batch_run_sums(Batch &B, const std::vector<int> &who, const std::vecto
     return QS_OK;
 }
 
-// Sample a run of damping-type sites from its sums.  Sites 0..j-1 that take
-// K1 are left as pending diagonal factors (K1 and a final 1/sqrt(norm)); a K2
-// branch is applied at once and the sums of the remaining sites recomputed.
-qs_status sample_run(Batch &B, int t, const TStep &run, std::vector<double> sums, uint64_t seed)
+// Branch choice of a RUN step from its sums (the same arithmetic as the
+// device sampler): returns the first site that takes K2 and its weight, or
+// -1 when every site takes K1.
+int sample_run_host(const TStep &run, const std::vector<double> &sums, uint64_t seed, uint64_t traj, double &nrm2,
+                    qs_status &err)
 {
-    TPrep &tp = B.prep[t];
-    size_t j0 = 0;  // first site covered by `sums`
-    while (j0 < run.sites.size()) {
-        double Z = sums[0];
-        size_t j = j0;
-        int k2_at = -1;
-        for (; j < run.sites.size(); ++j) {
-            const RunSite &rs = run.sites[j];
-            const double S = sums[1 + (j - j0)];
-            const double p2 = (1.0 - rs.a) * S / Z;
-            const double p1 = (Z - (1.0 - rs.a) * S) / Z;
-            const double u = qs::noise_uniform(seed, uint64_t(t), rs.site);
-            const int b = pick_branch({p1, p2}, u);
-            if (b == 0) {
-                Z -= (1.0 - rs.a) * S;
-                continue;
-            }
-            if (b < 0) return fail(QS_E_ZERO_NORM, "every Kraus branch has probability 0");
-            k2_at = int(j);
-            break;
+    err = QS_OK;
+    double Z = sums[0];
+    for (size_t j = 0; j < run.sites.size(); ++j) {
+        const RunSite &rs = run.sites[j];
+        const double c = -(rs.a - 1.0);
+        const double cs = c * sums[1 + j];
+        const double p2 = cs / Z;
+        const double p1 = (Z - cs) / Z;
+        const double u = qs::noise_uniform(seed, traj, rs.site);
+        const int b = pick_branch({p1, p2}, u);
+        if (b == 0) {
+            Z -= cs;
+            continue;
         }
-        // K1 factors of sites j0 .. j-1
-        for (size_t i = j0; i < j; ++i) tp.pending.push_back(one_qubit(run.sites[i].q, run.sites[i].kraus.data()));
-        if (k2_at < 0) {
-            const double sc = 1.0 / std::sqrt(Z);
-            const double m2[8] = {sc, 0, 0, 0, 0, 0, sc, 0};
-            tp.pending.push_back(one_qubit(0, m2));
-            return QS_OK;
+        if (b < 0) {
+            err = fail(QS_E_ZERO_NORM, "every Kraus branch has probability 0");
+            return -1;
         }
-        const RunSite &rs = run.sites[k2_at];
-        const double S = sums[1 + (k2_at - j0)];
-        const double nrm2 = (1.0 - rs.a) * S;  // squared norm after the K1s and this K2
-        tp.pending.push_back(one_qubit(rs.q, rs.kraus.data() + 8));
-        const double sc = 1.0 / std::sqrt(nrm2);
-        const double m2[8] = {sc, 0, 0, 0, 0, 0, sc, 0};
-        tp.pending.push_back(one_qubit(0, m2));
-        std::vector<int> who = {t};
-        std::vector<std::vector<qs::FlatOp>> lists = {tp.pending};
-        tp.pending.clear();
-        if (qs_status e = batch_gates(B, who, lists)) return e;
-        j0 = size_t(k2_at) + 1;
-        if (j0 >= run.sites.size()) return QS_OK;
-        std::vector<std::vector<int>> qv(1);
-        std::vector<std::vector<double>> av(1);
-        for (size_t i = j0; i < run.sites.size(); ++i) {
-            qv[0].push_back(run.sites[i].q);
-            av[0].push_back(run.sites[i].a);
+        nrm2 = cs;
+        return int(j);
+    }
+    return -1;
+}
+
+// <Z_q> of every listed trajectory from one batched pass of sums (a = 1).
+qs_status host_expect_z(Batch &B, const std::vector<int> &who)
+{
+    if (who.empty()) return QS_OK;
+    std::vector<std::vector<int>> qv(who.size());
+    std::vector<std::vector<double>> av(who.size());
+    for (size_t i = 0; i < who.size(); ++i)
+        for (int q = 0; q < B.prep[who[i]].n; ++q) {
+            qv[i].push_back(q);
+            av[i].push_back(1.0);
         }
-        std::vector<std::vector<double>> out;
-        if (qs_status e = batch_run_sums(B, who, qv, av, out)) return e;
-        sums = out[0];
+    std::vector<std::vector<double>> sums;
+    if (qs_status e = batch_run_sums(B, who, qv, av, sums)) return e;
+    for (size_t i = 0; i < who.size(); ++i) {
+        const int t = who[i];
+        const double Z = sums[i][0];
+        for (int q = 0; q < B.prep[t].n; ++q) B.z_out[B.zoff[t] + q] = (Z - 2.0 * sums[i][1 + q]) / Z;
     }
     return QS_OK;
 }
 
+// Host-sampled path: all listed trajectories advance one step at a time.
+qs_status run_host_sampled(Batch &B, const std::vector<int> &set)
+{
+    for (;;) {
+        std::vector<int> gate_who, run_who;
+        for (int t : set) {
+            const TPrep &tp = B.prep[t];
+            if (tp.cur >= tp.steps.size()) continue;
+            (tp.steps[tp.cur].run ? run_who : gate_who).push_back(t);
+        }
+        if (gate_who.empty() && run_who.empty()) break;
+        if (!gate_who.empty()) {
+            std::vector<const std::vector<qs::FlatOp> *> lists;
+            for (int t : gate_who) lists.push_back(&B.prep[t].steps[B.prep[t].cur].gates);
+            if (qs_status e = batch_gates(B, gate_who, lists)) return e;
+            for (int t : gate_who) ++B.prep[t].cur;
+            continue;  // runs wait for the gates that precede them
+        }
+        std::vector<std::vector<int>> qv;
+        std::vector<std::vector<double>> av;
+        for (int t : run_who) {
+            const TStep &r = B.prep[t].steps[B.prep[t].cur];
+            qv.emplace_back();
+            av.emplace_back();
+            for (auto &s2 : r.sites) {
+                qv.back().push_back(s2.q);
+                av.back().push_back(s2.a);
+            }
+        }
+        std::vector<std::vector<double>> sums;
+        if (qs_status e = batch_run_sums(B, run_who, qv, av, sums)) return e;
+        for (size_t i = 0; i < run_who.size(); ++i) {
+            const int t = run_who[i];
+            TPrep &tp = B.prep[t];
+            double nrm2 = 0;
+            qs_status err;
+            const int j = sample_run_host(tp.steps[tp.cur], sums[i], B.seed, uint64_t(t), nrm2, err);
+            if (err) return err;
+            if (j < 0) {
+                ++tp.cur;
+            } else {
+                jump_continuation(tp, tp.cur, size_t(j), nrm2);
+                ++B.st.jumps;
+            }
+        }
+    }
+    return host_expect_z(B, set);
+}
+
+// ---------------------------------------------------- device-sampled path --
+
+// One pass over `set` (complex64 states of >= 10 qubits): every remaining
+// step planned, one upload, one graph (or the same launches enqueued
+// directly), one read-back.  On return `set` holds the trajectories that
+// jumped (their steps rewritten from the jump on) and `demoted` those whose
+// plans need per-gate launches (they take the host-sampled path).
+qs_status run_device_pass(Batch &B, std::vector<int> &set, std::vector<int> &demoted)
+{
+    using clock = std::chrono::steady_clock;
+    const auto t0 = clock::now();
+    const int S = int(set.size());
+    const int w = qs::kRunMax + 1;
+    qs_state *s = B.master;
+    // ---- schedule: the rounds the host-sampled loop would run if no site jumped
+    struct Ent { int slot; size_t step; };
+    struct Round { bool run; std::vector<Ent> e; };
+    std::vector<Round> rounds;
+    {
+        std::vector<size_t> cur(S);
+        for (int i = 0; i < S; ++i) cur[i] = B.prep[set[i]].cur;
+        for (;;) {
+            Round g{false, {}}, r{true, {}};
+            for (int i = 0; i < S; ++i) {
+                const TPrep &tp = B.prep[set[i]];
+                if (cur[i] >= tp.steps.size()) continue;
+                (tp.steps[cur[i]].run ? r : g).e.push_back({i, cur[i]});
+            }
+            Round &take = g.e.empty() ? r : g;
+            if (take.e.empty()) break;
+            for (auto &e : take.e) ++cur[e.slot];
+            rounds.push_back(std::move(take));
+        }
+    }
+    // ---- plan every gate step, all in parallel
+    struct PlanEnt { size_t round; int slot; size_t step; std::vector<qs::PlanStep> plan; };
+    std::vector<PlanEnt> pe;
+    for (size_t r = 0; r < rounds.size(); ++r)
+        if (!rounds[r].run)
+            for (auto &e : rounds[r].e) pe.push_back({r, e.slot, e.step, {}});
+    parallel_for(pe.size(), [&](size_t k) {
+        const TPrep &tp = B.prep[set[pe[k].slot]];
+        plan_gate_list(B, tp.n, tp.steps[pe[k].step].gates, pe[k].plan);
+    });
+    std::vector<char> out(S, 0);  // plans with per-gate steps: host-sampled path instead
+    for (auto &p : pe)
+        for (auto &st : p.plan)
+            if (!st.sweep) out[p.slot] = 1;
+    // ---- launch list in round order; sweeps flattened in (round, sub-round, slot) order
+    enum { L_TILE, L_RUN, L_FINAL };
+    struct Launch {
+        int kind = L_TILE;
+        size_t a0 = 0, a1 = 0;      // L_TILE: sweeps [a0, a1) of one sub-round (expanded per tile width below)
+        int m = 0;
+        bool k5 = false;
+        size_t t0 = 0, tn = 0;      // tile tasks / run-sum tasks
+        size_t r0 = 0, rn = 0;      // run-sum args (rn = entries of the round)
+        size_t fc0 = 0;             // first / count arrays (2 rn entries)
+        size_t s0 = 0;              // sample args (rn entries)
+        int nmax = 0;
+    };
+    std::vector<Launch> pre;
+    std::vector<qs::PlanStep> all;
+    std::vector<int> all_slot;
+    std::vector<qs::RunSumArgs> rargs;
+    std::vector<qs::RunSumTask> rtasks;
+    std::vector<uint32_t> fc;
+    std::vector<qs::SampleArgs> sargs;
+    const uint64_t chunk = 1u << 16;
+    size_t max_rtasks = 0, max_rows = 0;
+    struct RunEnt { int slot; size_t step; const TStep *run; };  // run == NULL: final <Z> sums
+    auto add_run_launch = [&](int kind, const std::vector<RunEnt> &ents) {
+        Launch L;
+        L.kind = kind;
+        L.r0 = rargs.size();
+        L.t0 = rtasks.size();
+        L.fc0 = fc.size();
+        L.s0 = sargs.size();
+        L.rn = ents.size();
+        fc.resize(fc.size() + 2 * ents.size());
+        for (size_t i = 0; i < ents.size(); ++i) {
+            const int slot = ents[i].slot;
+            const int t = set[slot];
+            const TPrep &tp = B.prep[t];
+            qs::RunSumArgs a{};
+            a.amp = B.amp[t];
+            a.n_amp = uint64_t(1) << tp.n;
+            a.chunk_len = chunk;
+            a.slot = uint32_t(slot);
+            if (kind == L_RUN) {
+                const TStep &R = *ents[i].run;
+                a.J = int(R.sites.size());
+                qs::SampleArgs sa{};
+                sa.slot = uint32_t(slot);
+                sa.row = uint32_t(i);
+                sa.traj = uint64_t(t);
+                sa.step = uint32_t(ents[i].step);
+                sa.arg = uint32_t(rargs.size());
+                for (int j = 0; j < a.J; ++j) {
+                    a.q[j] = uint8_t(R.sites[j].q);
+                    a.am1[j] = R.sites[j].a - 1.0;
+                    sa.site[j] = uint32_t(R.sites[j].site);
+                }
+                sargs.push_back(sa);
+            } else {
+                a.J = tp.n;
+                for (int q = 0; q < tp.n; ++q) {
+                    a.q[q] = uint8_t(q);
+                    a.am1[q] = 0.0;
+                }
+            }
+            const uint32_t nch = uint32_t((a.n_amp + chunk - 1) / chunk);
+            fc[L.fc0 + i] = uint32_t(rtasks.size() - L.t0);
+            fc[L.fc0 + ents.size() + i] = nch;
+            for (uint32_t c = 0; c < nch; ++c) rtasks.push_back({uint32_t(rargs.size()), c});
+            rargs.push_back(a);
+            L.nmax = std::max(L.nmax, tp.n);
+        }
+        L.tn = rtasks.size() - L.t0;
+        max_rtasks = std::max(max_rtasks, L.tn);
+        max_rows = std::max(max_rows, L.rn);
+        pre.push_back(L);
+    };
+    {
+        size_t p = 0;
+        for (size_t r = 0; r < rounds.size(); ++r) {
+            if (!rounds[r].run) {
+                size_t e = p;
+                while (e < pe.size() && pe[e].round == r) ++e;
+                size_t sub = 0;
+                for (size_t i = p; i < e; ++i)
+                    if (!out[pe[i].slot]) sub = std::max(sub, pe[i].plan.size());
+                for (size_t k = 0; k < sub; ++k) {
+                    Launch L;
+                    L.kind = L_TILE;
+                    L.a0 = all.size();
+                    for (size_t i = p; i < e; ++i)
+                        if (!out[pe[i].slot] && k < pe[i].plan.size()) {
+                            all.push_back(std::move(pe[i].plan[k]));
+                            all_slot.push_back(pe[i].slot);
+                        }
+                    L.a1 = all.size();
+                    pre.push_back(L);
+                }
+                p = e;
+                continue;
+            }
+            std::vector<RunEnt> ents;
+            for (auto &e : rounds[r].e)
+                if (!out[e.slot]) ents.push_back({e.slot, e.step, &B.prep[set[e.slot]].steps[e.step]});
+            if (!ents.empty()) add_run_launch(L_RUN, ents);
+        }
+        std::vector<RunEnt> fin;
+        for (int i = 0; i < S; ++i)
+            if (!out[i]) fin.push_back({i, 0, nullptr});
+        if (!fin.empty()) add_run_launch(L_FINAL, fin);
+    }
+    TileProgram tp;
+    if (!all.empty()) build_tile_program(all, tp);
+    std::vector<qs::TileArgsDev> targs(all.size());
+    std::vector<qs::TileTask> ttasks;
+    std::vector<Launch> L;
+    for (const Launch &pl : pre) {
+        if (pl.kind != L_TILE) {
+            L.push_back(pl);
+            continue;
+        }
+        for (size_t k = pl.a0; k < pl.a1; ++k) {
+            const int t = set[all_slot[k]];
+            qs::TileArgsDev &ad = targs[k];
+            ad.amp = static_cast<float2 *>(B.amp[t]);
+            ad.op_off = uint32_t(tp.first[k]);
+            ad.slot = uint32_t(all_slot[k]);
+            ad.ta = make_tile_args(all[k].sw, B.prep[t].n);
+        }
+        for (int m = 10; m <= 13; ++m) {
+            Launch tl;
+            tl.kind = L_TILE;
+            tl.m = m;
+            tl.t0 = ttasks.size();
+            for (size_t k = pl.a0; k < pl.a1; ++k) {
+                if (targs[k].ta.m != m) continue;
+                for (size_t o = 0; o < all[k].sw.ops.size(); ++o) {
+                    const qs::TileOpDev &d = tp.ops[tp.first[k] + o];
+                    tl.k5 = tl.k5 || (d.kind == 0 && d.k == 5);
+                }
+                const uint32_t ntiles = uint32_t(1) << (B.prep[set[all_slot[k]]].n - m);
+                for (uint32_t tile = 0; tile < ntiles; ++tile) ttasks.push_back({uint32_t(k), tile});
+            }
+            tl.tn = ttasks.size() - tl.t0;
+            if (tl.tn) L.push_back(tl);
+        }
+    }
+    // ---- one upload: program, arguments, tasks, activity flags, freeze records
+    const size_t b_ops = tp.ops.size() * sizeof(qs::TileOpDev), b_data = tp.data.size() * sizeof(uint16_t);
+    const size_t o_data = align256(b_ops);
+    const size_t o_targs = o_data + align256(b_data);
+    const size_t o_ttasks = o_targs + align256(targs.size() * sizeof(qs::TileArgsDev));
+    const size_t o_rargs = o_ttasks + align256(ttasks.size() * sizeof(qs::TileTask));
+    const size_t o_rtasks = o_rargs + align256(rargs.size() * sizeof(qs::RunSumArgs));
+    const size_t o_fc = o_rtasks + align256(rtasks.size() * sizeof(qs::RunSumTask));
+    const size_t o_sargs = o_fc + align256(fc.size() * sizeof(uint32_t));
+    const size_t o_active = o_sargs + align256(sargs.size() * sizeof(qs::SampleArgs));
+    const size_t o_freeze = o_active + align256(size_t(S) * sizeof(int));
+    const size_t o_err = o_freeze + align256(size_t(S) * sizeof(qs::Freeze));
+    const size_t up_bytes = o_err + 256;
+    // device-only work space: partials, sums of one run round, final sums
+    const size_t o_part = 0;
+    const size_t o_sums = o_part + align256(std::max<size_t>(max_rtasks, 1) * w * sizeof(double));
+    const size_t o_zs = o_sums + align256(std::max<size_t>(max_rows, 1) * w * sizeof(double));
+    const size_t work_bytes = o_zs + align256(size_t(S) * w * sizeof(double));
+    HIP_TRY(hipStreamSynchronize(s->stream));  // the staging buffer may still feed an earlier copy
+    {
+        hipError_t e = B.prog.ensure(up_bytes);
+        if (e == hipSuccess) e = B.work.ensure(work_bytes);
+        if (e == hipSuccess) e = B.stage.ensure(up_bytes);
+        if (e == hipSuccess) e = B.back.ensure(o_err - o_freeze + 256 + size_t(S) * w * sizeof(double));
+        if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(QS_E_NOMEM, "trajectory pass buffers")
+                                                               : hip_fail(e, "trajectory pass buffers");
+    }
+    unsigned char *host = static_cast<unsigned char *>(B.stage.p);
+    auto put = [&](size_t off, const void *src, size_t bytes) {
+        if (bytes) std::memcpy(host + off, src, bytes);
+    };
+    put(0, tp.ops.data(), b_ops);
+    put(o_data, tp.data.data(), b_data);
+    put(o_targs, targs.data(), targs.size() * sizeof(qs::TileArgsDev));
+    put(o_ttasks, ttasks.data(), ttasks.size() * sizeof(qs::TileTask));
+    put(o_rargs, rargs.data(), rargs.size() * sizeof(qs::RunSumArgs));
+    put(o_rtasks, rtasks.data(), rtasks.size() * sizeof(qs::RunSumTask));
+    put(o_fc, fc.data(), fc.size() * sizeof(uint32_t));
+    put(o_sargs, sargs.data(), sargs.size() * sizeof(qs::SampleArgs));
+    {
+        int *act = reinterpret_cast<int *>(host + o_active);
+        qs::Freeze *fr = reinterpret_cast<qs::Freeze *>(host + o_freeze);
+        for (int i = 0; i < S; ++i) {
+            act[i] = out[i] ? 0 : 1;
+            fr[i] = qs::Freeze{-1, 0, 0.0};
+        }
+        *reinterpret_cast<int *>(host + o_err) = 0;
+    }
+    unsigned char *dev = static_cast<unsigned char *>(B.prog.p);
+    unsigned char *wk = static_cast<unsigned char *>(B.work.p);
+    HIP_TRY(hipMemcpyAsync(dev, host, up_bytes, hipMemcpyHostToDevice, s->stream));
+    const auto t1 = clock::now();
+    // ---- the pass's launches
+    const qs::TileOpDev *dops = reinterpret_cast<const qs::TileOpDev *>(dev);
+    const qs::TileArgsDev *dtargs = reinterpret_cast<const qs::TileArgsDev *>(dev + o_targs);
+    const qs::TileTask *dttasks = reinterpret_cast<const qs::TileTask *>(dev + o_ttasks);
+    const qs::RunSumArgs *drargs = reinterpret_cast<const qs::RunSumArgs *>(dev + o_rargs);
+    const qs::RunSumTask *drtasks = reinterpret_cast<const qs::RunSumTask *>(dev + o_rtasks);
+    const uint32_t *dfc = reinterpret_cast<const uint32_t *>(dev + o_fc);
+    const qs::SampleArgs *dsargs = reinterpret_cast<const qs::SampleArgs *>(dev + o_sargs);
+    int *dactive = reinterpret_cast<int *>(dev + o_active);
+    qs::Freeze *dfreeze = reinterpret_cast<qs::Freeze *>(dev + o_freeze);
+    int *derr = reinterpret_cast<int *>(dev + o_err);
+    double *dpart = reinterpret_cast<double *>(wk + o_part);
+    double *dsums = reinterpret_cast<double *>(wk + o_sums);
+    double *dzs = reinterpret_cast<double *>(wk + o_zs);
+    int64_t nl = 0;
+    auto enqueue = [&]() -> hipError_t {
+        for (const Launch &l : L) {
+            hipError_t e = hipSuccess;
+            if (l.kind == L_TILE) {
+                e = qs::launch_tile_multi(l.m, uint32_t(l.tn), dttasks + l.t0, dtargs, dops, dev + o_data, l.k5,
+                                          dactive, s->stream);
+                ++nl;
+            } else {
+                double *rows = l.kind == L_RUN ? dsums : dzs;
+                e = qs::launch_run_sums(B.dt, l.nmax, uint32_t(l.tn), drtasks + l.t0, drargs, dpart, dactive,
+                                        s->stream);
+                if (e == hipSuccess)
+                    e = qs::launch_run_sums_finish(dpart, dfc + l.fc0, dfc + l.fc0 + l.rn, int(l.rn), rows, s->stream);
+                if (e == hipSuccess && l.kind == L_RUN)
+                    e = qs::launch_sample_runs(dsargs + l.s0, uint32_t(l.rn), drargs, dsums, B.seed, dactive, dfreeze,
+                                               derr, s->stream);
+                nl += l.kind == L_RUN ? 3 : 2;
+            }
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    HIP_TRY(hipEventCreate(&ev0));
+    if (hipError_t e = hipEventCreate(&ev1)) {
+        hipEventDestroy(ev0);
+        return hip_fail(e, "event creation");
+    }
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    auto cleanup = [&](qs_status r) {
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
+        hipEventDestroy(ev0);
+        hipEventDestroy(ev1);
+        return r;
+    };
+    hipError_t e = hipEventRecord(ev0, s->stream);
+    if (e == hipSuccess) {
+        if (B.graph) {
+            e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                hipError_t el = enqueue();
+                e = hipStreamEndCapture(s->stream, &graph);
+                if (el != hipSuccess) e = el;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (e == hipSuccess) e = hipGraphLaunch(exec, s->stream);
+        } else {
+            e = enqueue();
+        }
+    }
+    if (e == hipSuccess) e = hipEventRecord(ev1, s->stream);
+    unsigned char *back = static_cast<unsigned char *>(B.back.p);
+    const size_t zb = o_err - o_freeze + 256;
+    if (e == hipSuccess) e = hipMemcpyAsync(back, dev + o_freeze, zb, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(back + zb, dzs, size_t(S) * w * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "trajectory pass"));
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ev0, ev1) == hipSuccess) B.st.device_seconds += 1e-3 * ms;
+    B.st.host_seconds += std::chrono::duration<double>(t1 - t0).count();
+    B.st.launches += nl;
+    ++B.st.passes;
+    if (*reinterpret_cast<const int *>(back + (o_err - o_freeze)))
+        return cleanup(fail(QS_E_ZERO_NORM, "every Kraus branch of a damping site has probability 0"));
+    // ---- results: completed trajectories write <Z_q>; jumped ones continue
+    const qs::Freeze *fr = reinterpret_cast<const qs::Freeze *>(back);
+    const double *zs = reinterpret_cast<const double *>(back + zb);
+    std::vector<int> next;
+    size_t row = 0;
+    for (int i = 0; i < S; ++i) {
+        const int t = set[i];
+        if (out[i]) {
+            demoted.push_back(t);
+            continue;
+        }
+        TPrep &tp = B.prep[t];
+        const double *z = zs + row * w;
+        ++row;
+        if (fr[i].step < 0) {
+            const double Z = z[0];
+            for (int q = 0; q < tp.n; ++q) B.z_out[B.zoff[t] + q] = (Z - 2.0 * z[1 + q]) / Z;
+            tp.cur = tp.steps.size();
+            continue;
+        }
+        jump_continuation(tp, size_t(fr[i].step), size_t(fr[i].j), fr[i].nrm2);
+        ++B.st.jumps;
+        next.push_back(t);
+    }
+    set.swap(next);
+    return cleanup(QS_OK);
+}
+
 qs_status run_trajectory_batch(const qs_circuit *const *circs, const int *widths, int count, qs_dtype dt,
-                               uint64_t seed, double *z_out, double *seconds)
+                               uint64_t seed, const TrajParams &par, bool device_ok, bool graph, double *z_out,
+                               qs_traj_stats &stats)
 {
     if (!circs || !widths || !z_out || count < 0) return fail(QS_E_INVAL, "NULL argument or negative count");
     if (dt != QS_C64 && dt != QS_C128) return fail(QS_E_INVAL, "unknown dtype %d", int(dt));
     if (count == 0) return QS_OK;
-    // the reported time covers everything from here: preparation (group
-    // expansion, state-independent branches), allocation, every launch and
-    // the final reductions
     const auto t0 = std::chrono::steady_clock::now();
     Batch B;
     B.dt = dt;
+    B.par = par;
+    B.graph = graph;
+    B.seed = seed;
+    B.z_out = z_out;
     B.prep.resize(count);
     size_t total = 0;
     for (int t = 0; t < count; ++t) {
@@ -1820,86 +2289,32 @@ qs_status run_trajectory_batch(const qs_circuit *const *circs, const int *widths
         hipError_t e = B.states.ensure(total);
         if (e != hipSuccess) return fail(QS_E_NOMEM, "device allocation of %zu bytes failed", total);
     }
-    size_t off = 0;
+    size_t off = 0, zo = 0;
     for (int t = 0; t < count; ++t) {
         B.amp.push_back(static_cast<unsigned char *>(B.states.p) + off);
         B.views.push_back(new View(B.master, B.amp.back(), widths[t]));
+        B.zoff.push_back(zo);
         off += amp_bytes(dt) << widths[t];
+        zo += size_t(widths[t]);
     }
     for (int t = 0; t < count; ++t)
         if (qs_status e = init_amplitudes(&B.views[t]->s)) return e;
-    std::vector<size_t> cursor(count, 0);
-    for (;;) {
-        std::vector<int> gate_who, run_who;
-        for (int t = 0; t < count; ++t) {
-            if (cursor[t] >= B.prep[t].steps.size()) continue;
-            (B.prep[t].steps[cursor[t]].run ? run_who : gate_who).push_back(t);
-        }
-        if (gate_who.empty() && run_who.empty()) break;
-        if (!gate_who.empty()) {
-            std::vector<std::vector<qs::FlatOp>> lists;
-            for (int t : gate_who) {
-                std::vector<qs::FlatOp> l = std::move(B.prep[t].pending);
-                B.prep[t].pending.clear();
-                auto &g = B.prep[t].steps[cursor[t]].gates;  // consumed here
-                l.insert(l.end(), std::make_move_iterator(g.begin()), std::make_move_iterator(g.end()));
-                lists.push_back(std::move(l));
-                ++cursor[t];
-            }
-            if (qs_status e = batch_gates(B, gate_who, lists)) return e;
-            continue;  // runs wait for the gates that precede them
-        }
-        std::vector<std::vector<int>> qv;
-        std::vector<std::vector<double>> av;
-        for (int t : run_who) {
-            const TStep &r = B.prep[t].steps[cursor[t]];
-            qv.emplace_back();
-            av.emplace_back();
-            for (auto &s2 : r.sites) {
-                qv.back().push_back(s2.q);
-                av.back().push_back(s2.a);
-            }
-        }
-        std::vector<std::vector<double>> sums;
-        if (qs_status e = batch_run_sums(B, run_who, qv, av, sums)) return e;
-        for (size_t i = 0; i < run_who.size(); ++i) {
-            const int t = run_who[i];
-            if (qs_status e = sample_run(B, t, B.prep[t].steps[cursor[t]], sums[i], seed)) return e;
-            ++cursor[t];
-        }
+    std::vector<int> dev_set, host_set;
+    for (int t = 0; t < count; ++t) (device_ok && device_sampled(B, t) ? dev_set : host_set).push_back(t);
+    B.st.graph = graph && !dev_set.empty();
+    while (!dev_set.empty()) {
+        std::vector<int> demoted;
+        if (qs_status e = run_device_pass(B, dev_set, demoted)) return e;
+        host_set.insert(host_set.end(), demoted.begin(), demoted.end());
     }
-    // remaining diagonal factors, then <Z_q> = (Z - 2 S_q) / Z for every qubit
-    {
-        std::vector<int> who;
-        std::vector<std::vector<qs::FlatOp>> lists;
-        for (int t = 0; t < count; ++t)
-            if (!B.prep[t].pending.empty()) {
-                who.push_back(t);
-                lists.push_back(std::move(B.prep[t].pending));
-            }
-        if (!who.empty())
-            if (qs_status e = batch_gates(B, who, lists)) return e;
-    }
-    std::vector<int> all(count);
-    std::vector<std::vector<int>> qv(count);
-    std::vector<std::vector<double>> av(count);
-    for (int t = 0; t < count; ++t) {
-        all[t] = t;
-        for (int q = 0; q < widths[t]; ++q) {
-            qv[t].push_back(q);
-            av[t].push_back(1.0);
-        }
-    }
-    std::vector<std::vector<double>> sums;
-    if (qs_status e = batch_run_sums(B, all, qv, av, sums)) return e;
-    size_t zo = 0;
-    for (int t = 0; t < count; ++t) {
-        const double Z = sums[t][0];
-        for (int q = 0; q < widths[t]; ++q) z_out[zo + q] = (Z - 2.0 * sums[t][1 + q]) / Z;
-        zo += size_t(widths[t]);
-    }
-    const auto t1 = std::chrono::steady_clock::now();
-    if (seconds) *seconds = std::chrono::duration<double>(t1 - t0).count();
+    B.st.host_sampled = int(host_set.size());
+    if (qs_status e = run_host_sampled(B, host_set)) return e;
+    HIP_TRY(hipStreamSynchronize(B.master->stream));
+    B.st.tile_qubits = par.m_cap;
+    B.st.k_max = par.kmax;
+    B.st.max_outer = par.max_outer;
+    B.st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    stats = B.st;
     return QS_OK;
 }
 
@@ -1941,13 +2356,13 @@ extern "C" {
 const char *qs_last_error(void) { return g_err.c_str(); }
 
 qs_status qs_set_memory_limit(size_t bytes)
-{
+try {
     g_mem_limit.store(bytes);
     return QS_OK;
-}
+} QS_ABI_CATCH
 
 qs_status qs_create(int n, qs_dtype dt, qs_state **out)
-{
+try {
     qs_status st = create_common(n, dt, out);
     if (st) return st;
     const size_t bytes = amp_bytes(dt) << n;
@@ -1979,11 +2394,11 @@ qs_status qs_create(int n, qs_dtype dt, qs_state **out)
     }
     *out = s;
     return QS_OK;
-}
+} QS_ABI_CATCH
 
 qs_status qs_create_from_buffer(int n, qs_dtype dt, void *buf, size_t bytes, void *stream,
                                 qs_state **out)
-{
+try {
     qs_status st = create_common(n, dt, out);
     if (st) return st;
     if (!buf) return fail(QS_E_INVAL, "device buffer is NULL");
@@ -2005,22 +2420,22 @@ qs_status qs_create_from_buffer(int n, qs_dtype dt, void *buf, size_t bytes, voi
     }
     *out = s;
     return QS_OK;
-}
+} QS_ABI_CATCH
 
 qs_status qs_destroy(qs_state *s)
-{
+try {
     free_state(s);
     return QS_OK;
-}
+} QS_ABI_CATCH
 
 qs_status qs_reset(qs_state *s)
-{
+try {
     if (qs_status st = check_state(s)) return st;
     return init_amplitudes(s);
-}
+} QS_ABI_CATCH
 
 qs_status qs_set_amplitudes(qs_state *s, const double *amps)
-{
+try {
     if (qs_status st = check_state(s)) return st;
     if (!amps) return fail(QS_E_INVAL, "amplitudes are NULL");
     const size_t na = size_t(1) << s->n;
@@ -2035,38 +2450,38 @@ qs_status qs_set_amplitudes(qs_state *s, const double *amps)
     }
     HIP_TRY(hipStreamSynchronize(s->stream));
     return QS_OK;
-}
+} QS_ABI_CATCH
 
 qs_status qs_info(const qs_state *s, int *n, qs_dtype *dt, void **dev, void **stream)
-{
+try {
     if (qs_status st = check_state(s)) return st;
     if (n) *n = s->n;
     if (dt) *dt = s->dt;
     if (dev) *dev = s->amp;
     if (stream) *stream = (void *)s->stream;
     return QS_OK;
-}
+} QS_ABI_CATCH
 
 qs_status qs_synchronize(qs_state *s)
-{
+try {
     if (qs_status st = check_state(s)) return st;
     HIP_TRY(hipStreamSynchronize(s->stream));
     return QS_OK;
-}
+} QS_ABI_CATCH
 
 qs_status qs_apply_gate(qs_state *s, const int *targets, int nt, const int *controls, int nc,
                         const double *m)
-{
+try {
     if (qs_status st = check_state(s)) return st;
     if (qs_status st = check_qubits(s->n, targets, nt, controls, nc, QS_MAX_TARGETS)) return st;
     if (qs_status st = check_matrix(m, nt)) return st;
     return apply_gate_host(s, targets, nt, controls, nc, m);
-}
+} QS_ABI_CATCH
 
 qs_status qs_apply_noisy_gate(qs_state *s, const int *targets, int nt, const int *controls, int nc,
                               const double *m, const double *kraus, int nk, double u, int *chosen,
                               double *p_chosen)
-{
+try {
     if (qs_status st = check_state(s)) return st;
     if (nc != 0) return fail(QS_E_UNSUPPORTED, "noisy gates with controls are not supported");
     if (qs_status st = check_qubits(s->n, targets, nt, controls, 0, QS_MAX_TARGETS)) return st;
@@ -2075,27 +2490,27 @@ qs_status qs_apply_noisy_gate(qs_state *s, const int *targets, int nt, const int
     if (!(u >= 0.0 && u < 1.0)) return fail(QS_E_INVAL, "u = %g not in [0, 1)", u);
     if (qs_status st = apply_gate_host(s, targets, nt, nullptr, 0, m)) return st;
     return apply_channel(s, targets, nt, kraus, nk, u, chosen, p_chosen);
-}
+} QS_ABI_CATCH
 
 // ------------------------------------------------------------- circuits --
 
 qs_status qs_circuit_create(qs_circuit **out)
-{
+try {
     if (!out) return fail(QS_E_INVAL, "out is NULL");
     *out = new (std::nothrow) qs_circuit();
     if (!*out) return fail(QS_E_NOMEM, "host allocation failed");
     return QS_OK;
-}
+} QS_ABI_CATCH
 
 qs_status qs_circuit_destroy(qs_circuit *c)
-{
+try {
     delete c;
     return QS_OK;
-}
+} QS_ABI_CATCH
 
 qs_status qs_circuit_append_gate(qs_circuit *c, const int *targets, int nt, const int *controls,
                                  int nc, const double *m)
-{
+try {
     if (!c) return fail(QS_E_INVAL, "circuit is NULL");
     if (qs_status st = check_qubits(QS_MAX_CIRCUIT_QUBITS, targets, nt, controls, nc, QS_MAX_TARGETS)) return st;
     if (qs_status st = check_matrix(m, nt)) return st;
@@ -2107,10 +2522,10 @@ qs_status qs_circuit_append_gate(qs_circuit *c, const int *targets, int nt, cons
     c->ops.push_back(std::move(op));
     c->changed();
     return QS_OK;
-}
+} QS_ABI_CATCH
 
 qs_status qs_circuit_append_noise(qs_circuit *c, const int *targets, int nt, const double *kraus, int nk)
-{
+try {
     if (!c) return fail(QS_E_INVAL, "circuit is NULL");
     if (qs_status st = check_qubits(QS_MAX_CIRCUIT_QUBITS, targets, nt, nullptr, 0, QS_MAX_TARGETS)) return st;
     if (qs_status st = check_kraus(kraus, nk, nt)) return st;
@@ -2127,7 +2542,7 @@ qs_status qs_circuit_append_noise(qs_circuit *c, const int *targets, int nt, con
     c->ops.push_back(std::move(op));
     c->changed();
     return QS_OK;
-}
+} QS_ABI_CATCH
 
 static qs_status push_marker(qs_circuit *c, qs::Op::Kind k, int q)
 {
@@ -2142,13 +2557,13 @@ static qs_status push_marker(qs_circuit *c, qs::Op::Kind k, int q)
     return QS_OK;
 }
 
-qs_status qs_circuit_begin_dagger(qs_circuit *c) { return push_marker(c, qs::Op::BEGIN_DAGGER, -1); }
-qs_status qs_circuit_end_dagger(qs_circuit *c) { return push_marker(c, qs::Op::END_DAGGER, -1); }
-qs_status qs_circuit_begin_control(qs_circuit *c, int q) { return push_marker(c, qs::Op::BEGIN_CONTROL, q); }
-qs_status qs_circuit_end_control(qs_circuit *c) { return push_marker(c, qs::Op::END_CONTROL, -1); }
+qs_status qs_circuit_begin_dagger(qs_circuit *c) try { return push_marker(c, qs::Op::BEGIN_DAGGER, -1); } QS_ABI_CATCH
+qs_status qs_circuit_end_dagger(qs_circuit *c) try { return push_marker(c, qs::Op::END_DAGGER, -1); } QS_ABI_CATCH
+qs_status qs_circuit_begin_control(qs_circuit *c, int q) try { return push_marker(c, qs::Op::BEGIN_CONTROL, q); } QS_ABI_CATCH
+qs_status qs_circuit_end_control(qs_circuit *c) try { return push_marker(c, qs::Op::END_CONTROL, -1); } QS_ABI_CATCH
 
 qs_status qs_circuit_counts(const qs_circuit *c, int64_t *gates, int64_t *noise, int64_t *logical)
-{
+try {
     if (!c) return fail(QS_E_INVAL, "circuit is NULL");
     std::vector<qs::FlatOp> flat;
     std::string err;
@@ -2166,11 +2581,11 @@ qs_status qs_circuit_counts(const qs_circuit *c, int64_t *gates, int64_t *noise,
     if (noise) *noise = z;
     if (logical) *logical = l;
     return QS_OK;
-}
+} QS_ABI_CATCH
 
 qs_status qs_circuit_plan_info(const qs_circuit *c, int n, qs_dtype dt, const qs_run_opts *opts,
                                int64_t *sweeps, int64_t *blocks, int64_t *logical)
-{
+try {
     if (!c) return fail(QS_E_INVAL, "circuit is NULL");
     if (n < 1 || n > QS_MAX_QUBITS) return fail(QS_E_INVAL, "n = %d not in [1, %d]", n, QS_MAX_QUBITS);
     qs_run_opts o{};
@@ -2232,7 +2647,7 @@ qs_status qs_circuit_plan_info(const qs_circuit *c, int n, qs_dtype dt, const qs
     if (blocks) *blocks = bl;
     if (logical) *logical = lg;
     return QS_OK;
-}
+} QS_ABI_CATCH
 
 }  // extern "C"
 
@@ -2318,7 +2733,7 @@ extern "C" {
 
 qs_status qs_circuit_autotune_result(const qs_circuit *c, int n, qs_dtype dt, int *tried, int *candidates,
                                      int *tile_qubits, int *k_max, double *seconds)
-{
+try {
     if (!c) return fail(QS_E_INVAL, "circuit is NULL");
     if (n < 1 || n > QS_MAX_QUBITS) return fail(QS_E_INVAL, "n = %d not in [1, %d]", n, QS_MAX_QUBITS);
     if (dt != QS_C64 && dt != QS_C128) return fail(QS_E_INVAL, "unknown dtype %d", int(dt));
@@ -2341,10 +2756,10 @@ qs_status qs_circuit_autotune_result(const qs_circuit *c, int n, qs_dtype dt, in
     if (k_max) *k_max = km;
     if (seconds) *seconds = sec;
     return QS_OK;
-}
+} QS_ABI_CATCH
 
 qs_status qs_run_circuit(qs_state *s, const qs_circuit *c, const qs_run_opts *opts)
-{
+try {
     if (qs_status st = check_state(s)) return st;
     if (!c) return fail(QS_E_INVAL, "circuit is NULL");
     qs_run_opts o{};
@@ -2359,7 +2774,7 @@ qs_status qs_run_circuit(qs_state *s, const qs_circuit *c, const qs_run_opts *op
     std::shared_ptr<const CachedPlan> cp;
     if (qs_status st = plan_circuit(s, c, o, cp)) return st;
     return execute_plan(s, *cp, o);
-}
+} QS_ABI_CATCH
 
 namespace {
 
@@ -2487,14 +2902,14 @@ qs_status remap(qs_state *s, int g, const int *lq, const void *buf, bool pack)
 }  // namespace
 
 qs_status qs_remap_pack(const qs_state *s, int g, const int *lq, void *device_buf)
-{
+try {
     return remap(const_cast<qs_state *>(s), g, lq, device_buf, true);
-}
+} QS_ABI_CATCH
 
 qs_status qs_remap_unpack(qs_state *s, int g, const int *lq, const void *device_buf)
-{
+try {
     return remap(s, g, lq, device_buf, false);
-}
+} QS_ABI_CATCH
 
 // ------------------------------------------------ partial-amplitude mode --
 
@@ -2908,7 +3323,7 @@ try {
 // -------------------------------------------------------------- readout --
 
 qs_status qs_amplitudes(const qs_state *cs, const uint64_t *idx, size_t m, double *out)
-{
+try {
     qs_state *s = const_cast<qs_state *>(cs);
     if (qs_status st = check_state(s)) return st;
     if (!out && m) return fail(QS_E_INVAL, "out is NULL");
@@ -2919,10 +3334,19 @@ qs_status qs_amplitudes(const qs_state *cs, const uint64_t *idx, size_t m, doubl
             HIP_TRY(hipMemcpyAsync(out, s->amp, na * 16, hipMemcpyDeviceToHost, s->stream));
             HIP_TRY(hipStreamSynchronize(s->stream));
         } else {
-            std::vector<float> f(2 * na);
-            HIP_TRY(hipMemcpyAsync(f.data(), s->amp, na * 8, hipMemcpyDeviceToHost, s->stream));
+            // the floats land in the upper half of `out` and are widened in
+            // place from the front: double k (bytes 8k..8k+8) never reaches
+            // an unread float (bytes from 8 na + 4 (k + 1)), so no staging
+            // copy of the state is allocated
+            unsigned char *base = reinterpret_cast<unsigned char *>(out);
+            HIP_TRY(hipMemcpyAsync(base + 8 * na, s->amp, na * 8, hipMemcpyDeviceToHost, s->stream));
             HIP_TRY(hipStreamSynchronize(s->stream));
-            for (size_t k = 0; k < 2 * na; ++k) out[k] = double(f[k]);
+            for (uint64_t k = 0; k < 2 * na; ++k) {
+                float f;
+                std::memcpy(&f, base + 8 * na + 4 * k, 4);
+                const double d = f;
+                std::memcpy(base + 8 * k, &d, 8);
+            }
         }
         return QS_OK;
     }
@@ -2945,10 +3369,10 @@ qs_status qs_amplitudes(const qs_state *cs, const uint64_t *idx, size_t m, doubl
     hipFree(dvals);
     if (e != hipSuccess) return hip_fail(e, "amplitude gather");
     return QS_OK;
-}
+} QS_ABI_CATCH
 
 qs_status qs_probabilities(const qs_state *cs, const int *qubits, int nq, double *out)
-{
+try {
     qs_state *s = const_cast<qs_state *>(cs);
     if (qs_status st = check_state(s)) return st;
     if (!out) return fail(QS_E_INVAL, "out is NULL");
@@ -2975,10 +3399,10 @@ qs_status qs_probabilities(const qs_state *cs, const int *qubits, int nq, double
     if (big) hipFree(dres);
     if (e != hipSuccess) return hip_fail(e, "probabilities");
     return QS_OK;
-}
+} QS_ABI_CATCH
 
 qs_status qs_norm(const qs_state *cs, double *out)
-{
+try {
     qs_state *s = const_cast<qs_state *>(cs);
     if (qs_status st = check_state(s)) return st;
     if (!out) return fail(QS_E_INVAL, "out is NULL");
@@ -2991,10 +3415,10 @@ qs_status qs_norm(const qs_state *cs, double *out)
     HIP_TRY(hipStreamSynchronize(s->stream));
     *out = s->hpin[0];
     return QS_OK;
-}
+} QS_ABI_CATCH
 
 qs_status qs_expect_z(const qs_state *cs, double *out)
-{
+try {
     qs_state *s = const_cast<qs_state *>(cs);
     if (qs_status st = check_state(s)) return st;
     if (!out) return fail(QS_E_INVAL, "out is NULL");
@@ -3008,21 +3432,102 @@ qs_status qs_expect_z(const qs_state *cs, double *out)
     HIP_TRY(hipStreamSynchronize(s->stream));
     std::memcpy(out, s->hpin, s->n * sizeof(double));
     return QS_OK;
-}
+} QS_ABI_CATCH
 
 // ---------------------------------------------------------- trajectories --
 
-qs_status qs_run_trajectories(const qs_circuit *const *circs, const int *widths, int count,
-                              qs_dtype dt, uint64_t seed, double *z_out, double *seconds)
+}  // extern "C"
+
+namespace {
+
+thread_local qs_traj_stats g_traj_stats{};
+
+// Autotuning records of trajectory batches (QS_PLAN_AUTOTUNE), process-wide,
+// keyed by dtype, batch size and the widths' range and total amplitudes.
+struct TrajTuneKey {
+    int dt, count, wmin, wmax;
+    uint64_t amps;
+    bool operator<(const TrajTuneKey &o) const
+    {
+        return std::tie(dt, count, wmin, wmax, amps) < std::tie(o.dt, o.count, o.wmin, o.wmax, o.amps);
+    }
+};
+std::mutex g_traj_tune_mu;
+std::map<TrajTuneKey, std::vector<double>> g_traj_tune;  // measured seconds per candidate (< 0: not yet run)
+
+// Candidate tile widths of device-sampled passes: (qubits per tile,
+// widest block, outer selector bits per op); the first is the default.
+const TrajParams kTrajCands[] = {{13, 4, 2}, {13, 4, 1}, {13, 4, 3}, {12, 4, 2}, {11, 4, 2}, {13, 5, 2}};
+constexpr int kNumTrajCands = int(sizeof(kTrajCands) / sizeof(kTrajCands[0]));
+
+}  // namespace
+
+extern "C" {
+
+qs_status qs_run_trajectories(const qs_circuit *const *circs, const int *widths, int count, qs_dtype dt,
+                              uint64_t seed, const qs_run_opts *opts, double *z_out, double *traj_per_s)
+try {
+    g_traj_stats = qs_traj_stats{};
+    qs_run_opts o{};
+    if (opts) o = *opts;
+    if (o.plan < QS_PLAN_UNFUSED || o.plan > QS_PLAN_AUTOTUNE) return fail(QS_E_INVAL, "unknown plan %d", o.plan);
+    if (o.k_max && (o.k_max < 4 || o.k_max > 5))
+        return fail(QS_E_INVAL, "k_max = %d: trajectory tiles take 4- or 5-qubit blocks (0 = default)", o.k_max);
+    if (o.tile_qubits && (o.tile_qubits < 10 || o.tile_qubits > 13))
+        return fail(QS_E_INVAL, "tile_qubits = %d not in [10, 13] (0 = default)", o.tile_qubits);
+    if (!widths && count > 0) return fail(QS_E_INVAL, "widths is NULL");
+    TrajParams par = kTrajCands[0];
+    if (o.k_max) par.kmax = o.k_max;
+    if (o.tile_qubits) par.m_cap = o.tile_qubits;
+    int cand = -1;
+    TrajTuneKey key{int(dt), count, 0, 0, 0};
+    if (o.plan == QS_PLAN_AUTOTUNE && dt == QS_C64 && count > 0) {
+        key.wmin = key.wmax = widths[0];
+        for (int t = 0; t < count; ++t) {
+            key.wmin = std::min(key.wmin, widths[t]);
+            key.wmax = std::max(key.wmax, widths[t]);
+            key.amps += (widths[t] >= 0 && widths[t] < 63) ? (uint64_t(1) << widths[t]) : 0;
+        }
+        std::lock_guard<std::mutex> lk(g_traj_tune_mu);
+        auto &rec = g_traj_tune[key];
+        if (rec.empty()) rec.assign(kNumTrajCands, -1.0);
+        for (int c = 0; c < kNumTrajCands && cand < 0; ++c)
+            if (rec[c] < 0) cand = c;
+        if (cand < 0) {
+            cand = 0;
+            for (int c = 1; c < kNumTrajCands; ++c)
+                if (rec[c] < rec[cand]) cand = c;
+        }
+        par = kTrajCands[cand];
+    }
+    qs_traj_stats st{};
+    const qs_status r = run_trajectory_batch(circs, widths, count, dt, seed, par, o.plan != QS_PLAN_UNFUSED,
+                                             o.direct_launch == 0, z_out, st);
+    if (r) return r;
+    if (cand >= 0) {
+        std::lock_guard<std::mutex> lk(g_traj_tune_mu);
+        auto &rec = g_traj_tune[key];
+        if (rec[cand] < 0 || st.seconds < rec[cand]) rec[cand] = st.seconds;
+        st.autotune_candidates = kNumTrajCands;
+        for (double v : rec) st.autotune_tried += v >= 0;
+    }
+    g_traj_stats = st;
+    if (traj_per_s) *traj_per_s = st.seconds > 0 ? double(count) / st.seconds : 0.0;
+    return QS_OK;
+} QS_ABI_CATCH
+
+qs_status qs_trajectory_stats(qs_traj_stats *out)
 {
-    return run_trajectory_batch(circs, widths, count, dt, seed, z_out, seconds);
+    if (!out) return fail(QS_E_INVAL, "out is NULL");
+    *out = g_traj_stats;
+    return QS_OK;
 }
 
 // ------------------------------------------------------------ cost model --
 
 
 qs_status qs_mlp_forward(const float *params, int f, int h, const float *x, int64_t n, float *y)
-{
+try {
     if (qs_status st = check_mlp(params, f, h)) return st;
     if (n < 0 || (n && (!x || !y))) return fail(QS_E_INVAL, "bad samples");
     if (n == 0) return QS_OK;
@@ -3037,11 +3542,11 @@ qs_status qs_mlp_forward(const float *params, int f, int h, const float *x, int6
     HIP_TRY(qs::launch_mlp_forward(dp, f, h, dx, n, dy, nullptr));
     HIP_TRY(hipMemcpy(y, dy, size_t(n) * sizeof(float), hipMemcpyDeviceToHost));
     return QS_OK;
-}
+} QS_ABI_CATCH
 
 qs_status qs_mlp_grad(const float *params, int f, int h, const float *x, const float *tv, int64_t n,
                       float *loss, float *grad)
-{
+try {
     if (qs_status st = check_mlp(params, f, h)) return st;
     if (n < 1 || !x || !tv || !loss || !grad) return fail(QS_E_INVAL, "bad samples");
     const size_t np = qs::mlp_num_params(f, h);
@@ -3059,11 +3564,11 @@ qs_status qs_mlp_grad(const float *params, int f, int h, const float *x, const f
     HIP_TRY(hipMemcpy(grad, dg, np * sizeof(float), hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(loss, dl, sizeof(float), hipMemcpyDeviceToHost));
     return QS_OK;
-}
+} QS_ABI_CATCH
 
 qs_status qs_mlp_train(float *params, int f, int h, const float *x, const float *tv, int64_t n, int steps,
                        int batch, float lr, uint64_t seed, float *loss)
-{
+try {
     if (qs_status st = check_mlp(params, f, h)) return st;
     if (n < 1 || !x || !tv) return fail(QS_E_INVAL, "bad samples");
     if (steps < 0 || batch < 1 || batch > 4096) return fail(QS_E_INVAL, "steps / batch out of range");
@@ -3099,10 +3604,10 @@ qs_status qs_mlp_train(float *params, int f, int h, const float *x, const float 
     HIP_TRY(hipMemcpy(params, dp, np * sizeof(float), hipMemcpyDeviceToHost));
     if (loss) HIP_TRY(hipMemcpy(loss, dl, sizeof(float), hipMemcpyDeviceToHost));
     return QS_OK;
-}
+} QS_ABI_CATCH
 
 qs_status qs_profile_samples(qs_state *s, float *features, float *y, int64_t capacity, int64_t *count)
-{
+try {
     if (qs_status st = check_state(s)) return st;
     if (capacity < 0 || (capacity && (!features || !y)) || !count) return fail(QS_E_INVAL, "bad output arrays");
     if (qs_status st = harvest(s)) return st;
@@ -3114,10 +3619,10 @@ qs_status qs_profile_samples(qs_state *s, float *features, float *y, int64_t cap
     s->samples.erase(s->samples.begin(), s->samples.begin() + c);
     *count = c;
     return QS_OK;
-}
+} QS_ABI_CATCH
 
 qs_status qs_cost_model_set(const float *params, int f, int h)
-{
+try {
     std::lock_guard<std::mutex> lk(g_model_mu);
     g_model_version.fetch_add(1);
     if (!params) {
@@ -3128,28 +3633,28 @@ qs_status qs_cost_model_set(const float *params, int f, int h)
     if (h != qs::kMlpHidden) return fail(QS_E_UNSUPPORTED, "hidden width must be %d", qs::kMlpHidden);
     g_model.assign(params, params + qs::mlp_num_params(f, h));
     return QS_OK;
-}
+} QS_ABI_CATCH
 
 // ------------------------------------------------------------- profiling --
 
 qs_status qs_profile_enable(qs_state *s, int on)
-{
+try {
     if (qs_status st = check_state(s)) return st;
     s->prof = on != 0;
     return QS_OK;
-}
+} QS_ABI_CATCH
 
 qs_status qs_profile_reset(qs_state *s)
-{
+try {
     if (qs_status st = check_state(s)) return st;
     if (qs_status st = harvest(s)) return st;
     for (auto &a : s->acc) a = ProfAcc{};
     return QS_OK;
-}
+} QS_ABI_CATCH
 
 qs_status qs_profile_query(qs_state *s, int kernel, int64_t *launches, double *total_ms,
                            double *alg_bytes, double *alg_flops)
-{
+try {
     if (qs_status st = check_state(s)) return st;
     if (kernel < 0 || kernel >= QS_K_COUNT) return fail(QS_E_INVAL, "unknown kernel class %d", kernel);
     if (qs_status st = harvest(s)) return st;
@@ -3159,11 +3664,13 @@ qs_status qs_profile_query(qs_state *s, int kernel, int64_t *launches, double *t
     if (alg_bytes) *alg_bytes = a.bytes;
     if (alg_flops) *alg_flops = a.flops;
     return QS_OK;
-}
+} QS_ABI_CATCH
 
 }  // extern "C"
 
 namespace qs {
 qs_status set_error(qs_status st, const char *msg) { return fail(st, "%s", msg); }
+const std::vector<Op> &circuit_ops(const qs_circuit *c) { return c->ops; }
+size_t memory_limit() { return g_mem_limit.load(); }
 qs_status run_on_state(qs_state *s, const qs_circuit *c, const qs_run_opts *o) { return qs_run_circuit(s, c, o); }
 }  // namespace qs

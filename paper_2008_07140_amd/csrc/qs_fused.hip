@@ -493,11 +493,13 @@ template <int M, int NT, bool K5>
 __global__ QS_TILE_ATTRS(NT, K5) void k_tile_multi(const TileTask *__restrict__ tasks,
                                                const TileArgsDev *__restrict__ args,
                                                const TileOpDev *__restrict__ ops,
-                                               const uint4 *__restrict__ data)
+                                               const uint4 *__restrict__ data,
+                                               const int *__restrict__ active)
 {
     __shared__ __attribute__((aligned(16))) float2 lds[(1 << M) + 64];
     const TileTask task = tasks[blockIdx.x];
     const TileArgsDev ad = args[task.arg];
+    if (active && !active[ad.slot]) return;  // uniform over the workgroup, before any barrier
     const uint64_t toff = thread_offset<NT>(ad.ta);
     tile_pass<M, NT, K5>(ad.amp, task.tile, ad.ta, toff, ops + ad.op_off, data, lds, lds + (1 << M));
 }
@@ -512,10 +514,10 @@ void launch_m(float2 *a, uint64_t grid, uint64_t ntiles, const TileArgs &ta, con
 
 template <int M, bool K5>
 void launch_multi_m(uint32_t ntasks, const TileTask *tasks, const TileArgsDev *args, const TileOpDev *ops,
-                    const uint4 *d, hipStream_t st)
+                    const uint4 *d, const int *active, hipStream_t st)
 {
     constexpr int NT = tile_threads(M, K5);
-    hipLaunchKernelGGL((k_tile_multi<M, NT, K5>), dim3(ntasks), dim3(NT), 0, st, tasks, args, ops, d);
+    hipLaunchKernelGGL((k_tile_multi<M, NT, K5>), dim3(ntasks), dim3(NT), 0, st, tasks, args, ops, d, active);
 }
 
 }  // namespace
@@ -542,19 +544,20 @@ hipError_t launch_tile(void *amp, int n, const TileArgs &ta, const TileOpDev *de
 }
 
 hipError_t launch_tile_multi(int m, uint32_t ntasks, const TileTask *tasks, const TileArgsDev *args,
-                             const TileOpDev *dev_ops, const void *dev_data, bool k5, hipStream_t st)
+                             const TileOpDev *dev_ops, const void *dev_data, bool k5, const int *active,
+                             hipStream_t st)
 {
     if (m < 10 || m > 13 || ntasks == 0) return hipErrorInvalidValue;
     const uint4 *d = (const uint4 *)dev_data;
     switch (m * 2 + int(k5)) {
-    case 20: launch_multi_m<10, false>(ntasks, tasks, args, dev_ops, d, st); break;
-    case 21: launch_multi_m<10, true>(ntasks, tasks, args, dev_ops, d, st); break;
-    case 22: launch_multi_m<11, false>(ntasks, tasks, args, dev_ops, d, st); break;
-    case 23: launch_multi_m<11, true>(ntasks, tasks, args, dev_ops, d, st); break;
-    case 24: launch_multi_m<12, false>(ntasks, tasks, args, dev_ops, d, st); break;
-    case 25: launch_multi_m<12, true>(ntasks, tasks, args, dev_ops, d, st); break;
-    case 26: launch_multi_m<13, false>(ntasks, tasks, args, dev_ops, d, st); break;
-    default: launch_multi_m<13, true>(ntasks, tasks, args, dev_ops, d, st); break;
+    case 20: launch_multi_m<10, false>(ntasks, tasks, args, dev_ops, d, active, st); break;
+    case 21: launch_multi_m<10, true>(ntasks, tasks, args, dev_ops, d, active, st); break;
+    case 22: launch_multi_m<11, false>(ntasks, tasks, args, dev_ops, d, active, st); break;
+    case 23: launch_multi_m<11, true>(ntasks, tasks, args, dev_ops, d, active, st); break;
+    case 24: launch_multi_m<12, false>(ntasks, tasks, args, dev_ops, d, active, st); break;
+    case 25: launch_multi_m<12, true>(ntasks, tasks, args, dev_ops, d, active, st); break;
+    case 26: launch_multi_m<13, false>(ntasks, tasks, args, dev_ops, d, active, st); break;
+    default: launch_multi_m<13, true>(ntasks, tasks, args, dev_ops, d, active, st); break;
     }
     return hipGetLastError();
 }

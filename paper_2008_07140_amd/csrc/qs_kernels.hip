@@ -348,6 +348,35 @@ __global__ __launch_bounds__(kBlock) void k_phase(typename Cpx<R>::T *a, uint64_
     }
 }
 
+// The common diagonal gate: one factor f != 1 on the amplitudes whose bits
+// in ix.pos read `o` (CZ, T, S, Z, CR after canonicalisation: all their
+// qubits are controls and the table has one entry).  U groups per thread,
+// all loads issued before any multiply or store, so each thread keeps U
+// amplitudes in flight (a load-multiply-store per group would wait on every
+// load, as the stores may alias the next loads).
+template <typename R, int U, bool STREAM>
+__global__ __launch_bounds__(kBlock) void k_phase1(typename Cpx<R>::T *a, uint64_t ngroups, IdxSpec ix,
+                                                   uint64_t o, R fr, R fi)
+{
+    using C = typename Cpx<R>::T;
+    const uint64_t per = uint64_t(kBlock) * U;
+    const uint64_t nchunks = (ngroups + per - 1) / per;
+    for (uint64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const uint64_t base = ch * per + threadIdx.x;
+        uint64_t idx[U];
+        C v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t t = base + uint64_t(u) * kBlock;
+            idx[u] = insert_zeros(t < ngroups ? t : 0, ix) | o;
+            if (t < ngroups) v[u] = ld_amp<C, STREAM>(a + idx[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (base + uint64_t(u) * kBlock < ngroups) st_amp<C, STREAM>(a + idx[u], cmul<C, R>(fr, fi, v[u]));
+    }
+}
+
 // ----------------------------------------------------------- reductions --
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -706,6 +735,21 @@ hipError_t phase_impl(void *amp, int n, const IdxSpec &ix, const int *tq, int nt
         if (x < (1 << nt) && !(re == 1.0 && im == 0.0)) da.active |= uint64_t(1) << x;
     }
     const uint64_t ng = uint64_t(1) << (n - ix.npos);
+    if (__builtin_popcountll(da.active) == 1) {
+        const int x = __builtin_ctzll(da.active);
+        uint64_t o = 0;
+        for (int b = 0; b < nt; ++b)
+            if ((x >> (nt - 1 - b)) & 1) o |= uint64_t(1) << tq[b];
+        constexpr int U1 = 8;
+        const uint64_t g1 = grid_for(ng, uint64_t(kBlock) * U1);
+        if (stream_ok<R>(ix))
+            hipLaunchKernelGGL((k_phase1<R, U1, true>), dim3(unsigned(g1)), dim3(kBlock), 0, st, (C *)amp, ng, ix,
+                               o, da.v[2 * x], da.v[2 * x + 1]);
+        else
+            hipLaunchKernelGGL((k_phase1<R, U1, false>), dim3(unsigned(g1)), dim3(kBlock), 0, st, (C *)amp, ng, ix,
+                               o, da.v[2 * x], da.v[2 * x + 1]);
+        return hipGetLastError();
+    }
     constexpr int U = 4;
     const uint64_t grid = grid_for(ng, uint64_t(kBlock) * U);
     if (stream_ok<R>(ix))

@@ -925,6 +925,8 @@ void plan_tiles_once(const std::vector<FlatOp> &flat, size_t k0, size_t e, int n
     }
 }
 
+}  // namespace
+
 // Relative cost of a tiled plan: a sweep costs its memory pass (1) plus
 // 0.15 per dense block beyond the two that hide under that pass, a gate
 // applied on its own one pass.  The ratio is the per-op time of the tile
@@ -945,26 +947,35 @@ double plan_cost(const std::vector<PlanStep> &steps)
     return c;
 }
 
-}  // namespace
-
 // With the tile-qubit search on, whole plans made with half and with all of
 // the random restarts are compared by plan_cost: more restarts find sweeps
 // that apply more gates, which is not always the cheaper plan (fewer sweeps
 // carrying more blocks).
-void plan_tiles(const std::vector<FlatOp> &flat, size_t k0, size_t e, int n, const TileParams &tp,
-                std::vector<PlanStep> &out)
+void plan_tiles_variants(const std::vector<FlatOp> &flat, size_t k0, size_t e, int n, const TileParams &tp,
+                         std::vector<std::vector<PlanStep>> &out)
 {
+    out.clear();
     if (!tp.search || tp.restarts < 2) {
-        plan_tiles_once(flat, k0, e, n, tp, out);
+        out.emplace_back();
+        plan_tiles_once(flat, k0, e, n, tp, out.back());
         return;
     }
     TileParams half = tp;
     half.restarts = tp.restarts / 2;
-    std::vector<PlanStep> a, b;
-    plan_tiles_once(flat, k0, e, n, half, a);
-    plan_tiles_once(flat, k0, e, n, tp, b);
-    std::vector<PlanStep> &best = plan_cost(b) < plan_cost(a) ? b : a;
-    out.insert(out.end(), std::make_move_iterator(best.begin()), std::make_move_iterator(best.end()));
+    out.resize(2);
+    plan_tiles_once(flat, k0, e, n, half, out[0]);
+    plan_tiles_once(flat, k0, e, n, tp, out[1]);
+}
+
+void plan_tiles(const std::vector<FlatOp> &flat, size_t k0, size_t e, int n, const TileParams &tp,
+                std::vector<PlanStep> &out)
+{
+    std::vector<std::vector<PlanStep>> v;
+    plan_tiles_variants(flat, k0, e, n, tp, v);
+    size_t bi = 0;
+    for (size_t i = 1; i < v.size(); ++i)
+        if (plan_cost(v[i]) < plan_cost(v[bi])) bi = i;
+    out.insert(out.end(), std::make_move_iterator(v[bi].begin()), std::make_move_iterator(v[bi].end()));
 }
 
 }  // namespace qs

@@ -57,6 +57,10 @@ int default_tile_qubits(int n);
 
 qs_status set_error(qs_status st, const char *msg);
 qs_status run_on_state(qs_state *s, const qs_circuit *c, const qs_run_opts *o);
+// The ops of a circuit as appended (groups not yet expanded).
+const std::vector<Op> &circuit_ops(const qs_circuit *c);
+// The process-wide qs_set_memory_limit bound (0 = none).
+size_t memory_limit();
 
 }  // namespace qs
 
@@ -110,8 +114,17 @@ struct PlanStep {
     CanonGate gate;
 };
 
-// Plan the gates flat[k, e) as tile sweeps.
+// Plan the gates flat[k, e) as tile sweeps (appended to out): of the whole
+// plans made with half and with all of tp.restarts, the one with the lower
+// fixed cost estimate.
 void plan_tiles(const std::vector<FlatOp> &flat, size_t k, size_t e, int n, const TileParams &tp,
                 std::vector<PlanStep> &out);
+// The candidate whole plans plan_tiles chooses between (one when the search
+// is off), for a cost model to choose instead.
+void plan_tiles_variants(const std::vector<FlatOp> &flat, size_t k, size_t e, int n, const TileParams &tp,
+                         std::vector<std::vector<PlanStep>> &out);
+// The fixed estimate plan_tiles ranks them by (memory passes plus 0.15 per
+// dense block beyond two per sweep).
+double plan_cost(const std::vector<PlanStep> &steps);
 
 }  // namespace qs

@@ -70,14 +70,17 @@ struct TileTask {
 struct TileArgsDev {
     float2 *amp;
     uint32_t op_off;  // first op of this state's sweep in the op array
-    uint32_t pad;
+    uint32_t slot;    // trajectory slot whose activity flag gates the sweep (device-sampled passes)
     TileArgs ta;
 };
 
 // k5: the op list holds 5-qubit blocks (selects the kernel configuration).
 hipError_t launch_tile(void *amp, int n, const TileArgs &ta, const TileOpDev *dev_ops,
                        const void *dev_data, bool k5, hipStream_t st);
+// active: NULL, or one flag per trajectory slot; workgroups of a slot whose
+// flag is 0 return at once (the state is left as it is).
 hipError_t launch_tile_multi(int m, uint32_t ntasks, const TileTask *tasks, const TileArgsDev *args,
-                             const TileOpDev *dev_ops, const void *dev_data, bool k5, hipStream_t st);
+                             const TileOpDev *dev_ops, const void *dev_data, bool k5, const int *active,
+                             hipStream_t st);
 
 }  // namespace qs

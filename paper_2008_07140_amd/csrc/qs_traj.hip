@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include "qs_internal.h"
+#include "qs_philox.h"
 #include "qs_traj.h"
 
 namespace qs {
@@ -33,11 +34,17 @@ __device__ __forceinline__ double wave_sum_d(double v)
 // rounding of w a_j for x = 1.
 template <typename C, bool WIDE>
 __global__ __launch_bounds__(kT) void k_run_sums(const RunSumTask *__restrict__ tasks,
-                                                 const RunSumArgs *__restrict__ args, double *partials)
+                                                 const RunSumArgs *__restrict__ args, double *partials,
+                                                 const int *__restrict__ active)
 {
     constexpr int NB = 8;
     const RunSumTask task = tasks[blockIdx.x];
     const RunSumArgs &d = args[task.arg];
+    if (active && !active[d.slot]) {  // a frozen trajectory: its sums are not used
+        double *out = partials + uint64_t(blockIdx.x) * (kRunMax + 1);
+        for (int v = threadIdx.x; v <= d.J; v += kT) out[v] = 0.0;
+        return;
+    }
     const C *a = reinterpret_cast<const C *>(d.amp);
     const uint32_t *qw = reinterpret_cast<const uint32_t *>(d.q);  // four qubit bytes per word
     const uint64_t start = uint64_t(task.chunk) * d.chunk_len;
@@ -108,24 +115,91 @@ __global__ __launch_bounds__(kT) void k_run_sums_finish(const double *partials, 
     }
 }
 
+// Branch choice of one run of damping-type sites (Sec. 2.4): with Z the
+// unnormalised squared norm before site j and c_j = 1 - a_j, the weights are
+// p(K2) = c_j S_j / Z and p(K1) = (Z - c_j S_j) / Z; the first b with
+// u < p_0 + ... + p_b is taken (if rounding leaves u beyond the total, the
+// last branch of nonzero weight).  K1 keeps the trajectory on the planned
+// path and lowers Z by c_j S_j; K2 freezes it for the host to continue.
+// The weights are written as plain expressions, without contraction, so
+// that they match the host's branch choice for the same sums.
+__global__ __launch_bounds__(kT) void k_sample_runs(const SampleArgs *__restrict__ sa, uint32_t count,
+                                                    const RunSumArgs *__restrict__ args,
+                                                    const double *__restrict__ sums, uint64_t seed,
+                                                    int *active, Freeze *freeze, int *err)
+{
+#pragma clang fp contract(off)
+    const uint32_t i = blockIdx.x * kT + threadIdx.x;
+    if (i >= count) return;
+    const SampleArgs s = sa[i];
+    if (!active[s.slot]) return;
+    const RunSumArgs &d = args[s.arg];
+    const double *row = sums + uint64_t(s.row) * (kRunMax + 1);
+    double Z = row[0];
+    for (int j = 0; j < d.J; ++j) {
+        const double c = -d.am1[j];
+        const double S = row[1 + j];
+        const double cs = c * S;
+        const double p2 = cs / Z;
+        const double p1 = (Z - cs) / Z;
+        const double u = noise_uniform(seed, s.traj, s.site[j]);
+        int b;
+        if (u < p1)
+            b = 0;
+        else if (u < p1 + p2)
+            b = 1;
+        else
+            b = p2 > 0.0 ? 1 : (p1 > 0.0 ? 0 : -1);
+        if (b == 0) {
+            Z -= cs;
+            continue;
+        }
+        if (b < 0) {
+            err[0] = 1;
+            active[s.slot] = 0;
+            return;
+        }
+        Freeze f;
+        f.step = int32_t(s.step);
+        f.j = j;
+        f.nrm2 = cs;
+        freeze[s.slot] = f;
+        active[s.slot] = 0;
+        return;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_run_sums(qs_dtype dt, int nmax, uint32_t ntasks, const RunSumTask *tasks, const RunSumArgs *args,
-                           double *partials, hipStream_t st)
+                           double *partials, const int *active, hipStream_t st)
 {
     if (ntasks == 0) return hipSuccess;
     const bool wide = nmax > 32;
     if (dt == QS_C128) {
         if (wide)
-            hipLaunchKernelGGL((k_run_sums<double2, true>), dim3(ntasks), dim3(kT), 0, st, tasks, args, partials);
+            hipLaunchKernelGGL((k_run_sums<double2, true>), dim3(ntasks), dim3(kT), 0, st, tasks, args, partials,
+                               active);
         else
-            hipLaunchKernelGGL((k_run_sums<double2, false>), dim3(ntasks), dim3(kT), 0, st, tasks, args, partials);
+            hipLaunchKernelGGL((k_run_sums<double2, false>), dim3(ntasks), dim3(kT), 0, st, tasks, args, partials,
+                               active);
     } else {
         if (wide)
-            hipLaunchKernelGGL((k_run_sums<float2, true>), dim3(ntasks), dim3(kT), 0, st, tasks, args, partials);
+            hipLaunchKernelGGL((k_run_sums<float2, true>), dim3(ntasks), dim3(kT), 0, st, tasks, args, partials,
+                               active);
         else
-            hipLaunchKernelGGL((k_run_sums<float2, false>), dim3(ntasks), dim3(kT), 0, st, tasks, args, partials);
+            hipLaunchKernelGGL((k_run_sums<float2, false>), dim3(ntasks), dim3(kT), 0, st, tasks, args, partials,
+                               active);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_sample_runs(const SampleArgs *sa, uint32_t count, const RunSumArgs *args, const double *sums,
+                              uint64_t seed, int *active, Freeze *freeze, int *err, hipStream_t st)
+{
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sample_runs, dim3((count + kT - 1) / kT), dim3(kT), 0, st, sa, count, args, sums, seed,
+                       active, freeze, err);
     return hipGetLastError();
 }
 

@@ -45,7 +45,22 @@ class QSError(RuntimeError):
 class RunOpts(C.Structure):
     _fields_ = [("plan", C.c_int), ("k_max", C.c_int), ("seed", C.c_uint64),
                 ("traj", C.c_uint64), ("chosen", C.POINTER(C.c_int64)),
-                ("chosen_len", C.c_int64), ("tile_qubits", C.c_int), ("tile_order", C.c_int)]
+                ("chosen_len", C.c_int64), ("tile_qubits", C.c_int), ("tile_order", C.c_int),
+                ("direct_launch", C.c_int)]
+
+
+class TrajStats(C.Structure):
+    _fields_ = [("passes", C.c_int), ("host_sampled", C.c_int), ("jumps", C.c_int64),
+                ("launches", C.c_int64), ("graph", C.c_int), ("tile_qubits", C.c_int),
+                ("k_max", C.c_int), ("max_outer", C.c_int), ("autotune_tried", C.c_int),
+                ("autotune_candidates", C.c_int), ("seconds", C.c_double),
+                ("host_seconds", C.c_double), ("device_seconds", C.c_double)]
+
+
+class SingleInfo(C.Structure):
+    _fields_ = [("vertices", C.c_int), ("tensors", C.c_int), ("fixed", C.c_int), ("sliced", C.c_int),
+                ("merges", C.c_int), ("max_rank", C.c_int), ("flops", C.c_double),
+                ("peak_bytes", C.c_double), ("batch", C.c_int)]
 
 
 class ScriptInfo(C.Structure):
@@ -81,11 +96,14 @@ _sig = {
     "qs_probabilities": ([P, P, I, P], I),
     "qs_norm": ([P, P], I),
     "qs_expect_z": ([P, P], I),
-    "qs_run_trajectories": ([P, P, I, I, U64, P, P], I),
+    "qs_run_trajectories": ([P, P, I, I, U64, C.POINTER(RunOpts), P, P], I),
+    "qs_trajectory_stats": ([C.POINTER(TrajStats)], I),
     "qs_remap_pack": ([P, I, P, P], I),
     "qs_remap_unpack": ([P, I, P, P], I),
     "qs_partial_amplitudes": ([P, I, I, U64, P, SZ, P, C.POINTER(RunOpts), P], I),
     "qs_partial_cuts": ([P, I, U64, P], I),
+    "qs_single_amplitudes": ([P, I, P, SZ, I, P, C.POINTER(SingleInfo)], I),
+    "qs_single_plan": ([P, I, I, C.POINTER(SingleInfo)], I),
     "qs_script_parse": ([C.c_char_p, PP, C.POINTER(ScriptInfo)], I),
     "qs_script_run": ([C.c_char_p, I, U64, I, P, I, P, SZ, C.POINTER(ScriptInfo)], I),
     "qs_philox_uniform": ([U64, U64, U64], D),
@@ -261,6 +279,22 @@ class Circuit:
         _check(_lib.qs_partial_amplitudes(self._h, n, dtype, part_a, _ptr(ix), ix.size,
                                           _ptr(out.view(np.float64)), C.byref(o), C.byref(c)))
         return out, c.value
+
+    def single_amplitudes(self, n: int, bits, nslice: int = 0):
+        """qs_single_amplitudes: (complex128 amplitudes <x|C|0...0> for each
+        bitstring x in `bits`, shape of the contraction as a dict)."""
+        b = np.ascontiguousarray(np.asarray(bits, dtype=np.uint64).reshape(-1))
+        out = np.empty(b.size, dtype=np.complex128)
+        info = SingleInfo()
+        _check(_lib.qs_single_amplitudes(self._h, n, _ptr(b), b.size, nslice, _ptr(out.view(np.float64)),
+                                         C.byref(info)))
+        return out, {f: getattr(info, f) for f, _ in SingleInfo._fields_}
+
+    def single_plan(self, n: int, nslice: int = 0) -> dict:
+        """qs_single_plan: the contraction's shape for one bitstring (host only)."""
+        info = SingleInfo()
+        _check(_lib.qs_single_plan(self._h, n, nslice, C.byref(info)))
+        return {f: getattr(info, f) for f, _ in SingleInfo._fields_}
 
     def autotune_result(self, n: int, dtype: int = C64):
         """(tried, candidates, tile_qubits, k_max, seconds) of QS_PLAN_AUTOTUNE
@@ -452,12 +486,19 @@ class State:
 
 
 def run_trajectories(circuits: Sequence[Circuit], widths: Sequence[int], dtype: int = C64,
-                     seed: int = 0):
-    """Returns (z [sum widths], seconds)."""
+                     seed: int = 0, plan: int = PLAN_GREEDY, k_max: int = 0, tile_qubits: int = 0,
+                     direct_launch: bool = False):
+    """qs_run_trajectories: (z [sum widths], statistics of the call as a dict,
+    including traj_per_s)."""
     arr = (C.c_void_p * len(circuits))(*[c.handle.value for c in circuits])
     w = _ints(widths)
     z = np.empty(int(w.sum()), dtype=np.float64)
-    sec = C.c_double()
+    o = RunOpts(plan=plan, k_max=k_max, tile_qubits=tile_qubits, direct_launch=1 if direct_launch else 0)
+    rate = C.c_double()
     _check(_lib.qs_run_trajectories(C.cast(arr, C.c_void_p), _ptr(w), len(circuits), dtype, seed,
-                                    _ptr(z), C.byref(sec)))
-    return z, sec.value
+                                    C.byref(o), _ptr(z), C.byref(rate)))
+    st = TrajStats()
+    _check(_lib.qs_trajectory_stats(C.byref(st)))
+    info = {f: getattr(st, f) for f, _ in TrajStats._fields_}
+    info["traj_per_s"] = rate.value
+    return z, info

@@ -196,22 +196,25 @@ def test_autotune_result_before_any_run(qs):
     assert (c.plan_info(20, qs.C64, qs.PLAN_AUTOTUNE) == c.plan_info(20, qs.C64, qs.PLAN_GREEDY))
 
 
-def test_run_opts_layout_matches_header(qs, tmp_path):
-    """The binding's RunOpts mirrors qs_run_opts field by field (offsets and
-    size from a C program built against include/qs.h), and the candidate
-    count of tile orders agrees."""
+@pytest.mark.parametrize("struct,cname", [("RunOpts", "qs_run_opts"), ("TrajStats", "qs_traj_stats"),
+                                          ("SingleInfo", "qs_single_info"), ("ScriptInfo", "qs_script_info")])
+def test_binding_structs_match_header(qs, tmp_path, struct, cname):
+    """Each ctypes structure of the binding mirrors its C struct field by
+    field (offsets and size from a C program built against include/qs.h),
+    and the candidate count of tile orders agrees."""
     import ctypes
     import subprocess
-    fields = [f for f, _ in qs.RunOpts._fields_]
+    cls = getattr(qs, struct)
+    fields = [f for f, _ in cls._fields_]
     src = tmp_path / "layout.c"
     src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"qs.h\"\nint main(void) {\n"
-                   + "".join('printf("%%zu\\n", offsetof(qs_run_opts, %s));\n' % f for f in fields)
-                   + 'printf("%zu\\n%d\\n", sizeof(qs_run_opts), QS_TILE_ORDERS);\nreturn 0;\n}\n')
+                   + "".join('printf("%%zu\\n", offsetof(%s, %s));\n' % (cname, f) for f in fields)
+                   + 'printf("%%zu\\n%%d\\n", sizeof(%s), QS_TILE_ORDERS);\nreturn 0;\n}\n' % cname)
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True,
                                           text=True).stdout.split()]
-    want = [getattr(qs.RunOpts, f).offset for f in fields] + [ctypes.sizeof(qs.RunOpts), qs.TILE_ORDERS]
+    want = [getattr(cls, f).offset for f in fields] + [ctypes.sizeof(cls), qs.TILE_ORDERS]
     assert got == want
 
 
@@ -349,3 +352,69 @@ def test_script_errors_name_the_line(qs):
             qs.script_parse(text)
         assert e.value.status == status, text
         assert qs.last_error().startswith(where + ":"), (text, qs.last_error())
+
+
+# ------------------------------------------------ single-amplitude mode --
+
+
+def test_single_graph_vertex_rules(qs):
+    """Fig. 2: a diagonal gate keeps its qubits' vertices (a), (c); any other
+    gate adds one vertex per target (b), (d), and a control keeps its vertex.
+    Every qubit's first vertex is fixed to 0 and its last to the measured bit
+    (a qubit whose first vertex is also its last is fixed once)."""
+    n = 5
+    h = cg.H_GATE
+    cnot = np.array([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 0, 1], [0, 0, 1, 0]], dtype=np.complex128)
+    diag_only = [cg.Gate((q,), (), cg.T_GATE) for q in range(n)] + \
+        [cg.Gate((0, 1), (), cg.CZ_GATE), cg.Gate((2, 4), (), cg.CZ_GATE)]
+    i = qs.Circuit(diag_only).single_plan(n)
+    assert i["vertices"] == n and i["fixed"] == n and i["tensors"] == len(diag_only)
+    dense = [cg.Gate((q,), (), h) for q in range(n)]
+    i = qs.Circuit(dense).single_plan(n)
+    assert i["vertices"] == 2 * n and i["fixed"] == 2 * n and i["tensors"] == n
+    # CNOT: the control keeps its vertex, the target gets one; a dense
+    # two-qubit gate gets two; CU3 (controlled U3) one
+    two = [cg.Gate((0, 1), (), cnot), cg.Gate((2, 3), (), cg.random_unitary(4, np.random.default_rng(1))),
+           cg.Gate((4,), (1,), cg.u3(0.3, 0.2, 0.1))]
+    i = qs.Circuit(two).single_plan(n)
+    assert i["vertices"] == n + 1 + 2 + 1
+    # identity gates are no edges
+    i = qs.Circuit([cg.Gate((q,), (), np.eye(2)) for q in range(n)]).single_plan(n)
+    assert i["vertices"] == n and i["tensors"] == 0 and i["merges"] == 0
+
+
+def test_single_graph_counts_on_workload_circuits(qs):
+    """On the grid random circuits (T and CZ diagonal, the other one-qubit
+    gates and CU3 dense on one target) the vertex count is n plus the
+    non-diagonal one-qubit gates; slicing fixes that many more vertices and
+    multiplies the graphs, and planning is deterministic."""
+    for rows, cols, depth, cu3 in ((4, 4, 8, 0.1), (7, 7, 10, 0.0), (6, 10, 10, 0.0)):
+        n = rows * cols
+        ops = cg.random_circuit(rows, cols, depth, seed=77, cu3_prob=cu3)
+        dense = sum(1 for o in ops if o.kind == "gate" and o.name not in ("t", "cz"))
+        c = qs.Circuit(ops)
+        i0 = c.single_plan(n)
+        assert i0["vertices"] == n + dense
+        assert i0["fixed"] == 2 * n and i0["sliced"] == 0 and i0["batch"] == 1
+        assert i0["tensors"] >= sum(1 for o in ops if o.kind == "gate")
+        i4 = c.single_plan(n, 4)
+        assert i4["sliced"] == 4 and i4["fixed"] == 2 * n + 4 and i4["batch"] == 16
+        assert c.single_plan(n) == i0
+
+
+def test_single_validation(qs):
+    c = qs.Circuit([cg.Gate((0,), (), cg.H_GATE)])
+    for n, ns, st in ((0, 0, -1), (63, 0, -1), (2, -1, -1), (2, 17, -1)):
+        with pytest.raises(qs.QSError) as e:
+            c.single_plan(n, ns)
+        assert e.value.status == st
+    with pytest.raises(qs.QSError) as e:
+        qs.Circuit([cg.Gate((5,), (), cg.H_GATE)]).single_plan(3)
+    assert e.value.status == -2
+    noisy = qs.Circuit([cg.Gate((0,), (), cg.I2), cg.Noise((0,), cg.kraus_depolarizing(0.1))])
+    with pytest.raises(qs.QSError) as e:
+        noisy.single_plan(2)
+    assert e.value.status == -6
+    with pytest.raises(qs.QSError) as e:
+        c.single_amplitudes(2, [4])  # bit 2 set on a 2-qubit circuit: rejected before any device work
+    assert e.value.status == -2

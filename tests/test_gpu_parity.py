@@ -524,6 +524,53 @@ def test_batched_trajectories_match_oracle_per_trajectory(qs, dtype):
         off += n
 
 
+def test_trajectory_passes_graph_direct_and_host_sampled_agree(qs):
+    """At amplified rates many trajectories jump, so the device-sampled path
+    needs several passes (each jump rewrites the trajectory from that site
+    on).  The captured-graph passes and the same launches enqueued directly
+    give bit-identical results; the host-sampled path (per-gate kernels,
+    branch choice on the host) makes the same choices, so <Z_q> agree to
+    complex64 rounding; and every trajectory is the oracle's run with the
+    same Philox draws."""
+    batch = _traj_batch(24, 10, 14, 6, 1300, 0.08)
+    circs = [qs.Circuit(ops) for _, ops in batch]
+    widths = [n for n, _ in batch]
+    zg, ig = qs.run_trajectories(circs, widths, dtype=qs.C64, seed=55)
+    zd, idr = qs.run_trajectories(circs, widths, dtype=qs.C64, seed=55, direct_launch=True)
+    zh, ih = qs.run_trajectories(circs, widths, dtype=qs.C64, seed=55, plan=qs.PLAN_UNFUSED)
+    assert ig["graph"] == 1 and idr["graph"] == 0 and ig["host_sampled"] == 0
+    assert ig["passes"] >= 2 and ig["jumps"] > 0 and ig["jumps"] == idr["jumps"] == ih["jumps"]
+    assert ih["passes"] == 0 and ih["host_sampled"] == len(batch)
+    assert np.array_equal(zg, zd)
+    assert np.max(np.abs(zg - zh)) <= 1e-4
+    off = 0
+    for t, (n, ops) in enumerate(batch):
+        psi, _ = oracle.run(n, ops, seed=55, traj=t)
+        assert np.max(np.abs(zg[off:off + n] - oracle.expect_z(psi))) <= 1e-4, (t, n)
+        off += n
+
+
+def test_trajectory_autotune_runs_every_width_set_exactly(qs):
+    """QS_PLAN_AUTOTUNE: each of the first calls for a batch shape runs the
+    next candidate width set (tile qubits, block width, outer bits) over the
+    whole batch; every call is an exact run (the oracle's <Z_q> per
+    trajectory), and once all are measured the fastest is kept."""
+    batch = _traj_batch(8, 14, 15, 4, 1400, 0.05)
+    circs = [qs.Circuit(ops) for _, ops in batch]
+    widths = [n for n, _ in batch]
+    want = np.concatenate([oracle.expect_z(oracle.run(n, ops, seed=57, traj=t)[0])
+                           for t, (n, ops) in enumerate(batch)])
+    seen = set()
+    ncand = None
+    for call in range(8):
+        z, info = qs.run_trajectories(circs, widths, dtype=qs.C64, seed=57, plan=qs.PLAN_AUTOTUNE)
+        assert np.max(np.abs(z - want)) <= 1e-4, call
+        ncand = info["autotune_candidates"]
+        assert info["autotune_tried"] == min(call + 1, ncand)
+        seen.add((info["tile_qubits"], info["k_max"], info["max_outer"]))
+    assert ncand >= 2 and len(seen) == ncand
+
+
 def test_batched_trajectories_wider_than_a_tile(qs):
     """States of 14..16 qubits span several 13-qubit tiles, so the batched
     sweeps select operators on the qubits outside the tile; each trajectory
@@ -663,11 +710,11 @@ def test_mlp_training_reduces_loss(qs):
     assert l1 < 0.05 * l0, (l0, l1)
 
 
-def test_learned_planner_parity_and_gain(qs):
-    """Samples come from profiled tile sweeps of random circuits under many
-    tile shapes; the network trained on them picks the tile shape of a
-    held-out circuit.  The learned plan must agree with the oracle, predict
-    held-out sweep times, and not run slower than the default plan."""
+@pytest.fixture(scope="module")
+def cost_model(qs):
+    """The planner's cost network trained on the simulator's own timings:
+    profiled tile sweeps of random circuits under every tile shape; 20% of
+    the samples are held out."""
     n = 24
     s = qs.State(n, qs.C64)
     s.profile(True)
@@ -680,17 +727,24 @@ def test_learned_planner_parity_and_gain(qs):
                 s.run(c, plan=qs.PLAN_GREEDY, k_max=k, tile_qubits=m)
     X, y = s.profile_samples()
     s.profile(False)
-    assert X.shape[0] > 200
+    s.close()
     rng = np.random.default_rng(0)
     perm = rng.permutation(X.shape[0])
     tr, te = perm[: int(0.8 * len(perm))], perm[int(0.8 * len(perm)):]
     p, _ = qs.mlp_train(qs.mlp_init(4), X[tr], y[tr], steps=3000, batch=256, lr=2e-3, seed=7)
-    pred = qs.mlp_forward(p, X[te])
-    corr = np.corrcoef(pred, y[te])[0, 1]
+    return p, X[te], y[te], X.shape[0]
+
+
+def test_cost_model_predicts_held_out_sweeps_and_learned_plans_are_exact(qs, cost_model):
+    """The trained network predicts held-out sweep times (correlation > 0.8),
+    and plans it chooses apply the circuit exactly (oracle, 16 and 20
+    qubits)."""
+    p, Xte, yte, nsamp = cost_model
+    assert nsamp > 200
+    corr = np.corrcoef(qs.mlp_forward(p, Xte), yte)[0, 1]
     assert corr > 0.8, corr
     qs.cost_model_set(p)
     try:
-        # parity of the learned plan with the oracle (16 and 20 qubits)
         for rows, cols, depth in [(4, 4, 20), (4, 5, 24)]:
             ops = cg.random_circuit(rows, cols, depth, seed=77, cu3_prob=0.1)
             ref, _ = oracle.run(rows * cols, ops)
@@ -698,26 +752,55 @@ def test_learned_planner_parity_and_gain(qs):
             t.run(qs.Circuit(ops), plan=qs.PLAN_LEARNED)
             assert infidelity(ref, t.amplitudes()) <= 1e-6
             t.close()
-        # measured gain on a held-out circuit
-        held = qs.Circuit(cg.random_circuit(4, 6, 24, seed=9999, cu3_prob=0.1))
-        times = {}
-        for plan in (qs.PLAN_GREEDY, qs.PLAN_LEARNED):
-            best = 1e9
-            for _ in range(3):
-                s.reset()
-                s.synchronize()
-                t0 = __import__("time").perf_counter()
-                s.run(held, plan=plan)
-                s.synchronize()
-                best = min(best, __import__("time").perf_counter() - t0)
-            times[plan] = best
-        print("learned vs greedy: %.4f s vs %.4f s (gain %.3fx)"
-              % (times[qs.PLAN_LEARNED], times[qs.PLAN_GREEDY],
-                 times[qs.PLAN_GREEDY] / times[qs.PLAN_LEARNED]))
-        assert times[qs.PLAN_LEARNED] <= 1.10 * times[qs.PLAN_GREEDY]
+    finally:
+        qs.cost_model_set(None)
+
+
+def test_learned_planner_measured_ratio_on_held_out_circuits(qs, cost_model):
+    """What the trained network gains over the plan without it, measured:
+    three held-out 24-qubit circuits, each plan warmed up past its
+    tile-order timing runs (QS_TILE_ORDERS + 1 runs), then the median of
+    five timed runs.  The ratio greedy / learned is printed per circuit
+    ("no gain" when the network keeps the greedy plan or does not beat
+    it).  The learned plan is the greedy plan unless the network predicts
+    it at least 3% cheaper, so a large loss would mean the network is
+    wrong about whole plans: the geometric mean must stay above 0.9."""
+    import time
+    p = cost_model[0]
+    n = 24
+    s = qs.State(n, qs.C64)
+    ratios = []
+    try:
+        for seed, (rows, cols) in zip((9991, 9992, 9993), ((4, 6), (6, 4), (3, 8))):
+            held = qs.Circuit(cg.random_circuit(rows, cols, 24, seed=seed, cu3_prob=0.1))
+            times = {}
+            for plan in (qs.PLAN_GREEDY, qs.PLAN_LEARNED):
+                qs.cost_model_set(p if plan == qs.PLAN_LEARNED else None)
+                for _ in range(qs.TILE_ORDERS + 1):
+                    s.reset()
+                    s.run(held, plan=plan)
+                runs = []
+                for _ in range(5):
+                    s.reset()
+                    s.synchronize()
+                    t0 = time.perf_counter()
+                    s.run(held, plan=plan)
+                    s.synchronize()
+                    runs.append(time.perf_counter() - t0)
+                times[plan] = float(np.median(runs))
+            qs.cost_model_set(p)
+            same = held.plan_info(n, qs.C64, qs.PLAN_LEARNED) == held.plan_info(n, qs.C64, qs.PLAN_GREEDY)
+            r = times[qs.PLAN_GREEDY] / times[qs.PLAN_LEARNED]
+            ratios.append(r)
+            print("held-out %dx%d: greedy %.4f s, learned %.4f s, greedy/learned %.3f%s"
+                  % (rows, cols, times[qs.PLAN_GREEDY], times[qs.PLAN_LEARNED], r,
+                     " (same plan: no gain)" if same else ("" if r > 1.0 else " (no gain)")), flush=True)
     finally:
         qs.cost_model_set(None)
         s.close()
+    gm = float(np.exp(np.mean(np.log(ratios))))
+    print("geometric mean greedy/learned %.3f" % gm, flush=True)
+    assert gm > 0.9
 
 
 # ------------------------------------------------ sharded states: remap --
@@ -1049,3 +1132,95 @@ def test_script_measure_outcomes_match_oracle_draws(qs):
         assert probs[creg[3]] == pytest.approx(1.0, abs=1e-12) and info["measures"] == 4
         seen.add(creg[0])
     assert seen == {0, 1}
+
+
+# ------------------------------------------------ single-amplitude mode --
+
+
+def _bitstrings(n, count, seed, extra=()):
+    rng = np.random.default_rng(seed)
+    b = rng.integers(0, 1 << n, size=count, dtype=np.uint64)
+    return np.concatenate([np.array(list(extra), dtype=np.uint64), b])
+
+
+@pytest.mark.parametrize("rows,cols,depth,nslice", [(3, 4, 10, 0), (4, 4, 12, 0), (4, 4, 12, 3), (4, 5, 8, 5)])
+def test_single_amplitudes_match_oracle(qs, rows, cols, depth, nslice):
+    """Sec. 2.3: <x|C|0...0> from the graphical model's eliminations equals
+    the oracle's full-amplitude entry x (complex128 bound 1e-12), with and
+    without slicing (2^nslice graphs summed)."""
+    n = rows * cols
+    ops = cg.random_circuit(rows, cols, depth, seed=1500 + n + depth, cu3_prob=0.1)
+    ref, _ = oracle.run(n, ops)
+    bits = _bitstrings(n, 64, n + nslice, [0, (1 << n) - 1, 1, 1 << (n - 1)])
+    print("[single] n=%d depth=%d nslice=%d" % (n, depth, nslice), flush=True)
+    got, info = qs.Circuit(ops).single_amplitudes(n, bits, nslice)
+    assert info["sliced"] == nslice and info["batch"] >= (1 << nslice)
+    assert np.max(np.abs(got - ref[bits.astype(np.int64)])) <= TOL128
+
+
+def test_single_amplitudes_every_gate_form_groups_and_idle_qubit(qs):
+    """Dense gates of 1-6 targets with controls, diagonal gates of up to four
+    qubits, DAGGER and CONTROL groups, and a qubit no gate touches (its
+    amplitudes with bit 9 set are exactly 0): all 1024 amplitudes of a
+    10-qubit circuit against the oracle's state."""
+    n = 10
+    ops = _mixed_circuit(9, 40, 1601)
+    full = ([cg.Marker("control", 8)] + list(ops[:12]) + [cg.Marker("endcontrol")]
+            + [cg.Marker("dagger")] + list(ops[12:30]) + [cg.Marker("enddagger")] + list(ops[30:])
+            + [cg.Gate((3,), (), cg.T_GATE), cg.Gate((0, 5), (), cg.CZ_GATE)])
+    ref, _ = oracle.run(n, full)
+    bits = np.arange(1 << n, dtype=np.uint64)
+    got, info = qs.Circuit(full).single_amplitudes(n, bits, 2)
+    assert np.max(np.abs(got - ref)) <= TOL128
+    assert np.all(got[512:] == 0)
+
+
+@pytest.mark.parametrize("parts", [2, 3])
+def test_single_amplitudes_wide_product_circuits(qs, parts):
+    """40 and 60 qubits (no full state fits anywhere): `parts` independent
+    20-qubit depth-8 random circuits on the qubits q with q mod parts = j,
+    interleaved gate by gate.  The graph falls apart into `parts`
+    components and every amplitude is the product of the oracle's
+    amplitudes of the parts."""
+    nh = 20
+    n = parts * nh
+    halves = [cg.random_circuit(4, 5, 8, seed=1700 + j, cu3_prob=0.1) for j in range(parts)]
+    placed = []
+    for j, h in enumerate(halves):
+        placed.append([cg.Gate(tuple(parts * q + j for q in o.targets),
+                               tuple(parts * q + j for q in o.controls), o.matrix, o.name) for o in h])
+    ops = [g for group in zip(*placed) for g in group]
+    refs = [oracle.run(nh, h)[0] for h in halves]
+    bits = _bitstrings(n, 48, 1750 + parts, [0, (1 << n) - 1, 1 << (n - 1)])
+    want = np.ones(bits.size, dtype=np.complex128)
+    for j in range(parts):
+        sub = np.zeros(bits.size, dtype=np.int64)
+        for b in range(nh):
+            sub |= ((bits >> np.uint64(parts * b + j)) & np.uint64(1)).astype(np.int64) << b
+        want *= refs[j][sub]
+    print("[single] %d qubits, %d parts" % (n, parts), flush=True)
+    got, info = qs.Circuit(ops).single_amplitudes(n, bits)
+    scale = np.max(np.abs(want))
+    assert np.max(np.abs(got - want)) <= 1e-10 * scale
+
+
+def test_single_amplitudes_in_bitstring_chunks(qs):
+    """A memory bound smaller than the tensors of every bitstring at once
+    makes the call process the bitstrings in chunks: the results are the
+    same as in one chunk and the oracle's."""
+    rows, cols, depth = 4, 4, 10
+    n = rows * cols
+    ops = cg.random_circuit(rows, cols, depth, seed=1801, cu3_prob=0.1)
+    ref, _ = oracle.run(n, ops)
+    bits = _bitstrings(n, 300, 1802)
+    c = qs.Circuit(ops)
+    one, i1 = c.single_amplitudes(n, bits, 1)
+    peak = c.single_plan(n, 1)["peak_bytes"]
+    qs.set_memory_limit(int(peak * 7))
+    try:
+        chunked, i2 = c.single_amplitudes(n, bits, 1)
+    finally:
+        qs.set_memory_limit(0)
+    assert i2["batch"] < i1["batch"]
+    assert np.max(np.abs(one - ref[bits.astype(np.int64)])) <= TOL128
+    assert np.max(np.abs(chunked - one)) <= 1e-15
