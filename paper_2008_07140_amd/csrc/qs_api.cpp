@@ -162,11 +162,13 @@ struct qs_circuit {
     mutable std::mutex mu;
     mutable std::map<PlanKey, std::shared_ptr<const CachedPlan>> cache;
     mutable std::map<std::pair<int, int>, Tuning> tuning;
+    mutable std::map<uint64_t, std::shared_ptr<const void>> other;  // plans of other modes (single-amplitude)
     void changed()
     {
         std::lock_guard<std::mutex> lk(mu);
         cache.clear();
         tuning.clear();
+        other.clear();
     }
 };
 
@@ -1588,7 +1590,37 @@ struct PinnedBuf {
 struct TrajParams {
     int m_cap = 13;     // qubits per tile (at most the state's width)
     int kmax = 4;       // widest dense block
-    int max_outer = 2;  // outer selector bits per op
+    int max_outer = 1;  // outer selector bits per op
+    int chunk = 128;    // trajectories per device-sampled pass job (0 = all at once)
+};
+
+// Device buffers, host staging and the graph of one device-sampled pass
+// job; a batch keeps two, so that the host builds the next job while the
+// device runs the current one.
+struct PassSlot {
+    DevBuf prog, work;
+    PinnedBuf stage, back;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, done = nullptr;
+    bool busy = false;            // launched, results not yet read
+    std::vector<int> set;         // the job's trajectories
+    std::vector<char> out;        // per trajectory: plan needs per-gate launches (host-sampled path)
+    size_t zb = 0, err_at = 0;    // read-back layout: freeze records, error flag, final sums
+    void drop_graph()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    }
+    ~PassSlot()
+    {
+        drop_graph();
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        if (done) (void)hipEventDestroy(done);
+    }
 };
 
 struct Batch {
@@ -1604,9 +1636,11 @@ struct Batch {
     DevBuf states, prog, red, work;
     PinnedBuf stage, back;       // uploads (written only after the stream has drained), read-backs
     std::vector<View *> views;
+    PassSlot slot[2];
     qs_traj_stats st{};
     ~Batch()
     {
+        if (master) (void)hipStreamSynchronize(master->stream);  // no buffer is freed under a running kernel
         for (auto *v : views) delete v;
         if (master) free_state(master);
     }
@@ -1897,15 +1931,16 @@ qs_status run_host_sampled(Batch &B, const std::vector<int> &set)
 
 // ---------------------------------------------------- device-sampled path --
 
-// One pass over `set` (complex64 states of >= 10 qubits): every remaining
-// step planned, one upload, one graph (or the same launches enqueued
-// directly), one read-back.  On return `set` holds the trajectories that
-// jumped (their steps rewritten from the jump on) and `demoted` those whose
-// plans need per-gate launches (they take the host-sampled path).
-qs_status run_device_pass(Batch &B, std::vector<int> &set, std::vector<int> &demoted)
+// Launch one pass job over the trajectories `job` (complex64 states of
+// >= 10 qubits) in slot P: every remaining step planned, one upload, one
+// graph (or the same launches enqueued directly) and the read-back of its
+// results, all enqueued on the batch's stream; finish_pass reads them.
+qs_status launch_pass(Batch &B, PassSlot &P, std::vector<int> job)
 {
     using clock = std::chrono::steady_clock;
     const auto t0 = clock::now();
+    P.set = std::move(job);
+    const std::vector<int> &set = P.set;
     const int S = int(set.size());
     const int w = qs::kRunMax + 1;
     qs_state *s = B.master;
@@ -1939,7 +1974,8 @@ qs_status run_device_pass(Batch &B, std::vector<int> &set, std::vector<int> &dem
         const TPrep &tp = B.prep[set[pe[k].slot]];
         plan_gate_list(B, tp.n, tp.steps[pe[k].step].gates, pe[k].plan);
     });
-    std::vector<char> out(S, 0);  // plans with per-gate steps: host-sampled path instead
+    P.out.assign(S, 0);  // plans with per-gate steps: host-sampled path instead
+    std::vector<char> &out = P.out;
     for (auto &p : pe)
         for (auto &st : p.plan)
             if (!st.sweep) out[p.slot] = 1;
@@ -2106,27 +2142,38 @@ qs_status run_device_pass(Batch &B, std::vector<int> &set, std::vector<int> &dem
     const size_t o_sums = o_part + align256(std::max<size_t>(max_rtasks, 1) * w * sizeof(double));
     const size_t o_zs = o_sums + align256(std::max<size_t>(max_rows, 1) * w * sizeof(double));
     const size_t work_bytes = o_zs + align256(size_t(S) * w * sizeof(double));
-    HIP_TRY(hipStreamSynchronize(s->stream));  // the staging buffer may still feed an earlier copy
+    // the slot's previous job has been read (finish_pass), so its staging
+    // and device buffers are free; a larger job regrows them, which waits
+    // for the stream (the other slot's job may still run on it)
     {
-        hipError_t e = B.prog.ensure(up_bytes);
-        if (e == hipSuccess) e = B.work.ensure(work_bytes);
-        if (e == hipSuccess) e = B.stage.ensure(up_bytes);
-        if (e == hipSuccess) e = B.back.ensure(o_err - o_freeze + 256 + size_t(S) * w * sizeof(double));
+        const size_t back_bytes = o_err - o_freeze + 256 + size_t(S) * w * sizeof(double);
+        if (up_bytes > P.prog.cap || work_bytes > P.work.cap) HIP_TRY(hipStreamSynchronize(s->stream));
+        hipError_t e = P.prog.ensure(up_bytes);
+        if (e == hipSuccess) e = P.work.ensure(work_bytes);
+        if (e == hipSuccess) e = P.stage.ensure(up_bytes);
+        if (e == hipSuccess) e = P.back.ensure(back_bytes);
+        if (e == hipSuccess && !P.ev0) e = hipEventCreate(&P.ev0);
+        if (e == hipSuccess && !P.ev1) e = hipEventCreate(&P.ev1);
+        if (e == hipSuccess && !P.done) e = hipEventCreateWithFlags(&P.done, hipEventDisableTiming);
         if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(QS_E_NOMEM, "trajectory pass buffers")
                                                                : hip_fail(e, "trajectory pass buffers");
     }
-    unsigned char *host = static_cast<unsigned char *>(B.stage.p);
-    auto put = [&](size_t off, const void *src, size_t bytes) {
-        if (bytes) std::memcpy(host + off, src, bytes);
-    };
-    put(0, tp.ops.data(), b_ops);
-    put(o_data, tp.data.data(), b_data);
-    put(o_targs, targs.data(), targs.size() * sizeof(qs::TileArgsDev));
-    put(o_ttasks, ttasks.data(), ttasks.size() * sizeof(qs::TileTask));
-    put(o_rargs, rargs.data(), rargs.size() * sizeof(qs::RunSumArgs));
-    put(o_rtasks, rtasks.data(), rtasks.size() * sizeof(qs::RunSumTask));
-    put(o_fc, fc.data(), fc.size() * sizeof(uint32_t));
-    put(o_sargs, sargs.data(), sargs.size() * sizeof(qs::SampleArgs));
+    unsigned char *host = static_cast<unsigned char *>(P.stage.p);
+    struct Piece { size_t off; const void *src; size_t bytes; };
+    std::vector<Piece> pieces = {{0, tp.ops.data(), b_ops},
+                                 {o_targs, targs.data(), targs.size() * sizeof(qs::TileArgsDev)},
+                                 {o_ttasks, ttasks.data(), ttasks.size() * sizeof(qs::TileTask)},
+                                 {o_rargs, rargs.data(), rargs.size() * sizeof(qs::RunSumArgs)},
+                                 {o_rtasks, rtasks.data(), rtasks.size() * sizeof(qs::RunSumTask)},
+                                 {o_fc, fc.data(), fc.size() * sizeof(uint32_t)},
+                                 {o_sargs, sargs.data(), sargs.size() * sizeof(qs::SampleArgs)}};
+    const size_t slice = size_t(1) << 20;  // the operand data dominates: copied in parallel slices
+    for (size_t o = 0; o < b_data; o += slice)
+        pieces.push_back({o_data + o, reinterpret_cast<const unsigned char *>(tp.data.data()) + o,
+                          std::min(slice, b_data - o)});
+    parallel_for(pieces.size(), [&](size_t i) {
+        if (pieces[i].bytes) std::memcpy(host + pieces[i].off, pieces[i].src, pieces[i].bytes);
+    });
     {
         int *act = reinterpret_cast<int *>(host + o_active);
         qs::Freeze *fr = reinterpret_cast<qs::Freeze *>(host + o_freeze);
@@ -2136,8 +2183,8 @@ qs_status run_device_pass(Batch &B, std::vector<int> &set, std::vector<int> &dem
         }
         *reinterpret_cast<int *>(host + o_err) = 0;
     }
-    unsigned char *dev = static_cast<unsigned char *>(B.prog.p);
-    unsigned char *wk = static_cast<unsigned char *>(B.work.p);
+    unsigned char *dev = static_cast<unsigned char *>(P.prog.p);
+    unsigned char *wk = static_cast<unsigned char *>(P.work.p);
     HIP_TRY(hipMemcpyAsync(dev, host, up_bytes, hipMemcpyHostToDevice, s->stream));
     const auto t1 = clock::now();
     // ---- the pass's launches
@@ -2177,59 +2224,61 @@ qs_status run_device_pass(Batch &B, std::vector<int> &set, std::vector<int> &dem
         }
         return hipSuccess;
     };
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    HIP_TRY(hipEventCreate(&ev0));
-    if (hipError_t e = hipEventCreate(&ev1)) {
-        hipEventDestroy(ev0);
-        return hip_fail(e, "event creation");
-    }
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    auto cleanup = [&](qs_status r) {
-        if (exec) hipGraphExecDestroy(exec);
-        if (graph) hipGraphDestroy(graph);
-        hipEventDestroy(ev0);
-        hipEventDestroy(ev1);
-        return r;
-    };
-    hipError_t e = hipEventRecord(ev0, s->stream);
+    hipError_t e = hipEventRecord(P.ev0, s->stream);
     if (e == hipSuccess) {
         if (B.graph) {
             e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
                 hipError_t el = enqueue();
-                e = hipStreamEndCapture(s->stream, &graph);
+                e = hipStreamEndCapture(s->stream, &P.graph);
                 if (el != hipSuccess) e = el;
             }
-            if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-            if (e == hipSuccess) e = hipGraphLaunch(exec, s->stream);
+            if (e == hipSuccess) e = hipGraphInstantiate(&P.exec, P.graph, nullptr, nullptr, 0);
+            if (e == hipSuccess) e = hipGraphLaunch(P.exec, s->stream);
         } else {
             e = enqueue();
         }
     }
-    if (e == hipSuccess) e = hipEventRecord(ev1, s->stream);
-    unsigned char *back = static_cast<unsigned char *>(B.back.p);
-    const size_t zb = o_err - o_freeze + 256;
-    if (e == hipSuccess) e = hipMemcpyAsync(back, dev + o_freeze, zb, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipEventRecord(P.ev1, s->stream);
+    unsigned char *back = static_cast<unsigned char *>(P.back.p);
+    P.zb = o_err - o_freeze + 256;
+    P.err_at = o_err - o_freeze;
+    if (e == hipSuccess) e = hipMemcpyAsync(back, dev + o_freeze, P.zb, hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(back + zb, dzs, size_t(S) * w * sizeof(double), hipMemcpyDeviceToHost, s->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-    if (e != hipSuccess) return cleanup(hip_fail(e, "trajectory pass"));
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, ev0, ev1) == hipSuccess) B.st.device_seconds += 1e-3 * ms;
+        e = hipMemcpyAsync(back + P.zb, dzs, size_t(S) * w * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipEventRecord(P.done, s->stream);
+    if (e != hipSuccess) {
+        P.drop_graph();
+        return hip_fail(e, "trajectory pass");
+    }
+    P.busy = true;
     B.st.host_seconds += std::chrono::duration<double>(t1 - t0).count();
     B.st.launches += nl;
-    ++B.st.passes;
-    if (*reinterpret_cast<const int *>(back + (o_err - o_freeze)))
-        return cleanup(fail(QS_E_ZERO_NORM, "every Kraus branch of a damping site has probability 0"));
-    // ---- results: completed trajectories write <Z_q>; jumped ones continue
+    ++B.st.graphs;
+    return QS_OK;
+}
+
+// Wait for slot P's job and read its results: completed trajectories write
+// <Z_q>; those whose run took K2 are rewritten from the jump on and go to
+// `next`; those whose plans need per-gate launches go to `demoted`.
+qs_status finish_pass(Batch &B, PassSlot &P, std::vector<int> &next, std::vector<int> &demoted)
+{
+    const int w = qs::kRunMax + 1;
+    P.busy = false;
+    hipError_t e = hipEventSynchronize(P.done);
+    P.drop_graph();
+    if (e != hipSuccess) return hip_fail(e, "trajectory pass");
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, P.ev0, P.ev1) == hipSuccess) B.st.device_seconds += 1e-3 * ms;
+    const unsigned char *back = static_cast<const unsigned char *>(P.back.p);
+    if (*reinterpret_cast<const int *>(back + P.err_at))
+        return fail(QS_E_ZERO_NORM, "every Kraus branch of a damping site has probability 0");
     const qs::Freeze *fr = reinterpret_cast<const qs::Freeze *>(back);
-    const double *zs = reinterpret_cast<const double *>(back + zb);
-    std::vector<int> next;
+    const double *zs = reinterpret_cast<const double *>(back + P.zb);
     size_t row = 0;
-    for (int i = 0; i < S; ++i) {
-        const int t = set[i];
-        if (out[i]) {
+    for (size_t i = 0; i < P.set.size(); ++i) {
+        const int t = P.set[i];
+        if (P.out[i]) {
             demoted.push_back(t);
             continue;
         }
@@ -2246,8 +2295,35 @@ qs_status run_device_pass(Batch &B, std::vector<int> &set, std::vector<int> &dem
         ++B.st.jumps;
         next.push_back(t);
     }
-    set.swap(next);
-    return cleanup(QS_OK);
+    return QS_OK;
+}
+
+// Device-sampled passes over `set` until no trajectory is left: each pass
+// splits its trajectories into jobs of B.par.chunk, launched alternately in
+// two slots, so that the host builds a job while the device runs the one
+// before it.
+qs_status run_device_sampled(Batch &B, std::vector<int> set, std::vector<int> &demoted)
+{
+    while (!set.empty()) {
+        const size_t C = B.par.chunk > 0 ? size_t(B.par.chunk) : set.size();
+        std::vector<int> next;
+        int k = 0;
+        for (size_t pos = 0; pos < set.size(); pos += C, ++k) {
+            PassSlot &P = B.slot[k & 1];
+            if (P.busy)
+                if (qs_status e = finish_pass(B, P, next, demoted)) return e;
+            std::vector<int> chunk(set.begin() + long(pos), set.begin() + long(std::min(set.size(), pos + C)));
+            if (qs_status e = launch_pass(B, P, std::move(chunk))) return e;
+        }
+        for (int j = 0; j < 2; ++j) {  // the older job first
+            PassSlot &P = B.slot[(k + j) & 1];
+            if (P.busy)
+                if (qs_status e = finish_pass(B, P, next, demoted)) return e;
+        }
+        ++B.st.passes;
+        set.swap(next);
+    }
+    return QS_OK;
 }
 
 qs_status run_trajectory_batch(const qs_circuit *const *circs, const int *widths, int count, qs_dtype dt,
@@ -2302,9 +2378,9 @@ qs_status run_trajectory_batch(const qs_circuit *const *circs, const int *widths
     std::vector<int> dev_set, host_set;
     for (int t = 0; t < count; ++t) (device_ok && device_sampled(B, t) ? dev_set : host_set).push_back(t);
     B.st.graph = graph && !dev_set.empty();
-    while (!dev_set.empty()) {
+    {
         std::vector<int> demoted;
-        if (qs_status e = run_device_pass(B, dev_set, demoted)) return e;
+        if (qs_status e = run_device_sampled(B, dev_set, demoted)) return e;
         host_set.insert(host_set.end(), demoted.begin(), demoted.end());
     }
     B.st.host_sampled = int(host_set.size());
@@ -2313,6 +2389,7 @@ qs_status run_trajectory_batch(const qs_circuit *const *circs, const int *widths
     B.st.tile_qubits = par.m_cap;
     B.st.k_max = par.kmax;
     B.st.max_outer = par.max_outer;
+    B.st.chunk = par.chunk;
     B.st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     stats = B.st;
     return QS_OK;
@@ -3455,9 +3532,11 @@ struct TrajTuneKey {
 std::mutex g_traj_tune_mu;
 std::map<TrajTuneKey, std::vector<double>> g_traj_tune;  // measured seconds per candidate (< 0: not yet run)
 
-// Candidate tile widths of device-sampled passes: (qubits per tile,
-// widest block, outer selector bits per op); the first is the default.
-const TrajParams kTrajCands[] = {{13, 4, 2}, {13, 4, 1}, {13, 4, 3}, {12, 4, 2}, {11, 4, 2}, {13, 5, 2}};
+// Candidate widths of device-sampled passes: (qubits per tile, widest
+// block, outer selector bits per op, trajectories per pass job); the first
+// is the default.
+const TrajParams kTrajCands[] = {{13, 4, 1, 128}, {13, 4, 1, 64}, {13, 4, 1, 0},
+                                 {13, 4, 2, 128}, {12, 4, 1, 128}, {13, 5, 1, 128}};
 constexpr int kNumTrajCands = int(sizeof(kTrajCands) / sizeof(kTrajCands[0]));
 
 }  // namespace
@@ -3671,6 +3750,17 @@ try {
 namespace qs {
 qs_status set_error(qs_status st, const char *msg) { return fail(st, "%s", msg); }
 const std::vector<Op> &circuit_ops(const qs_circuit *c) { return c->ops; }
+std::shared_ptr<const void> circuit_cache_get(const qs_circuit *c, uint64_t key)
+{
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto it = c->other.find(key);
+    return it == c->other.end() ? nullptr : it->second;
+}
+void circuit_cache_put(const qs_circuit *c, uint64_t key, std::shared_ptr<const void> v)
+{
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->other[key] = std::move(v);
+}
 size_t memory_limit() { return g_mem_limit.load(); }
 qs_status run_on_state(qs_state *s, const qs_circuit *c, const qs_run_opts *o) { return qs_run_circuit(s, c, o); }
 }  // namespace qs

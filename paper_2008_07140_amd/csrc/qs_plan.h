@@ -2,6 +2,7 @@
 // fusion planner (host side).
 #pragma once
 
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -59,6 +60,10 @@ qs_status set_error(qs_status st, const char *msg);
 qs_status run_on_state(qs_state *s, const qs_circuit *c, const qs_run_opts *o);
 // The ops of a circuit as appended (groups not yet expanded).
 const std::vector<Op> &circuit_ops(const qs_circuit *c);
+// Plans of other modes kept with a circuit, by key; dropped when the
+// circuit changes (thread-safe).
+std::shared_ptr<const void> circuit_cache_get(const qs_circuit *c, uint64_t key);
+void circuit_cache_put(const qs_circuit *c, uint64_t key, std::shared_ptr<const void> v);
 // The process-wide qs_set_memory_limit bound (0 = none).
 size_t memory_limit();
 

@@ -30,6 +30,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <new>
 #include <set>
 #include <string>
@@ -344,9 +345,8 @@ qs_status plan_merges(Plan &P, int trial)
 // lowest vertex first); the plan with the fewest flops is kept.
 constexpr int kTrials = 16;
 
-qs_status make_plan(const qs_circuit *c, int n, int nslice, Plan &P)
+qs_status make_plan_uncached(const qs_circuit *c, int n, int nslice, Plan &P)
 {
-    if (!c) return sfail(QS_E_INVAL, "circuit is NULL");
     Plan G;
     if (qs_status st = build_graph(c, n, nslice, G)) return st;
     qs_status last = QS_OK;
@@ -364,6 +364,23 @@ qs_status make_plan(const qs_circuit *c, int n, int nslice, Plan &P)
         }
     }
     return have ? QS_OK : last;
+}
+
+// Plans are kept with the circuit, per (n, nslice), until it changes.
+qs_status make_plan(const qs_circuit *c, int n, int nslice, std::shared_ptr<const Plan> &out)
+{
+    if (!c) return sfail(QS_E_INVAL, "circuit is NULL");
+    const uint64_t key = (uint64_t(0x5A) << 56) | (uint64_t(uint32_t(n)) << 8) | uint64_t(uint8_t(nslice));
+    if (n >= 1 && n <= QS_MAX_CIRCUIT_QUBITS && nslice >= 0 && nslice <= QS_SINGLE_MAX_SLICES)
+        if (auto v = qs::circuit_cache_get(c, key)) {
+            out = std::static_pointer_cast<const Plan>(v);
+            return QS_OK;
+        }
+    auto P = std::make_shared<Plan>();
+    if (qs_status st = make_plan_uncached(c, n, nslice, *P)) return st;
+    qs::circuit_cache_put(c, key, P);
+    out = P;
+    return QS_OK;
 }
 
 // ------------------------------------------------------------ memory plan --
@@ -440,8 +457,9 @@ extern "C" {
 
 qs_status qs_single_plan(const qs_circuit *c, int n, int nslice, qs_single_info *info)
 try {
-    Plan P;
-    if (qs_status st = make_plan(c, n, nslice, P)) return st;
+    std::shared_ptr<const Plan> PP;
+    if (qs_status st = make_plan(c, n, nslice, PP)) return st;
+    const Plan &P = *PP;
     std::vector<size_t> off;
     const uint32_t bt = uint32_t(1) << P.nslice;
     fill_info(P, bt, place(P, bt, off), info);
@@ -454,8 +472,9 @@ qs_status qs_single_amplitudes(const qs_circuit *c, int n, const uint64_t *bits,
                                qs_single_info *info)
 try {
     if (m && (!bits || !out)) return sfail(QS_E_INVAL, "bits or out is NULL");
-    Plan P;
-    if (qs_status st = make_plan(c, n, nslice, P)) return st;
+    std::shared_ptr<const Plan> PP;
+    if (qs_status st = make_plan(c, n, nslice, PP)) return st;
+    const Plan &P = *PP;
     for (size_t w = 0; w < m; ++w)
         if (n < 64 && (bits[w] >> n)) return sfail(QS_E_RANGE, "bitstring %zu sets a qubit >= %d", w, n);
     const uint32_t S = uint32_t(1) << P.nslice;

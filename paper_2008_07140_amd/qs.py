@@ -50,7 +50,8 @@ class RunOpts(C.Structure):
 
 
 class TrajStats(C.Structure):
-    _fields_ = [("passes", C.c_int), ("host_sampled", C.c_int), ("jumps", C.c_int64),
+    _fields_ = [("passes", C.c_int), ("graphs", C.c_int), ("chunk", C.c_int), ("host_sampled", C.c_int),
+                ("jumps", C.c_int64),
                 ("launches", C.c_int64), ("graph", C.c_int), ("tile_qubits", C.c_int),
                 ("k_max", C.c_int), ("max_outer", C.c_int), ("autotune_tried", C.c_int),
                 ("autotune_candidates", C.c_int), ("seconds", C.c_double),

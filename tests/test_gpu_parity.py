@@ -567,7 +567,7 @@ def test_trajectory_autotune_runs_every_width_set_exactly(qs):
         assert np.max(np.abs(z - want)) <= 1e-4, call
         ncand = info["autotune_candidates"]
         assert info["autotune_tried"] == min(call + 1, ncand)
-        seen.add((info["tile_qubits"], info["k_max"], info["max_outer"]))
+        seen.add((info["tile_qubits"], info["k_max"], info["max_outer"], info["chunk"]))
     assert ncand >= 2 and len(seen) == ncand
 
 
