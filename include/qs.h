@@ -242,6 +242,27 @@ qs_status qs_amplitudes(const qs_state *s, const uint64_t *idx, size_t m, double
  * that out[i] = |alpha_i|^2.  The state is unchanged.  nq <= 30. */
 qs_status qs_probabilities(const qs_state *s, const int *qubits, int nq, double *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * PMEASURE probabilities of qs_probabilities, computed by the same kernels,
+ * for a state held in caller-owned device memory, written to caller-owned
+ * device memory.  device_amps: 2^n amplitudes of dtype dt as a state stores
+ * them (16-byte aligned), only read; qubits / nq as in qs_probabilities
+ * (NULL = all n qubits, n-1 first); device_out: 2^nq doubles (8-byte
+ * aligned), only written.  Work is enqueued on hip_stream (a hipStream_t;
+ * NULL = the default stream) and the call returns without waiting; it
+ * makes no allocation of any kind (no hipMalloc, no host allocation).  The
+ * block partial sums live in a static device array of
+ * QS_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends; every call
+ * on one GPU shares it and overwrites what it reads (nothing needs to start
+ * at zero), so calls that overlap in time on one GPU race: order them on one
+ * stream.  Errors: QS_E_INVAL (pointers, alignment, n, dt, nq), QS_E_RANGE
+ * (qubits, or a reduction needing more than the static scratch),
+ * QS_E_UNSUPPORTED (nq > 30), QS_E_DEVICE. */
+#define QS_NOALLOC_SCRATCH_BYTES (8u * 1024u * 1024u + 512u)
+qs_status qs_probabilities_noalloc(const void *device_amps, int n, qs_dtype dt, const int *qubits, int nq,
+                                   double *device_out, void *hip_stream);
+
 /* Squared norm sum_i |alpha_i|^2, accumulated in FP64. */
 qs_status qs_norm(const qs_state *s, double *out);
 

@@ -15,6 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libqs.so")
 
 SOURCES = ["qs_kernels.hip", "qs_fused.hip", "qs_traj.hip", "qs_mlp.hip", "qs_remap.hip", "qs_single.hip",
+           "qs_noalloc.hip",
            "qs_api.cpp", "qs_plan.cpp", "qs_script.cpp", "qs_single.cpp"]
 HEADERS = ["qs_internal.h", "qs_plan.h", "qs_philox.h", "qs_tile.h", "qs_traj.h", "qs_mlp.h", "qs_single.h"]
 

@@ -42,17 +42,17 @@ using cd = std::complex<double>;
 
 namespace {
 
-thread_local std::string g_err;
+// Text of the last failure on this thread, in a fixed buffer (recording an
+// error allocates nothing).
+thread_local char g_err[512];
 std::atomic<size_t> g_mem_limit{0};
 
 qs_status fail(qs_status st, const char *fmt, ...)
 {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
     va_end(ap);
-    g_err = buf;
     return st;
 }
 
@@ -2430,7 +2430,7 @@ struct DevTmp {
 
 extern "C" {
 
-const char *qs_last_error(void) { return g_err.c_str(); }
+const char *qs_last_error(void) { return g_err; }
 
 qs_status qs_set_memory_limit(size_t bytes)
 try {
@@ -3477,6 +3477,36 @@ try {
     if (e != hipSuccess) return hip_fail(e, "probabilities");
     return QS_OK;
 } QS_ABI_CATCH
+
+qs_status qs_probabilities_noalloc(const void *device_amps, int n, qs_dtype dt, const int *qubits, int nq,
+                                   double *device_out, void *hip_stream)
+{
+    if (!device_amps || !device_out) return fail(QS_E_INVAL, "device_amps or device_out is NULL");
+    if (n < 1 || n > QS_MAX_QUBITS) return fail(QS_E_INVAL, "n = %d not in [1, %d]", n, QS_MAX_QUBITS);
+    if (dt != QS_C64 && dt != QS_C128) return fail(QS_E_INVAL, "unknown dtype %d", int(dt));
+    if (reinterpret_cast<uintptr_t>(device_amps) % 16 || reinterpret_cast<uintptr_t>(device_out) % 8)
+        return fail(QS_E_INVAL, "device_amps must be 16-byte and device_out 8-byte aligned");
+    int q[QS_MAX_QUBITS];
+    if (!qubits) {
+        nq = n;
+        for (int k = 0; k < n; ++k) q[k] = n - 1 - k;
+    } else {
+        if (qs_status st = check_qubits(n, qubits, nq, nullptr, 0, 30)) return st;
+        for (int k = 0; k < nq; ++k) q[k] = qubits[k];
+    }
+    if (nq > 30) return fail(QS_E_UNSUPPORTED, "PMEASURE over more than 30 qubits");
+    // the reductions that bin through the scratch take at most 1024 bins
+    const size_t need = qs::reduce_scratch_doubles(n, nq <= 10 ? (1 << nq) : 1);
+    if (need > qs::noalloc_scratch_doubles())
+        return fail(QS_E_RANGE, "the reduction needs %zu scratch doubles, the static scratch holds %zu", need,
+                    qs::noalloc_scratch_doubles());
+    double *scr = nullptr;
+    hipError_t e = qs::noalloc_scratch(&scr);
+    if (e != hipSuccess) return hip_fail(e, "static reduction scratch");
+    e = qs::launch_probs(dt, device_amps, n, q, nq, scr, device_out, static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return hip_fail(e, "probabilities");
+    return QS_OK;
+}
 
 qs_status qs_norm(const qs_state *cs, double *out)
 try {

@@ -95,6 +95,10 @@ hipError_t launch_remap(qs_dtype dt, void *shard, void *buf, int L, int g, const
 // acc = m (re, im) doubles): one branch of the partial-amplitude recombination
 hipError_t launch_partial_cmac(qs_dtype dt, const void *a, const void *b, const uint64_t *ia,
                                const uint64_t *ib, uint64_t m, double *acc, hipStream_t st);
+// Reduction scratch in a static device array (qs_noalloc.hip): the address
+// of the current device's copy (looked up once per device) and its size.
+hipError_t noalloc_scratch(double **out);
+size_t noalloc_scratch_doubles();
 // amp *= scale (real), used for renormalisation
 hipError_t launch_scale(qs_dtype dt, void *amp, uint64_t n_amp, double scale, hipStream_t st);
 

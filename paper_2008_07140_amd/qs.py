@@ -95,6 +95,7 @@ _sig = {
     "qs_circuit_plan_info": ([P, I, I, C.POINTER(RunOpts), P, P, P], I),
     "qs_amplitudes": ([P, P, SZ, P], I),
     "qs_probabilities": ([P, P, I, P], I),
+    "qs_probabilities_noalloc": ([P, I, I, P, I, P, P], I),
     "qs_norm": ([P, P], I),
     "qs_expect_z": ([P, P], I),
     "qs_run_trajectories": ([P, P, I, I, U64, C.POINTER(RunOpts), P, P], I),
@@ -346,6 +347,14 @@ def script_run(text: str, dtype: int = C128, seed: int = 0, plan: int = PLAN_UNF
     _check(_lib.qs_script_run(text.encode(), dtype, seed, plan, creg, info.creg, _ptr(probs), probs.size,
                               C.byref(info)))
     return ([creg[j] for j in range(info.creg)], probs if info.pmeasure_n else None, _info_dict(info))
+
+
+def probabilities_noalloc(device_amps: int, n: int, dtype: int, qubits, device_out: int, stream: int = 0):
+    """qs_probabilities_noalloc on raw device pointers (ints): enqueues the
+    reduction on `stream` and returns at once; nothing is allocated."""
+    q = None if qubits is None else _ints(qubits)
+    _check(_lib.qs_probabilities_noalloc(C.c_void_p(device_amps), n, dtype, _ptr(q), 0 if q is None else len(q),
+                                         C.c_void_p(device_out), C.c_void_p(stream or 0)))
 
 
 class State:
