@@ -74,13 +74,18 @@ def parse():
     return p.parse_args()
 
 
+# The device sources of the kernels whose counters bench.py reports: the
+# tile sweeps and the per-gate kernels of the fused and plain paths.
+PROFILED_SOURCES = ("qs_fused.hip", "qs_kernels.hip")
+
+
 def source_hash():
-    """Hash of the device code: every .hip source and the headers it includes
-    (transitively), so host-only changes (planner, executor) keep stored
-    counter readings valid."""
+    """Hash of the device code of the profiled paths: their .hip sources and
+    the headers those include (transitively), so host-only changes and
+    changes to other kernels keep stored counter readings valid."""
     import re
     csrc = os.path.join(ROOT, "paper_2008_07140_amd", "csrc")
-    files, todo = set(), [os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith(".hip")]
+    files, todo = set(), [os.path.join(csrc, f) for f in PROFILED_SOURCES]
     while todo:
         f = os.path.normpath(todo.pop())
         if f in files or not os.path.exists(f):
@@ -134,6 +139,12 @@ PROFILE_RUNS = [
      "--steps 1 --warmup 0 --no-cpu-baseline --trajectories 0 --no-by-target --no-extras --paths plain_c128"),
     ("pmc_write_plain_c128", "--pmc WRITE_SIZE",
      "--steps 1 --warmup 0 --no-cpu-baseline --trajectories 0 --no-by-target --no-extras --paths plain_c128"),
+    ("pmc_sq1_fused_c64", "--pmc GRBM_GUI_ACTIVE SQ_VALU_MFMA_BUSY_CYCLES SQ_ACTIVE_INST_VALU SQ_LDS_IDX_ACTIVE "
+     "SQ_LDS_BANK_CONFLICT SQ_ACTIVE_INST_LDS SQ_BUSY_CU_CYCLES SQ_WAVE_CYCLES SQ_WAVES",
+     "--steps 1 --warmup 0 --no-cpu-baseline --trajectories 0 --no-by-target --no-extras --paths fused_c64"),
+    ("pmc_sq2_fused_c64", "--pmc GRBM_GUI_ACTIVE SQ_INSTS_VALU SQ_INSTS_MFMA SQ_INSTS_LDS SQ_INSTS_VMEM_RD "
+     "SQ_INSTS_VMEM_WR SQ_INSTS_SALU SQ_INSTS_VALU_MFMA_MOPS_BF16 SQ_WAIT_INST_LDS",
+     "--steps 1 --warmup 0 --no-cpu-baseline --trajectories 0 --no-by-target --no-extras --paths fused_c64"),
     ("remap", "--kernel-trace --stats", "--remap"),
     ("pmc_fetch_copy", "--pmc FETCH_SIZE", "--copy-calibration"),
     ("pmc_write_copy", "--pmc WRITE_SIZE", "--copy-calibration"),
@@ -156,6 +167,8 @@ def kernel_class_of(name: str):
         return "tile"
     if f.startswith("k_dense1"):
         return "dense1"
+    if f.startswith("k_phase"):
+        return "phase"
     table = {"k_dense_small": "dense_small", "k_denseN": "denseN", "k_phase": "phase", "k_init": "init",
              "k_scale": "other"}
     if f in table:
@@ -190,6 +203,76 @@ def _counter_means(d, sub):
         c, t = acc.get(k, (0, 0.0))
         acc[k] = (c + 1, t + v)
     return {k: (c, t / c) for k, (c, t) in acc.items()}
+
+
+def _counters_by_name(d, sub, kernel_class):
+    """{counter: mean value per dispatch} over the dispatches of one kernel
+    class in a --pmc pass with several counters (one CSV row per dispatch and
+    counter)."""
+    import glob
+    files = glob.glob(os.path.join(d, sub, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        return None
+    acc = {}
+    for r in _csv_rows(files[0]):
+        if kernel_class_of(r["Kernel_Name"]) != kernel_class:
+            continue
+        c, t = acc.get(r["Counter_Name"], (0, 0.0))
+        acc[r["Counter_Name"]] = (c + 1, t + float(r["Counter_Value"]))
+    return {k: t / c for k, (c, t) in acc.items()}
+
+
+def summarize_sq(d, cmds, src, cu=256, simd=1024, xcd=8):
+    """profiles/counters_k_tile_rqc30_d40.md: instruction mix and unit
+    activity of the tile kernel from two --pmc passes of SQ counters, with
+    rocprofv3's own formulas for the derived ratios (CU_NUM = 256,
+    SIMD_NUM = 1024 on MI355X).  The counter CSV sums each counter over its
+    hardware instances; the formulas take the maximum of GRBM_GUI_ACTIVE over
+    the eight XCDs, which run the whole dispatch, so the sum / 8 stands in
+    for it."""
+    a = _counters_by_name(d, "pmc_sq1_fused_c64", "tile")
+    b = _counters_by_name(d, "pmc_sq2_fused_c64", "tile")
+    if not a or not b:
+        return
+    g = a.get("GRBM_GUI_ACTIVE", 0.0) / xcd
+    lines = ["# Tile kernel counters, 30-qubit depth-40 circuit (rqc30_d40), fused complex64 path", "",
+             "Two `rocprofv3 --pmc` passes over one step (28 `k_tile` dispatches: 4-qubit blocks on the",
+             "matrix cores, split-bf16); mean per dispatch, each counter summed over its hardware",
+             "instances.  Derived ratios use rocprofv3's formulas, with GRBM_GUI_ACTIVE / 8 (its sum",
+             "over the eight XCDs) for the maximum over XCDs (the dispatch's active cycles).", "",
+             "| counter | mean per dispatch |", "|---|---|"]
+    for k in sorted(set(a) | set(b)):
+        lines.append("| %s | %.4g |" % (k, a.get(k, b.get(k))))
+    lines += ["", "| derived | value | formula |", "|---|---|---|"]
+    if g:
+        lines.append("| active cycles per dispatch (one XCD) | %.4g (%.2f ms at 2.4 GHz) | GRBM_GUI_ACTIVE / 8 |"
+                     % (g, g / 2.4e6))
+        lines.append("| MFMA busy %% | %.1f | 100 SQ_VALU_MFMA_BUSY_CYCLES / (active cycles x %d SIMDs) |"
+                     % (100 * a["SQ_VALU_MFMA_BUSY_CYCLES"] / (g * simd), simd))
+        lines.append("| VALU busy %% | %.1f | 100 SQ_ACTIVE_INST_VALU / %d CUs / active cycles |"
+                     % (100 * a["SQ_ACTIVE_INST_VALU"] / cu / g, cu))
+        lines.append("| LDS active %% | %.1f | 100 SQ_LDS_IDX_ACTIVE / (active cycles x %d CUs) |"
+                     % (100 * a["SQ_LDS_IDX_ACTIVE"] / (g * cu), cu))
+    if a.get("SQ_LDS_IDX_ACTIVE", 0) > a.get("SQ_LDS_BANK_CONFLICT", 0):
+        lines.append("| LDS bank-conflict cycles / conflict-free LDS cycles | %.3f | SQ_LDS_BANK_CONFLICT / "
+                     "(SQ_LDS_IDX_ACTIVE - SQ_LDS_BANK_CONFLICT) |"
+                     % (a["SQ_LDS_BANK_CONFLICT"] / (a["SQ_LDS_IDX_ACTIVE"] - a["SQ_LDS_BANK_CONFLICT"])))
+    if a.get("SQ_WAVES"):
+        w = a["SQ_WAVES"]
+        lines.append("| waves per dispatch | %.0f | SQ_WAVES |" % w)
+        for k in ("SQ_INSTS_VALU", "SQ_INSTS_MFMA", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR",
+                  "SQ_INSTS_SALU"):
+            if k in b:
+                lines.append("| %s per wave | %.1f | %s / SQ_WAVES |" % (k[9:], b[k] / w, k))
+    if "SQ_INSTS_VALU_MFMA_MOPS_BF16" in b:
+        lines.append("| bf16 matrix-core flops per dispatch | %.4g | 512 SQ_INSTS_VALU_MFMA_MOPS_BF16 |"
+                     % (512 * b["SQ_INSTS_VALU_MFMA_MOPS_BF16"]))
+    lines += ["", "Commands (from the repository root, each pass its own process):", "", "```",
+              cmds["pmc_sq1_fused_c64"], cmds["pmc_sq2_fused_c64"],
+              "python3 bench.py --summarize-profiles %s" % PROFILE_DIR, "```", "", "Kernel sources hash: %s" % src]
+    with open(os.path.join(ROOT, "profiles", "counters_k_tile_rqc30_d40.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("wrote profiles/counters_k_tile_rqc30_d40.md")
 
 
 def _last_json(path):
@@ -315,7 +398,7 @@ def summarize_profiles(d):
                             "%.4g" % ab if ab else "", "%.3f" % (tb / cnt / ab) if ab else ""))
     lines += ["", "Commands (from the repository root, after `cd /tmp && export TMPDIR=/tmp` and with",
               "paths taken from the root; each pass is its own process):", "", "```"]
-    lines += [cmds[k] for k in cmds if k.startswith("pmc_")]
+    lines += [cmds[k] for k in cmds if k.startswith(("pmc_fetch", "pmc_write"))]
     lines += ["python3 bench.py --summarize-profiles %s" % PROFILE_DIR, "```", "",
               "Kernel sources hash: %s" % src]
     with open(os.path.join(prof, "hbm_traffic_rqc30_d40.md"), "w") as f:
@@ -364,6 +447,8 @@ def summarize_profiles(d):
         f.write("\n".join(kl) + "\n")
     if os.path.isdir(os.path.join(d, "remap")):
         summarize_remap(d, cmds["remap"], src)
+    if os.path.isdir(os.path.join(d, "pmc_sq1_fused_c64")):
+        summarize_sq(d, cmds, src)
     print("wrote profiles/traffic.json, profiles/hbm_traffic_rqc30_d40.md, profiles/kernel_stats_rqc30_d40.md")
 
 
