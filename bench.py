@@ -63,6 +63,8 @@ def parse():
                    help="bandwidth of the qubit-remap pack / unpack on a 30-qubit shard (one JSON line)")
     p.add_argument("--partial", action="store_true",
                    help="partial-amplitude mode on a 40-qubit depth-8 circuit (one JSON line)")
+    p.add_argument("--traj", action="store_true",
+                   help="only the batched-trajectory measurement (512 trajectories, one JSON line)")
     p.add_argument("--single", action="store_true",
                    help="single-amplitude mode on a 60-qubit depth-14 circuit (one JSON line)")
     p.add_argument("--config5", action="store_true",
@@ -146,6 +148,7 @@ PROFILE_RUNS = [
      "SQ_INSTS_VMEM_WR SQ_INSTS_SALU SQ_INSTS_VALU_MFMA_MOPS_BF16 SQ_WAIT_INST_LDS",
      "--steps 1 --warmup 0 --no-cpu-baseline --trajectories 0 --no-by-target --no-extras --paths fused_c64"),
     ("remap", "--kernel-trace --stats", "--remap"),
+    ("traj", "--kernel-trace --stats", "--traj"),
     ("pmc_fetch_copy", "--pmc FETCH_SIZE", "--copy-calibration"),
     ("pmc_write_copy", "--pmc WRITE_SIZE", "--copy-calibration"),
 ]
@@ -337,6 +340,38 @@ def summarize_remap(d, cmd, src):
     print("wrote profiles/kernel_stats_remap_l30.md")
 
 
+def summarize_traj(d, cmd, src):
+    """profiles/kernel_stats_trajectories.md: where a 512-trajectory batch
+    spends its device time (kernel trace of bench.py --traj), beside the
+    wall time and device time the library reports for the same calls."""
+    import glob
+    line = _last_json(os.path.join(d, "traj.log"))
+    st = glob.glob(os.path.join(d, "traj", "**", "*kernel_stats.csv"), recursive=True)
+    if not line or not st:
+        return
+    rows = _csv_rows(st[0])
+    calls = len(line.get("autotune_calls", [])) + 3 + 1  # tuning calls, timed calls, the direct-launch call
+    kl = ["# Kernel time, batched noisy trajectories (512 trajectories, 14-22 qubits, depth 24)", "",
+          "`rocprofv3 --kernel-trace --stats` of `bench.py --traj`: %d calls of the 512-trajectory batch" % calls,
+          "(the autotuner's candidates, three timed calls, one with direct launches) and the 4096-trajectory",
+          "accuracy batch at n = 10.", "",
+          "| kernel | calls | total ms | average us | % |", "|---|---|---|---|---|"]
+    for r in rows[:12]:
+        kl.append("| %s | %s | %.1f | %.1f | %s |" % (short_kernel(r["Name"]), r["Calls"],
+                                                       float(r["TotalDurationNs"]) / 1e6,
+                                                       float(r["AverageNs"]) / 1e3, r["Percentage"]))
+    kl += ["", "The fastest timed call of the same run (library statistics): %.3f s wall, %.3f s device time "
+           "(HIP events around each pass job), %.3f s of host planning, program build and upload, %d passes, "
+           "%d jumps, %d kernel launches in %s; %.0f trajectories/s."
+           % (line["seconds"], line["device_s"], line["host_s"], line["passes"], line["jumps"], line["launches"],
+              "captured HIP graphs" if line.get("graph") else "direct launches", line["traj_per_s"]),
+           "", "Command (from the repository root):", "", "```", cmd, "```", "",
+           "Kernel sources hash: %s" % src]
+    with open(os.path.join(ROOT, "profiles", "kernel_stats_trajectories.md"), "w") as f:
+        f.write("\n".join(kl) + "\n")
+    print("wrote profiles/kernel_stats_trajectories.md")
+
+
 def summarize_profiles(d):
     """Write profiles/traffic.json and the text summaries from rocprofv3 CSVs."""
     import glob
@@ -449,6 +484,8 @@ def summarize_profiles(d):
         summarize_remap(d, cmds["remap"], src)
     if os.path.isdir(os.path.join(d, "pmc_sq1_fused_c64")):
         summarize_sq(d, cmds, src)
+    if os.path.isdir(os.path.join(d, "traj")):
+        summarize_traj(d, cmds["traj"], src)
     print("wrote profiles/traffic.json, profiles/hbm_traffic_rqc30_d40.md, profiles/kernel_stats_rqc30_d40.md")
 
 
@@ -932,6 +969,11 @@ def main():
         return
     if args.single:
         single_bench(qs, cg)
+        return
+    if args.traj:
+        rec = trajectory_bench(qs, cg, args.trajectories or 512)
+        rec["metric"] = "batched noisy trajectories per second"
+        print(json.dumps(rec))
         return
     if args.plan == "learned":
         p, _ = train_cost_model(qs, cg, log_fn=log)

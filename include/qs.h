@@ -426,6 +426,8 @@ typedef struct {
     double flops;       /* real FP64 flops of the merges for one amplitude (all slices) */
     double peak_bytes;  /* device arena of the tensors (qs_single_plan: one bitstring) */
     int batch;          /* graphs contracted side by side per launch (bitstrings x slices) */
+    int own_low;        /* merge operands stored with their own vertices lowest (the others: the
+                         * summed vertices lowest), chosen so that merges write whole lines */
 } qs_single_info;
 
 /* Single-amplitude mode (Sec. 2.3, Figs. 2-3): amplitudes <x|C|0...0> of an

@@ -73,11 +73,13 @@ struct Ten {
     bool batched = false;     // depends on the bitstring or the slice
     int base = -1;            // initial tensor: its Base; -1 = made by a merge
     std::vector<int> layout;  // storage order asked for by its consumer, lowest bit first
+    bool own_low = false;     // as an operand: its own vertices lowest, then the summed ones
+    int producer = -1;        // the merge that makes it (-1 = initial tensor)
 };
 
 struct Merge {
     int x, y, z;
-    std::vector<int> b, m, n, k;  // shared kept, x only, y only, summed (each ascending)
+    std::vector<int> b, m, n, k;  // shared kept, x only, y only (each in the order of z's storage), summed
 };
 
 struct Plan {
@@ -316,6 +318,7 @@ qs_status plan_merges(Plan &P, int trial)
             for (int v : Y.idx) on[v].erase(y);
             alive[x] = alive[y] = 0;
             for (int v : M.k) left.erase(v);
+            z.producer = int(P.merges.size());
             M.z = add_tensor(std::move(z));
             alive.push_back(1);
             P.merges.push_back(std::move(M));
@@ -327,16 +330,57 @@ qs_status plan_merges(Plan &P, int trial)
             if (!P.tens[t].idx.empty()) return sfail(QS_E_DEVICE, "internal: tensor %zu left with indices", t);
             P.finals.push_back(int(t));
         }
-    // storage order of every operand, as its merge reads it: summed vertices
-    // lowest, then its own, then the shared kept ones
-    for (const Merge &M : P.merges) {
-        Ten &X = P.tens[M.x], &Y = P.tens[M.y];
-        X.layout = M.k;
-        X.layout.insert(X.layout.end(), M.m.begin(), M.m.end());
-        X.layout.insert(X.layout.end(), M.b.begin(), M.b.end());
-        Y.layout = M.k;
-        Y.layout.insert(Y.layout.end(), M.n.begin(), M.n.end());
-        Y.layout.insert(Y.layout.end(), M.b.begin(), M.b.end());
+    // Storage order of every operand, as its merge reads it: the summed
+    // vertices and the operand's own vertices in the low bits (either group
+    // lowest), then the shared kept ones.  A merge writes its result in the
+    // order its consumer reads it, so the merges are walked from the last:
+    // each one's vertex lists are ordered by their places in its result's
+    // storage (the consumer, later in the list, has fixed it) and the operand
+    // whose own vertices hold the lowest storage bit takes the fastest index
+    // n, so that neighbouring threads write neighbouring addresses.  For an
+    // operand made by an earlier merge, the group put lowest is the one
+    // whose leading vertices that merge writes from its tiled (own) index
+    // ranges rather than its batch of shared vertices.
+    for (size_t i = P.merges.size(); i-- > 0;) {
+        Merge &M = P.merges[i];
+        const Ten &Z = P.tens[M.z];
+        if (!Z.layout.empty()) {
+            std::map<int, int> pos;
+            for (size_t j = 0; j < Z.layout.size(); ++j) pos[Z.layout[j]] = int(j);
+            auto by_pos = [&](std::vector<int> &v) {
+                std::sort(v.begin(), v.end(), [&](int a, int b) { return pos[a] < pos[b]; });
+            };
+            by_pos(M.b);
+            by_pos(M.m);
+            by_pos(M.n);
+            const int v0 = Z.layout[0];
+            if (std::find(M.m.begin(), M.m.end(), v0) != M.m.end()) {
+                std::swap(M.x, M.y);
+                std::swap(M.m, M.n);
+            }
+        }
+        auto lay = [&](Ten &T, const std::vector<int> &own) {
+            std::vector<int> klow = M.k, olow = own;
+            klow.insert(klow.end(), own.begin(), own.end());
+            olow.insert(olow.end(), M.k.begin(), M.k.end());
+            bool use_own = false;
+            if (T.producer >= 0) {
+                const Merge &Pm = P.merges[size_t(T.producer)];
+                std::set<int> tiled(Pm.m.begin(), Pm.m.end());
+                tiled.insert(Pm.n.begin(), Pm.n.end());
+                auto lead = [&](const std::vector<int> &v) {
+                    size_t c = 0;
+                    while (c < v.size() && tiled.count(v[c])) ++c;
+                    return c;
+                };
+                use_own = lead(olow) > lead(klow);
+            }
+            T.own_low = use_own;
+            T.layout = use_own ? olow : klow;
+            T.layout.insert(T.layout.end(), M.b.begin(), M.b.end());
+        };
+        lay(P.tens[M.x], M.m);
+        lay(P.tens[M.y], M.n);
     }
     return QS_OK;
 }
@@ -447,6 +491,8 @@ void fill_info(const Plan &P, uint32_t bt, size_t peak, qs_single_info *info)
     info->flops = P.flops0 + P.flops1 * std::ldexp(1.0, P.nslice);
     info->peak_bytes = double(peak);
     info->batch = int(bt);
+    info->own_low = 0;
+    for (const Ten &t : P.tens) info->own_low += t.own_low;
 }
 
 constexpr double kSingleBudget = 64.0 * (1ull << 30);  // device arena of one call, at most
@@ -586,11 +632,14 @@ try {
             k.nm = int(M.m.size());
             k.nn = int(M.n.size());
             k.nk = int(M.k.size());
+            k.xo = X.own_low ? 1 : 0;
+            k.yo = Y.own_low ? 1 : 0;
             const std::vector<int> &L = Z.layout.empty() ? Z.idx : Z.layout;
             auto pos = [&](int v) { return uint8_t(std::find(L.begin(), L.end(), v) - L.begin()); };
             for (int j = 0; j < k.nb; ++j) k.pb[j] = pos(M.b[j]);
             for (int j = 0; j < k.nm; ++j) k.pm[j] = pos(M.m[j]);
             for (int j = 0; j < k.nn; ++j) k.pn[j] = pos(M.n[j]);
+            for (int j = 0; j < k.nb; ++j) k.bfast |= k.pb[j] == 0;
             const double outs = double(k.nbt) * std::ldexp(1.0, k.nb + k.nm + k.nn);
             int kern = qs::SA_THREAD;
             if (k.nm >= 6 && k.nn >= 6 && k.nk >= 3)

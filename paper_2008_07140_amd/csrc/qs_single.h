@@ -15,9 +15,11 @@ constexpr int kSaMaxBits = 40;  // indices of one tensor (a 2^40-entry tensor is
 // with t the batch element (a bitstring and a slice), b the shared vertices
 // kept, m / n the vertices of X / Y alone and k the summed ones.  X is
 // stored with k in the low bits, then m, then b (k + (m << nk) +
-// (b << (nk + nm))), Y likewise with n; Z's storage is what its own consumer
-// asks for, so logical bit j of b / m / n goes to storage bit pb[j] / pm[j] /
-// pn[j].  An operand without a batch dimension has batch stride 0.
+// (b << (nk + nm))), or, with xo set, m lowest (m + (k << nm) +
+// (b << (nk + nm))); Y likewise with n and yo.  Z's storage is what its own
+// consumer asks for, so logical bit j of b / m / n goes to storage bit
+// pb[j] / pm[j] / pn[j].  An operand without a batch dimension has batch
+// stride 0.
 struct SaContract {
     const double2 *x;
     const double2 *y;
@@ -25,6 +27,8 @@ struct SaContract {
     uint64_t sx, sy, sz;  // batch strides in amplitudes
     uint32_t nbt;         // batch elements of Z
     int nb, nm, nn, nk;   // bit counts
+    int bfast;            // tiled merges: neighbouring tiles take neighbouring b (Z's low bits are b)
+    int xo, yo;           // X / Y stored with their own vertices lowest
     uint8_t pb[kSaMaxBits], pm[kSaMaxBits], pn[kSaMaxBits];
 };
 

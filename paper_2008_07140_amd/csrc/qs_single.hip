@@ -28,6 +28,22 @@ __device__ __forceinline__ uint64_t deposit(uint64_t v, int nbits, const uint8_t
     return r;
 }
 
+// The bits of storage index a at positions pos[0..nbits) (inverse of deposit).
+__device__ __forceinline__ uint64_t extract(uint64_t a, int nbits, const uint8_t *pos)
+{
+    uint64_t r = 0;
+    for (int j = 0; j < nbits; ++j) r |= ((a >> pos[j]) & 1ull) << j;
+    return r;
+}
+
+// Start of operand row (b, o) and the stride between its summed entries:
+// k lowest ((b << no | o) << nk, stride 1) or own lowest ((b << nk) << no | o,
+// stride 2^no).
+__device__ __forceinline__ uint64_t row_start(uint64_t b, uint64_t o, int no, int nk, int own_low)
+{
+    return own_low ? (((b << nk) << no) | o) : (((b << no) | o) << nk);
+}
+
 __device__ __forceinline__ void cmac(double2 &acc, double2 a, double2 b)
 {
     acc.x = fma(a.x, b.x, acc.x);
@@ -36,21 +52,22 @@ __device__ __forceinline__ void cmac(double2 &acc, double2 a, double2 b)
     acc.y = fma(a.y, b.x, acc.y);
 }
 
-// One thread per result element (few summed vertices).
+// One thread per result element (few summed vertices), walked in the
+// result's storage order: the writes of a wave are contiguous, and each
+// thread reads its own rows of X and Y (2^nk neighbouring entries each).
 __global__ __launch_bounds__(kT) void k_sa_thread(SaContract c)
 {
     const int nr = c.nb + c.nm + c.nn;
     const uint64_t per = 1ull << nr, total = uint64_t(c.nbt) * per, K = 1ull << c.nk;
     for (uint64_t i = uint64_t(blockIdx.x) * kT + threadIdx.x; i < total; i += uint64_t(gridDim.x) * kT) {
-        const uint64_t t = i >> nr, rem = i & (per - 1);
-        const uint64_t n = rem & ((1ull << c.nn) - 1);
-        const uint64_t m = (rem >> c.nn) & ((1ull << c.nm) - 1);
-        const uint64_t b = rem >> (c.nn + c.nm);
-        const double2 *xp = c.x + t * c.sx + (((b << c.nm) | m) << c.nk);
-        const double2 *yp = c.y + t * c.sy + (((b << c.nn) | n) << c.nk);
+        const uint64_t t = i >> nr, a = i & (per - 1);
+        const uint64_t b = extract(a, c.nb, c.pb), m = extract(a, c.nm, c.pm), n = extract(a, c.nn, c.pn);
+        const double2 *xp = c.x + t * c.sx + row_start(b, m, c.nm, c.nk, c.xo);
+        const double2 *yp = c.y + t * c.sy + row_start(b, n, c.nn, c.nk, c.yo);
+        const uint64_t kx = c.xo ? (1ull << c.nm) : 1ull, ky = c.yo ? (1ull << c.nn) : 1ull;
         double2 acc = make_double2(0.0, 0.0);
-        for (uint64_t k = 0; k < K; ++k) cmac(acc, xp[k], yp[k]);
-        c.z[t * c.sz + deposit(b, c.nb, c.pb) + deposit(m, c.nm, c.pm) + deposit(n, c.nn, c.pn)] = acc;
+        for (uint64_t k = 0; k < K; ++k) cmac(acc, xp[k * kx], yp[k * ky]);
+        c.z[t * c.sz + a] = acc;
     }
 }
 
@@ -69,23 +86,23 @@ __global__ __launch_bounds__(kT) void k_sa_wave(SaContract c)
     const int lane = threadIdx.x & 63;
     const uint64_t nw = uint64_t(gridDim.x) * (kT / 64);
     for (uint64_t i = uint64_t(blockIdx.x) * (kT / 64) + (threadIdx.x >> 6); i < total; i += nw) {
-        const uint64_t t = i >> nr, rem = i & (per - 1);
-        const uint64_t n = rem & ((1ull << c.nn) - 1);
-        const uint64_t m = (rem >> c.nn) & ((1ull << c.nm) - 1);
-        const uint64_t b = rem >> (c.nn + c.nm);
-        const double2 *xp = c.x + t * c.sx + (((b << c.nm) | m) << c.nk);
-        const double2 *yp = c.y + t * c.sy + (((b << c.nn) | n) << c.nk);
+        const uint64_t t = i >> nr, a = i & (per - 1);
+        const uint64_t b = extract(a, c.nb, c.pb), m = extract(a, c.nm, c.pm), n = extract(a, c.nn, c.pn);
+        const double2 *xp = c.x + t * c.sx + row_start(b, m, c.nm, c.nk, c.xo);
+        const double2 *yp = c.y + t * c.sy + row_start(b, n, c.nn, c.nk, c.yo);
+        const uint64_t kx = c.xo ? (1ull << c.nm) : 1ull, ky = c.yo ? (1ull << c.nn) : 1ull;
         double2 acc = make_double2(0.0, 0.0);
-        for (uint64_t k = lane; k < K; k += 64) cmac(acc, xp[k], yp[k]);
+        for (uint64_t k = lane; k < K; k += 64) cmac(acc, xp[k * kx], yp[k * ky]);
         acc.x = wave_sum(acc.x);
         acc.y = wave_sum(acc.y);
-        if (lane == 0)
-            c.z[t * c.sz + deposit(b, c.nb, c.pb) + deposit(m, c.nm, c.pm) + deposit(n, c.nn, c.pn)] = acc;
+        if (lane == 0) c.z[t * c.sz + a] = acc;
     }
 }
 
 // 64 x 64 result tiles (nm, nn >= 6, nk >= 3): the summed vertices are
-// walked eight at a time through LDS, each thread accumulates 4 x 4 results.
+// walked eight at a time through LDS, each thread accumulates 4 x 4 results
+// (rows 4 ty .. 4 ty + 3, columns tx + 16 j, so that the lanes of a wave
+// read neighbouring LDS entries and write neighbouring results).
 __global__ __launch_bounds__(kT) void k_sa_tile(SaContract c)
 {
     __shared__ double2 xs[8][65];  // one spare entry per row: the eight rows written together
@@ -95,24 +112,57 @@ __global__ __launch_bounds__(kT) void k_sa_tile(SaContract c)
     const uint64_t total = uint64_t(c.nbt) * (1ull << c.nb) * tiles_per;
     const uint64_t K = 1ull << c.nk;
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    for (uint64_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
-        const uint64_t tb = tile / tiles_per, r = tile % tiles_per;
-        const uint64_t t = tb >> c.nb, b = tb & ((1ull << c.nb) - 1);
+    // Workgroups are dealt to the eight XCDs in turn (block i to XCD i mod 8),
+    // each with its own L2.  When the result's lowest storage bits are shared
+    // vertices (bfast), the eight neighbouring b of one line of results are
+    // given to blocks eight apart, which run on one XCD at about the same
+    // time, so their partial writes of each line meet in one L2.
+    const bool swap = c.bfast && c.nb >= 3 && (total & 63) == 0;
+    for (uint64_t blk = blockIdx.x; blk < total; blk += gridDim.x) {
+        const uint64_t tile = swap ? ((blk & ~uint64_t(63)) | ((blk & 7) << 3) | ((blk >> 3) & 7)) : blk;
+        uint64_t t, b, r;
+        if (c.bfast) {
+            // the result's lowest storage bits are shared vertices: workgroups
+            // running together take neighbouring b, whose writes share lines
+            b = tile & ((1ull << c.nb) - 1);
+            const uint64_t rest = tile >> c.nb;
+            t = rest / tiles_per;
+            r = rest % tiles_per;
+        } else {
+            const uint64_t tb = tile / tiles_per;
+            r = tile % tiles_per;
+            t = tb >> c.nb;
+            b = tb & ((1ull << c.nb) - 1);
+        }
         const uint64_t m0 = (r / nt) << 6, n0 = (r % nt) << 6;
-        const double2 *xp = c.x + t * c.sx + (((b << c.nm) | m0) << c.nk);
-        const double2 *yp = c.y + t * c.sy + (((b << c.nn) | n0) << c.nk);
+        const double2 *xp = c.x + t * c.sx + row_start(b, m0, c.nm, c.nk, c.xo);
+        const double2 *yp = c.y + t * c.sy + row_start(b, n0, c.nn, c.nk, c.yo);
         double2 acc[4][4];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
         for (uint64_t k0 = 0; k0 < K; k0 += 8) {
+            // 512 entries per operand: with k lowest, eight neighbouring lanes
+            // read one row's eight summed entries; with the own index lowest,
+            // 64 neighbouring lanes read one summed entry of 64 rows
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                const int e = threadIdx.x + h * kT;  // 512 elements: row e / 8, column e % 8
-                const int row = e >> 3, kk = e & 7;
-                xs[kk][row] = xp[(uint64_t(row) << c.nk) + k0 + kk];
-                ys[kk][row] = yp[(uint64_t(row) << c.nk) + k0 + kk];
+                const int e = threadIdx.x + h * kT;
+                if (c.xo) {
+                    const int row = e & 63, kk = e >> 6;
+                    xs[kk][row] = xp[((k0 + kk) << c.nm) + row];
+                } else {
+                    const int row = e >> 3, kk = e & 7;
+                    xs[kk][row] = xp[(uint64_t(row) << c.nk) + k0 + kk];
+                }
+                if (c.yo) {
+                    const int row = e & 63, kk = e >> 6;
+                    ys[kk][row] = yp[((k0 + kk) << c.nn) + row];
+                } else {
+                    const int row = e >> 3, kk = e & 7;
+                    ys[kk][row] = yp[(uint64_t(row) << c.nk) + k0 + kk];
+                }
             }
             __syncthreads();
 #pragma unroll
@@ -121,7 +171,7 @@ __global__ __launch_bounds__(kT) void k_sa_tile(SaContract c)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     a[i] = xs[kk][ty * 4 + i];
-                    bb[i] = ys[kk][tx * 4 + i];
+                    bb[i] = ys[kk][tx + 16 * i];  // neighbouring lanes, neighbouring entries
                 }
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
@@ -135,7 +185,7 @@ __global__ __launch_bounds__(kT) void k_sa_tile(SaContract c)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             zm[i] = deposit(m0 + ty * 4 + i, c.nm, c.pm);
-            zn[i] = deposit(n0 + tx * 4 + i, c.nn, c.pn);
+            zn[i] = deposit(n0 + tx + 16 * i, c.nn, c.pn);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i)

@@ -61,7 +61,7 @@ class TrajStats(C.Structure):
 class SingleInfo(C.Structure):
     _fields_ = [("vertices", C.c_int), ("tensors", C.c_int), ("fixed", C.c_int), ("sliced", C.c_int),
                 ("merges", C.c_int), ("max_rank", C.c_int), ("flops", C.c_double),
-                ("peak_bytes", C.c_double), ("batch", C.c_int)]
+                ("peak_bytes", C.c_double), ("batch", C.c_int), ("own_low", C.c_int)]
 
 
 class ScriptInfo(C.Structure):

@@ -1204,6 +1204,25 @@ def test_single_amplitudes_wide_product_circuits(qs, parts):
     assert np.max(np.abs(got - want)) <= 1e-10 * scale
 
 
+def test_single_amplitudes_36_qubit_product_with_both_operand_layouts(qs):
+    """A 36-qubit circuit of two independent 18-qubit depth-10 circuits on
+    the even and odd qubits: its merges store some operands with their own
+    vertices lowest and the others with the summed vertices lowest (both
+    forms are read by every merge kernel); the amplitudes are products of
+    the oracle's 18-qubit amplitudes."""
+    nh = 18
+    half = cg.random_circuit(3, 6, 10, seed=1901, cu3_prob=0.1)
+    half2 = cg.random_circuit(6, 3, 10, seed=1902, cu3_prob=0.1)
+    ops = _product_circuit(half, half2, nh)
+    bits = _bitstrings(2 * nh, 40, 1903, [0, (1 << 36) - 1])
+    want = _product_expected(half, half2, nh, bits)
+    c = qs.Circuit(ops)
+    info = c.single_plan(2 * nh)
+    assert info["own_low"] > 0 and info["own_low"] < info["tensors"]
+    got, _ = c.single_amplitudes(2 * nh, bits)
+    assert np.max(np.abs(got - want)) <= 1e-10 * np.max(np.abs(want))
+
+
 def test_single_amplitudes_in_bitstring_chunks(qs):
     """A memory bound smaller than the tensors of every bitstring at once
     makes the call process the bitstrings in chunks: the results are the
