@@ -563,10 +563,28 @@ void parallel_for(size_t count, F &&f)
     WorkerPool::get().run(count, [&f](size_t i) { f(i); });
 }
 
+// Device ops of a tiled plan and where their operand data goes.  The data is
+// kept in the per-step pieces it was built in and written once, by write(),
+// straight into the buffer it is uploaded from (a batch's pinned staging
+// area); materialize() gathers it into `data` for plans kept between runs.
 struct TileProgram {
     std::vector<qs::TileOpDev> ops;
-    std::vector<uint16_t> data;     // 16-byte aligned records
     std::vector<size_t> first;      // first op of each sweep step
+    size_t units = 0;               // uint16 count of the operand data (a multiple of 8)
+    std::vector<std::vector<uint16_t>> piece;        // per step
+    std::vector<size_t> piece_at;                    // uint16 offset of each piece
+    std::vector<const std::vector<uint32_t> *> table;  // per-lane offset tables
+    std::vector<size_t> table_at;                    // uint16 offset of each table
+    std::vector<uint16_t> data;     // materialize(): the whole operand data
+    size_t bytes() const { return units * sizeof(uint16_t); }
+    void write(uint16_t *dst) const;
+    void materialize()
+    {
+        data.resize(units);
+        write(data.data());
+        piece.clear();
+        piece.shrink_to_fit();
+    }
 };
 
 void pad16(std::vector<uint16_t> &d)
@@ -794,22 +812,24 @@ void build_sweep_program(const qs::Sweep &sw, std::vector<qs::TileOpDev> &ops, s
     pad16(data);
 }
 
-// Programs of all sweep steps (built in parallel), concatenated.
+// Programs of all sweep steps, built in parallel; the data stays in its
+// pieces until written.
 void build_tile_program(const std::vector<qs::PlanStep> &steps, TileProgram &tp)
 {
     const size_t ns = steps.size();
     std::vector<std::vector<qs::TileOpDev>> pops(ns);
-    std::vector<std::vector<uint16_t>> pdata(ns);
+    tp.piece.assign(ns, {});
     parallel_for(ns, [&](size_t i) {
-        if (steps[i].sweep) build_sweep_program(steps[i].sw, pops[i], pdata[i]);
+        if (steps[i].sweep) build_sweep_program(steps[i].sw, pops[i], tp.piece[i]);
     });
-    std::vector<size_t> dpos(ns);
+    tp.piece_at.assign(ns, 0);
+    tp.first.clear();
     size_t nops = 0, ndata = 0;
     for (size_t i = 0; i < ns; ++i) {
         tp.first.push_back(nops);
-        dpos[i] = ndata;
+        tp.piece_at[i] = ndata;
         nops += pops[i].size();
-        ndata += pdata[i].size();
+        ndata += tp.piece[i].size();
     }
     // per-lane LDS offset tables: one per distinct lane layout of the program
     // (block width, column bits and op bits packed into one key: 3 + 13 + 5 x 4
@@ -818,8 +838,8 @@ void build_tile_program(const std::vector<qs::PlanStep> &steps, TileProgram &tp)
     static std::shared_mutex memo_mu;
     static std::unordered_map<uint64_t, std::vector<uint32_t>> memo;  // entries are never erased
     std::unordered_map<uint64_t, uint32_t> slot_of;                    // key -> table slot
-    std::vector<const std::vector<uint32_t> *> table;                 // slot -> table
-    std::vector<uint32_t> table_at;                                    // slot -> offset, 16-byte units
+    tp.table.clear();
+    tp.table_at.clear();
     std::vector<uint32_t> op_slot(nops, UINT32_MAX);
     size_t dend = ndata;
     for (size_t i = 0, o = 0; i < ns; ++i)
@@ -841,33 +861,56 @@ void build_tile_program(const std::vector<qs::PlanStep> &steps, TileProgram &tp)
                     std::unique_lock<std::shared_mutex> lk(memo_mu);
                     lo = &memo.emplace(key, std::move(v)).first->second;
                 }
-                it = slot_of.emplace(key, uint32_t(table.size())).first;
-                table.push_back(lo);
-                table_at.push_back(uint32_t(dend / 8));
+                it = slot_of.emplace(key, uint32_t(tp.table.size())).first;
+                tp.table.push_back(lo);
+                tp.table_at.push_back(dend);
                 dend += lo->size() * 2;  // uint32 entries in uint16 units (multiples of 8)
             }
             op_slot[o] = it->second;
         }
     tp.ops.resize(nops);
-    tp.data.resize(dend);
-    parallel_for(ns + table.size(), [&](size_t i) {
-        if (i >= ns) {
-            const size_t t = i - ns;
-            std::memcpy(tp.data.data() + size_t(table_at[t]) * 8, table[t]->data(), table[t]->size() * sizeof(uint32_t));
-            return;
-        }
-        const uint32_t base = uint32_t(dpos[i] / 8);
+    parallel_for(ns, [&](size_t i) {
+        const uint32_t base = uint32_t(tp.piece_at[i] / 8);
         for (size_t j = 0; j < pops[i].size(); ++j) {
             const size_t o = tp.first[i] + j;
             qs::TileOpDev d = pops[i][j];
             d.data_off += base;
-            if (op_slot[o] != UINT32_MAX) d.offs_off = table_at[op_slot[o]];
+            if (op_slot[o] != UINT32_MAX) d.offs_off = uint32_t(tp.table_at[op_slot[o]] / 8);
             tp.ops[o] = d;
         }
-        if (!pdata[i].empty()) std::memcpy(tp.data.data() + dpos[i], pdata[i].data(), pdata[i].size() * sizeof(uint16_t));
     });
-    if (tp.data.empty()) tp.data.resize(8, 0);
+    tp.units = std::max<size_t>(dend, 8);
     if (tp.ops.empty()) tp.ops.resize(1);
+}
+
+void TileProgram::write(uint16_t *dst) const
+{
+    if (piece.empty() && !data.empty()) {
+        std::memcpy(dst, data.data(), bytes());
+        return;
+    }
+    // pieces are split into slices of at most 1 MiB so that a few large
+    // steps do not serialise the copy
+    struct Job { const uint16_t *src; size_t at, n; };
+    std::vector<Job> jobs;
+    const size_t slice = size_t(1) << 19;
+    auto add = [&](const uint16_t *src, size_t at, size_t n) {
+        for (size_t o = 0; o < n; o += slice) jobs.push_back({src + o, at + o, std::min(slice, n - o)});
+    };
+    size_t used = 0;
+    for (size_t i = 0; i < piece.size(); ++i) {
+        add(piece[i].data(), piece_at[i], piece[i].size());
+        used = std::max(used, piece_at[i] + piece[i].size());
+    }
+    for (size_t t = 0; t < table.size(); ++t) {
+        const size_t n = table[t]->size() * 2;
+        add(reinterpret_cast<const uint16_t *>(table[t]->data()), table_at[t], n);
+        used = std::max(used, table_at[t] + n);
+    }
+    if (used < units) std::memset(dst + used, 0, (units - used) * sizeof(uint16_t));
+    parallel_for(jobs.size(), [&](size_t i) {
+        std::memcpy(dst + jobs[i].at, jobs[i].src, jobs[i].n * sizeof(uint16_t));
+    });
 }
 
 qs::TileParams tile_params(int n, const qs_run_opts &o)
@@ -1019,12 +1062,12 @@ qs_status choose_tile_params(qs_state *s, const std::vector<qs::FlatOp> &flat, s
     return QS_OK;
 }
 
-// Upload a tile program into the state's plan buffer unless it is already
+// Upload a materialized tile program into the state's plan buffer unless it is already
 // there (repeated runs of a cached plan skip the upload and its wait).
 qs_status upload_program(qs_state *s, const TileProgram &tp, uint64_t id, size_t &doff)
 {
     const size_t ob = tp.ops.size() * sizeof(qs::TileOpDev);
-    const size_t db = tp.data.size() * sizeof(uint16_t);
+    const size_t db = tp.bytes();
     doff = ((ob + 255) / 256) * 256;
     if (id && s->prog_loaded == id) return QS_OK;
     const size_t total = doff + db;
@@ -1715,7 +1758,7 @@ qs_status batch_gates(Batch &B, const std::vector<int> &who, const std::vector<c
     size_t ntask = 0;
     for (auto &tl : tasks) ntask += tl.size();
     const size_t ob = tp.ops.size() * sizeof(qs::TileOpDev);
-    const size_t db = tp.data.size() * sizeof(uint16_t);
+    const size_t db = tp.bytes();
     const size_t ab = args.size() * sizeof(qs::TileArgsDev);
     const size_t total = align256(ob) + align256(db) + align256(ab) + align256(ntask * sizeof(qs::TileTask)) + 256;
     qs_state *s = B.master;
@@ -1734,7 +1777,7 @@ qs_status batch_gates(Batch &B, const std::vector<int> &who, const std::vector<c
     }
     const size_t o_data = align256(ob), o_args = o_data + align256(db), o_tasks = o_args + align256(ab);
     std::memcpy(host, tp.ops.data(), ob);
-    std::memcpy(host + o_data, tp.data.data(), db);
+    tp.write(reinterpret_cast<uint16_t *>(host + o_data));
     if (ab) std::memcpy(host + o_args, args.data(), ab);
     for (size_t k = 0; k < tasks.size(); ++k)
         if (!tasks[k].empty())
@@ -2125,7 +2168,7 @@ qs_status launch_pass(Batch &B, PassSlot &P, std::vector<int> job)
         }
     }
     // ---- one upload: program, arguments, tasks, activity flags, freeze records
-    const size_t b_ops = tp.ops.size() * sizeof(qs::TileOpDev), b_data = tp.data.size() * sizeof(uint16_t);
+    const size_t b_ops = tp.ops.size() * sizeof(qs::TileOpDev), b_data = tp.bytes();
     const size_t o_data = align256(b_ops);
     const size_t o_targs = o_data + align256(b_data);
     const size_t o_ttasks = o_targs + align256(targs.size() * sizeof(qs::TileArgsDev));
@@ -2167,13 +2210,10 @@ qs_status launch_pass(Batch &B, PassSlot &P, std::vector<int> job)
                                  {o_rtasks, rtasks.data(), rtasks.size() * sizeof(qs::RunSumTask)},
                                  {o_fc, fc.data(), fc.size() * sizeof(uint32_t)},
                                  {o_sargs, sargs.data(), sargs.size() * sizeof(qs::SampleArgs)}};
-    const size_t slice = size_t(1) << 20;  // the operand data dominates: copied in parallel slices
-    for (size_t o = 0; o < b_data; o += slice)
-        pieces.push_back({o_data + o, reinterpret_cast<const unsigned char *>(tp.data.data()) + o,
-                          std::min(slice, b_data - o)});
     parallel_for(pieces.size(), [&](size_t i) {
         if (pieces[i].bytes) std::memcpy(host + pieces[i].off, pieces[i].src, pieces[i].bytes);
     });
+    if (b_data) tp.write(reinterpret_cast<uint16_t *>(host + o_data));
     {
         int *act = reinterpret_cast<int *>(host + o_active);
         qs::Freeze *fr = reinterpret_cast<qs::Freeze *>(host + o_freeze);
@@ -2892,6 +2932,7 @@ qs_status plan_circuit(qs_state *s, const qs_circuit *c, const qs_run_opts &o,
                     qs::TileParams tp;
                     if (qs_status st = choose_tile_params(s, flat, k, e, o, tp, sp.steps)) return st;
                     build_tile_program(sp.steps, sp.prog);
+                    sp.prog.materialize();
                     sp.prog_id = g_prog_serial.fetch_add(1);
                     sp.tune = std::make_shared<OrderTune>();
                 } else if (o.plan == QS_PLAN_UNFUSED) {
