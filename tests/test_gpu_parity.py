@@ -331,6 +331,29 @@ def test_rqc30_product_circuit_sampled_amplitudes(qs):
         s.close()
 
 
+@pytest.mark.parametrize("m", [12, 13])
+def test_tile_sweeps_24_qubits_full_vector(qs, m):
+    """24 qubits, 2^11 or 2^12 tiles of 4-qubit blocks (more tiles than the
+    compute units hold at once): every amplitude is checked against the
+    product of two 12-qubit oracle states, under two tile orders."""
+    nh, n = 12, 24
+    half = cg.random_circuit(3, 4, 14, seed=1201, cu3_prob=0.1)
+    half2 = cg.random_circuit(4, 3, 14, seed=1202, cu3_prob=0.1)
+    ops = _product_circuit(half, half2, nh)
+    want = _product_expected(half, half2, nh, np.arange(1 << n, dtype=np.uint64))
+    c = qs.Circuit(ops)
+    info = c.plan_info(n, qs.C64, qs.PLAN_GREEDY, k_max=4, tile_qubits=m)
+    assert info["sweeps"] > 1
+    s = qs.State(n, qs.C64)
+    for order in (1, 3):
+        s.reset()
+        s.run(c, plan=qs.PLAN_GREEDY, k_max=4, tile_qubits=m, tile_order=order)
+        got = s.amplitudes()
+        assert infidelity(want, got) <= 1e-6, order
+        assert np.max(np.abs(got - want)) <= 1e-5, order
+    s.close()
+
+
 @pytest.mark.parametrize("nh,grid", [(16, (4, 4)), (17, (17, 1))])
 def test_product_circuit_above_30_qubits_sampled_amplitudes(qs, nh, grid):
     """32 and 34 qubits (states of 32 and 128 GiB as complex64) through the
