@@ -81,13 +81,13 @@ def parse():
 PROFILED_SOURCES = ("qs_fused.hip", "qs_kernels.hip")
 
 
-def source_hash():
+def source_hash(sources=PROFILED_SOURCES):
     """Hash of the device code of the profiled paths: their .hip sources and
     the headers those include (transitively), so host-only changes and
     changes to other kernels keep stored counter readings valid."""
     import re
     csrc = os.path.join(ROOT, "paper_2008_07140_amd", "csrc")
-    files, todo = set(), [os.path.join(csrc, f) for f in PROFILED_SOURCES]
+    files, todo = set(), [os.path.join(csrc, f) for f in sources]
     while todo:
         f = os.path.normpath(todo.pop())
         if f in files or not os.path.exists(f):
@@ -149,6 +149,7 @@ PROFILE_RUNS = [
      "--steps 1 --warmup 0 --no-cpu-baseline --trajectories 0 --no-by-target --no-extras --paths fused_c64"),
     ("remap", "--kernel-trace --stats", "--remap"),
     ("traj", "--kernel-trace --stats", "--traj"),
+    ("single", "--kernel-trace --stats", "--single"),
     ("pmc_fetch_copy", "--pmc FETCH_SIZE", "--copy-calibration"),
     ("pmc_write_copy", "--pmc WRITE_SIZE", "--copy-calibration"),
 ]
@@ -366,10 +367,41 @@ def summarize_traj(d, cmd, src):
            % (line["seconds"], line["device_s"], line["host_s"], line["passes"], line["jumps"], line["launches"],
               "captured HIP graphs" if line.get("graph") else "direct launches", line["traj_per_s"]),
            "", "Command (from the repository root):", "", "```", cmd, "```", "",
-           "Kernel sources hash: %s" % src]
+           "Kernel sources hash (qs_fused.hip, qs_traj.hip and their headers): %s" % src]
     with open(os.path.join(ROOT, "profiles", "kernel_stats_trajectories.md"), "w") as f:
         f.write("\n".join(kl) + "\n")
     print("wrote profiles/kernel_stats_trajectories.md")
+
+
+def summarize_single(d, cmd, src):
+    """profiles/kernel_stats_single_c60.md: where the single-amplitude mode
+    spends its device time (kernel trace of bench.py --single), beside the
+    figures of the same run."""
+    import glob
+    line = _last_json(os.path.join(d, "single.log"))
+    st = glob.glob(os.path.join(d, "single", "**", "*kernel_stats.csv"), recursive=True)
+    if not line or not st:
+        return
+    rows = _csv_rows(st[0])
+    kl = ["# Kernel time, single-amplitude mode (60-qubit 6x10 grid circuit, depth 14)", "",
+          "`rocprofv3 --kernel-trace --stats` of `bench.py --single`: one warm-up bitstring, then %d bitstrings"
+          % line["bitstrings"],
+          "in chunks of %d, every merge of the plan per chunk." % line["batch"], "",
+          "| kernel | calls | total ms | average us | % |", "|---|---|---|---|---|"]
+    for r in rows[:12]:
+        kl.append("| %s | %s | %.1f | %.1f | %s |" % (short_kernel(r["Name"]), r["Calls"],
+                                                       float(r["TotalDurationNs"]) / 1e6,
+                                                       float(r["AverageNs"]) / 1e3, r["Percentage"]))
+    kl += ["", "The same run: %d amplitudes in %.3f s (%.1f /s), %.2f TFLOP/s FP64 on the plan's algorithmic "
+           "flops (%.3g per amplitude), %d merges, largest merged tensor %d indices; planning %.2f s, once "
+           "per circuit, outside the timed calls."
+           % (line["bitstrings"], line["seconds"], line["value"], line["roofline"]["achieved"],
+              line["flops_per_amplitude"], line["merges"], line["max_rank"], line["planning_s"]),
+           "", "Command (from the repository root):", "", "```", cmd, "```", "",
+           "Kernel sources hash (qs_single.hip and its headers): %s" % src]
+    with open(os.path.join(ROOT, "profiles", "kernel_stats_single_c60.md"), "w") as f:
+        f.write("\n".join(kl) + "\n")
+    print("wrote profiles/kernel_stats_single_c60.md")
 
 
 def summarize_profiles(d):
@@ -485,7 +517,9 @@ def summarize_profiles(d):
     if os.path.isdir(os.path.join(d, "pmc_sq1_fused_c64")):
         summarize_sq(d, cmds, src)
     if os.path.isdir(os.path.join(d, "traj")):
-        summarize_traj(d, cmds["traj"], src)
+        summarize_traj(d, cmds["traj"], source_hash(("qs_fused.hip", "qs_traj.hip")))
+    if os.path.isdir(os.path.join(d, "single")):
+        summarize_single(d, cmds["single"], source_hash(("qs_single.hip",)))
     print("wrote profiles/traffic.json, profiles/hbm_traffic_rqc30_d40.md, profiles/kernel_stats_rqc30_d40.md")
 
 
