@@ -150,6 +150,7 @@ PROFILE_RUNS = [
     ("remap", "--kernel-trace --stats", "--remap"),
     ("traj", "--kernel-trace --stats", "--traj"),
     ("single", "--kernel-trace --stats", "--single"),
+    ("partial", "--kernel-trace --stats", "--partial"),
     ("pmc_fetch_copy", "--pmc FETCH_SIZE", "--copy-calibration"),
     ("pmc_write_copy", "--pmc WRITE_SIZE", "--copy-calibration"),
 ]
@@ -404,6 +405,34 @@ def summarize_single(d, cmd, src):
     print("wrote profiles/kernel_stats_single_c60.md")
 
 
+def summarize_partial(d, cmd, src):
+    """profiles/kernel_stats_partial_40q.md: device time of the partial-amplitude
+    mode (kernel trace of bench.py --partial), beside the figures of the same run."""
+    import glob
+    line = _last_json(os.path.join(d, "partial.log"))
+    st = glob.glob(os.path.join(d, "partial", "**", "*kernel_stats.csv"), recursive=True)
+    if not line or not st:
+        return
+    rows = _csv_rows(st[0])
+    kl = ["# Kernel time, partial-amplitude mode (%s)" % line["workload"], "",
+          "`rocprofv3 --kernel-trace --stats` of `bench.py --partial`: the circuit divided into parts of %s qubits "
+          "by %d cut gates (Eq. 4), %d sub-circuits, %d sampled amplitudes, once unfused and once with greedy "
+          "complex128 blocks." % (" and ".join(str(x) for x in line["parts"]), line["cuts"], line["sub_circuits"],
+                                  line["amplitudes"]), "",
+          "| kernel | calls | total ms | average us | % |", "|---|---|---|---|---|"]
+    for r in rows[:12]:
+        kl.append("| %s | %s | %.1f | %.1f | %s |" % (short_kernel(r["Name"]), r["Calls"],
+                                                       float(r["TotalDurationNs"]) / 1e6,
+                                                       float(r["AverageNs"]) / 1e3, r["Percentage"]))
+    kl += ["", "The same run (wall time of each whole call): " + "; ".join(
+        "%s %.3f s, %.0f amplitudes/s" % (r["path"], r["seconds"], r["amplitudes_per_s"]) for r in line["runs"]) + ".",
+        "", "Command (from the repository root):", "", "```", cmd, "```", "",
+        "Kernel sources hash: %s" % src]
+    with open(os.path.join(ROOT, "profiles", "kernel_stats_partial_40q.md"), "w") as f:
+        f.write("\n".join(kl) + "\n")
+    print("wrote profiles/kernel_stats_partial_40q.md")
+
+
 def summarize_profiles(d):
     """Write profiles/traffic.json and the text summaries from rocprofv3 CSVs."""
     import glob
@@ -518,6 +547,8 @@ def summarize_profiles(d):
         summarize_sq(d, cmds, src)
     if os.path.isdir(os.path.join(d, "traj")):
         summarize_traj(d, cmds["traj"], source_hash(("qs_fused.hip", "qs_traj.hip")))
+    if os.path.isdir(os.path.join(d, "partial")):
+        summarize_partial(d, cmds["partial"], src)
     if os.path.isdir(os.path.join(d, "single")):
         summarize_single(d, cmds["single"], source_hash(("qs_single.hip",)))
     print("wrote profiles/traffic.json, profiles/hbm_traffic_rqc30_d40.md, profiles/kernel_stats_rqc30_d40.md")
