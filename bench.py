@@ -740,15 +740,28 @@ def partial_bench(qs, cg, rows=8, cols=5, depth=8, top_rows=4, m=1 << 20, seed=6
     idx = np.random.default_rng(seed + 1).integers(0, 1 << n, size=m, dtype=np.uint64)
     cuts = c.partial_cuts(n, part_a)
     runs = []
-    for name, dt, plan in (("c128_unfused", qs.C128, qs.PLAN_UNFUSED), ("c128_greedy", qs.C128, qs.PLAN_GREEDY)):
+    ref = None
+    for name, dt, plan in (("c128_unfused", qs.C128, qs.PLAN_UNFUSED), ("c128_greedy", qs.C128, qs.PLAN_GREEDY),
+                           ("c64_greedy", qs.C64, qs.PLAN_GREEDY)):
         t0 = time.perf_counter()
         amps, _ = c.partial_amplitudes(n, part_a, idx, dtype=dt, plan=plan)
         sec = time.perf_counter() - t0
         p = np.abs(amps) ** 2
+        rec_run = {"path": name, "seconds": round(sec, 3), "amplitudes_per_s": round(m / sec, 1),
+                   "mean_prob_times_2n": round(float(p.mean() * 2.0 ** n), 4)}
+        extra = ""
+        if ref is None:
+            ref = amps
+        else:
+            # agreement with the unfused complex128 run on the same indices
+            d = amps - ref
+            rec_run["max_abs_diff_vs_c128_unfused"] = float(np.max(np.abs(d)))
+            rec_run["rel_l2_vs_c128_unfused"] = float(np.linalg.norm(d) / np.linalg.norm(ref))
+            extra = "; vs c128 unfused: max|d| %.2e, rel l2 %.2e" % (rec_run["max_abs_diff_vs_c128_unfused"],
+                                                                    rec_run["rel_l2_vs_c128_unfused"])
         log("partial %s: %d qubits, %d cuts, %d sub-circuits, %d amplitudes in %.2f s (%.0f amplitudes/s); "
-            "mean |amp|^2 * 2^n = %.3f" % (name, n, cuts, 2 << cuts, m, sec, m / sec, p.mean() * 2.0 ** n))
-        runs.append({"path": name, "seconds": round(sec, 3), "amplitudes_per_s": round(m / sec, 1),
-                     "mean_prob_times_2n": round(float(p.mean() * 2.0 ** n), 4)})
+            "mean |amp|^2 * 2^n = %.3f%s" % (name, n, cuts, 2 << cuts, m, sec, m / sec, p.mean() * 2.0 ** n, extra))
+        runs.append(rec_run)
     rec = {"metric": "partial-amplitude mode: sampled amplitudes per second", "unit": "amplitudes/s",
            "value": max(r["amplitudes_per_s"] for r in runs),
            "workload": "%dx%d grid random circuit, %d qubits, depth %d, %d gates" % (rows, cols, n, depth,

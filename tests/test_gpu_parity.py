@@ -1043,7 +1043,8 @@ def test_partial_amplitudes_per_branch_path_matches_tree_walk(qs):
 def test_partial_amplitudes_30_qubits_against_full_state(qs):
     """At 30 qubits (6 x 5 grid, depth 8, divided between rows 2 and 3: 10
     cuts, two 15-qubit parts), 4096 sampled amplitudes equal those of the
-    complex128 full-amplitude path (which the tests above pin to the oracle)."""
+    complex128 full-amplitude path (which the tests above pin to the oracle);
+    with complex64 tiled sub-circuits, to the complex64 bar."""
     n, part_a = 30, (1 << 15) - 1
     ops = cg.random_circuit(6, 5, 8, seed=7002)
     c = qs.Circuit(ops)
@@ -1055,6 +1056,9 @@ def test_partial_amplitudes_30_qubits_against_full_state(qs):
     got, cuts = c.partial_amplitudes(n, part_a, idx)
     assert cuts == 10
     assert np.max(np.abs(got - full)) <= 1e-13
+    # complex64 sub-circuits of 15 qubits run as tile sweeps
+    got64, _ = c.partial_amplitudes(n, part_a, idx, dtype=qs.C64, plan=qs.PLAN_GREEDY)
+    _check_c64_sample(got64, full)
 
 
 def test_partial_amplitudes_40_qubits_two_divisions_agree(qs):
