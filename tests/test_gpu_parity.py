@@ -106,6 +106,36 @@ def test_diagonal_and_controlled_forms(qs):
         assert np.max(np.abs(got - ref)) <= TOL128, (t, c)
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_gates_on_the_lowest_qubits_whole_runs(qs, dtype):
+    """Diagonal gates with a qubit inside the 128-byte run (bits 0-2 of
+    complex128, 0-3 of complex64) and single-target gates with such a
+    control and the target above it move whole runs and change only the
+    selected amplitudes: every form against the oracle, on 12 qubits."""
+    n = 12
+    rng = np.random.default_rng(31)
+    dt = qs.C128 if dtype == "c128" else qs.C64
+    s = qs.State(n, dt)
+    psi = cg.random_state(n, 33)
+    s.set_amplitudes(psi)
+    ref = psi.copy()
+    gates = [
+        ((0, 1), (), cg.CZ_GATE), ((2, 9), (), cg.CZ_GATE), ((11, 3), (), cg.CZ_GATE),
+        ((1,), (), cg.T_GATE), ((0,), (), cg.rz(0.4)), ((3,), (), cg.T_GATE),
+        ((1, 2), (), oracle.named_gate("CR", (0.9,))), ((0, 1, 2), (), oracle.named_gate("TOFFOLI")),
+        ((5,), (1,), cg.u3(0.3, 0.8, -1.1)), ((7,), (0, 2), cg.u3(1.3, -0.2, 0.5)),
+        ((4,), (3,), cg.u3(0.6, 0.1, 0.9)), ((10,), (2, 8), cg.random_unitary(2, rng)),
+        ((6,), (0,), cg.PZ),
+    ]
+    tol = TOL128 if dt == qs.C128 else 2e-6
+    for t, c, m in gates:
+        s.apply_gate(t, c, m)
+        oracle.apply(ref, t, c, m)
+        got = s.amplitudes()
+        assert np.max(np.abs(got - ref)) <= tol, (t, c)
+    s.close()
+
+
 def test_edge_sizes(qs):
     # n = 1, gate on every qubit of the state, controls on all others
     for n in [1, 2, 6]:
