@@ -875,28 +875,35 @@ def trajectory_bench(qs, cg, count, seed=4001, reps=3):
     return res
 
 
-def train_cost_model(qs, cg, n=28, circuits=8, log_fn=None):
+def train_cost_model(qs, cg, n=28, circuits=8, log_fn=None, ns=None):
     """Train the planner's cost network on sweep timings that the simulator
-    records itself: random circuits on an n-qubit complex64 state, run under
-    every candidate tile shape, each sweep's features and measured time per
-    amplitude a sample; Adam on the GPU with the library's kernels."""
+    records itself: random circuits on n-qubit complex64 states (each size in
+    ns, default n alone), run under every candidate tile shape, each sweep's
+    features and measured time per amplitude a sample; Adam on the GPU with
+    the library's kernels."""
     import numpy as np
-    s = qs.State(n, qs.C64)
-    s.profile(True)
-    shapes = [(r, n // r) for r in range(2, n // 2 + 1) if n % r == 0]
-    for i in range(circuits):
-        rows, cols = shapes[i % len(shapes)]
-        c = qs.Circuit(cg.random_circuit(rows, cols, 12, seed=9000 + i, cu3_prob=0.1))
-        for m in (11, 12, 13):
-            for k in (4, 5):
-                s.reset()
-                s.run(c, plan=qs.PLAN_GREEDY, k_max=k, tile_qubits=m)
-    X, y = s.profile_samples()
-    s.profile(False)
-    s.close()
+    Xs, ys = [], []
+    for nn in (ns or (n,)):
+        s = qs.State(nn, qs.C64)
+        s.profile(True)
+        shapes = [(r, nn // r) for r in range(2, nn // 2 + 1) if nn % r == 0]
+        for i in range(circuits):
+            rows, cols = shapes[i % len(shapes)]
+            c = qs.Circuit(cg.random_circuit(rows, cols, 12, seed=9000 + i, cu3_prob=0.1))
+            for m in (11, 12, 13):
+                for k in (4, 5):
+                    s.reset()
+                    s.run(c, plan=qs.PLAN_GREEDY, k_max=k, tile_qubits=m)
+        X, y = s.profile_samples()
+        s.profile(False)
+        s.close()
+        Xs.append(X)
+        ys.append(y)
+    X, y = np.concatenate(Xs), np.concatenate(ys)
     p, loss = qs.mlp_train(qs.mlp_init(4), X, y, steps=3000, batch=256, lr=2e-3, seed=7)
     if log_fn:
-        log_fn("cost model: %d sweep samples at %d qubits, final loss %.4f" % (X.shape[0], n, loss))
+        log_fn("cost model: %d sweep samples at %s qubits, final loss %.4f"
+               % (X.shape[0], "/".join(str(v) for v in (ns or (n,))), loss))
     return p, int(X.shape[0])
 
 
@@ -925,7 +932,9 @@ def config5(qs, cg, torch):
     del ref
     out["c128_greedy_k3"] = {"seconds": ref_s, "gates_per_s": gates / ref_s}
     log("c128 reference: %.1f s" % ref_s)
-    p, nsamp = train_cost_model(qs, cg, log_fn=log)
+    # sweeps of two sizes, so that the network sees how a sweep's time per
+    # amplitude moves with the state size before it ranks 34-qubit plans
+    p, nsamp = train_cost_model(qs, cg, log_fn=log, ns=(28, 30))
     out["cost_model_samples"] = nsamp
     st = qs.State(n, qs.C64)
     for name, plan in (("learned", qs.PLAN_LEARNED), ("greedy", qs.PLAN_GREEDY), ("unfused", qs.PLAN_UNFUSED)):
