@@ -932,9 +932,7 @@ def config5(qs, cg, torch):
     del ref
     out["c128_greedy_k3"] = {"seconds": ref_s, "gates_per_s": gates / ref_s}
     log("c128 reference: %.1f s" % ref_s)
-    # sweeps of two sizes, so that the network sees how a sweep's time per
-    # amplitude moves with the state size before it ranks 34-qubit plans
-    p, nsamp = train_cost_model(qs, cg, log_fn=log, ns=(28, 30))
+    p, nsamp = train_cost_model(qs, cg, log_fn=log)
     out["cost_model_samples"] = nsamp
     st = qs.State(n, qs.C64)
     for name, plan in (("learned", qs.PLAN_LEARNED), ("greedy", qs.PLAN_GREEDY), ("unfused", qs.PLAN_UNFUSED)):
