@@ -410,7 +410,10 @@ def test_product_circuit_above_30_qubits_sampled_amplitudes(qs, nh, grid):
     assert info["sweeps"] > 1
     s.run(c, plan=qs.PLAN_GREEDY, k_max=4, tile_qubits=13)
     got = s.amplitudes(idx)
-    assert abs(s.norm() - 1) < 1e-5
+    # a split-bfloat16 block (hi + lo operands, about 16 significant bits)
+    # is unitary to about 2^-16, so the squared norm may drift by about that
+    # much per fused block of the plan
+    assert abs(s.norm() - 1) < info["blocks"] * 2.0 ** -16
     s.close()
     _check_c64_sample(got, want)
     if n == 32:
