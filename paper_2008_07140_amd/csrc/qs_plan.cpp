@@ -686,8 +686,8 @@ void plan_tiles_once(const std::vector<FlatOp> &flat, size_t k0, size_t e, int n
             // sweep then applies more gates, until no swap helps.  Among the
             // local optima keep the one whose sweep plus the next sweep (its
             // deferred gates, searched the same way from their greedy set),
-            // and with a lookahead of 3 the sweep after that, apply the most
-            // gates; ties keep the earliest candidate.  Counts
+            // and so on up to `lookahead` sweeps, apply the most gates; ties
+            // keep the earliest candidate.  Counts
             // come from the scan below with Q fixed, post-pass rules
             // included, so the chosen Q's lists come from the same scan.
             auto scan_on = [&](const std::vector<size_t> &rem, uint64_t Qf, std::vector<size_t> *app,
@@ -779,18 +779,16 @@ void plan_tiles_once(const std::vector<FlatOp> &flat, size_t k0, size_t e, int n
                 if (cands.size() > 1) {
                     std::vector<size_t> app, def;
                     scan_on(remaining, cands[ci].first, &app, &def);
-                    int c2 = 0;
-                    if (!def.empty()) {
-                        const uint64_t q2 = climb(def, greedy_q(def), c2);
-                        if (tp.lookahead >= 3) {
-                            std::vector<size_t> app2, def2;
-                            scan_on(def, q2, &app2, &def2);
-                            int c3 = 0;
-                            if (!def2.empty()) climb(def2, greedy_q(def2), c3);
-                            score += c3;
-                        }
+                    // the following sweeps, each from its greedy set
+                    for (int l = 2; l <= tp.lookahead && !def.empty(); ++l) {
+                        int cl = 0;
+                        const uint64_t ql = climb(def, greedy_q(def), cl);
+                        score += cl;
+                        if (l == tp.lookahead) break;
+                        std::vector<size_t> a2, d2;
+                        scan_on(def, ql, &a2, &d2);
+                        def.swap(d2);
                     }
-                    score += c2;
                 }
                 if (score > bscore) {
                     bscore = score;
@@ -962,10 +960,12 @@ double plan_cost(const std::vector<PlanStep> &steps)
 // the random restarts are compared by plan_cost: more restarts find sweeps
 // that apply more gates, which is not always the cheaper plan (fewer sweeps
 // carrying more blocks).  On states of at least 24 qubits the same two are
-// made with a lookahead of three sweeps as well (on the 30-qubit depth-40
-// circuit: 28 sweeps with 186 blocks against 195; on the 34-qubit depth-24
-// one it finds 12 sweeps with 96 blocks, which the estimate ranks behind 13
-// with 87, as measured).
+// made with lookaheads of three, four and five sweeps as well: the search
+// is greedy per sweep, and a wider set of plans gives the estimate more to
+// choose from (on the 30-qubit depth-40 circuit: 28 sweeps with 183-186
+// blocks against 195 with the two-sweep lookahead alone; on the 34-qubit
+// depth-24 one a lookahead of three finds 12 sweeps with 96 blocks, which
+// the estimate ranks behind 13 with 87, as measured).
 void plan_tiles_variants(const std::vector<FlatOp> &flat, size_t k0, size_t e, int n, const TileParams &tp,
                          std::vector<std::vector<PlanStep>> &out)
 {
@@ -976,7 +976,7 @@ void plan_tiles_variants(const std::vector<FlatOp> &flat, size_t k0, size_t e, i
         return;
     }
     std::vector<TileParams> vs;
-    for (int la = 2; la <= (n >= 24 ? 3 : 2); ++la) {
+    for (int la = 2; la <= (n >= 24 ? 5 : 2); ++la) {
         TileParams half = tp, all = tp;
         half.restarts = tp.restarts / 2;
         half.lookahead = all.lookahead = la;

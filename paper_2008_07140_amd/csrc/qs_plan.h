@@ -109,7 +109,7 @@ struct TileParams {
     int max_outer = kMaxOuter;  // outer selector bits per op (0..kMaxOuter)
     bool search = true;  // improve each sweep's tile qubits by local search
     int restarts = 32;   // extra random starting sets for that search
-    int lookahead = 2;   // sweeps scored per candidate tile set (2 or 3)
+    int lookahead = 2;   // sweeps scored per candidate tile set
 };
 
 // One step of a tiled plan: a tile sweep, or a gate that does not fit a tile
@@ -122,8 +122,8 @@ struct PlanStep {
 
 // Plan the gates flat[k, e) as tile sweeps (appended to out): of the whole
 // plans made with half and with all of tp.restarts (and, on states of at
-// least 24 qubits, the same two with a lookahead of three sweeps), the one
-// with the lower fixed cost estimate.
+// least 24 qubits, the same two with lookaheads of three to five sweeps),
+// the one with the lower fixed cost estimate.
 void plan_tiles(const std::vector<FlatOp> &flat, size_t k, size_t e, int n, const TileParams &tp,
                 std::vector<PlanStep> &out);
 // The candidate whole plans plan_tiles chooses between (one when the search
