@@ -6,6 +6,7 @@
 #include <chrono>
 #include <complex>
 #include <cstring>
+#include <exception>
 #include <map>
 #include <memory>
 #include <thread>
@@ -984,13 +985,27 @@ void plan_tiles_variants(const std::vector<FlatOp> &flat, size_t k0, size_t e, i
         vs.push_back(all);
     }
     // the variants are independent: one thread each (plan_tiles_once only
-    // reads the gate list)
+    // reads the gate list); an exception in a thread (an allocation that
+    // fails) is passed on to the caller after every thread has ended
     out.resize(vs.size());
+    std::vector<std::exception_ptr> err(vs.size());
     std::vector<std::thread> th;
     for (size_t i = 1; i < vs.size(); ++i)
-        th.emplace_back([&, i] { plan_tiles_once(flat, k0, e, n, vs[i], out[i]); });
-    plan_tiles_once(flat, k0, e, n, vs[0], out[0]);
+        th.emplace_back([&, i] {
+            try {
+                plan_tiles_once(flat, k0, e, n, vs[i], out[i]);
+            } catch (...) {
+                err[i] = std::current_exception();
+            }
+        });
+    try {
+        plan_tiles_once(flat, k0, e, n, vs[0], out[0]);
+    } catch (...) {
+        err[0] = std::current_exception();
+    }
     for (std::thread &t : th) t.join();
+    for (const std::exception_ptr &x : err)
+        if (x) std::rethrow_exception(x);
 }
 
 void plan_tiles(const std::vector<FlatOp> &flat, size_t k0, size_t e, int n, const TileParams &tp,
