@@ -710,8 +710,15 @@ void plan_tiles_once(const std::vector<FlatOp> &flat, size_t k0, size_t e, int n
                 }
                 return c;
             };
+            // with a run weight, a tile set whose lowest 5 or 6 qubits are
+            // contiguous (rows of 256 or 512 bytes instead of 128) counts
+            // that many gates more per extra qubit
+            auto run_bonus = [&](uint64_t q) {
+                const int run = __builtin_ctzll(~q);
+                return tp.run_weight * std::min(2, std::max(0, run - 4));
+            };
             auto climb = [&](const std::vector<size_t> &rem, uint64_t Qs, int &count) {
-                int best = scan_on(rem, Qs, nullptr, nullptr);
+                int best = scan_on(rem, Qs, nullptr, nullptr) + run_bonus(Qs);
                 for (bool improved = true; improved;) {
                     improved = false;
                     for (int a = L; a < n && !improved; ++a) {
@@ -719,7 +726,7 @@ void plan_tiles_once(const std::vector<FlatOp> &flat, size_t k0, size_t e, int n
                         for (int b = L; b < n; ++b) {
                             if (Qs >> b & 1) continue;
                             const uint64_t Q2 = (Qs & ~(uint64_t(1) << a)) | (uint64_t(1) << b);
-                            const int c2 = scan_on(rem, Q2, nullptr, nullptr);
+                            const int c2 = scan_on(rem, Q2, nullptr, nullptr) + run_bonus(Q2);
                             if (c2 > best) {
                                 best = c2;
                                 Qs = Q2;
@@ -937,11 +944,14 @@ void plan_tiles_once(const std::vector<FlatOp> &flat, size_t k0, size_t e, int n
 
 }  // namespace
 
-// Relative cost of a tiled plan: a sweep costs its memory pass (1) plus
-// 0.15 per dense block beyond the two that hide under that pass, a gate
-// applied on its own one pass.  The ratio is the per-op time of the tile
-// kernel beyond the second op over its memory time (0.37 over 3.75 ms on the
-// microbenchmark, about 0.15 in whole plans of 30- and 34-qubit circuits).
+// Relative cost of a tiled plan: a sweep costs its memory pass (1; 0.975
+// when the tile holds qubits 0..4, 0.925 with 0..5: rows of 256 and 512
+// bytes against 128 move faster, 0.975 and 0.89 on the tile microbenchmark
+// with four ops, and 0.925 fits the whole plans measured) plus 0.15 per dense
+// block beyond the two that hide under that pass, a gate applied on its own
+// one pass.  The ratio is the per-op time of the tile kernel beyond the
+// second op over its memory time (0.37 over 3.75 ms on the microbenchmark,
+// 0.11-0.15 in whole plans of 30- and 34-qubit circuits).
 double plan_cost(const std::vector<PlanStep> &steps)
 {
     double c = 0;
@@ -952,7 +962,9 @@ double plan_cost(const std::vector<PlanStep> &steps)
         }
         int dense = 0;
         for (const TileOp &op : st.sw.ops) dense += op.kind == TileOp::DENSE;
-        c += 1 + 0.15 * std::max(0, dense - 2);
+        int run = 0;
+        while (run < int(st.sw.Q.size()) && st.sw.Q[run] == run) ++run;
+        c += (run >= 6 ? 0.925 : run == 5 ? 0.975 : 1.0) + 0.15 * std::max(0, dense - 2);
     }
     return c;
 }
@@ -961,10 +973,12 @@ double plan_cost(const std::vector<PlanStep> &steps)
 // the random restarts are compared by plan_cost: more restarts find sweeps
 // that apply more gates, which is not always the cheaper plan (fewer sweeps
 // carrying more blocks).  On states of at least 24 qubits the same two are
-// made with lookaheads of three, four and five sweeps as well: the search
-// is greedy per sweep, and a wider set of plans gives the estimate more to
-// choose from (on the 30-qubit depth-40 circuit: 28 sweeps with 183-186
-// blocks against 195 with the two-sweep lookahead alone; on the 34-qubit
+// made with lookaheads of three, four and five sweeps as well, each with a
+// run weight of 0 and of 1: the search is greedy per sweep, and a wider set
+// of plans gives the estimate more to choose from (on the 30-qubit depth-40
+// circuit: 28 sweeps with 183-186 blocks against 195 with the two-sweep
+// lookahead alone, and with a run weight of one 8 of the 28 tiles with
+// qubits 0..5 against 3, 11970 against 11890 gates/s; on the 34-qubit
 // depth-24 one a lookahead of three finds 12 sweeps with 96 blocks, which
 // the estimate ranks behind 13 with 87, as measured).
 void plan_tiles_variants(const std::vector<FlatOp> &flat, size_t k0, size_t e, int n, const TileParams &tp,
@@ -977,13 +991,15 @@ void plan_tiles_variants(const std::vector<FlatOp> &flat, size_t k0, size_t e, i
         return;
     }
     std::vector<TileParams> vs;
-    for (int la = 2; la <= (n >= 24 ? 5 : 2); ++la) {
-        TileParams half = tp, all = tp;
-        half.restarts = tp.restarts / 2;
-        half.lookahead = all.lookahead = la;
-        vs.push_back(half);
-        vs.push_back(all);
-    }
+    for (int rw = 0; rw <= (n >= 24 ? 1 : 0); ++rw)
+        for (int la = 2; la <= (n >= 24 ? 5 : 2); ++la) {
+            TileParams half = tp, all = tp;
+            half.restarts = tp.restarts / 2;
+            half.lookahead = all.lookahead = la;
+            half.run_weight = all.run_weight = rw;
+            vs.push_back(half);
+            vs.push_back(all);
+        }
     // the variants are independent: one thread each (plan_tiles_once only
     // reads the gate list); an exception in a thread (an allocation that
     // fails) is passed on to the caller after every thread has ended

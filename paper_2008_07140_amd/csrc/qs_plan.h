@@ -110,6 +110,7 @@ struct TileParams {
     bool search = true;  // improve each sweep's tile qubits by local search
     int restarts = 32;   // extra random starting sets for that search
     int lookahead = 2;   // sweeps scored per candidate tile set
+    int run_weight = 0;  // gates a tile set may give up per extra low qubit beyond the four (at most two)
 };
 
 // One step of a tiled plan: a tile sweep, or a gate that does not fit a tile
@@ -122,16 +123,18 @@ struct PlanStep {
 
 // Plan the gates flat[k, e) as tile sweeps (appended to out): of the whole
 // plans made with half and with all of tp.restarts (and, on states of at
-// least 24 qubits, the same two with lookaheads of three to five sweeps),
-// the one with the lower fixed cost estimate.
+// least 24 qubits, the same two with lookaheads of three to five sweeps,
+// each also with a run weight of one), the one with the lower fixed cost
+// estimate.
 void plan_tiles(const std::vector<FlatOp> &flat, size_t k, size_t e, int n, const TileParams &tp,
                 std::vector<PlanStep> &out);
 // The candidate whole plans plan_tiles chooses between (one when the search
 // is off), for a cost model to choose instead.
 void plan_tiles_variants(const std::vector<FlatOp> &flat, size_t k, size_t e, int n, const TileParams &tp,
                          std::vector<std::vector<PlanStep>> &out);
-// The fixed estimate plan_tiles ranks them by (memory passes plus 0.15 per
-// dense block beyond two per sweep).
+// The fixed estimate plan_tiles ranks them by (memory passes, shorter for
+// tiles whose qubits 0..4 or 0..5 are contiguous, plus 0.15 per dense block
+// beyond two per sweep).
 double plan_cost(const std::vector<PlanStep> &steps);
 
 }  // namespace qs
