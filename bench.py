@@ -363,7 +363,7 @@ def summarize_traj(d, cmd, src):
                                                        float(r["TotalDurationNs"]) / 1e6,
                                                        float(r["AverageNs"]) / 1e3, r["Percentage"]))
     kl += ["", "The fastest timed call of the same run (library statistics): %.3f s wall, %.3f s device time "
-           "(HIP events around each pass job), %.3f s of host planning, program build and upload, %d passes, "
+           "(HIP events around each job), %.3f s of host planning, program build and upload, %d passes, "
            "%d jumps, %d kernel launches in %s; %.0f trajectories/s."
            % (line["seconds"], line["device_s"], line["host_s"], line["passes"], line["jumps"], line["launches"],
               "captured HIP graphs" if line.get("graph") else "direct launches", line["traj_per_s"]),
@@ -859,7 +859,7 @@ def trajectory_bench(qs, cg, count, seed=4001, reps=3):
         "widths %s; direct launches %.3f s)" % (count, best["seconds"], count / best["seconds"], best["passes"],
                                                best["jumps"], best["device_seconds"], best["host_seconds"],
                                                res["widths_chosen"], direct["seconds"]))
-    # accuracy of the trajectory mean at n = 10 (BASELINE config 4's check)
+    # accuracy of the trajectory mean at n = 10 against the exact density matrix
     n, T = 10, 4096
     ops = cg.random_circuit(2, 5, 24, seed=4010, dep1=1e-3, dep2=1e-2, damping=5e-4)
     zdm = np.loadtxt(os.path.join(ROOT, "tests", "golden", "dm_n10_d24_workload_rates.txt"))

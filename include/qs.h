@@ -286,25 +286,27 @@ qs_status qs_expect_z(const qs_state *s, double *out);
  * once and executed as one captured HIP graph (opts->direct_launch = 0) of
  * batched sweeps, batched FP64 run sums and a sampling kernel that draws
  * each damping site's uniform on the device and picks its branch.  A
- * trajectory whose site takes K2 stops there for the pass; the host
- * rewrites its remaining steps (K1 of the earlier sites of the run, K2,
- * renormalisation, the rest of the run) and runs such trajectories in the
- * next pass.  Complex128 states, narrower states and plans with gates too
+ * trajectory whose site takes K2 stops there; once its job has finished,
+ * the host rewrites its remaining steps (K1 of the earlier sites of the run,
+ * K2, renormalisation, the rest of the run) and queues it for the next job.  Complex128 states, narrower states and plans with gates too
  * wide for a tile take the host-sampled path (one batched step at a time,
  * sums read back and sampled on the host); so does every state with
- * opts->plan = QS_PLAN_UNFUSED.  A pass runs in jobs of at most 128
- * trajectories, launched so that the host plans one job while the device runs
+ * opts->plan = QS_PLAN_UNFUSED.  Device-sampled trajectories run in jobs of
+ * at most 128, launched so that the host plans one job while the device runs
  * the one before.  opts (may be NULL): plan QS_PLAN_GREEDY (default widths:
  * 13-qubit tiles, 4-qubit blocks, 1 outer selector bit per op, 128
  * trajectories per job) or QS_PLAN_AUTOTUNE (each of the first calls for a batch of the same
  * dtype, size and widths runs the next untried candidate width set and
- * times the whole call; later calls use the fastest: qs_trajectory_stats
- * reports the choice), k_max (4 or 5; 0 = default), tile_qubits (10..13;
+ * times the whole call; a call that had to enlarge the job buffers kept
+ * between calls is not recorded and its candidate runs again; later calls
+ * use the fastest: qs_trajectory_stats reports the choice), k_max (4 or 5; 0 = default), tile_qubits (10..13;
  * 0 = default), direct_launch.  The branch choices do not depend on any of
  * these.  *traj_per_s (may be NULL) receives count / the wall time of the
  * whole call after argument checks: preparation of every trajectory,
  * planning, device allocation, uploads, all launches and the final
- * reductions.  Synchronous.  Errors: QS_E_INVAL (arguments, widths),
+ * reductions.  Synchronous.  The job buffers (device program and work
+ * space, pinned host staging) stay allocated after the call, one set per
+ * device, and are reused by the next call.  Errors: QS_E_INVAL (arguments, widths),
  * QS_E_RANGE (a qubit >= the trajectory's width), QS_E_UNSUPPORTED (noise
  * inside a group, or a channel of another form), QS_E_ZERO_NORM,
  * QS_E_NOMEM, QS_E_DEVICE. */
@@ -314,9 +316,9 @@ qs_status qs_run_trajectories(const qs_circuit *const *circs, const int *widths,
 
 /* Statistics of the last qs_run_trajectories call on the calling thread. */
 typedef struct {
-    int passes;             /* device-sampled passes over the batch (later ones: trajectories that jumped) */
-    int graphs;             /* pass jobs (each one HIP graph, or one set of launches) */
-    int chunk;              /* trajectories per pass job (0 = the whole pass in one job) */
+    int passes;             /* the most device-sampled jobs one trajectory ran in (more than one: it jumped) */
+    int graphs;             /* device-sampled jobs (each one HIP graph, or one set of launches) */
+    int chunk;              /* trajectories per job at most (0 = all waiting trajectories in one job) */
     int host_sampled;       /* trajectories that took the host-sampled path */
     int64_t jumps;          /* K2 branches taken */
     int64_t launches;       /* kernel launches enqueued (inside graphs included) */
@@ -327,8 +329,8 @@ typedef struct {
     int autotune_tried;     /* QS_PLAN_AUTOTUNE: candidates measured so far for this batch shape */
     int autotune_candidates;
     double seconds;         /* wall time of the call */
-    double host_seconds;    /* of which: planning, program build and upload of the passes (host) */
-    double device_seconds;  /* device time of the passes (HIP events around each) */
+    double host_seconds;    /* of which: planning, program build and upload of the jobs (host) */
+    double device_seconds;  /* device time of the jobs (HIP events around each) */
 } qs_traj_stats;
 
 qs_status qs_trajectory_stats(qs_traj_stats *out);

@@ -1638,7 +1638,7 @@ struct TrajParams {
     int m_cap = 13;     // qubits per tile (at most the state's width)
     int kmax = 4;       // widest dense block
     int max_outer = 1;  // outer selector bits per op
-    int chunk = 128;    // trajectories per device-sampled pass job (0 = all at once)
+    int chunk = 128;    // trajectories per device-sampled job at most (0 = all waiting at once)
 };
 
 // Device buffers, host staging and the graph of one device-sampled pass
@@ -1670,6 +1670,39 @@ struct PassSlot {
     }
 };
 
+// Pass slots outlive a batch: their device buffers, pinned staging buffers
+// and events are allocated by the first batches on a device and reused by
+// later ones (pinning a staging buffer of a hundred megabytes costs tens of
+// milliseconds, a large share of a batch).  One idle pair is kept per device
+// until the process ends; a batch that finds none (another thread holds it)
+// makes its own.
+std::mutex g_slot_mu;
+std::map<int, std::unique_ptr<PassSlot[]>> *g_slot_pool = new std::map<int, std::unique_ptr<PassSlot[]>>;
+
+std::unique_ptr<PassSlot[]> take_slots(int dev)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_slot_mu);
+        auto it = g_slot_pool->find(dev);
+        if (it != g_slot_pool->end() && it->second) return std::move(it->second);
+    }
+    return std::unique_ptr<PassSlot[]>(new PassSlot[2]);
+}
+
+// Only after every job of the batch has finished (its stream has drained).
+void give_slots(int dev, std::unique_ptr<PassSlot[]> p)
+{
+    for (int i = 0; i < 2; ++i) {
+        p[i].drop_graph();
+        p[i].busy = false;
+        p[i].set.clear();
+        p[i].out.clear();
+    }
+    std::lock_guard<std::mutex> lk(g_slot_mu);
+    auto &q = (*g_slot_pool)[dev];
+    if (!q) q = std::move(p);
+}
+
 struct Batch {
     qs_state *master = nullptr;  // scratch and stream owner (a 1-qubit state)
     qs_dtype dt;
@@ -1683,13 +1716,16 @@ struct Batch {
     DevBuf states, prog, red, work;
     PinnedBuf stage, back;       // uploads (written only after the stream has drained), read-backs
     std::vector<View *> views;
-    PassSlot slot[2];
+    int dev = 0;
+    std::unique_ptr<PassSlot[]> slot;  // two, from take_slots
+    bool grew = false;                 // a job had to enlarge a slot's buffers
     qs_traj_stats st{};
     ~Batch()
     {
         if (master) (void)hipStreamSynchronize(master->stream);  // no buffer is freed under a running kernel
         for (auto *v : views) delete v;
         if (master) free_state(master);
+        if (slot) give_slots(dev, std::move(slot));
     }
 };
 
@@ -2195,6 +2231,8 @@ qs_status launch_pass(Batch &B, PassSlot &P, std::vector<int> job)
     {
         const size_t back_bytes = o_err - o_freeze + 256 + size_t(S) * w * sizeof(double);
         if (up_bytes > P.prog.cap || work_bytes > P.work.cap) HIP_TRY(hipStreamSynchronize(s->stream));
+        if (up_bytes > P.prog.cap || work_bytes > P.work.cap || up_bytes > P.stage.cap || back_bytes > P.back.cap)
+            B.grew = true;
         hipError_t e = P.prog.ensure(up_bytes);
         if (e == hipSuccess) e = P.work.ensure(work_bytes);
         if (e == hipSuccess) e = P.stage.ensure(up_bytes);
@@ -2342,38 +2380,49 @@ qs_status finish_pass(Batch &B, PassSlot &P, std::vector<int> &next, std::vector
     return QS_OK;
 }
 
-// Device-sampled passes over `set` until no trajectory is left: each pass
-// splits its trajectories into jobs of B.par.chunk, launched alternately in
-// two slots, so that the host builds a job while the device runs the one
-// before it.
+// Device-sampled jobs over `set` until no trajectory is left.  Trajectories
+// wait in `pending`, in order; a job takes up to B.par.chunk of them.  Jobs
+// go alternately to two slots, so that the host builds a job while the device
+// runs the one before it; before a slot is reused its previous job is
+// finished, and that job's trajectories that jumped join `pending` at once:
+// they run in the next job instead of after the rest of the batch.  The
+// passes reported are the most jobs any one trajectory ran in.
 qs_status run_device_sampled(Batch &B, std::vector<int> set, std::vector<int> &demoted)
 {
-    while (!set.empty()) {
-        const size_t C = B.par.chunk > 0 ? size_t(B.par.chunk) : set.size();
+    const size_t C = B.par.chunk > 0 ? size_t(B.par.chunk) : std::max<size_t>(set.size(), 1);
+    std::vector<int> pending(std::move(set)), runs(B.prep.size(), 0);
+    size_t head = 0;
+    int passes = 0;
+    auto finish = [&](PassSlot &P) -> qs_status {
         std::vector<int> next;
-        int k = 0;
-        for (size_t pos = 0; pos < set.size(); pos += C, ++k) {
-            PassSlot &P = B.slot[k & 1];
-            if (P.busy)
-                if (qs_status e = finish_pass(B, P, next, demoted)) return e;
-            std::vector<int> chunk(set.begin() + long(pos), set.begin() + long(std::min(set.size(), pos + C)));
-            if (qs_status e = launch_pass(B, P, std::move(chunk))) return e;
+        if (qs_status e = finish_pass(B, P, next, demoted)) return e;
+        pending.insert(pending.end(), next.begin(), next.end());
+        return QS_OK;
+    };
+    for (int k = 0;; ++k) {
+        PassSlot &P = B.slot[k & 1], &O = B.slot[(k + 1) & 1];  // P holds the older job
+        if (P.busy)
+            if (qs_status e = finish(P)) return e;
+        if (head == pending.size()) {  // nothing waiting: the newer job may still add some
+            if (!O.busy) break;
+            if (qs_status e = finish(O)) return e;
+            if (head == pending.size()) break;
         }
-        for (int j = 0; j < 2; ++j) {  // the older job first
-            PassSlot &P = B.slot[(k + j) & 1];
-            if (P.busy)
-                if (qs_status e = finish_pass(B, P, next, demoted)) return e;
-        }
-        ++B.st.passes;
-        set.swap(next);
+        const size_t take = std::min(C, pending.size() - head);
+        std::vector<int> job(pending.begin() + long(head), pending.begin() + long(head + take));
+        head += take;
+        for (int t : job) passes = std::max(passes, ++runs[size_t(t)]);
+        if (qs_status e = launch_pass(B, P, std::move(job))) return e;
     }
+    B.st.passes += passes;
     return QS_OK;
 }
 
 qs_status run_trajectory_batch(const qs_circuit *const *circs, const int *widths, int count, qs_dtype dt,
                                uint64_t seed, const TrajParams &par, bool device_ok, bool graph, double *z_out,
-                               qs_traj_stats &stats)
+                               qs_traj_stats &stats, bool &cold)
 {
+    cold = false;
     if (!circs || !widths || !z_out || count < 0) return fail(QS_E_INVAL, "NULL argument or negative count");
     if (dt != QS_C64 && dt != QS_C128) return fail(QS_E_INVAL, "unknown dtype %d", int(dt));
     if (count == 0) return QS_OK;
@@ -2405,6 +2454,8 @@ qs_status run_trajectory_batch(const qs_circuit *const *circs, const int *widths
     const size_t lim = g_mem_limit.load();
     if (lim && total > lim) return fail(QS_E_NOMEM, "batch of %zu bytes exceeds the memory limit", total);
     if (qs_status e = qs_create(1, dt, &B.master)) return e;
+    HIP_TRY(hipGetDevice(&B.dev));
+    B.slot = take_slots(B.dev);
     {
         hipError_t e = B.states.ensure(total);
         if (e != hipSuccess) return fail(QS_E_NOMEM, "device allocation of %zu bytes failed", total);
@@ -2436,6 +2487,7 @@ qs_status run_trajectory_batch(const qs_circuit *const *circs, const int *widths
     B.st.chunk = par.chunk;
     B.st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     stats = B.st;
+    cold = B.grew;
     return QS_OK;
 }
 
@@ -3610,8 +3662,8 @@ std::map<TrajTuneKey, std::vector<double>> g_traj_tune;  // measured seconds per
 // Candidate widths of device-sampled passes: (qubits per tile, widest
 // block, outer selector bits per op, trajectories per pass job); the first
 // is the default.
-const TrajParams kTrajCands[] = {{13, 4, 1, 128}, {13, 4, 1, 64}, {13, 4, 1, 0},
-                                 {13, 4, 2, 128}, {12, 4, 1, 128}, {13, 5, 1, 128}};
+const TrajParams kTrajCands[] = {{13, 4, 1, 128}, {13, 4, 1, 64}, {13, 4, 1, 0}, {13, 4, 2, 128},
+                                 {13, 4, 2, 64},  {12, 4, 1, 128}, {13, 5, 1, 128}};
 constexpr int kNumTrajCands = int(sizeof(kTrajCands) / sizeof(kTrajCands[0]));
 
 }  // namespace
@@ -3655,13 +3707,16 @@ try {
         par = kTrajCands[cand];
     }
     qs_traj_stats st{};
+    bool cold = false;
     const qs_status r = run_trajectory_batch(circs, widths, count, dt, seed, par, o.plan != QS_PLAN_UNFUSED,
-                                             o.direct_launch == 0, z_out, st);
+                                             o.direct_launch == 0, z_out, st, cold);
     if (r) return r;
     if (cand >= 0) {
         std::lock_guard<std::mutex> lk(g_traj_tune_mu);
         auto &rec = g_traj_tune[key];
-        if (rec[cand] < 0 || st.seconds < rec[cand]) rec[cand] = st.seconds;
+        // a call that enlarged the reused job buffers paid for allocations
+        // later calls do not make: not recorded, the candidate runs again
+        if (!cold && (rec[cand] < 0 || st.seconds < rec[cand])) rec[cand] = st.seconds;
         st.autotune_candidates = kNumTrajCands;
         for (double v : rec) st.autotune_tried += v >= 0;
     }

@@ -610,21 +610,26 @@ def test_trajectory_autotune_runs_every_width_set_exactly(qs):
     """QS_PLAN_AUTOTUNE: each of the first calls for a batch shape runs the
     next candidate width set (tile qubits, block width, outer bits) over the
     whole batch; every call is an exact run (the oracle's <Z_q> per
-    trajectory), and once all are measured the fastest is kept."""
+    trajectory), and once all are measured the fastest is kept.  A call that
+    had to enlarge the job buffers kept between calls is not recorded (its
+    candidate runs again), so a call adds at most one measured candidate."""
     batch = _traj_batch(8, 14, 15, 4, 1400, 0.05)
     circs = [qs.Circuit(ops) for _, ops in batch]
     widths = [n for n, _ in batch]
     want = np.concatenate([oracle.expect_z(oracle.run(n, ops, seed=57, traj=t)[0])
                            for t, (n, ops) in enumerate(batch)])
     seen = set()
-    ncand = None
-    for call in range(8):
+    ncand, tried = None, 0
+    for call in range(24):
         z, info = qs.run_trajectories(circs, widths, dtype=qs.C64, seed=57, plan=qs.PLAN_AUTOTUNE)
         assert np.max(np.abs(z - want)) <= 1e-4, call
         ncand = info["autotune_candidates"]
-        assert info["autotune_tried"] == min(call + 1, ncand)
+        assert info["autotune_tried"] in (tried, tried + 1), call
+        tried = info["autotune_tried"]
         seen.add((info["tile_qubits"], info["k_max"], info["max_outer"], info["chunk"]))
-    assert ncand >= 2 and len(seen) == ncand
+        if tried == ncand:
+            break
+    assert ncand >= 2 and tried == ncand and len(seen) == ncand
 
 
 def test_batched_trajectories_wider_than_a_tile(qs):
