@@ -81,12 +81,22 @@ def parse():
 PROFILED_SOURCES = ("qs_fused.hip", "qs_kernels.hip")
 
 
-def source_hash(sources=PROFILED_SOURCES):
-    """Hash of the device code of the profiled paths: their .hip sources and
-    the headers those include (transitively), so host-only changes and
-    changes to other kernels keep stored counter readings valid."""
+def _code_only(text: bytes) -> bytes:
+    """C/C++ source without comments, each run of white space one blank."""
     import re
-    csrc = os.path.join(ROOT, "paper_2008_07140_amd", "csrc")
+    t = re.sub(rb"/\*.*?\*/", b" ", text, flags=re.S)
+    t = re.sub(rb"//[^\n]*", b" ", t)
+    return b" ".join(t.split())
+
+
+def source_hash(sources=PROFILED_SOURCES, root=None):
+    """Hash of the device code of the profiled paths: their .hip sources and
+    the headers those include (transitively), comments and layout left out,
+    so host-only changes, comment edits and changes to other kernels keep
+    stored counter readings valid."""
+    import re
+    root = root or ROOT
+    csrc = os.path.join(root, "paper_2008_07140_amd", "csrc")
     files, todo = set(), [os.path.join(csrc, f) for f in sources]
     while todo:
         f = os.path.normpath(todo.pop())
@@ -98,9 +108,9 @@ def source_hash(sources=PROFILED_SOURCES):
                 todo.append(os.path.join(os.path.dirname(f), inc))
     h = hashlib.sha256()
     for f in sorted(files):
-        h.update(os.path.relpath(f, ROOT).encode())
+        h.update(os.path.relpath(f, root).encode())
         with open(f, "rb") as fh:
-            h.update(fh.read())
+            h.update(_code_only(fh.read()))
     return h.hexdigest()[:16]
 
 

@@ -418,3 +418,23 @@ def test_single_validation(qs):
     with pytest.raises(qs.QSError) as e:
         c.single_amplitudes(2, [4])  # bit 2 set on a 2-qubit circuit: rejected before any device work
     assert e.value.status == -2
+
+
+def test_profile_source_hash_ignores_comments_only(tmp_path):
+    """Stored counter readings are keyed by a hash of the profiled device
+    sources with comments and layout left out: a comment edit keeps the
+    key, a change to the code changes it."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    csrc = tmp_path / "paper_2008_07140_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    (csrc / "k.h").write_text("// header\nconstexpr int kW = 4;  /* width */\n")
+    (csrc / "k.hip").write_text('#include "k.h"\n__global__ void k(int *p) { p[0] = kW; }  // store\n')
+    h0 = bench.source_hash(("k.hip",), root=str(tmp_path))
+    (csrc / "k.h").write_text("/* a longer\n   header comment */\nconstexpr int kW = 4;\n")
+    (csrc / "k.hip").write_text('#include "k.h"\n// the kernel\n__global__ void k(int *p)\n{\n    p[0] = kW;\n}\n')
+    assert bench.source_hash(("k.hip",), root=str(tmp_path)) == h0
+    (csrc / "k.h").write_text("constexpr int kW = 5;\n")
+    assert bench.source_hash(("k.hip",), root=str(tmp_path)) != h0
