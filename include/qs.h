@@ -329,7 +329,7 @@ typedef struct {
     int autotune_tried;     /* QS_PLAN_AUTOTUNE: candidates measured so far for this batch shape */
     int autotune_candidates;
     double seconds;         /* wall time of the call */
-    double host_seconds;    /* of which: planning, program build and upload of the jobs (host) */
+    double host_seconds;    /* of which: trajectory preparation, planning, program build and upload of the jobs (host) */
     double device_seconds;  /* device time of the jobs (HIP events around each) */
 } qs_traj_stats;
 

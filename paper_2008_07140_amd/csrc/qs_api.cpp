@@ -1716,6 +1716,9 @@ struct Batch {
     DevBuf states, prog, red, work;
     PinnedBuf stage, back;       // uploads (written only after the stream has drained), read-backs
     std::vector<View *> views;
+    const qs_circuit *const *circs = nullptr;  // the call's circuits and widths
+    const int *widths = nullptr;
+    std::vector<char> ready;   // trajectory prepared (prepare_some)
     int dev = 0;
     std::unique_ptr<PassSlot[]> slot;  // two, from take_slots
     bool grew = false;                 // a job had to enlarge a slot's buffers
@@ -1730,6 +1733,33 @@ struct Batch {
 };
 
 bool device_sampled(const Batch &B, int t) { return B.dt == QS_C64 && B.prep[t].n >= 10; }
+
+// Prepare the trajectories of `ts` not prepared yet, in parallel (each job's
+// just before it is built, so that preparing the rest of the batch overlaps
+// the device's work on the first jobs); the first failure is reported on
+// the calling thread.
+qs_status prepare_some(Batch &B, const std::vector<int> &ts)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<int> todo;
+    for (int t : ts)
+        if (!B.ready[size_t(t)]) todo.push_back(t);
+    std::vector<qs_status> pst(todo.size(), QS_OK);
+    parallel_for(todo.size(), [&](size_t i) {
+        const int t = todo[i];
+        pst[i] = prepare_trajectory(B.circs[t], B.widths[t], B.seed, uint64_t(t), B.prep[t]);
+    });
+    for (size_t i = 0; i < todo.size(); ++i) {
+        const int t = todo[i];
+        if (pst[i] != QS_OK) {  // again on this thread, which reports the error
+            B.prep[t] = TPrep();
+            return prepare_trajectory(B.circs[t], B.widths[t], B.seed, uint64_t(t), B.prep[t]);
+        }
+        B.ready[size_t(t)] = 1;
+    }
+    B.st.host_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return QS_OK;
+}
 
 // Plan one gate list of a trajectory: tile sweeps for complex64 states of at
 // least 10 qubits (gates wider than a tile block stay per-gate steps), the
@@ -2412,6 +2442,7 @@ qs_status run_device_sampled(Batch &B, std::vector<int> set, std::vector<int> &d
         std::vector<int> job(pending.begin() + long(head), pending.begin() + long(head + take));
         head += take;
         for (int t : job) passes = std::max(passes, ++runs[size_t(t)]);
+        if (qs_status e = prepare_some(B, job)) return e;
         if (qs_status e = launch_pass(B, P, std::move(job))) return e;
     }
     B.st.passes += passes;
@@ -2433,23 +2464,16 @@ qs_status run_trajectory_batch(const qs_circuit *const *circs, const int *widths
     B.graph = graph;
     B.seed = seed;
     B.z_out = z_out;
+    B.circs = circs;
+    B.widths = widths;
     B.prep.resize(count);
+    B.ready.assign(size_t(count), 0);
     size_t total = 0;
     for (int t = 0; t < count; ++t) {
         if (!circs[t]) return fail(QS_E_INVAL, "circuit %d is NULL", t);
         if (widths[t] < 1 || widths[t] > qs::kRunMax) return fail(QS_E_INVAL, "width %d not in [1, %d]", widths[t], qs::kRunMax);
         total += amp_bytes(dt) << widths[t];
-    }
-    {
-        std::vector<qs_status> pst(count, QS_OK);
-        parallel_for(size_t(count), [&](size_t t) {
-            pst[t] = prepare_trajectory(circs[t], widths[t], seed, uint64_t(t), B.prep[t]);
-        });
-        for (int t = 0; t < count; ++t)
-            if (pst[t] != QS_OK) {  // again on this thread, which reports the error
-                B.prep[t] = TPrep();
-                return prepare_trajectory(circs[t], widths[t], seed, uint64_t(t), B.prep[t]);
-            }
+        B.prep[t].n = widths[t];  // the rest when its job is built (prepare_some)
     }
     const size_t lim = g_mem_limit.load();
     if (lim && total > lim) return fail(QS_E_NOMEM, "batch of %zu bytes exceeds the memory limit", total);
@@ -2479,6 +2503,7 @@ qs_status run_trajectory_batch(const qs_circuit *const *circs, const int *widths
         host_set.insert(host_set.end(), demoted.begin(), demoted.end());
     }
     B.st.host_sampled = int(host_set.size());
+    if (qs_status e = prepare_some(B, host_set)) return e;
     if (qs_status e = run_host_sampled(B, host_set)) return e;
     HIP_TRY(hipStreamSynchronize(B.master->stream));
     B.st.tile_qubits = par.m_cap;

@@ -647,6 +647,27 @@ def test_batched_trajectories_wider_than_a_tile(qs):
         off += n
 
 
+def test_trajectory_error_in_a_later_job_then_a_clean_batch(qs):
+    """Trajectories are prepared job by job (at most 128 per job): a circuit
+    with a qubit beyond its trajectory's width in the second job still fails
+    the call with QS_E_RANGE, and the next call, on the job buffers kept
+    from the failed one, matches the oracle."""
+    batch = _traj_batch(6, 10, 11, 3, 920, 0.05)
+    circs = [qs.Circuit(ops) for _, ops in batch]
+    widths = [n for n, _ in batch]
+    r, c = cg.grid_shape(12)
+    bad = qs.Circuit(cg.random_circuit(r, c, 3, 921, dep1=0.05, dep2=0.05, damping=0.05))
+    with pytest.raises(qs.QSError) as err:
+        qs.run_trajectories(circs * 25 + [bad], widths * 25 + [10], dtype=qs.C64, seed=35)
+    assert err.value.status == -2  # QS_E_RANGE
+    z, _ = qs.run_trajectories(circs, widths, dtype=qs.C64, seed=35)
+    off = 0
+    for t, (n, ops) in enumerate(batch):
+        psi, _ = oracle.run(n, ops, seed=35, traj=t)
+        assert np.max(np.abs(z[off:off + n] - oracle.expect_z(psi))) <= 1e-4, (t, n)
+        off += n
+
+
 @pytest.mark.parametrize("n,T", [(12, 3), (33, 1)])
 def test_batched_trajectories_product_state_closed_form(qs, n, T):
     """Ry(theta_q) on every qubit, then amplitude damping on every qubit in
