@@ -2364,6 +2364,11 @@ qs_status launch_pass(Batch &B, PassSlot &P, std::vector<int> job)
         return hip_fail(e, "trajectory pass");
     }
     P.busy = true;
+    // the job's plans and operand pieces are many small allocations: freed
+    // in parallel (on one thread, as the locals go out of scope, about 5 ms
+    // per job of 64 trajectories, while the device waits for the next job)
+    parallel_for(all.size(), [&](size_t i) { all[i] = qs::PlanStep(); });
+    parallel_for(tp.piece.size(), [&](size_t i) { std::vector<uint16_t>().swap(tp.piece[i]); });
     B.st.host_seconds += std::chrono::duration<double>(t1 - t0).count();
     B.st.launches += nl;
     ++B.st.graphs;

@@ -26,18 +26,28 @@ __device__ __forceinline__ double wave_sum_d(double v)
     return v;
 }
 
-// WIDE: states of more than 32 qubits (64-bit index arithmetic).  A thread
-// holds the weights of NB amplitudes and walks the sites once per group, so
-// each site's qubit and a_j - 1 (uniform, scalar loads) serve NB amplitudes.
-// Per site the bit x_{q_j} enters as 0.0 / 1.0: S_j += x w and
-// w += w x (a_j - 1), two FMAs and a multiply, exact for x = 0 and one
-// rounding of w a_j for x = 1.
+// A workgroup sums one chunk of the state, in groups of NB kT amplitudes
+// i = b0 + k kT + tid (k < NB, tid < kT): chunks and so b0 are multiples of
+// NB kT, so index bits 0..7 are bits of tid, bits 8..10 bits of k and the
+// higher bits bits of b0, the same for the whole workgroup.  The factor
+// prod_{i<j} a_i^{x_{q_i}} of site j splits the same way into a per-thread
+// part fT (sites on bits 0..7), a part uK_j(k) (bits 8..10; a table in LDS
+// that also holds x_{q_j} when q_j is such a bit) and a per-group part fG
+// (higher bits), so that
+//   S_j = sum over groups and threads of fG fT x_{q_j} sum_k uK_j(k) w_k,
+// where x_{q_j} stands only when q_j is a thread or group bit: per site one
+// FP64 FMA per amplitude and a few operations per group, instead of a bit
+// test, a conversion and three operations per amplitude.  WIDE: states of
+// more than 32 qubits (64-bit group bits).
 template <typename C, bool WIDE>
 __global__ __launch_bounds__(kT) void k_run_sums(const RunSumTask *__restrict__ tasks,
                                                  const RunSumArgs *__restrict__ args, double *partials,
                                                  const int *__restrict__ active)
 {
     constexpr int NB = 8;
+    constexpr uint32_t kTBits = 8, kKBits = 3;  // index bits of tid and of k
+    static_assert(kT == 1 << kTBits && NB == 1 << kKBits, "index bits");
+    __shared__ double uk[kRunMax][NB];
     const RunSumTask task = tasks[blockIdx.x];
     const RunSumArgs &d = args[task.arg];
     if (active && !active[d.slot]) {  // a frozen trajectory: its sums are not used
@@ -47,38 +57,64 @@ __global__ __launch_bounds__(kT) void k_run_sums(const RunSumTask *__restrict__ 
     }
     const C *a = reinterpret_cast<const C *>(d.amp);
     const uint32_t *qw = reinterpret_cast<const uint32_t *>(d.q);  // four qubit bytes per word
+    auto qubit = [&](int j) { return (qw[j >> 2] >> (8 * (j & 3))) & 0xffu; };
+    const int J = d.J;
+    // uK_j(k) = prod over sites l < j on bits 8..10 set in k of a_l, times
+    // x_{q_j}(k) when q_j is one of those bits (chunks start at multiples of
+    // NB kT: the host's chunk length is 2^16)
+    for (int e = int(threadIdx.x); e < J * NB; e += kT) {
+        const int j = e / NB, k = e % NB;
+        double f = 1.0;
+        for (int l = 0; l < j; ++l) {
+            const uint32_t ql = qubit(l);
+            if (ql >= kTBits && ql < kTBits + kKBits && ((k >> (ql - kTBits)) & 1)) f = fma(f, d.am1[l], f);
+        }
+        const uint32_t qj = qubit(j);
+        if (qj >= kTBits && qj < kTBits + kKBits && !((k >> (qj - kTBits)) & 1)) f = 0.0;
+        uk[j][k] = f;
+    }
+    __syncthreads();
     const uint64_t start = uint64_t(task.chunk) * d.chunk_len;
     uint64_t end = start + d.chunk_len;
     if (end > d.n_amp) end = d.n_amp;
     double z = 0.0, S[kRunMax];
 #pragma unroll
     for (int j = 0; j < kRunMax; ++j) S[j] = 0.0;
-    for (uint64_t i0 = start + threadIdx.x; i0 < end; i0 += uint64_t(NB) * kT) {
+    for (uint64_t b0 = start; b0 < end; b0 += uint64_t(NB) * kT) {
         double w[NB];
-        uint32_t lo[NB], hi[NB];
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
-            const uint64_t i = i0 + uint64_t(k) * kT;
+            const uint64_t i = b0 + uint64_t(k) * kT + threadIdx.x;
             w[k] = 0.0;
             if (i < end) {
                 const auto v = a[i];
                 w[k] = double(v.x) * double(v.x) + double(v.y) * double(v.y);
             }
-            lo[k] = uint32_t(i);
-            hi[k] = WIDE ? uint32_t(i >> 32) : 0u;
             z += w[k];
         }
+        double fT = 1.0, fG = 1.0;
+        // the table is read where it is used, group after group (kept in
+        // registers across groups it would need 2 kRunMax NB of them)
+        asm volatile("" ::: "memory");
 #pragma unroll
         for (int j = 0; j < kRunMax; ++j)
-            if (j < d.J) {
-                const uint32_t q = (qw[j >> 2] >> (8 * (j & 3))) & 0xffu;
+            if (j < J) {
+                const uint32_t q = qubit(j);
                 const double am1 = d.am1[j];
+                double V = uk[j][0] * w[0];
 #pragma unroll
-                for (int k = 0; k < NB; ++k) {
-                    const uint32_t bit = (WIDE && q >= 32) ? (hi[k] >> (q - 32)) & 1u : (lo[k] >> q) & 1u;
-                    const double x = double(bit);
-                    S[j] = fma(x, w[k], S[j]);
-                    w[k] = fma(w[k], x * am1, w[k]);
+                for (int k = 1; k < NB; ++k) V = fma(uk[j][k], w[k], V);
+                if (q < kTBits) {
+                    const double x = double((threadIdx.x >> q) & 1u);
+                    S[j] = fma(fG * (fT * x), V, S[j]);
+                    fT = fma(fT, x * am1, fT);
+                } else if (q >= kTBits + kKBits) {
+                    if (WIDE ? ((b0 >> q) & 1u) != 0 : ((uint32_t(b0) >> q) & 1u) != 0) {
+                        S[j] = fma(fG * fT, V, S[j]);
+                        fG = fma(fG, am1, fG);
+                    }
+                } else {
+                    S[j] = fma(fG * fT, V, S[j]);
                 }
             }
     }
