@@ -14,7 +14,7 @@ constexpr int kRunMax = 36;  // qubits per run of damping-type sites (and <Z_q> 
 struct RunSumArgs {
     const void *amp;     // state of 2^n amplitudes (double2 / float2)
     uint64_t n_amp;
-    uint64_t chunk_len;  // amplitudes per workgroup (a multiple of 2048: k_run_sums reads index bits from it)
+    uint64_t chunk_len;  // amplitudes per workgroup (a multiple of 8192: k_run_sums reads index bits from it)
     int J;               // number of sites in the run
     uint32_t slot;       // trajectory slot whose activity flag gates the work (device-sampled passes)
     double am1[kRunMax]; // |K1_11|^2 - 1 of site j (0 for plain <Z> sums)

@@ -26,115 +26,148 @@ __device__ __forceinline__ double wave_sum_d(double v)
     return v;
 }
 
-// A workgroup sums one chunk of the state, in groups of NB kT amplitudes
-// i = b0 + k kT + tid (k < NB, tid < kT): chunks and so b0 are multiples of
-// NB kT, so index bits 0..7 are bits of tid, bits 8..10 bits of k and the
-// higher bits bits of b0, the same for the whole workgroup.  The factor
-// prod_{i<j} a_i^{x_{q_i}} of site j splits the same way into a per-thread
-// part fT (sites on bits 0..7), a part uK_j(k) (bits 8..10; a table in LDS
-// that also holds x_{q_j} when q_j is such a bit) and a per-group part fG
-// (higher bits), so that
-//   S_j = sum over groups and threads of fG fT x_{q_j} sum_k uK_j(k) w_k,
-// where x_{q_j} stands only when q_j is a thread or group bit: per site one
-// FP64 FMA per amplitude and a few operations per group, instead of a bit
-// test, a conversion and three operations per amplitude.  WIDE: states of
-// more than 32 qubits (64-bit group bits).
-template <typename C, bool WIDE>
+// A workgroup sums one chunk of the state in passes of NG NB kT amplitudes
+// i = b0 + g NB kT + k kT + tid (g < NG, k < NB, tid < kT): chunks and so b0
+// are multiples of NG NB kT, so index bits 0..7 are bits of tid, bits
+// 8..10 bits of k, bits 11..12 bits of g and the higher bits bits of b0,
+// the same for the whole workgroup.  The factor prod_{i<j} a_i^{x_{q_i}} of
+// site j splits the same way into a per-thread part fT (sites on bits
+// 0..7), a part uK_j(k) (bits 8..10; a table in LDS that also holds
+// x_{q_j} when q_j is such a bit) and per-g parts fG_g (higher bits), so
+//   S_j = sum over passes and threads of fT x sum_g fG_g sum_k uK_j(k) w_gk,
+// where x = x_{q_j} stands when q_j is a thread, g or b0 bit: per site one
+// FP64 FMA per amplitude and a few operations per g.  The sites' qubits,
+// a_j - 1 and the table sit in LDS, so a pass waits on no scalar load, and
+// each thread keeps NG NB = 32 loads in flight.  JM: the most sites of a
+// run (at most the widest state); WIDE: states of more than 32 qubits.
+template <typename C, bool WIDE, int JM>
 __global__ __launch_bounds__(kT) void k_run_sums(const RunSumTask *__restrict__ tasks,
                                                  const RunSumArgs *__restrict__ args, double *partials,
                                                  const int *__restrict__ active)
 {
-    constexpr int NB = 8;
-    constexpr uint32_t kTBits = 8, kKBits = 3;  // index bits of tid and of k
-    static_assert(kT == 1 << kTBits && NB == 1 << kKBits, "index bits");
-    __shared__ double uk[kRunMax][NB];
+    constexpr int NB = 8, NG = 4;
+    constexpr uint32_t kTBits = 8, kKBits = 3, kGBits = 2;
+    static_assert(kT == 1 << kTBits && NB == 1 << kKBits && NG == 1 << kGBits, "index bits");
+    static_assert(JM <= kRunMax, "sites");
+    constexpr uint64_t kPass = uint64_t(NG) * NB * kT;
+    __shared__ double s_uk[JM][NB];
+    __shared__ double s_am1[JM];
+    __shared__ uint32_t s_q[JM];
+    __shared__ double s_red[kT / 64][JM + 1];
     const RunSumTask task = tasks[blockIdx.x];
     const RunSumArgs &d = args[task.arg];
+    double *out = partials + uint64_t(blockIdx.x) * (kRunMax + 1);
     if (active && !active[d.slot]) {  // a frozen trajectory: its sums are not used
-        double *out = partials + uint64_t(blockIdx.x) * (kRunMax + 1);
         for (int v = threadIdx.x; v <= d.J; v += kT) out[v] = 0.0;
         return;
     }
     const C *a = reinterpret_cast<const C *>(d.amp);
-    const uint32_t *qw = reinterpret_cast<const uint32_t *>(d.q);  // four qubit bytes per word
-    auto qubit = [&](int j) { return (qw[j >> 2] >> (8 * (j & 3))) & 0xffu; };
-    const int J = d.J;
-    // uK_j(k) = prod over sites l < j on bits 8..10 set in k of a_l, times
-    // x_{q_j}(k) when q_j is one of those bits (chunks start at multiples of
-    // NB kT: the host's chunk length is 2^16)
-    for (int e = int(threadIdx.x); e < J * NB; e += kT) {
-        const int j = e / NB, k = e % NB;
-        double f = 1.0;
-        for (int l = 0; l < j; ++l) {
-            const uint32_t ql = qubit(l);
-            if (ql >= kTBits && ql < kTBits + kKBits && ((k >> (ql - kTBits)) & 1)) f = fma(f, d.am1[l], f);
-        }
-        const uint32_t qj = qubit(j);
-        if (qj >= kTBits && qj < kTBits + kKBits && !((k >> (qj - kTBits)) & 1)) f = 0.0;
-        uk[j][k] = f;
+    const int J = d.J;  // at most JM (the host picks JM from the widest state)
+    if (int(threadIdx.x) < J) {
+        s_q[threadIdx.x] = uint32_t(d.q[threadIdx.x]);
+        s_am1[threadIdx.x] = d.am1[threadIdx.x];
     }
     __syncthreads();
-    const uint64_t start = uint64_t(task.chunk) * d.chunk_len;
+    // uK_j(k) = prod over sites l < j on bits 8..10 set in k of a_l, times
+    // x_{q_j}(k) when q_j is one of those bits
+    if (threadIdx.x < NB) {
+        const int k = int(threadIdx.x);
+        double f = 1.0;
+        for (int j = 0; j < J; ++j) {
+            const uint32_t q = s_q[j];
+            const bool kb = q >= kTBits && q < kTBits + kKBits;
+            const bool bit = kb && ((k >> (q - kTBits)) & 1);
+            s_uk[j][k] = (kb && !bit) ? 0.0 : f;
+            if (bit) f = fma(f, s_am1[j], f);
+        }
+    }
+    __syncthreads();
+    const uint64_t start = uint64_t(task.chunk) * d.chunk_len;  // a multiple of kPass
     uint64_t end = start + d.chunk_len;
     if (end > d.n_amp) end = d.n_amp;
-    double z = 0.0, S[kRunMax];
+    double z = 0.0, S[JM];
 #pragma unroll
-    for (int j = 0; j < kRunMax; ++j) S[j] = 0.0;
-    for (uint64_t b0 = start; b0 < end; b0 += uint64_t(NB) * kT) {
-        double w[NB];
+    for (int j = 0; j < JM; ++j) S[j] = 0.0;
+    for (uint64_t b0 = start; b0 < end; b0 += kPass) {
+        double w[NG][NB];
 #pragma unroll
-        for (int k = 0; k < NB; ++k) {
-            const uint64_t i = b0 + uint64_t(k) * kT + threadIdx.x;
-            w[k] = 0.0;
-            if (i < end) {
-                const auto v = a[i];
-                w[k] = double(v.x) * double(v.x) + double(v.y) * double(v.y);
+        for (int g = 0; g < NG; ++g)
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                const uint64_t i = b0 + uint64_t(g * NB + k) * kT + threadIdx.x;
+                w[g][k] = 0.0;
+                if (i < end) {
+                    const auto v = a[i];
+                    w[g][k] = double(v.x) * double(v.x) + double(v.y) * double(v.y);
+                }
+                z += w[g][k];
             }
-            z += w[k];
-        }
-        double fT = 1.0, fG = 1.0;
-        // the table is read where it is used, group after group (kept in
-        // registers across groups it would need 2 kRunMax NB of them)
+        double fT = 1.0, fG[NG];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) fG[g] = 1.0;
+        // the site data is read where it is used, pass after pass (kept in
+        // registers across passes it would take JM (NB + 2) of them)
         asm volatile("" ::: "memory");
 #pragma unroll
-        for (int j = 0; j < kRunMax; ++j)
+        for (int j = 0; j < JM; ++j)
             if (j < J) {
-                const uint32_t q = qubit(j);
-                const double am1 = d.am1[j];
-                double V = uk[j][0] * w[0];
+                const uint32_t q = __builtin_amdgcn_readfirstlane(s_q[j]);
+                const double am1 = s_am1[j];
+                double V[NG];
 #pragma unroll
-                for (int k = 1; k < NB; ++k) V = fma(uk[j][k], w[k], V);
-                if (q < kTBits) {
-                    const double x = double((threadIdx.x >> q) & 1u);
-                    S[j] = fma(fG * (fT * x), V, S[j]);
-                    fT = fma(fT, x * am1, fT);
-                } else if (q >= kTBits + kKBits) {
-                    if (WIDE ? ((b0 >> q) & 1u) != 0 : ((uint32_t(b0) >> q) & 1u) != 0) {
-                        S[j] = fma(fG * fT, V, S[j]);
-                        fG = fma(fG, am1, fG);
+                for (int g = 0; g < NG; ++g) {
+                    V[g] = s_uk[j][0] * w[g][0];
+#pragma unroll
+                    for (int k = 1; k < NB; ++k) V[g] = fma(s_uk[j][k], w[g][k], V[g]);
+                }
+                if (q < kTBits + kKBits) {  // x in fT (thread bit) or in the table (k bit)
+                    double T = fG[0] * V[0];
+#pragma unroll
+                    for (int g = 1; g < NG; ++g) T = fma(fG[g], V[g], T);
+                    if (q < kTBits) {
+                        const double x = double((threadIdx.x >> q) & 1u);
+                        S[j] = fma(fT * x, T, S[j]);
+                        fT = fma(fT, x * am1, fT);
+                    } else {
+                        S[j] = fma(fT, T, S[j]);
                     }
-                } else {
-                    S[j] = fma(fG * fT, V, S[j]);
+                } else if (q == kTBits + kKBits) {  // bit 0 of g
+#pragma unroll
+                    for (int g = 1; g < NG; g += 2) {
+                        S[j] = fma(fT * fG[g], V[g], S[j]);
+                        fG[g] = fma(fG[g], am1, fG[g]);
+                    }
+                } else if (q == kTBits + kKBits + 1) {  // bit 1 of g
+#pragma unroll
+                    for (int g = NG / 2; g < NG; ++g) {
+                        S[j] = fma(fT * fG[g], V[g], S[j]);
+                        fG[g] = fma(fG[g], am1, fG[g]);
+                    }
+                } else if (WIDE ? ((b0 >> q) & 1u) != 0 : ((uint32_t(b0) >> q) & 1u) != 0) {
+#pragma unroll
+                    for (int g = 0; g < NG; ++g) {
+                        S[j] = fma(fT * fG[g], V[g], S[j]);
+                        fG[g] = fma(fG[g], am1, fG[g]);
+                    }
                 }
             }
     }
-    __shared__ double lds[kT / 64];
-    double *out = partials + uint64_t(blockIdx.x) * (kRunMax + 1);
-    auto reduce = [&](double v, int slot) {
-        v = wave_sum_d(v);
-        __syncthreads();
-        if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double s = 0.0;
-            for (int k = 0; k < kT / 64; ++k) s += lds[k];
-            out[slot] = s;
-        }
-    };
-    reduce(z, 0);
+    // one barrier: each wave sums its lanes, then thread v adds the waves' v-th sums
+    const int lane = int(threadIdx.x & 63), wave = int(threadIdx.x >> 6);
+    z = wave_sum_d(z);
+    if (lane == 0) s_red[wave][0] = z;
 #pragma unroll
-    for (int j = 0; j < kRunMax; ++j)
-        if (j < d.J) reduce(S[j], 1 + j);
+    for (int j = 0; j < JM; ++j)
+        if (j < J) {
+            const double v = wave_sum_d(S[j]);
+            if (lane == 0) s_red[wave][1 + j] = v;
+        }
+    __syncthreads();
+    if (int(threadIdx.x) <= J) {
+        double s = 0.0;
+        for (int k = 0; k < kT / 64; ++k) s += s_red[k][threadIdx.x];
+        out[threadIdx.x] = s;
+    }
 }
 
 // out[t * (kRunMax + 1) + v] = sum of partials over the workgroups of state t
@@ -211,21 +244,16 @@ hipError_t launch_run_sums(qs_dtype dt, int nmax, uint32_t ntasks, const RunSumT
                            double *partials, const int *active, hipStream_t st)
 {
     if (ntasks == 0) return hipSuccess;
-    const bool wide = nmax > 32;
-    if (dt == QS_C128) {
-        if (wide)
-            hipLaunchKernelGGL((k_run_sums<double2, true>), dim3(ntasks), dim3(kT), 0, st, tasks, args, partials,
-                               active);
-        else
-            hipLaunchKernelGGL((k_run_sums<double2, false>), dim3(ntasks), dim3(kT), 0, st, tasks, args, partials,
-                               active);
-    } else {
-        if (wide)
-            hipLaunchKernelGGL((k_run_sums<float2, true>), dim3(ntasks), dim3(kT), 0, st, tasks, args, partials,
-                               active);
-        else
-            hipLaunchKernelGGL((k_run_sums<float2, false>), dim3(ntasks), dim3(kT), 0, st, tasks, args, partials,
-                               active);
+    if (nmax < 1 || nmax > kRunMax) return hipErrorInvalidValue;
+    // a run's sites sit on distinct qubits: at most nmax of them
+    const int v = (nmax > 32 ? 2 : nmax > 24 ? 1 : 0) + (dt == QS_C128 ? 3 : 0);
+    switch (v) {
+    case 0: hipLaunchKernelGGL((k_run_sums<float2, false, 24>), dim3(ntasks), dim3(kT), 0, st, tasks, args, partials, active); break;
+    case 1: hipLaunchKernelGGL((k_run_sums<float2, false, 36>), dim3(ntasks), dim3(kT), 0, st, tasks, args, partials, active); break;
+    case 2: hipLaunchKernelGGL((k_run_sums<float2, true, 36>), dim3(ntasks), dim3(kT), 0, st, tasks, args, partials, active); break;
+    case 3: hipLaunchKernelGGL((k_run_sums<double2, false, 24>), dim3(ntasks), dim3(kT), 0, st, tasks, args, partials, active); break;
+    case 4: hipLaunchKernelGGL((k_run_sums<double2, false, 36>), dim3(ntasks), dim3(kT), 0, st, tasks, args, partials, active); break;
+    default: hipLaunchKernelGGL((k_run_sums<double2, true, 36>), dim3(ntasks), dim3(kT), 0, st, tasks, args, partials, active); break;
     }
     return hipGetLastError();
 }
