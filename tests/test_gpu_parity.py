@@ -668,15 +668,17 @@ def test_trajectory_error_in_a_later_job_then_a_clean_batch(qs):
         off += n
 
 
-@pytest.mark.parametrize("n,T", [(12, 3), (33, 1)])
-def test_batched_trajectories_product_state_closed_form(qs, n, T):
+@pytest.mark.parametrize("n,T,dtype", [(12, 3, "c64"), (28, 1, "c64"), (33, 1, "c64"),
+                                       (12, 3, "c128"), (26, 1, "c128"), (33, 1, "c128")])
+def test_batched_trajectories_product_state_closed_form(qs, n, T, dtype):
     """Ry(theta_q) on every qubit, then amplitude damping on every qubit in
     ascending order (one run of n damping sites): the state stays a product
     state, so each trajectory is n independent one-qubit Sec. 2.4 steps with
     the same Philox draws (site q is the q-th damping site), done here per
-    qubit with the oracle's one-qubit noisy gate.  At 33 qubits (a 64 GiB
-    complex64 state) the run sums take their 64-bit-index kernel.  The batch
-    run twice gives bit-identical results."""
+    qubit with the oracle's one-qubit noisy gate.  The widths reach every
+    form of the run-sum kernel: runs of up to 24 or 36 sites, and at 33
+    qubits (a 64 GiB complex64 or 128 GiB complex128 state) 64-bit group
+    bits.  The batch run twice gives bit-identical results."""
     rng = np.random.default_rng(5150 + n)
     theta = rng.uniform(0.0, np.pi, n)
     gamma = rng.uniform(0.05, 0.6, n)
@@ -686,7 +688,9 @@ def test_batched_trajectories_product_state_closed_form(qs, n, T):
         ops.append(cg.Noise((q,), cg.kraus_amplitude_damping(gamma[q]), "amplitude_damping"))
     c = qs.Circuit(ops)
     seed = 91
-    z, _ = qs.run_trajectories([c] * T, [n] * T, dtype=qs.C64, seed=seed)
+    dt = qs.C64 if dtype == "c64" else qs.C128
+    tol = 1e-4 if dtype == "c64" else 1e-9
+    z, _ = qs.run_trajectories([c] * T, [n] * T, dtype=dt, seed=seed)
     for t in range(T):
         want = np.empty(n)
         for q in range(n):
@@ -695,9 +699,9 @@ def test_batched_trajectories_product_state_closed_form(qs, n, T):
                                oracle.uniform(seed, t, q))
             p0, p1 = abs(psi[0]) ** 2, abs(psi[1]) ** 2
             want[q] = (p0 - p1) / (p0 + p1)
-        assert np.max(np.abs(z[t * n:(t + 1) * n] - want)) <= 1e-4, t
+        assert np.max(np.abs(z[t * n:(t + 1) * n] - want)) <= tol, t
     if n <= 16:
-        z2, _ = qs.run_trajectories([c] * T, [n] * T, dtype=qs.C64, seed=seed)
+        z2, _ = qs.run_trajectories([c] * T, [n] * T, dtype=dt, seed=seed)
         assert np.array_equal(z, z2)
 
 
