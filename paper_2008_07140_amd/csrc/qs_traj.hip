@@ -89,17 +89,25 @@ __global__ __launch_bounds__(kT) void k_run_sums(const RunSumTask *__restrict__ 
 #pragma unroll
     for (int j = 0; j < JM; ++j) S[j] = 0.0;
     for (uint64_t b0 = start; b0 < end; b0 += kPass) {
+        // all NG NB loads are issued before any is used: an index past the
+        // chunk reads the chunk's first amplitude and its weight is zeroed
+        // (a load under a branch would be waited for on its own)
+        C v[NG][NB];
+#pragma unroll
+        for (int g = 0; g < NG; ++g)
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                const uint64_t i = b0 + uint64_t(g * NB + k) * kT + threadIdx.x;
+                v[g][k] = a[i < end ? i : start];
+            }
         double w[NG][NB];
 #pragma unroll
         for (int g = 0; g < NG; ++g)
 #pragma unroll
             for (int k = 0; k < NB; ++k) {
                 const uint64_t i = b0 + uint64_t(g * NB + k) * kT + threadIdx.x;
-                w[g][k] = 0.0;
-                if (i < end) {
-                    const auto v = a[i];
-                    w[g][k] = double(v.x) * double(v.x) + double(v.y) * double(v.y);
-                }
+                const C u = v[g][k];
+                w[g][k] = i < end ? double(u.x) * double(u.x) + double(u.y) * double(u.y) : 0.0;
                 z += w[g][k];
             }
         double fT = 1.0, fG[NG];
