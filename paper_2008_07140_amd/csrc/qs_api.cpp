@@ -1425,6 +1425,37 @@ bool scalar_channel(const std::vector<double> &kr, int nk, int nt, std::vector<d
     return true;
 }
 
+// scalar_channel for trajectory preparation: a circuit repeats a few
+// channels at many sites, and the answer depends only on the Kraus
+// matrices, so the last few answers are kept per thread (compared by
+// content; the K_b^dagger K_b products of a two-qubit depolarizing channel
+// are otherwise most of a trajectory's preparation).
+bool scalar_channel_cached(const std::vector<double> &kr, int nk, int nt, std::vector<double> &c)
+{
+    struct Entry {
+        int nk = -1, nt = -1;
+        bool ok = false;
+        std::vector<double> kr, c;
+    };
+    constexpr int kEntries = 4;
+    thread_local Entry cache[kEntries];
+    thread_local int next = 0;
+    for (const Entry &e : cache)
+        if (e.nk == nk && e.nt == nt && e.kr.size() == kr.size() &&
+            std::memcmp(e.kr.data(), kr.data(), kr.size() * sizeof(double)) == 0) {
+            c = e.c;
+            return e.ok;
+        }
+    Entry &e = cache[next];
+    next = (next + 1) % kEntries;
+    e.ok = scalar_channel(kr, nk, nt, e.c);
+    e.nk = nk;
+    e.nt = nt;
+    e.kr = kr;
+    c = e.c;
+    return e.ok;
+}
+
 // two one-qubit Kraus operators, K1 = diag(1, k), K2 acting only on |1>
 bool damping_channel(const std::vector<double> &kr, int nk, int nt, double &a)
 {
@@ -1481,7 +1512,7 @@ qs_status prepare_trajectory(const qs_circuit *c, int n, uint64_t seed, uint64_t
         const double u = qs::noise_uniform(seed, traj, site);
         std::vector<double> cb;
         double a = 0;
-        if (scalar_channel(f.m, f.nk, nt, cb)) {
+        if (scalar_channel_cached(f.m, f.nk, nt, cb)) {
             const int b = pick_branch(cb, u);
             if (b < 0) return fail(QS_E_ZERO_NORM, "every Kraus branch has probability 0");
             const int d = 1 << nt;
