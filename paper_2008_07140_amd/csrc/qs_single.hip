@@ -330,27 +330,37 @@ __global__ __launch_bounds__(kT) void k_sa_tile(SaContract c)
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
+        // 512 entries per operand and k-step: with k lowest, eight
+        // neighbouring lanes read one row's eight summed entries; with the
+        // own index lowest, 64 neighbouring lanes read one summed entry of 64
+        // rows.  A thread's four loads are issued together (addresses by
+        // select, no load under a branch), and the next k-step's are in
+        // flight while this one is multiplied.
+        const int e0 = int(threadIdx.x), e1 = int(threadIdx.x) + kT;
+        auto xat = [&](uint64_t k0, int e) -> uint64_t {
+            return c.xo ? (((k0 + uint64_t(e >> 6)) << c.nm) + uint64_t(e & 63))
+                        : ((uint64_t(e >> 3) << c.nk) + k0 + uint64_t(e & 7));
+        };
+        auto yat = [&](uint64_t k0, int e) -> uint64_t {
+            return c.yo ? (((k0 + uint64_t(e >> 6)) << c.nn) + uint64_t(e & 63))
+                        : ((uint64_t(e >> 3) << c.nk) + k0 + uint64_t(e & 7));
+        };
+        double2 x0 = xp[xat(0, e0)], x1 = xp[xat(0, e1)], y0 = yp[yat(0, e0)], y1 = yp[yat(0, e1)];
+        // LDS slot of entry e: [k][row]
+        const int xk0 = c.xo ? e0 >> 6 : e0 & 7, xr0 = c.xo ? e0 & 63 : e0 >> 3;
+        const int xk1 = c.xo ? e1 >> 6 : e1 & 7, xr1 = c.xo ? e1 & 63 : e1 >> 3;
+        const int yk0 = c.yo ? e0 >> 6 : e0 & 7, yr0 = c.yo ? e0 & 63 : e0 >> 3;
+        const int yk1 = c.yo ? e1 >> 6 : e1 & 7, yr1 = c.yo ? e1 & 63 : e1 >> 3;
         for (uint64_t k0 = 0; k0 < K; k0 += 8) {
-            // 512 entries per operand: with k lowest, eight neighbouring lanes
-            // read one row's eight summed entries; with the own index lowest,
-            // 64 neighbouring lanes read one summed entry of 64 rows
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int e = threadIdx.x + h * kT;
-                if (c.xo) {
-                    const int row = e & 63, kk = e >> 6;
-                    xs[kk][row] = xp[((k0 + kk) << c.nm) + row];
-                } else {
-                    const int row = e >> 3, kk = e & 7;
-                    xs[kk][row] = xp[(uint64_t(row) << c.nk) + k0 + kk];
-                }
-                if (c.yo) {
-                    const int row = e & 63, kk = e >> 6;
-                    ys[kk][row] = yp[((k0 + kk) << c.nn) + row];
-                } else {
-                    const int row = e >> 3, kk = e & 7;
-                    ys[kk][row] = yp[(uint64_t(row) << c.nk) + k0 + kk];
-                }
+            xs[xk0][xr0] = x0;
+            xs[xk1][xr1] = x1;
+            ys[yk0][yr0] = y0;
+            ys[yk1][yr1] = y1;
+            if (k0 + 8 < K) {
+                x0 = xp[xat(k0 + 8, e0)];
+                x1 = xp[xat(k0 + 8, e1)];
+                y0 = yp[yat(k0 + 8, e0)];
+                y1 = yp[yat(k0 + 8, e1)];
             }
             __syncthreads();
 #pragma unroll
