@@ -186,8 +186,19 @@ __global__ __launch_bounds__(kT) void k_run_sums_finish(const double *partials, 
     const int w = kRunMax + 1;
     for (int idx = blockIdx.x * kT + threadIdx.x; idx < nstates * w; idx += gridDim.x * kT) {
         const int t = idx / w, v = idx % w;
+        const uint32_t n = count[t];
+        const double *p = partials + uint64_t(first[t]) * w + v;
         double s = 0.0;
-        for (uint32_t b = 0; b < count[t]; ++b) s += partials[uint64_t(first[t] + b) * w + v];
+        uint32_t b = 0;
+        // eight loads in flight at a time, added in the same order as one by one
+        for (; b + 8 <= n; b += 8) {
+            double q[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) q[k] = p[uint64_t(b + k) * w];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) s += q[k];
+        }
+        for (; b < n; ++b) s += p[uint64_t(b) * w];
         out[idx] = s;
     }
 }
