@@ -217,44 +217,56 @@ __global__ __launch_bounds__(kT) void k_sample_runs(const SampleArgs *__restrict
                                                     int *active, Freeze *freeze, int *err)
 {
 #pragma clang fp contract(off)
-    const uint32_t i = blockIdx.x * kT + threadIdx.x;
-    if (i >= count) return;
+    // one wave per run, lane j for site j: every site's draw and branch are
+    // computed at once, each against the norm left if all earlier sites took
+    // K1 (Z_j = Z - c_0 S_0 - ... - c_{j-1} S_{j-1}, subtracted in that
+    // order, as a walk over the sites would); the first site that does not
+    // take K1 decides, exactly as the walk stops there
+    static_assert(kRunMax <= 64, "a site per lane");
+    const uint32_t i = blockIdx.x * (kT / 64) + (threadIdx.x >> 6);
+    const int j = int(threadIdx.x & 63);
+    if (i >= count) return;  // whole waves
     const SampleArgs s = sa[i];
     if (!active[s.slot]) return;
     const RunSumArgs &d = args[s.arg];
     const double *row = sums + uint64_t(s.row) * (kRunMax + 1);
-    double Z = row[0];
-    for (int j = 0; j < d.J; ++j) {
+    const int J = d.J;
+    double cs = 0.0;
+    if (j < J) {
         const double c = -d.am1[j];
         const double S = row[1 + j];
-        const double cs = c * S;
+        cs = c * S;
+    }
+    double Z = row[0];
+    for (int k = 0; k + 1 < J; ++k) {
+        const double ck = __shfl(cs, k);
+        if (k < j) Z -= ck;
+    }
+    int b = 0;
+    if (j < J) {
         const double p2 = cs / Z;
         const double p1 = (Z - cs) / Z;
         const double u = noise_uniform(seed, s.traj, s.site[j]);
-        int b;
         if (u < p1)
             b = 0;
         else if (u < p1 + p2)
             b = 1;
         else
             b = p2 > 0.0 ? 1 : (p1 > 0.0 ? 0 : -1);
-        if (b == 0) {
-            Z -= cs;
-            continue;
-        }
-        if (b < 0) {
-            err[0] = 1;
-            active[s.slot] = 0;
-            return;
-        }
-        Freeze f;
-        f.step = int32_t(s.step);
-        f.j = j;
-        f.nrm2 = cs;
-        freeze[s.slot] = f;
+    }
+    const uint64_t stop = __ballot(b != 0);
+    if (!stop || j != __builtin_ctzll(stop)) return;
+    if (b < 0) {
+        err[0] = 1;
         active[s.slot] = 0;
         return;
     }
+    Freeze f;
+    f.step = int32_t(s.step);
+    f.j = j;
+    f.nrm2 = cs;
+    freeze[s.slot] = f;
+    active[s.slot] = 0;
 }
 
 }  // namespace
@@ -281,8 +293,9 @@ hipError_t launch_sample_runs(const SampleArgs *sa, uint32_t count, const RunSum
                               uint64_t seed, int *active, Freeze *freeze, int *err, hipStream_t st)
 {
     if (count == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sample_runs, dim3((count + kT - 1) / kT), dim3(kT), 0, st, sa, count, args, sums, seed,
-                       active, freeze, err);
+    constexpr uint32_t runs_per_block = kT / 64;  // one wave per run
+    hipLaunchKernelGGL(k_sample_runs, dim3((count + runs_per_block - 1) / runs_per_block), dim3(kT), 0, st, sa,
+                       count, args, sums, seed, active, freeze, err);
     return hipGetLastError();
 }
 
