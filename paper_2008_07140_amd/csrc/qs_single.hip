@@ -107,33 +107,6 @@ __device__ __forceinline__ uint64_t y_row(const SaContract &c, uint64_t a)
     return row_start(extract(a, c.nb, c.pb), extract(a, c.nn, c.pn), c.nn, c.nk, c.yo);
 }
 
-// The contract's bit positions copied to LDS once per workgroup: the
-// per-kernel row offsets walk them bit by bit, and read from the argument
-// block each step was a memory round trip of its own.
-struct SaPosLds {
-    uint8_t b[kSaMaxBits], m[kSaMaxBits], n[kSaMaxBits];
-};
-
-__device__ __forceinline__ void stage_positions(const SaContract &c, SaPosLds &p)
-{
-    for (int i = int(threadIdx.x); i < 3 * kSaMaxBits; i += kT) {
-        const int w = i / kSaMaxBits, j = i % kSaMaxBits;
-        const uint8_t v = w == 0 ? c.pb[j] : w == 1 ? c.pm[j] : c.pn[j];
-        (w == 0 ? p.b : w == 1 ? p.m : p.n)[j] = v;
-    }
-    __syncthreads();
-}
-
-__device__ __forceinline__ uint64_t x_row(const SaContract &c, const SaPosLds &p, uint64_t a)
-{
-    return row_start(extract(a, c.nb, p.b), extract(a, c.nm, p.m), c.nm, c.nk, c.xo);
-}
-
-__device__ __forceinline__ uint64_t y_row(const SaContract &c, const SaPosLds &p, uint64_t a)
-{
-    return row_start(extract(a, c.nb, p.b), extract(a, c.nn, p.n), c.nn, c.nk, c.yo);
-}
-
 // The per-result form for results of at least 2^8 entries: a wave takes
 // blocks of 256 consecutive results (storage order), R = 4 per lane, lane l
 // and step r on result 64 r + l of the block.  The row offsets of the block
@@ -155,14 +128,12 @@ __global__ __launch_bounds__(kT) void k_sa_rows(SaContract c)
     const double2 *__restrict__ Y = c.y;
     double2 *__restrict__ Z = c.z;
     const uint32_t lane = threadIdx.x & 63;
-    __shared__ SaPosLds pos;
-    stage_positions(c, pos);
-    const uint64_t lx = x_row(c, pos, lane), ly = y_row(c, pos, lane);
+    const uint64_t lx = x_row(c, lane), ly = y_row(c, lane);
     uint64_t rx[R], ry[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        rx[r] = x_row(c, pos, uint64_t(r) << 6);
-        ry[r] = y_row(c, pos, uint64_t(r) << 6);
+        rx[r] = x_row(c, uint64_t(r) << 6);
+        ry[r] = y_row(c, uint64_t(r) << 6);
     }
     const uint64_t w0 = __builtin_amdgcn_readfirstlane(blockIdx.x * (kT / 64) + (threadIdx.x >> 6));
     const uint64_t nw = uint64_t(gridDim.x) * (kT / 64);
@@ -224,13 +195,11 @@ __global__ __launch_bounds__(kT) void k_sa_pairs(SaContract c)
     double2 *__restrict__ Z = c.z;
     const uint32_t lane = threadIdx.x & 63, k = lane & 1;
     const uint32_t zl = (lane >> 1) + (k << 5);  // result of this lane within 64
-    __shared__ SaPosLds pos;
-    stage_positions(c, pos);
     uint64_t rx[R], ry[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        rx[r] = x_row(c, pos, uint64_t(r) << 6);
-        ry[r] = y_row(c, pos, uint64_t(r) << 6);
+        rx[r] = x_row(c, uint64_t(r) << 6);
+        ry[r] = y_row(c, uint64_t(r) << 6);
     }
     const uint64_t w0 = __builtin_amdgcn_readfirstlane(blockIdx.x * (kT / 64) + (threadIdx.x >> 6));
     const uint64_t nw = uint64_t(gridDim.x) * (kT / 64);
